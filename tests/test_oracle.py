@@ -1,0 +1,333 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: a second,
+independent route to the same quantity (FFT vs plane-wave convolution vs
+explicit real-space sums), a closed form (plasmon formula, rank-one case,
+second-order limit), an identity of the method (full subspace = full basis,
+projected static matrix = eigenvalues) or an invariant (Hermiticity,
+negative semidefiniteness, monotonicity in the subspace size, signs).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import rpa
+from synth import systems as sy
+
+
+@pytest.fixture(scope="module")
+def small():
+    spec = sy.small_spec()
+    s = sy.make_system(spec, 7)
+    w, mchi = rpa.w_matrix(s.a, s.fft, s.miller, s.coeff, s.n_v, s.ecut_chi)
+    d = np.array([s.energy[s.n_v + c] - s.energy[v]
+                  for v in range(s.n_v) for c in range(s.n_c)])
+    return s, w, mchi, d
+
+
+# ---------------------------------------------------------------- quadrature
+
+def test_gauss_legendre_matches_library_and_is_exact():
+    for n in (4, 16, 20, 64):
+        x, w = rpa.gauss_legendre(n)
+        xl, wl = np.polynomial.legendre.leggauss(n)
+        assert np.max(np.abs(np.sort(x) - xl)) < 1e-14
+        assert np.max(np.abs(w[np.argsort(x)] - wl)) < 1e-14
+        assert abs(np.sum(w) - 2.0) < 1e-14
+        for k in range(0, 2 * n):          # exact through degree 2n - 1
+            exact = 0.0 if k % 2 else 2.0 / (k + 1)
+            assert abs(np.dot(w, x ** k) - exact) < 1e-13
+
+
+def test_semi_infinite_rule():
+    om, wt = rpa.semi_infinite_rule(64)
+    assert abs(np.dot(wt, 1.0 / (1.0 + om ** 2)) - math.pi / 2) < 1e-12
+    assert abs(np.dot(wt, 1.0 / (1.0 + om) ** 2) - 1.0) < 1e-12
+    om2, wt2 = sy.frequency_grid(16)
+    o3, w3 = rpa.semi_infinite_rule(16)
+    assert np.allclose(np.sort(om2), np.sort(o3), rtol=1e-13)
+    assert np.allclose(wt2[np.argsort(om2)], w3[np.argsort(o3)], rtol=1e-12)
+
+
+# ------------------------------------------------------ pair matrix (Eq. 3)
+
+def test_pair_matrix_three_independent_routes(small):
+    s, w, mchi, _ = small
+    cv, cc = s.coeff[: s.n_v], s.coeff[s.n_v:]
+    psi = rpa.orbitals_realspace(s.a, s.fft, s.miller, s.coeff)
+    m_fft = rpa.pair_matrix_fft(s.a, s.fft, psi[: s.n_v], psi[s.n_v:], mchi)
+    m_conv = rpa.pair_matrix_convolution(s.miller, cv, cc, mchi)
+    m_brute = rpa.pair_matrix_realspace_bruteforce(
+        s.a, s.fft, s.miller, cv[:2], cc[:5], mchi)
+    scale = np.max(np.abs(m_conv))
+    assert scale > 1e-3
+    assert np.max(np.abs(m_fft - m_conv)) < 1e-14 * max(1.0, scale) * 10
+    assert np.max(np.abs(m_brute - m_conv[:2, :5])) < 1e-13
+
+
+def test_pair_matrix_aliases_on_a_too_small_grid(small):
+    s, _, mchi, _ = small
+    npsi = int(np.max(np.abs(s.miller)))
+    nchi = int(np.max(np.abs(mchi)))
+    bad = 2 * npsi + nchi  # one short of the alias-free bound
+    psi = rpa.orbitals_realspace(s.a, (bad,) * 3, s.miller, s.coeff)
+    m_bad = rpa.pair_matrix_fft(s.a, (bad,) * 3, psi[:1], psi[s.n_v:],
+                                mchi)
+    m_conv = rpa.pair_matrix_convolution(s.miller, s.coeff[:1],
+                                         s.coeff[s.n_v:], mchi)
+    assert np.max(np.abs(m_bad - m_conv)) > 1e-8
+
+
+def test_pair_matrix_at_g0_is_overlap(small):
+    s, *_ = small
+    g0 = np.zeros((1, 3), dtype=np.int64)
+    psi = rpa.orbitals_realspace(s.a, s.fft, s.miller, s.coeff)
+    m = rpa.pair_matrix_fft(s.a, s.fft, psi, psi, g0)[:, :, 0]
+    assert np.max(np.abs(m - np.eye(s.n_bands))) < 1e-13
+
+
+def test_chi_gvector_count_closed_shells():
+    # |n|^2 <= 17, 97, 244 hold 305, 3959, 15967 lattice points with G = 0.
+    for spec, ng in ((sy.TINY, 304), (sy.MEDIUM, 3958),
+                     (sy.LARGE_SHARE, 15966)):
+        if ng > 5000:
+            continue  # the python triple loop is slow; counted in synth
+        m = rpa.chi_gvectors(spec.a, sy.ecut_from_shell(spec.a, spec.nsq_chi))
+        assert m.shape[0] == ng
+        assert not np.any(np.all(m == 0, axis=1))
+
+
+# ---------------------------------------------------------- chi0 (Eq. 6)
+
+def test_chi0_hermitian_nsd_and_trace(small):
+    s, w, mchi, d = small
+    delta = rpa.pair_weights(s.energy, s.n_v, 0.0)
+    cb = rpa.chibar(s.a, w, delta)
+    assert np.max(np.abs(cb - cb.conj().T)) < 1e-15 * np.max(np.abs(cb)) * 10
+    lam = np.linalg.eigvalsh(cb)
+    assert lam[-1] < 1e-14 * abs(lam[0])
+    # trace = sum over pairs of Delta_p |W_p|^2 / Omega, accumulated per pair
+    tr = sum(-4.0 / d[p] * np.vdot(w[p], w[p]).real for p in range(len(d)))
+    assert abs(np.trace(cb).real - tr / s.a ** 3) < 1e-13 * abs(tr)
+
+
+def test_chi0_paper_form_and_symmetrized_form(small):
+    s, w, mchi, _ = small
+    psi = rpa.orbitals_realspace(s.a, s.fft, s.miller, s.coeff)
+    m = rpa.pair_matrix_fft(s.a, s.fft, psi[: s.n_v], psi[s.n_v:], mchi)
+    dvc = rpa.energy_factor(s.energy[: s.n_v], s.energy[s.n_v:], 0.3)
+    c0 = rpa.chi0(s.a, m, dvc)
+    cb = rpa.chibar(s.a, w, dvc.ravel())
+    assert np.allclose(rpa.symmetrize_chi0(s.a, c0, mchi), cb, rtol=0,
+                       atol=1e-15 * np.max(np.abs(cb)) * 10)
+    # a single matrix element by an explicit pair loop
+    g, gp = 3, 11
+    ref = sum(np.conj(m[v, c, g]) * dvc[v, c] * m[v, c, gp]
+              for v in range(s.n_v) for c in range(s.n_c)) / s.a ** 3
+    assert abs(c0[g, gp] - ref) < 1e-15 * abs(ref) * 100
+
+
+def test_chi0_rank_bound():
+    spec = sy.small_spec(n_v=1, n_c=3)
+    s = sy.make_system(spec, 3)
+    w, _ = rpa.w_matrix(s.a, s.fft, s.miller, s.coeff, s.n_v, s.ecut_chi)
+    cb = rpa.chibar(s.a, w, rpa.pair_weights(s.energy, s.n_v, 0.0))
+    lam = np.linalg.eigvalsh(cb)
+    assert np.sum(np.abs(lam) > 1e-12 * abs(lam[0])) == 3
+
+
+def test_chi0_block_invariance(small):
+    s, w, _, _ = small
+    delta = rpa.pair_weights(s.energy, s.n_v, 0.0)
+    full = rpa.chibar(s.a, w, delta)
+    nc = s.n_c
+    acc = np.zeros_like(full)
+    for v0 in range(0, s.n_v, 3):
+        v1 = min(s.n_v, v0 + 3)
+        acc += rpa.chibar(s.a, w[v0 * nc: v1 * nc], delta[v0 * nc: v1 * nc])
+    assert np.max(np.abs(acc - full)) < 1e-14 * np.max(np.abs(full)) * 10
+
+
+def test_chi0_independent_of_orbital_phases(small):
+    s, w, mchi, _ = small
+    rng = np.random.default_rng(99)
+    ph = np.exp(2j * math.pi * rng.uniform(size=s.n_bands))
+    w2, _ = rpa.w_matrix(s.a, s.fft, s.miller, s.coeff * ph[:, None], s.n_v,
+                         s.ecut_chi)
+    delta = rpa.pair_weights(s.energy, s.n_v, 0.7)
+    a = rpa.chibar(s.a, w, delta)
+    b = rpa.chibar(s.a, w2, delta)
+    assert np.max(np.abs(a - b)) < 1e-14 * np.max(np.abs(a)) * 10
+
+
+# ------------------------------------------------ E_c: closed forms (Eq. 1)
+
+def test_full_rpa_equals_plasmon_formula(small):
+    s, w, _, d = small
+    exact = rpa.plasmon_ec(s.a, w, d)
+    om64, wt64 = rpa.semi_infinite_rule(64)
+    r64 = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                                 s.n_v, s.ecut_chi, 10 ** 9, om64, wt64, w=w)
+    om16, wt16 = sy.frequency_grid(16)
+    r16 = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                                 s.n_v, s.ecut_chi, 10 ** 9, om16, wt16, w=w)
+    assert exact < 0
+    assert abs(r64["ec"] - exact) < 1e-9 * abs(exact)
+    assert abs(r16["ec"] - exact) < 1e-6 * abs(exact)
+
+
+def test_rank_one_closed_form():
+    """N_v = N_c = 1: F(w) = ln(1 + x) - x, x = 4ak/(a^2 + w^2), and the exact
+    integral E_c = 1/2 (sqrt(a^2 + 4ak) - a - 2k).
+
+    The per-node check is absolute-plus-relative: at high frequency F is far
+    below the rounding of an FP64 log-determinant of a near-identity matrix.
+    """
+    spec = sy.small_spec(n_v=1, n_c=1)
+    s = sy.make_system(spec, 11)
+    w, _ = rpa.w_matrix(s.a, s.fft, s.miller, s.coeff, 1, s.ecut_chi)
+    a_ = s.energy[1] - s.energy[0]
+    k = float(np.vdot(w[0], w[0]).real) / s.a ** 3
+    # 1/2 (sqrt(a^2 + 4ak) - a - 2k), rewritten without cancellation
+    root = math.sqrt(a_ * a_ + 4 * a_ * k)
+    exact = -4.0 * a_ * k * k / (root + a_) ** 2
+    om, wt = rpa.semi_infinite_rule(64)
+    r = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy, 1,
+                               s.ecut_chi, 10 ** 9, om, wt, w=w)
+    x = 4.0 * a_ * k / (a_ * a_ + om * om)
+    f_exact = np.log1p(x) - x
+    assert np.all(np.abs(r["integrand"] - f_exact)
+                  <= 1e-14 + 1e-8 * np.abs(f_exact))
+    assert abs(rpa.quadrature(wt, f_exact) - exact) < 1e-12 * abs(exact)
+    assert abs(r["ec"] - exact) < 1e-4 * abs(exact)
+
+
+def test_second_order_limit(small):
+    s, w, _, d = small
+    om, wt = rpa.semi_infinite_rule(64)
+    mp2 = rpa.direct_mp2(s.a, w, d)
+    quad2 = rpa.second_order_quadrature(s.a, w, s.energy, s.n_v, om, wt)
+    assert abs(quad2 - mp2) < 1e-8 * abs(mp2)
+    errs = []
+    for lam in (1e-1, 1e-2):
+        r = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                                   s.n_v, s.ecut_chi, 10 ** 9, om, wt,
+                                   coupling=lam, w=w)
+        errs.append(abs(r["ec"] / lam ** 2 - quad2) / abs(quad2))
+    # the remainder is O(lambda): ten times smaller coupling, ~ten times less
+    assert errs[1] < 1e-3
+    assert 5.0 < errs[0] / errs[1] < 20.0
+
+
+# ------------------------------------------------- static subspace (7, 8)
+
+def test_subspace_full_size_equals_full_basis(small):
+    s, w, mchi, _ = small
+    om, wt = sy.frequency_grid(16)
+    ng = w.shape[1]
+    full = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                                  s.n_v, s.ecut_chi, 10 ** 9, om, wt, w=w)
+    cb0 = rpa.chibar(s.a, w, rpa.pair_weights(s.energy, s.n_v, 0.0))
+    lam, cs, _ = rpa.subspace(cb0, ng)
+    f = [rpa.trace_log_cholesky(
+        rpa.chibar(s.a, rpa.project(w, cs),
+                   rpa.pair_weights(s.energy, s.n_v, o))) for o in om]
+    ec = rpa.quadrature(wt, f)
+    # equal up to rounding of the two routes (C_s unitary)
+    assert abs(ec - full["ec"]) < 1e-10 * abs(full["ec"])
+
+
+def test_subspace_projection_identities(small):
+    s, w, _, _ = small
+    cb0 = rpa.chibar(s.a, w, rpa.pair_weights(s.energy, s.n_v, 0.0))
+    lam, cs, gap = rpa.subspace(cb0, 12)
+    assert gap > 1e-8
+    allv = np.linalg.eigvalsh(cb0)
+    assert np.allclose(lam, allv[:12], rtol=0, atol=1e-14 * abs(allv[0]) * 10)
+    assert np.max(np.abs(cs.conj().T @ cs - np.eye(12))) < 1e-13
+    ws = rpa.project(w, cs)
+    d0 = rpa.chibar(s.a, ws, rpa.pair_weights(s.energy, s.n_v, 0.0))
+    assert np.max(np.abs(d0 - np.diag(lam))) < 1e-13 * abs(lam[0])
+    dj = rpa.pair_weights(s.energy, s.n_v, 1.3)
+    direct = cs.conj().T @ rpa.chibar(s.a, w, dj) @ cs
+    assert np.max(np.abs(rpa.chibar(s.a, ws, dj) - direct)) < 1e-13 * abs(lam[0])
+
+
+def test_subspace_monotone_and_signs(small):
+    s, w, _, _ = small
+    om, wt = sy.frequency_grid(16)
+    ng = w.shape[1]
+    prev = None
+    for n in (4, 10, 20, 35, ng):
+        r = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                                   s.n_v, s.ecut_chi, n, om, wt, w=w)
+        assert r["ec"] <= 0.0
+        assert np.all(r["integrand"] <= 1e-15)
+        if prev is not None:
+            assert r["ec"] <= prev["ec"] + 1e-15
+            assert np.all(r["integrand"] <= prev["integrand"] + 1e-15)
+        prev = r
+
+
+def test_subspace_keeps_the_largest_magnitude_end(small):
+    s, w, _, _ = small
+    om, wt = sy.frequency_grid(16)
+    cb0 = rpa.chibar(s.a, w, rpa.pair_weights(s.energy, s.n_v, 0.0))
+    lam, vec = np.linalg.eigh(cb0)
+    n = 10
+
+    def ec_of(cs):
+        f = [rpa.trace_log_cholesky(rpa.chibar(
+            s.a, rpa.project(w, cs), rpa.pair_weights(s.energy, s.n_v, o)))
+            for o in om]
+        return rpa.quadrature(wt, f)
+
+    top = ec_of(vec[:, :n])
+    bottom = ec_of(vec[:, -n:])
+    r = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                               s.n_v, s.ecut_chi, n, om, wt, w=w)
+    assert abs(r["ec"] - top) < 1e-13 * abs(top)
+    assert abs(top) > 10 * abs(bottom)
+
+
+def test_trace_log_three_ways(small):
+    s, w, _, _ = small
+    cb = rpa.chibar(s.a, w, rpa.pair_weights(s.energy, s.n_v, 0.5))
+    mu = np.linalg.eigvalsh(cb)
+    ref = float(np.sum(np.log1p(-mu) + mu))
+    assert abs(rpa.trace_log_cholesky(cb) - ref) < 1e-12 * abs(ref)
+    assert abs(rpa.trace_log_lu(cb) - ref) < 1e-12 * abs(ref)
+
+
+def test_exponent_sign_relabels_g(small):
+    # e^{-iG.r} instead of e^{+iG.r} maps G -> -G; the G set is symmetric,
+    # so the correlation energy is unchanged.
+    s, w, mchi, _ = small
+    psi = rpa.orbitals_realspace(s.a, s.fft, s.miller, s.coeff)
+    m_neg = rpa.pair_matrix_fft(s.a, s.fft, psi[: s.n_v], psi[s.n_v:], -mchi)
+    w_neg = rpa.scaled_pair_matrix(s.a, m_neg, mchi)
+    om, wt = sy.frequency_grid(16)
+    a = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                               s.n_v, s.ecut_chi, 10, om, wt, w=w)
+    b = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                               s.n_v, s.ecut_chi, 10, om, wt, w=w_neg)
+    assert abs(a["ec"] - b["ec"]) < 1e-12 * abs(a["ec"])
+
+
+def test_tiny_workload_against_plasmon_formula():
+    """The tiny workload itself: 16-point rule vs the exact integral."""
+    s = sy.make_system(sy.TINY, 1000)
+    w, mchi = rpa.w_matrix(s.a, s.fft, s.miller, s.coeff, s.n_v, s.ecut_chi)
+    assert w.shape == (16 * 240, 304)
+    om, wt = sy.frequency_grid(16)
+    full = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                                  s.n_v, s.ecut_chi, 304, om, wt, w=w)
+    sub = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                                 s.n_v, s.ecut_chi, 75, om, wt, w=w)
+    d = np.repeat(s.energy[s.n_v:][None, :], s.n_v, 0) \
+        - s.energy[: s.n_v][:, None]
+    exact = rpa.plasmon_ec(s.a, w, d.ravel())
+    assert abs(full["ec"] - exact) < 1e-7 * abs(exact)
+    assert full["ec"] < sub["ec"] < 0.0
+    assert sub["gap"] > 1e-8
