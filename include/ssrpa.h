@@ -1,0 +1,249 @@
+/*
+ * ssrpa.h -- C ABI of the static-subspace RPA hot path on AMD MI355X (gfx950).
+ *
+ * The library computes the random-phase-approximation correlation energy of a
+ * plane-wave system at one q-point (q = 0) and the Gamma point, following the
+ * Method section of Weinberg et al., "Static Subspace Approximation for Random
+ * Phase Approximation Correlation Energies: Implementation and Performance"
+ * (arXiv:2405.20258):
+ *
+ *   orbitals psi_n(G), energies e_n, cell, chi0 cutoff       (problem statement)
+ *   -> pair matrix elements M_vc(G) by batched 3-D FFTs      (Eq. 3)
+ *   -> static chi0(G,G'; 0) = M^H Delta M / Omega, streamed over valence
+ *      blocks                                               (Eqs. 6, 15)
+ *   -> the N_eig eigenvectors of v^1/2 chi0 v^1/2 with the largest |eigenvalue|
+ *      (static subspace)
+ *   -> chi0_s(i w_j) = M_s^H Delta(i w_j) M_s in that subspace (Eqs. 7, 8)
+ *   -> F_j = ln det(1 - chi0_s v) + Tr chi0_s v, from a triangular factor
+ *   -> E_c = (1/2 pi) sum_j w_j F_j                          (Eq. 1)
+ *
+ * Conventions (Hartree atomic units throughout):
+ *  - Valence bands 0..n_v-1 have occupation 1, conduction bands n_v..n_b-1
+ *    occupation 0; spin degeneracy 2; one k-point of weight 1.
+ *  - Delta_vc(i w) = -4 (e_c - e_v) / ((e_c - e_v)^2 + w^2): the resonant and
+ *    anti-resonant terms of Eq. (2) together, so chi0 is Hermitian and
+ *    negative semidefinite at every imaginary frequency.
+ *  - M_vc(G) = <psi_v| e^{+iG.r} |psi_c>; chi0_GG' = (1/Omega) sum_vc
+ *    conj(M_vc(G)) Delta_vc M_vc(G') (Eq. 6), with 1/Omega exactly once.
+ *  - v(G) = 4 pi / |G|^2; the symmetrized matrix is v^1/2 chi0 v^1/2.
+ *  - The chi0 basis is {G != 0 : |G|^2 / 2 <= ecut_chi}, in the order reported
+ *    by ssrpa_chi_gvectors (lexicographic in the Miller indices).
+ *
+ * Memory and ownership:
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *    memory on the context's device (e.g. torch tensor data_ptr()).
+ *  - The caller owns every buffer it passes in; the library never frees or
+ *    keeps caller pointers beyond the call.  The library owns a device copy of
+ *    the orbitals and all workspace (within the context's HBM budget) until
+ *    the matching *_destroy.
+ *  - Complex arrays are interleaved (re, im) doubles, row-major.
+ *  - Calls are ordered on the HIP stream passed in (NULL = the default
+ *    stream).  Host outputs are valid when a call returns; device outputs are
+ *    valid once the stream has reached the call's end.
+ *
+ * Errors: every entry point returns an ssrpa_status; none throws or aborts.
+ * A failed call leaves the system usable, except after SSRPA_ERR_HIP (a HIP
+ * runtime error), after which the context should be destroyed.  The text of
+ * the last error of a context is available from ssrpa_last_error.
+ * One context per host thread; a context is not thread safe.
+ */
+#ifndef SSRPA_H
+#define SSRPA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SSRPA_API __attribute__((visibility("default")))
+
+typedef enum ssrpa_status {
+  SSRPA_OK = 0,
+  SSRPA_ERR_ARG = 1,      /* invalid argument (null, size, range)            */
+  SSRPA_ERR_ALIAS = 2,    /* FFT grid below the alias-free bound             */
+  SSRPA_ERR_NOMEM = 3,    /* HBM budget or device allocation exhausted       */
+  SSRPA_ERR_HIP = 4,      /* HIP runtime error                               */
+  SSRPA_ERR_NUMERIC = 5,  /* factorization failed (matrix not positive etc.) */
+  SSRPA_ERR_STATE = 6     /* call order (e.g. no subspace yet)               */
+} ssrpa_status;
+
+/* Arithmetic of the chi0 / projection / subspace contractions.  The static
+ * eigendecomposition and the per-frequency log-determinant are always FP64. */
+typedef enum ssrpa_precision {
+  SSRPA_FP64 = 0,    /* FP64 MFMA, FP64 accumulation                          */
+  SSRPA_FP32 = 1,    /* FP32 MFMA, FP32 accumulation per K chunk, FP64 across  */
+  SSRPA_BF16X3 = 2   /* x = hi + lo in bfloat16; hi*hi + hi*lo + lo*hi on BF16
+                        MFMA, FP32 accumulation per K chunk, FP64 across       */
+} ssrpa_precision;
+
+typedef struct ssrpa_context ssrpa_context;
+typedef struct ssrpa_system ssrpa_system;
+typedef struct ssrpa_ticket ssrpa_ticket;
+
+/* The problem statement: orbitals in a plane-wave basis with their energies,
+ * the cell, the FFT grid and the chi0 cutoff (Method section, Eqs. 2-3). */
+typedef struct ssrpa_system_desc {
+  double lattice[9];      /* bohr; rows are a1, a2, a3                        */
+  int32_t fft[3];         /* N1, N2, N3, each 2^i 3^j <= 128; must satisfy
+                             N_i >= 2 max|n_psi,i| + max|n_chi,i| + 1, else
+                             SSRPA_ERR_ALIAS                                  */
+  int32_t n_pw;           /* wavefunction plane waves                         */
+  const int32_t *miller;  /* host, n_pw x 3 Miller indices of the plane waves */
+  int32_t n_v;            /* valence bands (occupied)                         */
+  int32_t n_c;            /* conduction bands (empty)                         */
+  const double *coeff;    /* (n_v + n_c) x n_pw complex, one band per row;
+                             orthonormal rows; host or device (see below)     */
+  int32_t coeff_on_device;/* 0: coeff is host memory, 1: device memory        */
+  const double *energy;   /* host, n_v + n_c band energies (Ha), each
+                             conduction energy above every valence energy    */
+  double ecut_chi;        /* Ha; chi0 basis {G != 0 : |G|^2/2 <= ecut_chi}     */
+} ssrpa_system_desc;
+
+/* Human-readable name of a status code (static string). */
+SSRPA_API const char *ssrpa_status_string(ssrpa_status s);
+
+/* Text of the most recent error on this context ("" if none). */
+SSRPA_API const char *ssrpa_last_error(const ssrpa_context *ctx);
+
+/* Library version string, e.g. "0.1.0 gfx950". */
+SSRPA_API const char *ssrpa_version(void);
+
+/* Create a context on HIP device `hip_device`.  `hbm_budget_bytes` caps the
+ * device memory the library allocates for this context (0 = 90% of the
+ * device's free memory at creation).  *out receives the handle. */
+SSRPA_API ssrpa_status ssrpa_context_create(int hip_device,
+                                            size_t hbm_budget_bytes,
+                                            ssrpa_context **out);
+SSRPA_API ssrpa_status ssrpa_context_destroy(ssrpa_context *ctx);
+
+/* Device bytes currently held and the high-water mark of this context. */
+SSRPA_API ssrpa_status ssrpa_context_memory(const ssrpa_context *ctx,
+                                            size_t *in_use, size_t *high_water);
+
+/* Device footprint (bytes) of a whole E_c solve for `desc` with `n_eig`
+ * subspace vectors (n_eig >= N_G: full basis), `n_freq` frequencies, the
+ * given precision and `valence_block` valence bands per block (0: all).
+ * Host-only; touches no device.  The valence-block algorithm (Eqs. 14-15)
+ * bounds the pair-matrix part of this number by the block size. */
+SSRPA_API ssrpa_status ssrpa_footprint(const ssrpa_system_desc *desc,
+                                       int n_eig, int n_freq,
+                                       ssrpa_precision precision,
+                                       int valence_block, size_t *bytes);
+
+/* Largest valence block (<= n_v) whose footprint fits `budget_bytes`;
+ * 0 in *valence_block (and SSRPA_ERR_NOMEM) if even one band does not fit. */
+SSRPA_API ssrpa_status ssrpa_plan_valence_block(const ssrpa_system_desc *desc,
+                                                int n_eig, int n_freq,
+                                                ssrpa_precision precision,
+                                                size_t budget_bytes,
+                                                int *valence_block);
+
+/* Validate `desc`, build the chi0 G set, copy the orbitals to the device and
+ * transform them to the real-space grid (orbital staging; the wavefunctions
+ * stay resident, as in the valence-block algorithm where they are the
+ * memory floor).  Enqueued on `hip_stream` and synchronized before return. */
+SSRPA_API ssrpa_status ssrpa_system_create(ssrpa_context *ctx,
+                                           const ssrpa_system_desc *desc,
+                                           void *hip_stream,
+                                           ssrpa_system **out);
+SSRPA_API ssrpa_status ssrpa_system_destroy(ssrpa_system *sys);
+
+/* Number of chi0 basis vectors N_G and (if `miller` is not NULL) their host
+ * n_g x 3 Miller indices in the library's order. */
+SSRPA_API ssrpa_status ssrpa_chi_gvectors(const ssrpa_system *sys, int *n_g,
+                                          int32_t *miller);
+
+/* Real-space orbitals psi_n(r_j) = Omega^-1/2 sum_G c_n(G) e^{iG.r_j} on the
+ * grid r_j = j1/N1 a1 + j2/N2 a2 + j3/N3 a3, written to device memory `psi`
+ * as (n_v + n_c) x N3 x N2 x N1 complex (j1 fastest). */
+SSRPA_API ssrpa_status ssrpa_orbitals_realspace(ssrpa_system *sys, double *psi,
+                                                void *hip_stream);
+
+/* Pair matrix elements of Eq. (3) for valence bands v0..v0+n_vb-1 and every
+ * conduction band: device output `m`, (n_vb * n_c) x N_G complex with row
+ * p = (v - v0) * n_c + c.  scaled = 1 multiplies by v(G)^1/2 (the W used by
+ * the contractions), scaled = 0 gives M itself. */
+SSRPA_API ssrpa_status ssrpa_pair_matrix(ssrpa_system *sys, int v0, int n_vb,
+                                         int scaled, double *m,
+                                         void *hip_stream);
+
+/* Static polarizability chi0(G, G'; i0) of Eq. (6), accumulated over valence
+ * blocks of `valence_block` bands (0: automatic from the HBM budget), Eq. (15).
+ * The symmetrized matrix stays resident for ssrpa_subspace.  If `chi0` is not
+ * NULL it receives the N_G x N_G complex device matrix: the paper's chi0
+ * (with 1/Omega) if symmetrized = 0, v^1/2 chi0 v^1/2 if symmetrized = 1. */
+SSRPA_API ssrpa_status ssrpa_chi0_static(ssrpa_system *sys,
+                                         ssrpa_precision precision,
+                                         int valence_block, double *chi0,
+                                         int symmetrized, void *hip_stream);
+
+/* Static subspace: the n_eig eigenpairs of the resident v^1/2 chi0 v^1/2 with
+ * the largest |eigenvalue| (the most negative), computed in FP64 on the GPU.
+ * `eigval` (host, n_eig) receives them in ascending order; `basis` (device,
+ * nullable) the N_G x n_eig complex eigenvector columns C_s.  Requires
+ * ssrpa_chi0_static first (SSRPA_ERR_STATE otherwise). 1 <= n_eig <= N_G. */
+SSRPA_API ssrpa_status ssrpa_subspace(ssrpa_system *sys, int n_eig,
+                                      double *eigval, double *basis,
+                                      void *hip_stream);
+
+/* Correlation energy by quadrature of Eq. (1) over `n_freq` imaginary
+ * frequencies `omega` (host, Ha) with weights `weight` (host).
+ *  n_eig < N_G: static-subspace form; requires ssrpa_subspace(sys, n_eig, ..)
+ *               first (SSRPA_ERR_STATE otherwise).
+ *  n_eig >= N_G: full G basis (no subspace needed).
+ * `coupling` scales the interaction (1.0 for RPA; F_j = ln det(1 - l X) +
+ * l Tr X).  Outputs: *ec (host); integrand (host, nullable) the n_freq values
+ * F_j; chi_sub (device, nullable) the n_freq x n x n complex matrices
+ * v^1/2 chi0_s(i w_j) v^1/2 (n = min(n_eig, N_G)).  Precision applies to the
+ * projection and per-frequency contractions; the pair matrix is recomputed
+ * per valence block when there is more than one block. */
+SSRPA_API ssrpa_status ssrpa_correlation_energy(ssrpa_system *sys, int n_eig,
+                                                int n_freq, const double *omega,
+                                                const double *weight,
+                                                ssrpa_precision precision,
+                                                int valence_block,
+                                                double coupling, double *ec,
+                                                double *integrand,
+                                                double *chi_sub,
+                                                void *hip_stream);
+
+/* F_j = ln det(I - l X_j) + l Tr X_j for a batch of Hermitian matrices X_j
+ * (device, n_mat x n x n complex), by Cholesky factors in FP64 on the GPU.
+ * `f` is host memory (n_mat).  SSRPA_ERR_NUMERIC if some I - l X_j is not
+ * positive definite.  The per-frequency step of the correlation energy,
+ * exposed for direct use. */
+SSRPA_API ssrpa_status ssrpa_trace_log(ssrpa_context *ctx, const double *x,
+                                       int n, int n_mat, double coupling,
+                                       double *f, void *hip_stream);
+
+/* Gauss-Legendre rule with n points mapped to [0, inf) by
+ * w = omega0 (1 + x)/(1 - x), weight 2 omega0 w_x / (1 - x)^2 (host). */
+SSRPA_API ssrpa_status ssrpa_frequency_grid(int n, double omega0,
+                                            double *omega, double *weight);
+
+/* ---- serving: the same solve, enqueued without blocking the caller ------ */
+
+/* Start a whole E_c solve (system creation from `desc` is done by the
+ * caller beforehand) on `hip_stream`, running the chi0 -> subspace -> E_c
+ * stages on the device in stream order; returns at once with a ticket.
+ * Different systems on different streams overlap on the device. */
+SSRPA_API ssrpa_status ssrpa_correlation_energy_enqueue(
+    ssrpa_system *sys, int n_eig, int n_freq, const double *omega,
+    const double *weight, ssrpa_precision precision, int valence_block,
+    void *hip_stream, ssrpa_ticket **ticket);
+
+/* *done = 1 once the ticket's solve has finished (non-blocking). */
+SSRPA_API ssrpa_status ssrpa_ticket_query(ssrpa_ticket *t, int *done);
+
+/* Block until the solve finishes; write E_c and (nullable) the n_freq
+ * integrand values; free the ticket.  Returns the solve's status. */
+SSRPA_API ssrpa_status ssrpa_ticket_wait(ssrpa_ticket *t, double *ec,
+                                         double *integrand);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSRPA_H */

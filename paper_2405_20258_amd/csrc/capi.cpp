@@ -1,0 +1,849 @@
+// Host runtime and C ABI of the ssrpa library.
+//
+// The driver follows the valence-block algorithm of the paper
+// (Implementation section, Eqs. 14-15): the pair matrix is produced one block
+// of valence bands at a time and its contribution to chi0 accumulated, so the
+// memory floor is the resident real-space orbitals; the block loop runs twice
+// (static chi0 first, then every frequency in the subspace), and when one
+// block covers all valence bands its pair matrix is kept so the pair FFTs run
+// only once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <thread>
+
+#include "internal.hpp"
+
+namespace ssrpa {
+
+void fail(ssrpa_status code, const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  throw Error(code, buf);
+}
+
+void *Context::alloc(size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    if (in_use + bytes > budget)
+      fail(SSRPA_ERR_NOMEM, "HBM budget exceeded: %zu in use + %zu requested > %zu",
+           in_use, bytes, budget);
+    in_use += bytes;
+    high_water = std::max(high_water, in_use);
+  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    std::lock_guard<std::mutex> g(mu);
+    in_use -= bytes;
+    fail(SSRPA_ERR_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  return p;
+}
+
+void Context::release(void *p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  std::lock_guard<std::mutex> g(mu);
+  in_use -= bytes == 0 ? 8 : bytes;
+}
+
+DevBuf::DevBuf(Context *ctx, size_t bytes) : ctx_(ctx), bytes_(bytes) {
+  ptr_ = ctx->alloc(bytes);
+}
+
+DevBuf::~DevBuf() {
+  if (ptr_ && ctx_) ctx_->release(ptr_, bytes_);
+}
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+bool is_235(int n) {
+  if (n < 1) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+void invert3(const double *a, double *inv, double *det) {
+  const double d = a[0] * (a[4] * a[8] - a[5] * a[7]) -
+                   a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                   a[2] * (a[3] * a[7] - a[4] * a[6]);
+  *det = d;
+  inv[0] = (a[4] * a[8] - a[5] * a[7]) / d;
+  inv[1] = (a[2] * a[7] - a[1] * a[8]) / d;
+  inv[2] = (a[1] * a[5] - a[2] * a[4]) / d;
+  inv[3] = (a[5] * a[6] - a[3] * a[8]) / d;
+  inv[4] = (a[0] * a[8] - a[2] * a[6]) / d;
+  inv[5] = (a[2] * a[3] - a[0] * a[5]) / d;
+  inv[6] = (a[3] * a[7] - a[4] * a[6]) / d;
+  inv[7] = (a[1] * a[6] - a[0] * a[7]) / d;
+  inv[8] = (a[0] * a[4] - a[1] * a[3]) / d;
+}
+
+double gnorm2(const Geometry &g, int n1, int n2, int n3) {
+  double v[3];
+  for (int c = 0; c < 3; ++c)
+    v[c] = n1 * g.recip[c] + n2 * g.recip[3 + c] + n3 * g.recip[6 + c];
+  return v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+}
+
+// Validate a description and derive the geometry (no device work).
+Geometry make_geometry(const ssrpa_system_desc *d) {
+  SSRPA_REQUIRE(d, SSRPA_ERR_ARG, "null system description");
+  SSRPA_REQUIRE(d->n_v >= 1 && d->n_c >= 1, SSRPA_ERR_ARG,
+                "need at least one valence and one conduction band");
+  SSRPA_REQUIRE(d->n_pw >= d->n_v + d->n_c, SSRPA_ERR_ARG,
+                "%d bands exceed %d plane waves", d->n_v + d->n_c, d->n_pw);
+  SSRPA_REQUIRE(d->miller && d->coeff && d->energy, SSRPA_ERR_ARG,
+                "null miller/coeff/energy pointer");
+  SSRPA_REQUIRE(d->ecut_chi > 0.0 && std::isfinite(d->ecut_chi), SSRPA_ERR_ARG,
+                "ecut_chi must be positive");
+  Geometry g{};
+  std::memcpy(g.lattice, d->lattice, sizeof(g.lattice));
+  double inv[9], det;
+  invert3(g.lattice, inv, &det);
+  SSRPA_REQUIRE(std::isfinite(det) && std::fabs(det) > 1e-12, SSRPA_ERR_ARG,
+                "singular lattice");
+  g.volume = std::fabs(det);
+  // B = 2 pi A^-T: row j of B is 2 pi times column j of A^-1
+  for (int j = 0; j < 3; ++j)
+    for (int c = 0; c < 3; ++c) g.recip[3 * j + c] = 2.0 * kPi * inv[3 * c + j];
+  g.n1 = d->fft[0];
+  g.n2 = d->fft[1];
+  g.n3 = d->fft[2];
+  for (int i = 0; i < 3; ++i)
+    SSRPA_REQUIRE(is_235(d->fft[i]) && d->fft[i] <= 128 && d->fft[i] >= 2,
+                  SSRPA_ERR_ARG, "FFT size %d must be 2^i 3^j in [2, 128]",
+                  d->fft[i]);
+  // chi0 set: G != 0, |G|^2/2 <= ecut, lexicographic in (n1, n2, n3)
+  const double gmax = std::sqrt(2.0 * d->ecut_chi);
+  int nb[3];
+  for (int i = 0; i < 3; ++i) {
+    const double al = std::sqrt(g.lattice[3 * i] * g.lattice[3 * i] +
+                                g.lattice[3 * i + 1] * g.lattice[3 * i + 1] +
+                                g.lattice[3 * i + 2] * g.lattice[3 * i + 2]);
+    nb[i] = (int)std::floor(gmax * al / (2.0 * kPi)) + 1;
+    SSRPA_REQUIRE(nb[i] < 512, SSRPA_ERR_ARG, "ecut_chi too large");
+  }
+  g.m1 = g.m2 = g.m3 = 0;
+  for (int a = -nb[0]; a <= nb[0]; ++a)
+    for (int b = -nb[1]; b <= nb[1]; ++b)
+      for (int c = -nb[2]; c <= nb[2]; ++c) {
+        if (a == 0 && b == 0 && c == 0) continue;
+        const double g2 = gnorm2(g, a, b, c);
+        if (0.5 * g2 <= d->ecut_chi) {
+          g.miller_chi.push_back(a);
+          g.miller_chi.push_back(b);
+          g.miller_chi.push_back(c);
+          g.sqrt_v.push_back(std::sqrt(4.0 * kPi / g2));
+          g.m1 = std::max(g.m1, std::abs(a));
+          g.m2 = std::max(g.m2, std::abs(b));
+          g.m3 = std::max(g.m3, std::abs(c));
+        }
+      }
+  g.n_g = (int)g.sqrt_v.size();
+  SSRPA_REQUIRE(g.n_g >= 1, SSRPA_ERR_ARG, "empty chi0 basis (ecut_chi too small)");
+  g.ld_g = round_up(g.n_g, 64);
+  // alias-free bound N_i >= 2 max|n_psi,i| + max|n_chi,i| + 1
+  int mp[3] = {0, 0, 0};
+  for (int p = 0; p < d->n_pw; ++p)
+    for (int i = 0; i < 3; ++i) mp[i] = std::max(mp[i], std::abs(d->miller[3 * p + i]));
+  const int mc[3] = {g.m1, g.m2, g.m3};
+  for (int i = 0; i < 3; ++i)
+    SSRPA_REQUIRE(d->fft[i] >= 2 * mp[i] + mc[i] + 1, SSRPA_ERR_ALIAS,
+                  "FFT size %d along axis %d is below the alias-free bound %d",
+                  d->fft[i], i, 2 * mp[i] + mc[i] + 1);
+  SSRPA_REQUIRE((long)(2 * g.m1 + 1) * g.n2 < (1 << 20), SSRPA_ERR_ARG,
+                "grid too large");
+  return g;
+}
+
+size_t bytes_c(size_t n) { return 16 * n; }
+
+struct Footprint {
+  size_t resident, block, subspace, freq, eig, total;
+};
+
+Footprint footprint_of(const ssrpa_system_desc *d, const Geometry &g, int n_eig,
+                       int n_freq, int vb) {
+  Footprint f{};
+  const size_t nb = (size_t)d->n_v + d->n_c;
+  const size_t box = (size_t)g.n1 * g.n2 * g.n3;
+  const size_t ng = g.n_g, ldg = g.ld_g;
+  const bool full = n_eig >= g.n_g;
+  const size_t ne = full ? ng : (size_t)n_eig;
+  const size_t lde = full ? ldg : (size_t)round_up(n_eig, 64);
+  const size_t pairs = (size_t)vb * d->n_c;
+  f.resident = bytes_c(nb * box) + bytes_c(ng * ng) + 64 * ldg + bytes_c((size_t)d->n_pw);
+  f.block = pairs * (2 * ldg * 8 + 8);
+  f.subspace = full ? 0 : pairs * 2 * lde * 8 + bytes_c(ldg * lde);
+  const size_t tiles = (lde / 64) * (lde / 64 + 1) / 2;
+  f.freq = 2 * bytes_c(ne * ne) * n_freq + tiles * 64 * 64 * 16 * (size_t)n_freq * 2;
+  f.eig = full ? 0 : bytes_c(ng * ng) + 6 * ng * lde * 8 + 3 * bytes_c(ldg * lde);
+  // the static pass: chi0 partial tiles
+  const size_t gt = (ldg / 64) * (ldg / 64 + 1) / 2;
+  const size_t stat = gt * 64 * 64 * 16 * 2;
+  f.total = f.resident + f.block + std::max(stat, f.subspace + f.freq + f.eig) +
+            (64u << 20);
+  return f;
+}
+
+struct Stream {
+  hipStream_t s;
+  explicit Stream(void *p) : s(static_cast<hipStream_t>(p)) {}
+};
+
+ssrpa_status finish(Context *ctx, const std::exception_ptr &ep) {
+  try {
+    std::rethrow_exception(ep);
+  } catch (const Error &e) {
+    if (ctx) ctx->last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    if (ctx) ctx->last_error = "host allocation failed";
+    return SSRPA_ERR_NOMEM;
+  } catch (const std::exception &e) {
+    if (ctx) ctx->last_error = e.what();
+    return SSRPA_ERR_ARG;
+  } catch (...) {
+    if (ctx) ctx->last_error = "unknown error";
+    return SSRPA_ERR_ARG;
+  }
+}
+
+template <class F>
+ssrpa_status guarded(Context *ctx, F &&f) {
+  try {
+    if (ctx) ctx->last_error.clear();
+    f();
+    return SSRPA_OK;
+  } catch (...) {
+    return finish(ctx, std::current_exception());
+  }
+}
+
+void set_device(Context *ctx) { SSRPA_HIP(hipSetDevice(ctx->device)); }
+
+int resolve_block(System &sys, int requested, int n_eig, int n_freq) {
+  if (requested > 0) return std::min(requested, sys.n_v);
+  // largest block whose pair matrices fit in the remaining budget
+  Context *ctx = sys.ctx;
+  size_t free_b;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    free_b = ctx->budget > ctx->in_use ? ctx->budget - ctx->in_use : 0;
+  }
+  const bool full = n_eig >= sys.geo.n_g;
+  const size_t lde = full ? 0 : (size_t)round_up(std::max(n_eig, 1), 64);
+  const size_t per_band = (size_t)sys.n_c * (2 * sys.geo.ld_g * 8 + 8 + 2 * lde * 8);
+  const size_t reserve = (size_t)1 << 30;
+  const size_t avail = free_b > reserve ? free_b - reserve : 0;
+  int vb = (int)std::min<size_t>(sys.n_v, avail / std::max<size_t>(per_band, 1));
+  SSRPA_REQUIRE(vb >= 1, SSRPA_ERR_NOMEM,
+                "one valence band of pair matrices (%zu bytes) exceeds the budget",
+                per_band);
+  (void)n_freq;
+  return vb;
+}
+
+// Pair matrix of one block (cached when one block covers all valence bands).
+const double *block_pairs(System &sys, int v0, int nvb, DevBuf &scratch,
+                          hipStream_t s) {
+  const bool single = (v0 == 0 && nvb == sys.n_v);
+  const size_t bytes = (size_t)nvb * sys.n_c * 2 * sys.geo.ld_g * sizeof(double);
+  if (single && sys.w_cache_valid) return sys.w_cache.as<double>();
+  DevBuf &dst = single ? sys.w_cache : scratch;
+  dst.ensure(sys.ctx, bytes);
+  launch_pair_matrix(sys, v0, nvb, true, dst.as<double>(), s);
+  if (single) sys.w_cache_valid = true;
+  return dst.as<double>();
+}
+
+void static_chi0(System &sys, ssrpa_precision prec, int vb, hipStream_t s) {
+  Context *ctx = sys.ctx;
+  const Geometry &g = sys.geo;
+  if (sys.chibar0.empty())
+    sys.chibar0 = DevBuf(ctx, bytes_c((size_t)g.n_g * g.n_g));
+  DevBuf scratch, de, ws;
+  DevBuf om(ctx, sizeof(double));
+  fill_zero(om.as(), sizeof(double), s);
+  for (int v0 = 0; v0 < sys.n_v; v0 += vb) {
+    const int nvb = std::min(vb, sys.n_v - v0);
+    const double *w = block_pairs(sys, v0, nvb, scratch, s);
+    de.ensure(ctx, sizeof(double) * (size_t)nvb * sys.n_c);
+    pair_energy_diffs(sys.energy_d.as<double>(), sys.n_v, v0, nvb, sys.n_c,
+                      de.as<double>(), s);
+    HerkArgs h{};
+    h.a = w;
+    h.lda = 2L * g.ld_g;
+    h.im_off = g.ld_g;
+    h.ncol = g.n_g;
+    h.ld = g.ld_g;
+    h.k = (long)nvb * sys.n_c;
+    h.de = de.as<double>();
+    h.omega = om.as<double>();
+    h.n_omega = 1;
+    h.wscale = 1.0 / g.volume;
+    herk(ctx, h, prec, sys.chibar0.as<double>(), 0, v0 > 0 ? 1 : 0, ws, s);
+  }
+  SSRPA_HIP(hipStreamSynchronize(s));
+  sys.have_chi0 = true;
+  sys.sub = Subspace();
+}
+
+void compute_subspace(System &sys, int n_eig, hipStream_t s) {
+  Context *ctx = sys.ctx;
+  const Geometry &g = sys.geo;
+  SSRPA_REQUIRE(sys.have_chi0, SSRPA_ERR_STATE,
+                "ssrpa_chi0_static must run before ssrpa_subspace");
+  SSRPA_REQUIRE(n_eig >= 1 && n_eig <= g.n_g, SSRPA_ERR_ARG,
+                "n_eig=%d outside [1, %d]", n_eig, g.n_g);
+  Subspace sub;
+  sub.n_eig = n_eig;
+  sub.ld_e = round_up(n_eig, 64);
+  sub.basis = DevBuf(ctx, sizeof(double) * 2 * (size_t)g.ld_g * sub.ld_e);
+  DevBuf ev(ctx, sizeof(double) * n_eig);
+  eig_lowest(ctx, sys.chibar0.as<double>(), g.n_g, n_eig, ev.as<double>(),
+             sub.basis.as<double>(), sub.ld_e, sys.dev_flag.as<int>(), s);
+  sub.eigval.resize(n_eig);
+  SSRPA_HIP(hipMemcpyAsync(sub.eigval.data(), ev.as(), sizeof(double) * n_eig,
+                           hipMemcpyDeviceToHost, s));
+  SSRPA_HIP(hipStreamSynchronize(s));
+  for (double x : sub.eigval)
+    SSRPA_REQUIRE(std::isfinite(x), SSRPA_ERR_NUMERIC, "eigensolver produced %g", x);
+  sys.sub = std::move(sub);
+}
+
+struct EcResult {
+  double ec = 0.0;
+  std::vector<double> f;
+};
+
+EcResult energy(System &sys, int n_eig, int n_freq, const double *omega,
+                const double *weight, ssrpa_precision prec, int vb,
+                double coupling, double *chi_sub, hipStream_t s) {
+  Context *ctx = sys.ctx;
+  const Geometry &g = sys.geo;
+  SSRPA_REQUIRE(n_freq >= 1 && omega && weight, SSRPA_ERR_ARG,
+                "need at least one frequency");
+  for (int j = 0; j < n_freq; ++j)
+    SSRPA_REQUIRE(std::isfinite(omega[j]) && std::isfinite(weight[j]),
+                  SSRPA_ERR_ARG, "non-finite frequency or weight");
+  const bool full = n_eig >= g.n_g;
+  if (!full)
+    SSRPA_REQUIRE(sys.sub.n_eig == n_eig && !sys.sub.basis.empty(), SSRPA_ERR_STATE,
+                  "no subspace of size %d (call ssrpa_subspace first)", n_eig);
+  const int n = full ? g.n_g : n_eig;
+  const int ld = full ? g.ld_g : sys.sub.ld_e;
+  DevBuf own_chis;
+  double *chis = chi_sub;
+  if (!chis) {
+    own_chis = DevBuf(ctx, bytes_c((size_t)n * n * n_freq));
+    chis = own_chis.as<double>();
+  }
+  DevBuf fw(ctx, sizeof(double) * (3 * (size_t)n_freq + 8));
+  double *om_d = fw.as<double>();
+  double *w_d = om_d + n_freq;
+  double *f_d = w_d + n_freq;
+  double *ec_d = f_d + n_freq;
+  SSRPA_HIP(hipMemcpyAsync(om_d, omega, sizeof(double) * n_freq,
+                           hipMemcpyHostToDevice, s));
+  SSRPA_HIP(hipMemcpyAsync(w_d, weight, sizeof(double) * n_freq,
+                           hipMemcpyHostToDevice, s));
+  DevBuf scratch, de, ws, wsub;
+  for (int v0 = 0; v0 < sys.n_v; v0 += vb) {
+    const int nvb = std::min(vb, sys.n_v - v0);
+    const long rows = (long)nvb * sys.n_c;
+    const double *w = block_pairs(sys, v0, nvb, scratch, s);
+    de.ensure(ctx, sizeof(double) * rows);
+    pair_energy_diffs(sys.energy_d.as<double>(), sys.n_v, v0, nvb, sys.n_c,
+                      de.as<double>(), s);
+    HerkArgs h{};
+    if (full) {
+      h.a = w;
+      h.lda = 2L * g.ld_g;
+      h.im_off = g.ld_g;
+    } else {
+      // W_s = W C_s  (Eq. 7)
+      wsub.ensure(ctx, sizeof(double) * 2 * (size_t)rows * ld);
+      GemmArgs gm{};
+      gm.a = w; gm.lda = 2L * g.ld_g; gm.a_im = g.ld_g;
+      gm.b = sys.sub.basis.as<double>(); gm.ldb = 2L * ld; gm.b_im = ld;
+      gm.c = wsub.as<double>(); gm.ldc = 2L * ld; gm.c_im = ld;
+      gm.m = rows; gm.n = ld; gm.k = g.ld_g;
+      gm.alpha = 1.0; gm.beta = 0.0;
+      gemm(ctx, gm, prec, s);
+      h.a = wsub.as<double>();
+      h.lda = 2L * ld;
+      h.im_off = ld;
+    }
+    h.ncol = n;
+    h.ld = ld;
+    h.k = rows;
+    h.de = de.as<double>();
+    h.omega = om_d;
+    h.n_omega = n_freq;
+    h.wscale = 1.0 / g.volume;
+    herk(ctx, h, prec, chis, 2L * n * n, v0 > 0 ? 1 : 0, ws, s);
+  }
+  fill_zero(sys.dev_flag.as(), sizeof(int), s);
+  trace_log(ctx, chis, n, n_freq, coupling, f_d, sys.dev_flag.as<int>(), s);
+  quadrature(w_d, f_d, n_freq, ec_d, s);
+  EcResult r;
+  r.f.resize(n_freq);
+  int flag = 0;
+  SSRPA_HIP(hipMemcpyAsync(r.f.data(), f_d, sizeof(double) * n_freq,
+                           hipMemcpyDeviceToHost, s));
+  SSRPA_HIP(hipMemcpyAsync(&r.ec, ec_d, sizeof(double), hipMemcpyDeviceToHost, s));
+  SSRPA_HIP(hipMemcpyAsync(&flag, sys.dev_flag.as(), sizeof(int),
+                           hipMemcpyDeviceToHost, s));
+  SSRPA_HIP(hipStreamSynchronize(s));
+  SSRPA_REQUIRE(flag == 0, SSRPA_ERR_NUMERIC,
+                "1 - chi0_s v is not positive definite at some frequency");
+  return r;
+}
+
+}  // namespace
+}  // namespace ssrpa
+
+using namespace ssrpa;
+
+struct ssrpa_context : Context {};
+struct ssrpa_system : System {};
+struct ssrpa_ticket {
+  std::thread th;
+  std::atomic<int> done{0};
+  ssrpa_status status = SSRPA_OK;
+  double ec = 0.0;
+  std::vector<double> f;
+};
+
+extern "C" {
+
+const char *ssrpa_status_string(ssrpa_status s) {
+  switch (s) {
+    case SSRPA_OK: return "ok";
+    case SSRPA_ERR_ARG: return "invalid argument";
+    case SSRPA_ERR_ALIAS: return "FFT grid below the alias-free bound";
+    case SSRPA_ERR_NOMEM: return "out of device memory (HBM budget)";
+    case SSRPA_ERR_HIP: return "HIP runtime error";
+    case SSRPA_ERR_NUMERIC: return "numerical failure";
+    case SSRPA_ERR_STATE: return "invalid call order";
+  }
+  return "unknown status";
+}
+
+const char *ssrpa_last_error(const ssrpa_context *ctx) {
+  return ctx ? ctx->last_error.c_str() : "";
+}
+
+const char *ssrpa_version(void) { return "0.1.0 gfx950"; }
+
+ssrpa_status ssrpa_context_create(int hip_device, size_t hbm_budget_bytes,
+                                  ssrpa_context **out) {
+  if (!out) return SSRPA_ERR_ARG;
+  *out = nullptr;
+  auto *ctx = new (std::nothrow) ssrpa_context();
+  if (!ctx) return SSRPA_ERR_NOMEM;
+  ssrpa_status st = guarded(ctx, [&] {
+    int n = 0;
+    SSRPA_HIP(hipGetDeviceCount(&n));
+    SSRPA_REQUIRE(hip_device >= 0 && hip_device < n, SSRPA_ERR_ARG,
+                  "device %d not present (%d devices)", hip_device, n);
+    ctx->device = hip_device;
+    SSRPA_HIP(hipSetDevice(hip_device));
+    size_t fr = 0, tot = 0;
+    SSRPA_HIP(hipMemGetInfo(&fr, &tot));
+    ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
+  });
+  if (st != SSRPA_OK) {
+    delete ctx;
+    return st;
+  }
+  *out = ctx;
+  return SSRPA_OK;
+}
+
+ssrpa_status ssrpa_context_destroy(ssrpa_context *ctx) {
+  if (!ctx) return SSRPA_ERR_ARG;
+  delete ctx;
+  return SSRPA_OK;
+}
+
+ssrpa_status ssrpa_context_memory(const ssrpa_context *ctx, size_t *in_use,
+                                  size_t *high_water) {
+  if (!ctx) return SSRPA_ERR_ARG;
+  auto *c = const_cast<ssrpa_context *>(ctx);
+  std::lock_guard<std::mutex> g(c->mu);
+  if (in_use) *in_use = c->in_use;
+  if (high_water) *high_water = c->high_water;
+  return SSRPA_OK;
+}
+
+ssrpa_status ssrpa_footprint(const ssrpa_system_desc *desc, int n_eig,
+                             int n_freq, ssrpa_precision precision,
+                             int valence_block, size_t *bytes) {
+  (void)precision;
+  if (!bytes) return SSRPA_ERR_ARG;
+  return guarded(nullptr, [&] {
+    const Geometry g = make_geometry(desc);
+    SSRPA_REQUIRE(n_eig >= 1 && n_freq >= 1, SSRPA_ERR_ARG, "bad n_eig/n_freq");
+    const int vb = valence_block > 0 ? std::min(valence_block, desc->n_v) : desc->n_v;
+    *bytes = footprint_of(desc, g, n_eig, n_freq, vb).total;
+  });
+}
+
+ssrpa_status ssrpa_plan_valence_block(const ssrpa_system_desc *desc, int n_eig,
+                                      int n_freq, ssrpa_precision precision,
+                                      size_t budget_bytes, int *valence_block) {
+  (void)precision;
+  if (!valence_block) return SSRPA_ERR_ARG;
+  *valence_block = 0;
+  return guarded(nullptr, [&] {
+    const Geometry g = make_geometry(desc);
+    SSRPA_REQUIRE(n_eig >= 1 && n_freq >= 1, SSRPA_ERR_ARG, "bad n_eig/n_freq");
+    int lo = 1, hi = desc->n_v, best = 0;
+    while (lo <= hi) {
+      const int mid = (lo + hi) / 2;
+      if (footprint_of(desc, g, n_eig, n_freq, mid).total <= budget_bytes) {
+        best = mid;
+        lo = mid + 1;
+      } else {
+        hi = mid - 1;
+      }
+    }
+    SSRPA_REQUIRE(best >= 1, SSRPA_ERR_NOMEM,
+                  "even one valence band per block exceeds %zu bytes", budget_bytes);
+    *valence_block = best;
+  });
+}
+
+ssrpa_status ssrpa_system_create(ssrpa_context *ctx, const ssrpa_system_desc *desc,
+                                 void *hip_stream, ssrpa_system **out) {
+  if (!ctx || !out) return SSRPA_ERR_ARG;
+  *out = nullptr;
+  ssrpa_system *sys = nullptr;
+  ssrpa_status st = guarded(ctx, [&] {
+    set_device(ctx);
+    Geometry g = make_geometry(desc);
+    hipStream_t s = Stream(hip_stream).s;
+    sys = new ssrpa_system();
+    sys->ctx = ctx;
+    sys->geo = std::move(g);
+    sys->n_v = desc->n_v;
+    sys->n_c = desc->n_c;
+    sys->n_b = desc->n_v + desc->n_c;
+    sys->n_pw = desc->n_pw;
+    sys->energy.assign(desc->energy, desc->energy + sys->n_b);
+    for (int i = 0; i < sys->n_b; ++i)
+      SSRPA_REQUIRE(std::isfinite(sys->energy[i]), SSRPA_ERR_ARG, "non-finite energy");
+    double vmax = -INFINITY, cmin = INFINITY;
+    for (int i = 0; i < sys->n_v; ++i) vmax = std::max(vmax, sys->energy[i]);
+    for (int i = sys->n_v; i < sys->n_b; ++i) cmin = std::min(cmin, sys->energy[i]);
+    SSRPA_REQUIRE(cmin > vmax, SSRPA_ERR_ARG,
+                  "every conduction energy must lie above every valence energy");
+    const Geometry &gg = sys->geo;
+    const size_t box = (size_t)gg.n1 * gg.n2 * gg.n3;
+    sys->energy_d = DevBuf(ctx, sizeof(double) * sys->n_b);
+    SSRPA_HIP(hipMemcpyAsync(sys->energy_d.as(), sys->energy.data(),
+                             sizeof(double) * sys->n_b, hipMemcpyHostToDevice, s));
+    // per-G tables
+    std::vector<int> code(gg.n_g);
+    std::vector<double> scale(2 * (size_t)gg.ld_g, 0.0);
+    const double on = gg.volume / (double)box;
+    for (int i = 0; i < gg.n_g; ++i) {
+      const int a = gg.miller_chi[3 * i], b = gg.miller_chi[3 * i + 1],
+                c = gg.miller_chi[3 * i + 2];
+      const int col = (a + gg.m1) * gg.n2 + ((b % gg.n2) + gg.n2) % gg.n2;
+      const int k3 = ((c % gg.n3) + gg.n3) % gg.n3;
+      code[i] = col | (k3 << 20);
+      scale[i] = on * gg.sqrt_v[i];
+      scale[gg.ld_g + i] = on;
+    }
+    sys->gcol = DevBuf(ctx, sizeof(int) * gg.n_g);
+    sys->sqrtv_d = DevBuf(ctx, sizeof(double) * 2 * (size_t)gg.ld_g + sizeof(double) * gg.n_g);
+    SSRPA_HIP(hipMemcpyAsync(sys->gcol.as(), code.data(), sizeof(int) * gg.n_g,
+                             hipMemcpyHostToDevice, s));
+    SSRPA_HIP(hipMemcpyAsync(sys->sqrtv_d.as(), scale.data(),
+                             sizeof(double) * 2 * (size_t)gg.ld_g,
+                             hipMemcpyHostToDevice, s));
+    // plain v^1/2 after the two scale tables (for chi0 <-> symmetrized)
+    SSRPA_HIP(hipMemcpyAsync(sys->sqrtv_d.as<double>() + 2 * (size_t)gg.ld_g,
+                             gg.sqrt_v.data(), sizeof(double) * gg.n_g,
+                             hipMemcpyHostToDevice, s));
+    sys->dev_flag = DevBuf(ctx, 64);
+    fill_zero(sys->dev_flag.as(), 64, s);
+    upload_twiddles(*sys);
+    // orbital staging: coefficients -> psi(r)
+    std::vector<int> bidx(sys->n_pw);
+    for (int p = 0; p < sys->n_pw; ++p) {
+      const int a = ((desc->miller[3 * p] % gg.n1) + gg.n1) % gg.n1;
+      const int b = ((desc->miller[3 * p + 1] % gg.n2) + gg.n2) % gg.n2;
+      const int c = ((desc->miller[3 * p + 2] % gg.n3) + gg.n3) % gg.n3;
+      bidx[p] = (c * gg.n2 + b) * gg.n1 + a;
+    }
+    std::vector<int> seen(box, 0);
+    for (int p = 0; p < sys->n_pw; ++p) {
+      SSRPA_REQUIRE(!seen[bidx[p]], SSRPA_ERR_ARG, "duplicate plane wave %d", p);
+      seen[bidx[p]] = 1;
+    }
+    DevBuf bidx_d(ctx, sizeof(int) * sys->n_pw);
+    SSRPA_HIP(hipMemcpyAsync(bidx_d.as(), bidx.data(), sizeof(int) * sys->n_pw,
+                             hipMemcpyHostToDevice, s));
+    const size_t cbytes = sizeof(double) * 2 * (size_t)sys->n_pw * sys->n_b;
+    DevBuf coeff_d;
+    const double *cptr = desc->coeff;
+    if (!desc->coeff_on_device) {
+      coeff_d = DevBuf(ctx, cbytes);
+      SSRPA_HIP(hipMemcpyAsync(coeff_d.as(), desc->coeff, cbytes,
+                               hipMemcpyHostToDevice, s));
+      cptr = coeff_d.as<double>();
+    }
+    sys->psi_r = DevBuf(ctx, bytes_c(box * sys->n_b));
+    launch_orbital_fft(*sys, cptr, bidx_d.as<int>(), s);
+    SSRPA_HIP(hipStreamSynchronize(s));
+  });
+  if (st != SSRPA_OK) {
+    delete sys;
+    return st;
+  }
+  *out = sys;
+  return SSRPA_OK;
+}
+
+ssrpa_status ssrpa_system_destroy(ssrpa_system *sys) {
+  if (!sys) return SSRPA_ERR_ARG;
+  (void)hipSetDevice(sys->ctx->device);
+  (void)hipDeviceSynchronize();
+  delete sys;
+  return SSRPA_OK;
+}
+
+ssrpa_status ssrpa_chi_gvectors(const ssrpa_system *sys, int *n_g,
+                                int32_t *miller) {
+  if (!sys || !n_g) return SSRPA_ERR_ARG;
+  *n_g = sys->geo.n_g;
+  if (miller)
+    std::memcpy(miller, sys->geo.miller_chi.data(), sizeof(int32_t) * 3 * sys->geo.n_g);
+  return SSRPA_OK;
+}
+
+ssrpa_status ssrpa_orbitals_realspace(ssrpa_system *sys, double *psi,
+                                      void *hip_stream) {
+  if (!sys || !psi) return SSRPA_ERR_ARG;
+  return guarded(sys->ctx, [&] {
+    set_device(sys->ctx);
+    hipStream_t s = Stream(hip_stream).s;
+    const size_t n = (size_t)sys->geo.n1 * sys->geo.n2 * sys->geo.n3 * sys->n_b;
+    copy_interleaved(sys->psi_r.as<double>(), psi, n, s);
+    SSRPA_HIP(hipStreamSynchronize(s));
+  });
+}
+
+ssrpa_status ssrpa_pair_matrix(ssrpa_system *sys, int v0, int n_vb, int scaled,
+                               double *m, void *hip_stream) {
+  if (!sys || !m) return SSRPA_ERR_ARG;
+  return guarded(sys->ctx, [&] {
+    set_device(sys->ctx);
+    SSRPA_REQUIRE(v0 >= 0 && n_vb >= 1 && v0 + n_vb <= sys->n_v, SSRPA_ERR_ARG,
+                  "valence range [%d, %d) outside [0, %d)", v0, v0 + n_vb, sys->n_v);
+    hipStream_t s = Stream(hip_stream).s;
+    const Geometry &g = sys->geo;
+    const long rows = (long)n_vb * sys->n_c;
+    DevBuf w(sys->ctx, sizeof(double) * 2 * (size_t)rows * g.ld_g);
+    launch_pair_matrix(*sys, v0, n_vb, scaled != 0, w.as<double>(), s);
+    planar_to_interleaved(w.as<double>(), (int)rows, g.n_g, g.ld_g, m, s);
+    SSRPA_HIP(hipStreamSynchronize(s));
+  });
+}
+
+ssrpa_status ssrpa_chi0_static(ssrpa_system *sys, ssrpa_precision precision,
+                               int valence_block, double *chi0, int symmetrized,
+                               void *hip_stream) {
+  if (!sys) return SSRPA_ERR_ARG;
+  return guarded(sys->ctx, [&] {
+    set_device(sys->ctx);
+    SSRPA_REQUIRE(precision >= SSRPA_FP64 && precision <= SSRPA_BF16X3,
+                  SSRPA_ERR_ARG, "unknown precision %d", (int)precision);
+    SSRPA_REQUIRE(valence_block >= 0, SSRPA_ERR_ARG, "negative valence block");
+    hipStream_t s = Stream(hip_stream).s;
+    const int vb = resolve_block(*sys, valence_block, 0, 1);
+    if (vb < sys->n_v) {
+      sys->w_cache.reset();
+      sys->w_cache_valid = false;
+    }
+    static_chi0(*sys, precision, vb, s);
+    if (chi0) {
+      const Geometry &g = sys->geo;
+      copy_interleaved(sys->chibar0.as<double>(), chi0, (size_t)g.n_g * g.n_g, s);
+      if (!symmetrized)
+        scale_sym(chi0, g.n_g, sys->sqrtv_d.as<double>() + 2 * (size_t)g.ld_g, 1, s);
+      SSRPA_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
+ssrpa_status ssrpa_subspace(ssrpa_system *sys, int n_eig, double *eigval,
+                            double *basis, void *hip_stream) {
+  if (!sys) return SSRPA_ERR_ARG;
+  return guarded(sys->ctx, [&] {
+    set_device(sys->ctx);
+    hipStream_t s = Stream(hip_stream).s;
+    compute_subspace(*sys, n_eig, s);
+    if (eigval) std::memcpy(eigval, sys->sub.eigval.data(), sizeof(double) * n_eig);
+    if (basis) {
+      planar_to_interleaved(sys->sub.basis.as<double>(), sys->geo.n_g, n_eig,
+                            sys->sub.ld_e, basis, s);
+      SSRPA_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
+ssrpa_status ssrpa_correlation_energy(ssrpa_system *sys, int n_eig, int n_freq,
+                                      const double *omega, const double *weight,
+                                      ssrpa_precision precision, int valence_block,
+                                      double coupling, double *ec,
+                                      double *integrand, double *chi_sub,
+                                      void *hip_stream) {
+  if (!sys || !ec) return SSRPA_ERR_ARG;
+  return guarded(sys->ctx, [&] {
+    set_device(sys->ctx);
+    SSRPA_REQUIRE(precision >= SSRPA_FP64 && precision <= SSRPA_BF16X3,
+                  SSRPA_ERR_ARG, "unknown precision %d", (int)precision);
+    SSRPA_REQUIRE(n_eig >= 1, SSRPA_ERR_ARG, "n_eig must be >= 1");
+    SSRPA_REQUIRE(std::isfinite(coupling), SSRPA_ERR_ARG, "bad coupling");
+    hipStream_t s = Stream(hip_stream).s;
+    const int vb = resolve_block(*sys, valence_block, n_eig, n_freq);
+    if (vb < sys->n_v) {
+      sys->w_cache.reset();
+      sys->w_cache_valid = false;
+    }
+    EcResult r = energy(*sys, n_eig, n_freq, omega, weight, precision, vb,
+                        coupling, chi_sub, s);
+    *ec = r.ec;
+    if (integrand) std::memcpy(integrand, r.f.data(), sizeof(double) * n_freq);
+  });
+}
+
+ssrpa_status ssrpa_trace_log(ssrpa_context *ctx, const double *x, int n,
+                             int n_mat, double coupling, double *f,
+                             void *hip_stream) {
+  if (!ctx || !x || !f) return SSRPA_ERR_ARG;
+  return guarded(ctx, [&] {
+    set_device(ctx);
+    SSRPA_REQUIRE(n >= 1 && n_mat >= 1, SSRPA_ERR_ARG, "empty batch");
+    hipStream_t s = Stream(hip_stream).s;
+    DevBuf fd(ctx, sizeof(double) * n_mat + 64);
+    int *flag = reinterpret_cast<int *>(fd.as<double>() + n_mat);
+    fill_zero(flag, sizeof(int), s);
+    trace_log(ctx, x, n, n_mat, coupling, fd.as<double>(), flag, s);
+    int hflag = 0;
+    SSRPA_HIP(hipMemcpyAsync(f, fd.as(), sizeof(double) * n_mat,
+                             hipMemcpyDeviceToHost, s));
+    SSRPA_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    SSRPA_HIP(hipStreamSynchronize(s));
+    SSRPA_REQUIRE(hflag == 0, SSRPA_ERR_NUMERIC,
+                  "I - c X is not positive definite for some matrix");
+  });
+}
+
+ssrpa_status ssrpa_frequency_grid(int n, double omega0, double *omega,
+                                  double *weight) {
+  if (n < 1 || !(omega0 > 0.0) || !omega || !weight) return SSRPA_ERR_ARG;
+  // Gauss-Legendre nodes by Newton's method on P_n, weights
+  // 2 / ((1 - x^2) P_n'(x)^2); then the map to [0, inf).
+  for (int i = 0; i < n; ++i) {
+    long double x = cosl(3.14159265358979323846264338327950288L * (i + 0.75L) / (n + 0.5L));
+    long double dp = 1.0L;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1.0L, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const long double p2 = ((2.0L * k - 1.0L) * x * p1 - (k - 1.0L) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = x; p0 = 1.0L; }
+      dp = n * (x * p1 - p0) / (x * x - 1.0L);
+      const long double dx = p1 / dp;
+      x -= dx;
+      if (fabsl(dx) < 1e-19L) break;
+    }
+    {
+      long double p0 = 1.0L, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const long double p2 = ((2.0L * k - 1.0L) * x * p1 - (k - 1.0L) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = x; p0 = 1.0L; }
+      dp = n * (x * p1 - p0) / (x * x - 1.0L);
+    }
+    const long double wx = 2.0L / ((1.0L - x * x) * dp * dp);
+    // ascending order: node i of the loop is the (n-1-i)-th smallest
+    const int o = n - 1 - i;
+    omega[o] = (double)(omega0 * (1.0L + x) / (1.0L - x));
+    weight[o] = (double)(2.0L * omega0 * wx / ((1.0L - x) * (1.0L - x)));
+  }
+  return SSRPA_OK;
+}
+
+ssrpa_status ssrpa_correlation_energy_enqueue(ssrpa_system *sys, int n_eig,
+                                              int n_freq, const double *omega,
+                                              const double *weight,
+                                              ssrpa_precision precision,
+                                              int valence_block, void *hip_stream,
+                                              ssrpa_ticket **ticket) {
+  if (!sys || !ticket || !omega || !weight || n_freq < 1) return SSRPA_ERR_ARG;
+  auto *t = new (std::nothrow) ssrpa_ticket();
+  if (!t) return SSRPA_ERR_NOMEM;
+  std::vector<double> om(omega, omega + n_freq), wt(weight, weight + n_freq);
+  t->th = std::thread([=]() {
+    ssrpa_status st = SSRPA_OK;
+    double ec = 0.0;
+    std::vector<double> f(n_freq);
+    st = ssrpa_chi0_static(sys, precision, valence_block, nullptr, 1, hip_stream);
+    if (st == SSRPA_OK && n_eig < sys->geo.n_g)
+      st = ssrpa_subspace(sys, n_eig, nullptr, nullptr, hip_stream);
+    if (st == SSRPA_OK)
+      st = ssrpa_correlation_energy(sys, n_eig, n_freq, om.data(), wt.data(),
+                                    precision, valence_block, 1.0, &ec, f.data(),
+                                    nullptr, hip_stream);
+    t->status = st;
+    t->ec = ec;
+    t->f = std::move(f);
+    t->done.store(1);
+  });
+  *ticket = t;
+  return SSRPA_OK;
+}
+
+ssrpa_status ssrpa_ticket_query(ssrpa_ticket *t, int *done) {
+  if (!t || !done) return SSRPA_ERR_ARG;
+  *done = t->done.load();
+  return SSRPA_OK;
+}
+
+ssrpa_status ssrpa_ticket_wait(ssrpa_ticket *t, double *ec, double *integrand) {
+  if (!t) return SSRPA_ERR_ARG;
+  if (t->th.joinable()) t->th.join();
+  const ssrpa_status st = t->status;
+  if (ec) *ec = t->ec;
+  if (integrand && !t->f.empty())
+    std::memcpy(integrand, t->f.data(), sizeof(double) * t->f.size());
+  delete t;
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,556 @@
+// FP64 Hermitian eigensolver for the static-subspace basis: the n_eig
+// eigenpairs of the static v^1/2 chi0 v^1/2 with the largest |eigenvalue|
+// (paper, Method: the projector onto the subspace is built from the
+// eigenvectors of the static polarizability with the greatest absolute
+// eigenvalues).  The matrix is negative semidefinite, so these are the n_eig
+// smallest (most negative) eigenvalues.
+//
+// Steps, all on the GPU:
+//  1. Householder reduction A = Q T_c Q^H to Hermitian tridiagonal form, one
+//     reflector H_k = I - tau u u^H per column (tau real); per step a matrix-
+//     vector product p = tau A' u and the rank-two update A' -= u w^H + w u^H,
+//     w = p - (tau/2)(u^H p) u.  Reflector k is stored in row k of the work
+//     matrix (the part of the row that the reduction no longer needs).
+//  2. A diagonal unitary D makes T = D^H T_c D real symmetric with off-
+//     diagonal |e_k|.
+//  3. Sturm-sequence bisection for the n_eig smallest eigenvalues of T (one
+//     thread per eigenvalue).
+//  4. Inverse iteration on T - lambda I with a partially pivoted tridiagonal
+//     LU (one thread per group of nearly equal eigenvalues; vectors of one
+//     group are orthogonalized against each other at every iteration).
+//  5. Back-transformation C = Q D Z.
+//  6. One Newton-Schulz step C <- C (3I - C^H C) / 2 restores orthonormality
+//     to rounding level (the inverse-iteration vectors of different groups
+//     are orthogonal only to about eps |T| / gap).
+#include <cfloat>
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace ssrpa {
+
+namespace {
+
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Block-wide sum (blockDim multiple of 64, <= 1024); all threads get it.
+__device__ double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int i = 0; i < nw; ++i) t += red[i];
+  return t;
+}
+
+// ------------------------------------------------ Householder reduction
+
+struct TriWork {
+  double2 *a;     // n x n work matrix (interleaved)
+  double *tau;    // n
+  double *d;      // n   diagonal of T
+  double2 *e;     // n   complex off-diagonal of T_c (e[k] = T_c[k+1][k])
+  double2 *p;     // n   scratch vector
+  double2 *w;     // n   scratch vector
+};
+
+// Reflector for column k: x = A[k+1:, k] = conj(A[k][k+1:]).
+__global__ __launch_bounds__(256) void hh_make_kernel(TriWork t, int n, int k) {
+  __shared__ double red[16];
+  const int m = n - k - 1;
+  double2 *row = t.a + (long)k * n + k + 1;
+  double s = 0.0;
+  for (int i = threadIdx.x + 1; i < m; i += blockDim.x) {
+    const double2 v = row[i];
+    s += v.x * v.x + v.y * v.y;
+  }
+  const double rest = block_sum(s, red);      // sum_{i>0} |x_i|^2
+  const double2 a0c = row[0];                 // conj(x0)
+  const double2 x0 = make_double2(a0c.x, -a0c.y);
+  const double ax0 = hypot(x0.x, x0.y);
+  const double nrm2 = rest + ax0 * ax0;
+  __syncthreads();
+  if (m == 1 || rest == 0.0) {
+    // already of the form e_k e_1: no reflection (H = I)
+    if (threadIdx.x == 0) {
+      t.tau[k] = 0.0;
+      t.e[k] = x0;
+      t.d[k] = t.a[(long)k * n + k].x;
+    }
+    return;
+  }
+  const double nrm = sqrt(nrm2);
+  const double2 ph = ax0 > 0.0 ? make_double2(x0.x / ax0, x0.y / ax0)
+                               : make_double2(1.0, 0.0);
+  // beta = -phase |x|; u = x - beta e_1; |u|^2 = 2 |x| (|x| + |x0|)
+  const double2 beta = make_double2(-ph.x * nrm, -ph.y * nrm);
+  const double tau = 1.0 / (nrm * (nrm + ax0));
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const double2 v = row[i];
+    double2 u = make_double2(v.x, -v.y);      // x_i
+    if (i == 0) u = make_double2(x0.x - beta.x, x0.y - beta.y);
+    row[i] = u;                               // store u (not conjugated)
+  }
+  if (threadIdx.x == 0) {
+    t.tau[k] = tau;
+    t.e[k] = beta;
+    t.d[k] = t.a[(long)k * n + k].x;
+  }
+}
+
+// p_i = tau sum_j A[k+1+i][k+1+j] u_j, one wave per row.
+__global__ __launch_bounds__(256) void hh_hemv_kernel(TriWork t, int n, int k) {
+  const int m = n - k - 1;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= m) return;
+  const double tau = t.tau[k];
+  const double2 *u = t.a + (long)k * n + k + 1;
+  const double2 *ar = t.a + (long)(k + 1 + i) * n + k + 1;
+  double sr = 0.0, si = 0.0;
+  for (int j = lane; j < m; j += 64) {
+    const double2 a = ar[j], b = u[j];
+    sr += a.x * b.x - a.y * b.y;
+    si += a.x * b.y + a.y * b.x;
+  }
+  sr = wave_sum(sr);
+  si = wave_sum(si);
+  if (lane == 0) t.p[i] = make_double2(tau * sr, tau * si);
+}
+
+// w = p - (tau/2)(u^H p) u
+__global__ __launch_bounds__(256) void hh_w_kernel(TriWork t, int n, int k) {
+  __shared__ double red[16];
+  const int m = n - k - 1;
+  const double tau = t.tau[k];
+  const double2 *u = t.a + (long)k * n + k + 1;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const double2 c = cmulc(u[i], t.p[i]);
+    s += c.x;  // u^H A u is real
+  }
+  const double K = 0.5 * tau * block_sum(s, red);
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const double2 pi = t.p[i], ui = u[i];
+    t.w[i] = make_double2(pi.x - K * ui.x, pi.y - K * ui.y);
+  }
+}
+
+// A'[i][j] -= u_i conj(w_j) + w_i conj(u_j)
+__global__ __launch_bounds__(256) void hh_her2_kernel(TriWork t, int n, int k) {
+  const int m = n - k - 1;
+  const int i = blockIdx.y;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (i >= m || j >= m) return;
+  if (t.tau[k] == 0.0) return;
+  const double2 *u = t.a + (long)k * n + k + 1;
+  const double2 ui = u[i], wi = t.w[i], uj = u[j], wj = t.w[j];
+  double2 *x = t.a + (long)(k + 1 + i) * n + k + 1 + j;
+  const double2 a = cmulc(wj, ui);  // ui conj(wj)
+  const double2 b = cmulc(uj, wi);  // wi conj(uj)
+  double2 v = *x;
+  v.x -= a.x + b.x;
+  v.y -= a.y + b.y;
+  *x = v;
+}
+
+__global__ void hh_last_kernel(TriWork t, int n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) t.d[n - 1] = t.a[(long)(n - 1) * n + n - 1].x;
+}
+
+// --------------------------------------------------- real tridiagonal T
+
+struct TriReal {
+  const double *d;   // n
+  double *e;         // n-1, |e_k| (real symmetric off-diagonal)
+  double2 *phase;    // n, D = diag(phase)
+  double *bounds;    // [lo, hi, tnorm, pivmin]
+};
+
+__global__ void tri_phase_kernel(const double2 *__restrict__ ec, TriReal r,
+                                 int n) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double2 ph = make_double2(1.0, 0.0);
+  r.phase[0] = ph;
+  double lo = INFINITY, hi = -INFINITY, emax2 = 0.0, tn = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double ek_prev = k > 0 ? r.e[k - 1] : 0.0;
+    double ek = 0.0;
+    if (k < n - 1) {
+      const double2 c = ec[k];
+      ek = hypot(c.x, c.y);
+      r.e[k] = ek;
+      // phase_{k+1} = phase_k e_k / |e_k|
+      double2 q = ek > 0.0 ? make_double2(c.x / ek, c.y / ek) : make_double2(1.0, 0.0);
+      ph = make_double2(ph.x * q.x - ph.y * q.y, ph.x * q.y + ph.y * q.x);
+      const double nr = hypot(ph.x, ph.y);
+      ph.x /= nr;
+      ph.y /= nr;
+      r.phase[k + 1] = ph;
+      emax2 = fmax(emax2, ek * ek);
+    }
+    const double rad = ek_prev + ek;
+    lo = fmin(lo, r.d[k] - rad);
+    hi = fmax(hi, r.d[k] + rad);
+    tn = fmax(tn, fabs(r.d[k]) + rad);
+  }
+  const double span = fmax(hi - lo, tn) * 2.0 * DBL_EPSILON + DBL_MIN;
+  r.bounds[0] = lo - span;
+  r.bounds[1] = hi + span;
+  r.bounds[2] = tn;
+  r.bounds[3] = fmax(DBL_MIN, DBL_MIN * emax2);
+}
+
+// number of eigenvalues of T below sigma
+__device__ int sturm_count(const double *d, const double *e, int n,
+                           double sigma, double pivmin) {
+  double q = d[0] - sigma;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int cnt = q < 0.0;
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - sigma - e[i - 1] * e[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+__global__ void bisect_kernel(TriReal r, int n, int n_eig,
+                              double *__restrict__ lam) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_eig) return;
+  double lo = r.bounds[0], hi = r.bounds[1];
+  const double pivmin = r.bounds[3];
+  for (int it = 0; it < 128; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+    if (sturm_count(r.d, r.e, n, mid, pivmin) > i)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  lam[i] = 0.5 * (lo + hi);
+}
+
+// ------------------------------------------------------ inverse iteration
+
+struct InvIt {
+  const double *d;
+  const double *e;
+  const double *lam;
+  const double *bounds;
+  double *z;         // n x ldz (row-major, column j = eigenvector j)
+  int ldz;
+  double *u0, *u1, *u2, *ml;   // n x ldz each
+  unsigned char *pv;           // n x ldz
+  double gtol_rel;             // grouping tolerance relative to |T|
+};
+
+__device__ __forceinline__ double start_value(int row, int col) {
+  unsigned x = (unsigned)row * 2654435761u ^ ((unsigned)col * 2246822519u + 0x9e3779b9u);
+  x ^= x >> 15; x *= 2246822519u; x ^= x >> 13; x *= 3266489917u; x ^= x >> 16;
+  return (double)(x & 0xFFFFFF) / 8388608.0 - 1.0;  // (-1, 1)
+}
+
+// LU of T - lam I with partial pivoting (rows i and i+1 swap when the
+// subdiagonal entry is larger); U has bandwidth 2.
+__device__ void tri_lu(const InvIt &q, int n, int col, double lam, double tiny) {
+  const long ld = q.ldz;
+  double r0 = q.d[0] - lam, r1 = n > 1 ? q.e[0] : 0.0;
+  for (int i = 0; i < n - 1; ++i) {
+    const double b = q.e[i];
+    const double dn = q.d[i + 1] - lam;
+    const double en = (i + 1 < n - 1) ? q.e[i + 1] : 0.0;
+    const long o = (long)i * ld + col;
+    if (fabs(r0) >= fabs(b)) {
+      if (r0 == 0.0) r0 = tiny;
+      const double mlt = b / r0;
+      q.u0[o] = r0; q.u1[o] = r1; q.u2[o] = 0.0; q.ml[o] = mlt; q.pv[o] = 0;
+      r0 = dn - mlt * r1;
+      r1 = en;
+    } else {
+      const double mlt = r0 / b;
+      q.u0[o] = b; q.u1[o] = dn; q.u2[o] = en; q.ml[o] = mlt; q.pv[o] = 1;
+      r0 = r1 - mlt * dn;
+      r1 = -mlt * en;
+    }
+  }
+  if (r0 == 0.0) r0 = tiny;
+  const long o = (long)(n - 1) * ld + col;
+  q.u0[o] = r0; q.u1[o] = 0.0; q.u2[o] = 0.0; q.ml[o] = 0.0; q.pv[o] = 0;
+}
+
+// x <- (T - lam I)^-1 x (x is column col of z), then normalize.
+__device__ void tri_solve(const InvIt &q, int n, int col) {
+  const long ld = q.ldz;
+  double *x = q.z + col;
+  for (int i = 0; i < n - 1; ++i) {
+    const long o = (long)i * ld + col;
+    double a = x[i * ld], b = x[(i + 1) * ld];
+    if (q.pv[o]) { const double t = a; a = b; b = t; }
+    x[i * ld] = a;
+    x[(i + 1) * ld] = b - q.ml[o] * a;
+  }
+  double xp1 = 0.0, xp2 = 0.0;
+  for (int i = n - 1; i >= 0; --i) {
+    const long o = (long)i * ld + col;
+    const double v = (x[i * ld] - q.u1[o] * xp1 - q.u2[o] * xp2) / q.u0[o];
+    x[i * ld] = v;
+    xp2 = xp1;
+    xp1 = v;
+  }
+}
+
+__device__ void normalize_col(const InvIt &q, int n, int col) {
+  const long ld = q.ldz;
+  double s = 0.0, mx = 0.0;
+  for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(q.z[i * ld + col]));
+  if (mx == 0.0) return;
+  for (int i = 0; i < n; ++i) {
+    const double v = q.z[i * ld + col] / mx;
+    s += v * v;
+  }
+  const double f = 1.0 / (mx * sqrt(s));
+  for (int i = 0; i < n; ++i) q.z[i * ld + col] *= f;
+}
+
+__global__ void inverse_iteration_kernel(InvIt q, int n, int n_eig) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_eig) return;
+  const double tn = q.bounds[2];
+  const double gtol = q.gtol_rel * tn;
+  // a group starts where the gap to the previous eigenvalue exceeds gtol
+  if (j > 0 && q.lam[j] - q.lam[j - 1] <= gtol) return;
+  int j1 = j + 1;
+  while (j1 < n_eig && q.lam[j1] - q.lam[j1 - 1] <= gtol) ++j1;
+  const double tiny = DBL_EPSILON * fmax(tn, DBL_MIN);
+  const long ld = q.ldz;
+  for (int c = j; c < j1; ++c) {
+    // separate exactly equal shifts inside a group by a few ulps of |T|
+    const double lam = q.lam[c] + (c - j) * 8.0 * tiny;
+    tri_lu(q, n, c, lam, tiny);
+    for (int i = 0; i < n; ++i) q.z[i * ld + c] = start_value(i, c);
+    for (int it = 0; it < 4; ++it) {
+      tri_solve(q, n, c);
+      // modified Gram-Schmidt against earlier vectors of the group
+      for (int o = j; o < c; ++o) {
+        double dot = 0.0;
+        for (int i = 0; i < n; ++i) dot += q.z[i * ld + o] * q.z[i * ld + c];
+        for (int i = 0; i < n; ++i) q.z[i * ld + c] -= dot * q.z[i * ld + o];
+      }
+      normalize_col(q, n, c);
+    }
+  }
+}
+
+// ------------------------------------------------------ back-transform
+
+// C[row][col] = phase[row] z[row][col], planar rows (re at 0, im at +ld_e).
+__global__ void phase_apply_kernel(const double *__restrict__ z, int ldz,
+                                   const double2 *__restrict__ phase, int n,
+                                   int n_eig, double *__restrict__ c, int ld_e,
+                                   int rows_pad) {
+  const long total = (long)rows_pad * ld_e;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int row = (int)(idx / ld_e), col = (int)(idx % ld_e);
+    double re = 0.0, im = 0.0;
+    if (row < n && col < n_eig) {
+      const double v = z[(long)row * ldz + col];
+      const double2 ph = phase[row];
+      re = ph.x * v;
+      im = ph.y * v;
+    }
+    c[(long)row * 2 * ld_e + col] = re;
+    c[(long)row * 2 * ld_e + ld_e + col] = im;
+  }
+}
+
+// Apply H_{n-2} ... H_0 (in that order, H_0 last) to columns [c0, c0+16).
+__global__ __launch_bounds__(256) void apply_reflectors_kernel(
+    const double2 *__restrict__ a, const double *__restrict__ tau, int n,
+    double *__restrict__ c, int ld_e, int n_eig) {
+  __shared__ double sr[16][17], si[16][17];
+  const int col = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int rs = threadIdx.x >> 4;
+  const bool active = col < n_eig;
+  const long ldc = 2L * ld_e;
+  for (int k = n - 2; k >= 0; --k) {
+    const double tk = tau[k];
+    if (tk == 0.0) continue;
+    const int m = n - k - 1;
+    const double2 *u = a + (long)k * n + k + 1;
+    double dr = 0.0, di = 0.0;
+    if (active) {
+      for (int i = rs; i < m; i += 16) {
+        const double2 ui = u[i];
+        const double *cr = c + (long)(k + 1 + i) * ldc + col;
+        const double xr = cr[0], xi = cr[ld_e];
+        dr += ui.x * xr + ui.y * xi;   // conj(u) x
+        di += ui.x * xi - ui.y * xr;
+      }
+    }
+    sr[rs][threadIdx.x & 15] = dr;
+    si[rs][threadIdx.x & 15] = di;
+    __syncthreads();
+    double tr = 0.0, ti = 0.0;
+    for (int s = 0; s < 16; ++s) {
+      tr += sr[s][threadIdx.x & 15];
+      ti += si[s][threadIdx.x & 15];
+    }
+    tr *= tk;
+    ti *= tk;
+    if (active) {
+      for (int i = rs; i < m; i += 16) {
+        const double2 ui = u[i];
+        double *cr = c + (long)(k + 1 + i) * ldc + col;
+        cr[0] -= ui.x * tr - ui.y * ti;
+        cr[ld_e] -= ui.x * ti + ui.y * tr;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// B = 1.5 I - 0.5 G  (G interleaved n_eig x n_eig) into planar ld_e x ld_e
+__global__ void newton_schulz_coeff_kernel(const double *__restrict__ g,
+                                           int n_eig, int ld_e,
+                                           double *__restrict__ b) {
+  const long total = (long)ld_e * ld_e;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(idx / ld_e), cc = (int)(idx % ld_e);
+    double re = 0.0, im = 0.0;
+    if (r < n_eig && cc < n_eig) {
+      re = -0.5 * g[2L * ((long)r * n_eig + cc)];
+      im = -0.5 * g[2L * ((long)r * n_eig + cc) + 1];
+      if (r == cc) re += 1.5;
+    }
+    b[(long)r * 2 * ld_e + cc] = re;
+    b[(long)r * 2 * ld_e + ld_e + cc] = im;
+  }
+}
+
+}  // namespace
+
+void eig_lowest(Context *ctx, const double *a_in, int n, int n_eig,
+                double *eigval, double *basis, int ld_e, int *flag,
+                hipStream_t s) {
+  (void)flag;
+  SSRPA_REQUIRE(n >= 1 && n_eig >= 1 && n_eig <= n, SSRPA_ERR_ARG,
+                "eig: bad sizes n=%d n_eig=%d", n, n_eig);
+  const int rows_pad = round_up(n, 64);
+  DevBuf wa(ctx, sizeof(double2) * (size_t)n * n);
+  DevBuf vecs(ctx, sizeof(double) * 2 * (size_t)n + sizeof(double2) * 4 * (size_t)n + 64);
+  copy_interleaved(a_in, wa.as<double>(), (size_t)n * n, s);
+  TriWork t;
+  t.a = wa.as<double2>();
+  double *base = vecs.as<double>();
+  t.tau = base;
+  t.d = base + n;
+  t.e = reinterpret_cast<double2 *>(base + 2 * n);
+  t.p = t.e + n;
+  t.w = t.p + n;
+  double2 *phase = t.w + n;
+  for (int k = 0; k < n - 1; ++k) {
+    const int m = n - k - 1;
+    hipLaunchKernelGGL(hh_make_kernel, dim3(1), dim3(256), 0, s, t, n, k);
+    if (m > 1) {
+      hipLaunchKernelGGL(hh_hemv_kernel, dim3((m + 3) / 4), dim3(256), 0, s, t,
+                         n, k);
+      hipLaunchKernelGGL(hh_w_kernel, dim3(1), dim3(256), 0, s, t, n, k);
+      hipLaunchKernelGGL(hh_her2_kernel, dim3((m + 255) / 256, m), dim3(256), 0,
+                         s, t, n, k);
+    }
+  }
+  hipLaunchKernelGGL(hh_last_kernel, dim3(1), dim3(64), 0, s, t, n);
+  SSRPA_HIP(hipGetLastError());
+
+  DevBuf rw(ctx, sizeof(double) * ((size_t)n + 8));
+  TriReal r;
+  r.d = t.d;
+  r.e = rw.as<double>();
+  r.phase = phase;
+  r.bounds = rw.as<double>() + n;
+  hipLaunchKernelGGL(tri_phase_kernel, dim3(1), dim3(64), 0, s,
+                     (const double2 *)t.e, r, n);
+  hipLaunchKernelGGL(bisect_kernel, dim3((n_eig + 63) / 64), dim3(64), 0, s, r,
+                     n, n_eig, eigval);
+  SSRPA_HIP(hipGetLastError());
+
+  // inverse iteration workspace: z, u0, u1, u2, ml (doubles) + pivots
+  const int ldz = n_eig;
+  const size_t nz = (size_t)n * ldz;
+  DevBuf iw(ctx, sizeof(double) * 5 * nz + nz + 64);
+  InvIt q;
+  q.d = t.d;
+  q.e = r.e;
+  q.lam = eigval;
+  q.bounds = r.bounds;
+  q.z = iw.as<double>();
+  q.ldz = ldz;
+  q.u0 = q.z + nz;
+  q.u1 = q.u0 + nz;
+  q.u2 = q.u1 + nz;
+  q.ml = q.u2 + nz;
+  q.pv = reinterpret_cast<unsigned char *>(q.ml + nz);
+  // eigenvalues closer than 1e-7 |T| form one group (orthogonalized inside)
+  q.gtol_rel = 1e-7;
+  hipLaunchKernelGGL(inverse_iteration_kernel, dim3((n_eig + 63) / 64), dim3(64),
+                     0, s, q, n, n_eig);
+  SSRPA_HIP(hipGetLastError());
+
+  const long tot = (long)rows_pad * ld_e;
+  hipLaunchKernelGGL(phase_apply_kernel,
+                     dim3((unsigned)std::min<long>((tot + 255) / 256, 65536)),
+                     dim3(256), 0, s, q.z, ldz, (const double2 *)phase, n, n_eig,
+                     basis, ld_e, rows_pad);
+  hipLaunchKernelGGL(apply_reflectors_kernel, dim3((n_eig + 15) / 16), dim3(256),
+                     0, s, (const double2 *)t.a, t.tau, n, basis, ld_e, n_eig);
+  SSRPA_HIP(hipGetLastError());
+
+  // Newton-Schulz: C <- C (1.5 I - 0.5 C^H C)
+  DevBuf gram(ctx, sizeof(double2) * (size_t)n_eig * n_eig);
+  DevBuf coef(ctx, sizeof(double) * 2 * (size_t)ld_e * ld_e);
+  DevBuf cnew(ctx, sizeof(double) * 2 * (size_t)rows_pad * ld_e);
+  DevBuf ws;
+  HerkArgs h{};
+  h.a = basis;
+  h.lda = 2L * ld_e;
+  h.im_off = ld_e;
+  h.ncol = n_eig;
+  h.ld = ld_e;
+  h.k = n;
+  h.n_omega = 1;
+  h.unit_weight = 1;
+  herk(ctx, h, SSRPA_FP64, gram.as<double>(), 0, 0, ws, s);
+  const long tc = (long)ld_e * ld_e;
+  hipLaunchKernelGGL(newton_schulz_coeff_kernel,
+                     dim3((unsigned)std::min<long>((tc + 255) / 256, 65536)),
+                     dim3(256), 0, s, gram.as<double>(), n_eig, ld_e,
+                     coef.as<double>());
+  GemmArgs g{};
+  g.a = basis; g.lda = 2L * ld_e; g.a_im = ld_e;
+  g.b = coef.as<double>(); g.ldb = 2L * ld_e; g.b_im = ld_e;
+  g.c = cnew.as<double>(); g.ldc = 2L * ld_e; g.c_im = ld_e;
+  g.m = rows_pad; g.n = ld_e; g.k = ld_e;
+  g.alpha = 1.0; g.beta = 0.0;
+  gemm(ctx, g, SSRPA_FP64, s);
+  SSRPA_HIP(hipMemcpyAsync(basis, cnew.as(), sizeof(double) * 2 * (size_t)rows_pad * ld_e,
+                           hipMemcpyDeviceToDevice, s));
+  SSRPA_HIP(hipStreamSynchronize(s));  // work buffers are freed on return
+}
+
+}  // namespace ssrpa

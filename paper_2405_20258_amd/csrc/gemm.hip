@@ -1,0 +1,365 @@
+// Dense complex contractions on the MFMA units of gfx950.
+//
+//  * herk:  X_j = A^H diag(d_j) A for a batch of weight vectors d_j, the form
+//           of the polarizability sum chi0 = M^H Delta M / Omega (paper,
+//           Eq. 6; per valence block, Eq. 15) and of its subspace version
+//           chi0_s = M_s^H Delta M_s (Eq. 8).  d_j,p = -4 de_p / (de_p^2 +
+//           w_j^2) / Omega, computed from the pair energy gaps while the
+//           operand tile is staged, so Delta is never stored.
+//  * gemm:  C = alpha A B + beta C, used for the projection M_s = M C_s
+//           (Eq. 7) and for small basis updates.
+//
+// Operands are planar complex: every row holds its real parts, then (at a
+// fixed offset) its imaginary parts.  A complex product is four real MFMA
+// products: Re = ArBr + AiBi (conjugated A) or ArBr - AiBi, and
+// Im = ArBi - AiBr or ArBi + AiBr.
+//
+// FP64 path: v_mfma_f64_16x16x4f64.  One 256-thread block owns a 64 x 64
+// complex output tile; each wave owns a 32 x 32 quadrant (2 x 2 MFMA tiles,
+// real and imaginary accumulators).  The K loop stages 16-row chunks of both
+// operands through LDS.  HERK computes only lower-triangle tiles and splits K
+// over blocks when there are too few tiles; the partial tiles are summed in a
+// fixed order by a second kernel that also mirrors the Hermitian upper half,
+// so results are deterministic run to run.
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace ssrpa {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kT = 64;    // output tile (complex)
+constexpr int kKc = 16;   // K rows per LDS stage
+constexpr int kPad = 2;   // LDS row padding (doubles)
+
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Output element (row, col) held by lane `l` in accumulator slot e of a
+// 16 x 16 f64 MFMA tile: 16-lane groups hold 4 consecutive rows.
+__device__ __forceinline__ int acc_row(int l, int e) { return 4 * (l >> 4) + e; }
+__device__ __forceinline__ int acc_col(int l) { return l & 15; }
+
+// Spread consecutive block ids over the 8 XCDs so that neighbouring tiles
+// (which share operand panels) run on the same XCD and share its L2.
+__device__ __forceinline__ int xcd_remap(int b, int total) {
+  const int per = total / 8;
+  if (b >= per * 8) return b;
+  return (b & 7) * per + (b >> 3);
+}
+
+// Lower-triangle tile t -> (I, J), I >= J, t = I (I + 1) / 2 + J.
+__device__ __forceinline__ int2 tri_tile(int t) {
+  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while (I * (I + 1) / 2 > t) --I;
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  return make_int2(I, t - I * (I + 1) / 2);
+}
+
+__device__ __forceinline__ double pair_weight(const HerkArgs &h, long p,
+                                              double om) {
+  if (h.unit_weight) return 1.0;
+  const double de = h.de[p];
+  return -4.0 * de / (de * de + om * om) * h.wscale;
+}
+
+// ---------------------------------------------------------------- HERK f64
+
+__global__ __launch_bounds__(256) void herk_f64_kernel(
+    HerkArgs h, int n_tiles, long kchunk, double *__restrict__ partial) {
+  __shared__ double As[2][kKc][kT + kPad];
+  __shared__ double Bs[2][kKc][kT + kPad];
+  __shared__ double wk[kKc];
+  const int tile_id = xcd_remap(blockIdx.x, n_tiles);
+  const int split = blockIdx.y;
+  const int om_i = blockIdx.z;
+  const int2 tile = tri_tile(tile_id);
+  const int I0 = tile.x * kT, J0 = tile.y * kT;
+  const double om = h.unit_weight ? 0.0 : h.omega[om_i];
+  const long kbeg = split * kchunk;
+  const long kend = min(h.k, kbeg + kchunk);
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  d4 re[2][2], im[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      re[i][j] = d4{0, 0, 0, 0};
+      im[i][j] = d4{0, 0, 0, 0};
+    }
+
+  // staging map: 256 threads x 4 loads of double2 cover 2 ops x 2 parts x
+  // 16 rows x 64 columns.
+  for (long k0 = kbeg; k0 < kend; k0 += kKc) {
+    if (threadIdx.x < kKc) {
+      const long p = k0 + threadIdx.x;
+      wk[threadIdx.x] = p < kend ? pair_weight(h, p, om) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int idx = threadIdx.x + it * 256;   // 0..1023
+      const int op = idx >> 9;                   // 0: A (rows I), 1: B (cols J)
+      const int part = (idx >> 8) & 1;           // 0 re, 1 im
+      const int r = (idx >> 4) & 15;             // k row in chunk
+      const int c2 = (idx & 15) * 2;             // column pair (0..30) x2 -> 64
+      const long p = k0 + r;
+      const int col0 = op ? J0 : I0;
+      double2 v = make_double2(0.0, 0.0), u = make_double2(0.0, 0.0);
+      if (p < kend) {
+        const double *src = h.a + p * h.lda + part * h.im_off + col0;
+        v = *reinterpret_cast<const double2 *>(src + c2);
+        u = *reinterpret_cast<const double2 *>(src + c2 + 32);
+      }
+      const double sc = op ? wk[r] : 1.0;
+      double *dst = op ? &Bs[part][r][0] : &As[part][r][0];
+      dst[c2] = v.x * sc;
+      dst[c2 + 1] = v.y * sc;
+      dst[c2 + 32] = u.x * sc;
+      dst[c2 + 33] = u.y * sc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kKc; ks += 4) {
+      const int kr = ks + (lane >> 4);
+      const int cl = lane & 15;
+      double ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ar[i] = As[0][kr][wr + i * 16 + cl];
+        ai[i] = As[1][kr][wr + i * 16 + cl];
+        br[i] = Bs[0][kr][wc + i * 16 + cl];
+        bi[i] = Bs[1][kr][wc + i * 16 + cl];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          re[i][j] = mfma64(ar[i], br[j], re[i][j]);
+          re[i][j] = mfma64(ai[i], bi[j], re[i][j]);
+          im[i][j] = mfma64(ar[i], bi[j], im[i][j]);
+          im[i][j] = mfma64(-ai[i], br[j], im[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+  // partial tile: [om][split][tile][part][64][64]
+  double *out = partial + (((long)om_i * gridDim.y + split) * n_tiles + tile_id) *
+                              2L * kT * kT;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = wr + i * 16 + acc_row(lane, e);
+        const int c = wc + j * 16 + acc_col(lane);
+        out[r * kT + c] = re[i][j][e];
+        out[kT * kT + r * kT + c] = im[i][j][e];
+      }
+}
+
+// Sum split partials in order and write the Hermitian matrix (both halves).
+__global__ void herk_reduce_kernel(const double *__restrict__ partial,
+                                   int n_tiles,
+                                   int nsplit, int ncol, double *__restrict__ out,
+                                   long out_stride, int beta) {
+  const int tile_id = blockIdx.x;
+  const int om_i = blockIdx.y;
+  const int2 tile = tri_tile(tile_id);
+  const int I0 = tile.x * kT, J0 = tile.y * kT;
+  double *o = out + om_i * out_stride;
+  for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
+    const int r = e / kT, c = e % kT;
+    const int g = I0 + r, gp = J0 + c;
+    if (g >= ncol || gp >= ncol) continue;
+    if (tile.x == tile.y && r < c) continue;
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < nsplit; ++s) {
+      const double *p = partial +
+                        (((long)om_i * nsplit + s) * n_tiles + tile_id) * 2L * kT * kT;
+      sr += p[e];
+      si += p[kT * kT + e];
+    }
+    if (g == gp) si = 0.0;  // exact: the diagonal of A^H D A is real
+    double *d1 = o + 2L * ((long)g * ncol + gp);
+    double *d2 = o + 2L * ((long)gp * ncol + g);
+    if (beta) {
+      d1[0] += sr;
+      d1[1] += si;
+      if (g != gp) {
+        d2[0] += sr;
+        d2[1] -= si;
+      }
+    } else {
+      d1[0] = sr;
+      d1[1] = si;
+      if (g != gp) {
+        d2[0] = sr;
+        d2[1] = -si;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- GEMM f64
+
+__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g, int m_tiles,
+                                                      int n_tiles) {
+  __shared__ double As[2][kKc][kT + kPad];  // [part][k][m]
+  __shared__ double Bs[2][kKc][kT + kPad];  // [part][k][n]
+  const int total = m_tiles * n_tiles;
+  const int b = xcd_remap(blockIdx.x, total);
+  const int mt = b / n_tiles, nt = b % n_tiles;
+  const long M0 = (long)mt * kT;
+  const int N0 = nt * kT;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  d4 re[2][2], im[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      re[i][j] = d4{0, 0, 0, 0};
+      im[i][j] = d4{0, 0, 0, 0};
+    }
+  for (int k0 = 0; k0 < g.k; k0 += kKc) {
+    // A: 64 rows x 16 k x 2 parts = 2048 doubles: thread -> (row, part, 8 k)
+    {
+      const int row = threadIdx.x >> 2;        // 0..63
+      const int part = (threadIdx.x >> 1) & 1;
+      const int kq = (threadIdx.x & 1) * 8;     // 0 or 8
+      const long m = M0 + row;
+      double v[8];
+      if (m < g.m) {
+        const double *src = g.a + m * g.lda + part * g.a_im + k0 + kq;
+#pragma unroll
+        for (int x = 0; x < 8; x += 2) {
+          const double2 t = *reinterpret_cast<const double2 *>(src + x);
+          v[x] = t.x;
+          v[x + 1] = t.y;
+        }
+      } else {
+#pragma unroll
+        for (int x = 0; x < 8; ++x) v[x] = 0.0;
+      }
+#pragma unroll
+      for (int x = 0; x < 8; ++x) As[part][kq + x][row] = v[x];
+    }
+    // B: 16 k x 64 cols x 2 parts = 2048 doubles: thread -> (k, part, 8 cols)
+    {
+      const int kr = threadIdx.x >> 4;          // 0..15
+      const int part = (threadIdx.x >> 3) & 1;
+      const int cq = (threadIdx.x & 7) * 8;     // 0..56
+      const double *src = g.b + (long)(k0 + kr) * g.ldb + part * g.b_im + N0 + cq;
+#pragma unroll
+      for (int x = 0; x < 8; x += 2) {
+        const double2 t = *reinterpret_cast<const double2 *>(src + x);
+        Bs[part][kr][cq + x] = t.x;
+        Bs[part][kr][cq + x + 1] = t.y;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kKc; ks += 4) {
+      const int kr = ks + (lane >> 4);
+      const int cl = lane & 15;
+      double ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ar[i] = As[0][kr][wr + i * 16 + cl];
+        ai[i] = As[1][kr][wr + i * 16 + cl];
+        br[i] = Bs[0][kr][wc + i * 16 + cl];
+        bi[i] = Bs[1][kr][wc + i * 16 + cl];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          re[i][j] = mfma64(ar[i], br[j], re[i][j]);
+          re[i][j] = mfma64(-ai[i], bi[j], re[i][j]);
+          im[i][j] = mfma64(ar[i], bi[j], im[i][j]);
+          im[i][j] = mfma64(ai[i], br[j], im[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const long m = M0 + wr + i * 16 + acc_row(lane, e);
+        const int n = N0 + wc + j * 16 + acc_col(lane);
+        if (m >= g.m) continue;
+        double *cr = g.c + m * g.ldc + n;
+        double *ci = cr + g.c_im;
+        const double vr = g.alpha * re[i][j][e];
+        const double vi = g.alpha * im[i][j][e];
+        if (g.beta != 0.0) {
+          *cr = vr + g.beta * *cr;
+          *ci = vi + g.beta * *ci;
+        } else {
+          *cr = vr;
+          *ci = vi;
+        }
+      }
+}
+
+}  // namespace
+
+void herk(Context *ctx, const HerkArgs &h, ssrpa_precision prec, double *out,
+          long out_stride, int beta, DevBuf &ws, hipStream_t s) {
+  (void)prec;  // reduced-precision paths are dispatched in gemm_mixed.hip
+  SSRPA_REQUIRE(h.ld % kT == 0 && h.ncol <= h.ld, SSRPA_ERR_ARG,
+                "herk: bad padding");
+  const int T = h.ld / kT;
+  const int n_tiles = T * (T + 1) / 2;
+  // split K so that there are at least ~2 blocks per CU
+  const long kr = (h.k + kKc - 1) / kKc;
+  long nsplit = (512 + (long)n_tiles * h.n_omega - 1) / ((long)n_tiles * h.n_omega);
+  nsplit = std::max(1L, std::min(nsplit, std::max(1L, kr / 8)));
+  long kchunk = ((kr + nsplit - 1) / nsplit) * kKc;
+  nsplit = (h.k + kchunk - 1) / kchunk;
+  if (nsplit < 1) nsplit = 1;
+  const size_t need = sizeof(double) * 2L * kT * kT * n_tiles * nsplit * h.n_omega;
+  ws.ensure(ctx, need);
+  DevBuf *wsb = &ws;
+  if (h.k > 0) {
+    hipLaunchKernelGGL(herk_f64_kernel, dim3(n_tiles, (unsigned)nsplit, h.n_omega),
+                       dim3(256), 0, s, h, n_tiles, kchunk,
+                       wsb->as<double>());
+    SSRPA_HIP(hipGetLastError());
+  } else {
+    fill_zero(wsb->as(), need, s);
+  }
+  hipLaunchKernelGGL(herk_reduce_kernel, dim3(n_tiles, h.n_omega), dim3(256), 0,
+                     s, wsb->as<double>(), n_tiles, (int)nsplit, h.ncol,
+                     out, out_stride, beta);
+  SSRPA_HIP(hipGetLastError());
+}
+
+void gemm(Context *ctx, const GemmArgs &g, ssrpa_precision prec, hipStream_t s) {
+  (void)ctx;
+  (void)prec;
+  SSRPA_REQUIRE(g.k % kT == 0 && g.n % kT == 0, SSRPA_ERR_ARG,
+                "gemm: k and n must be padded to 64");
+  if (g.m <= 0) return;
+  const long m_tiles = (g.m + kT - 1) / kT;
+  const int n_tiles = g.n / kT;
+  SSRPA_REQUIRE(m_tiles * n_tiles < (1L << 31), SSRPA_ERR_ARG, "gemm too large");
+  hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)(m_tiles * n_tiles)),
+                     dim3(256), 0, s, g, (int)m_tiles, n_tiles);
+  SSRPA_HIP(hipGetLastError());
+}
+
+}  // namespace ssrpa

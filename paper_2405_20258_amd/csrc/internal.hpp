@@ -1,0 +1,213 @@
+// Internal declarations of the ssrpa library: runtime objects, device buffer
+// ownership and the kernel launchers shared between translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ssrpa.h"
+
+namespace ssrpa {
+
+// Error carried from deep inside the runtime to the C ABI boundary, where it
+// becomes a status code plus the context's last-error text.
+struct Error : std::runtime_error {
+  ssrpa_status code;
+  Error(ssrpa_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(ssrpa_status code, const char *fmt, ...);
+
+#define SSRPA_HIP(expr)                                                       \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      ::ssrpa::fail(SSRPA_ERR_HIP, "%s failed at %s:%d: %s", #expr, __FILE__, \
+                    __LINE__, hipGetErrorString(e_));                         \
+  } while (0)
+
+#define SSRPA_REQUIRE(cond, code, ...)              \
+  do {                                              \
+    if (!(cond)) ::ssrpa::fail((code), __VA_ARGS__); \
+  } while (0)
+
+struct Context;
+
+// Device allocation charged against a context's HBM budget; freed on
+// destruction.  Move-only.
+class DevBuf {
+ public:
+  DevBuf() = default;
+  DevBuf(Context *ctx, size_t bytes);
+  ~DevBuf();
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  DevBuf(DevBuf &&o) noexcept { swap(o); }
+  DevBuf &operator=(DevBuf &&o) noexcept {
+    DevBuf t(std::move(o));
+    swap(t);
+    return *this;
+  }
+  void swap(DevBuf &o) noexcept {
+    std::swap(ctx_, o.ctx_);
+    std::swap(ptr_, o.ptr_);
+    std::swap(bytes_, o.bytes_);
+  }
+  template <class T = void>
+  T *as() const { return static_cast<T *>(ptr_); }
+  size_t bytes() const { return bytes_; }
+  bool empty() const { return ptr_ == nullptr; }
+  void reset() { DevBuf t; swap(t); }
+  // Grow to at least `bytes` (contents discarded when reallocated).
+  void ensure(Context *ctx, size_t bytes) {
+    if (bytes_ < bytes || ctx_ != ctx) { reset(); *this = DevBuf(ctx, bytes); }
+  }
+
+ private:
+  Context *ctx_ = nullptr;
+  void *ptr_ = nullptr;
+  size_t bytes_ = 0;
+};
+
+struct Context {
+  int device = 0;
+  size_t budget = 0;
+  size_t in_use = 0;
+  size_t high_water = 0;
+  std::string last_error;
+  std::mutex mu;  // guards the byte accounting (serving threads share it)
+  void *alloc(size_t bytes);
+  void release(void *p, size_t bytes);
+};
+
+// Geometry of the real-space grid and the chi0 G set, derived once per system.
+struct Geometry {
+  double lattice[9];
+  double recip[9];   // rows b1, b2, b3 with a_i . b_j = 2 pi delta_ij
+  double volume;
+  int n1, n2, n3;
+  int m1, m2, m3;    // max |n_i| over the chi0 set
+  int n_g;           // chi0 basis size
+  int ld_g;          // n_g rounded up to a multiple of 64 (zero padded)
+  std::vector<int32_t> miller_chi;  // n_g x 3
+  std::vector<double> sqrt_v;       // v(G)^1/2 per chi0 vector
+};
+
+// Resident subspace state after ssrpa_subspace.
+struct Subspace {
+  int n_eig = 0;
+  int ld_e = 0;                  // n_eig rounded up to 64
+  std::vector<double> eigval;    // host copy, ascending
+  DevBuf basis;                  // planar rows: ld_g rows x [re(ld_e) | im(ld_e)]
+};
+
+struct System {
+  Context *ctx = nullptr;
+  Geometry geo;
+  int n_v = 0, n_c = 0, n_b = 0, n_pw = 0;
+  std::vector<double> energy;
+  DevBuf energy_d;               // n_b doubles
+  DevBuf psi_r;                  // n_b x N3 x N2 x N1 complex (interleaved)
+  DevBuf gcol;                   // per G: int (column index | n3 mod N3 << 20)
+  DevBuf sqrtv_d;                // per G: v(G)^1/2 * Omega / N
+  DevBuf fft_tw;                 // twiddle tables for N1, N2, N3
+  DevBuf chibar0;                // n_g x n_g complex (interleaved), symmetrized
+  bool have_chi0 = false;
+  Subspace sub;
+  // Pair matrix of the last block when a single block covers all valence
+  // bands: reused by the second pass (the pair FFTs then run once).
+  DevBuf w_cache;
+  int w_cache_prec = -1;
+  bool w_cache_valid = false;
+  // Device-side error flag (non-positive pivot, etc.): int.
+  DevBuf dev_flag;
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (all enqueue on `s`, never synchronize).
+// ---------------------------------------------------------------------------
+
+// FFT stage (fft.hip)
+void upload_twiddles(System &sys);
+// psi_r <- orbitals on the grid; box_index_dev[pw] = linear grid index of
+// the plane wave's Miller triple (mod N).
+void launch_orbital_fft(System &sys, const double *coeff_dev,
+                        const int *box_index_dev, hipStream_t s);
+// Pair matrix for valence bands [v0, v0+nvb): W rows p = (v - v0) * n_c + c,
+// planar layout: row stride 2*ld_g doubles, re at [0, ld_g), im at
+// [ld_g, 2 ld_g); the padding columns are written as zeros.
+// scaled: multiply by v(G)^1/2 (else plain M).
+void launch_pair_matrix(System &sys, int v0, int nvb, bool scaled, double *w,
+                        hipStream_t s);
+
+// Contractions (gemm.hip)
+struct HerkArgs {
+  const double *a;     // planar rows, row stride lda doubles, im at +im_off
+  long lda;
+  long im_off;
+  int ncol;            // output dimension (G or eigen index), <= ld (pad 64)
+  int ld;              // padded ncol (multiple of 64)
+  long k;              // rows (pairs)
+  const double *de;    // per row: e_c - e_v
+  const double *omega; // per output matrix: imaginary frequency
+  int n_omega;
+  double wscale;       // multiplies Delta (1/Omega)
+  int unit_weight;     // 1: weights all 1 (Gram matrices), ignore de/omega
+};
+// out_j (+)= A^H diag(d_j) A for every j, written as full Hermitian
+// ncol x ncol interleaved complex matrices at out + j * out_stride (doubles).
+// beta: 0 overwrite, 1 accumulate.
+// ws: caller-owned workspace for split-K partial tiles (grown as needed).
+void herk(Context *ctx, const HerkArgs &h, ssrpa_precision prec, double *out,
+          long out_stride, int beta, DevBuf &ws, hipStream_t s);
+// C = alpha * A * B + beta * C for complex planar operands:
+//   A: m x k rows (row stride lda, im at +a_im), B: k x n (row stride ldb,
+//   im at +b_im), C: m x n (row stride ldc, im at +c_im).  k is a multiple of
+//   64 (zero padded), n is padded to 64 in all three operands.
+struct GemmArgs {
+  const double *a; long lda; long a_im;
+  const double *b; long ldb; long b_im;
+  double *c; long ldc; long c_im;
+  long m; int n; int k;
+  double alpha, beta;
+};
+void gemm(Context *ctx, const GemmArgs &g, ssrpa_precision prec, hipStream_t s);
+
+// Eigensolver (eig.hip): n_eig most negative eigenpairs of a Hermitian n x n
+// interleaved matrix (not modified).  eigval: device (n_eig); basis: planar
+// rows (ld_rows >= n rows, row stride 2*ld_e, im at +ld_e), padded rows/cols
+// zero.
+void eig_lowest(Context *ctx, const double *a, int n, int n_eig, double *eigval,
+                double *basis, int ld_e, int *flag, hipStream_t s);
+
+// Log-determinants (chol.hip): f[j] = ln det(I - c X_j) + c Tr X_j for
+// interleaved n x n Hermitian X_j at x + j*n*n; f device (n_mat).  Sets
+// *flag (device int) nonzero on a non-positive pivot.
+void trace_log(Context *ctx, const double *x, int n, int n_mat, double coupling,
+               double *f, int *flag, hipStream_t s);
+// ec[0] = (1/2pi) sum_j w[j] f[j]   (device scalars)
+void quadrature(const double *w, const double *f, int n, double *ec,
+                hipStream_t s);
+
+// Layout helpers (util.hip)
+void fill_zero(void *p, size_t bytes, hipStream_t s);
+// interleaved n x n Hermitian, scaled elementwise by s_i s_j
+void scale_sym(double *x, int n, const double *sv, int inverse, hipStream_t s);
+// planar rows (row stride 2*ld, im at +ld) -> interleaved rows x cols
+void planar_to_interleaved(const double *src, int rows, int cols, int ld,
+                           double *dst, hipStream_t s);
+void pair_energy_diffs(const double *energy, int n_v_total, int v0, int nvb,
+                       int n_c, double *de, hipStream_t s);
+void copy_interleaved(const double *src, double *dst, size_t n_complex,
+                      hipStream_t s);
+
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+}  // namespace ssrpa

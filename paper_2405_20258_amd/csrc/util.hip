@@ -1,0 +1,109 @@
+// Small layout kernels: zero fill, symmetric scaling, planar <-> interleaved
+// conversion and the per-pair energy gaps e_c - e_v.
+#include "internal.hpp"
+
+namespace ssrpa {
+
+namespace {
+
+__global__ void fill_zero_kernel(double *p, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+__global__ void fill_zero_bytes_kernel(unsigned char *p, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+__global__ void scale_sym_kernel(double *x, int n, const double *sv,
+                                 int inverse) {
+  const long total = (long)n * n;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(idx / n), c = (int)(idx % n);
+    double f = sv[r] * sv[c];
+    if (inverse) f = 1.0 / f;
+    x[2 * idx] *= f;
+    x[2 * idx + 1] *= f;
+  }
+}
+
+__global__ void planar_to_interleaved_kernel(const double *src, int rows,
+                                             int cols, int ld, double *dst) {
+  const long total = (long)rows * cols;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(idx / cols), c = (int)(idx % cols);
+    dst[2 * idx] = src[(long)r * 2 * ld + c];
+    dst[2 * idx + 1] = src[(long)r * 2 * ld + ld + c];
+  }
+}
+
+__global__ void pair_de_kernel(const double *energy, int n_v, int v0, int nvb,
+                               int n_c, double *de) {
+  const long total = (long)nvb * n_c;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int v = v0 + (int)(idx / n_c), c = (int)(idx % n_c);
+    de[idx] = energy[n_v + c] - energy[v];
+  }
+}
+
+__global__ void copy_kernel(const double *src, double *dst, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+unsigned grid_for(long n) {
+  return (unsigned)std::max(1L, std::min((n + 255) / 256, 65536L));
+}
+
+}  // namespace
+
+void fill_zero(void *p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  if (bytes % 8 == 0 && ((uintptr_t)p % 8) == 0) {
+    const long n = (long)(bytes / 8);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(n)), dim3(256), 0, s,
+                       (double *)p, n);
+  } else {
+    hipLaunchKernelGGL(fill_zero_bytes_kernel, dim3(grid_for((long)bytes)),
+                       dim3(256), 0, s, (unsigned char *)p, (long)bytes);
+  }
+  SSRPA_HIP(hipGetLastError());
+}
+
+void scale_sym(double *x, int n, const double *sv, int inverse, hipStream_t s) {
+  hipLaunchKernelGGL(scale_sym_kernel, dim3(grid_for((long)n * n)), dim3(256), 0,
+                     s, x, n, sv, inverse);
+  SSRPA_HIP(hipGetLastError());
+}
+
+void planar_to_interleaved(const double *src, int rows, int cols, int ld,
+                           double *dst, hipStream_t s) {
+  hipLaunchKernelGGL(planar_to_interleaved_kernel,
+                     dim3(grid_for((long)rows * cols)), dim3(256), 0, s, src,
+                     rows, cols, ld, dst);
+  SSRPA_HIP(hipGetLastError());
+}
+
+void pair_energy_diffs(const double *energy, int n_v, int v0, int nvb, int n_c,
+                       double *de, hipStream_t s) {
+  hipLaunchKernelGGL(pair_de_kernel, dim3(grid_for((long)nvb * n_c)), dim3(256),
+                     0, s, energy, n_v, v0, nvb, n_c, de);
+  SSRPA_HIP(hipGetLastError());
+}
+
+void copy_interleaved(const double *src, double *dst, size_t n_complex,
+                      hipStream_t s) {
+  const long n = (long)(2 * n_complex);
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(256), 0, s, src, dst,
+                     n);
+  SSRPA_HIP(hipGetLastError());
+}
+
+}  // namespace ssrpa

@@ -1,0 +1,345 @@
+"""GPU parity: every step of the HIP path against the FP64 oracle.
+
+Inputs are the seeded synthetic systems of synth/systems.py.  The HIP path
+is reached only through the C ABI (ctypes binding); the oracle runs on the
+CPU (or its stored outputs in tests/golden/ are read).
+
+Tolerances (FP64 path): pair matrix elements 1e-12 relative to the largest
+element; chi0 1e-10 in max-norm relative; eigenvalues 1e-10 relative to the
+largest |eigenvalue|; subspace projector 1e-8 absolute; per-frequency F_j
+and E_c 1e-10 relative.  Eigenvectors are compared through the projector
+C_s C_s^H because each vector is defined only up to a phase.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2405_20258_amd import ssrpa
+    ctx = ssrpa.Context(0)
+    yield torch, ssrpa, ctx
+    ctx.close()
+
+
+def ragged_system():
+    from synth import systems as sy
+    # 18 = 2 * 3 * 3 grid, N_G = 80 (not a multiple of 64), 5 x 37 pairs
+    spec = sy.small_spec(a=9.0, fft=18, n_v=5, n_c=37, nsq_chi=6, e_psi=4.0)
+    return sy.make_system(spec, 42)
+
+
+def label_index(miller):
+    return {tuple(int(x) for x in m): i for i, m in enumerate(miller)}
+
+
+def test_gvectors_and_orbitals(env):
+    torch, ssrpa, ctx = env
+    from oracle import rpa
+    s = ragged_system()
+    _log("orbitals ragged 18^3")
+    g = ssrpa.System.from_synthetic(ctx, s)
+    mg = g.gvectors()
+    mo = rpa.chi_gvectors(s.a, s.ecut_chi)
+    assert sorted(map(tuple, mg.tolist())) == sorted(map(tuple, mo.tolist()))
+    n1, n2, n3 = s.fft
+    psi = torch.empty((s.n_bands, n3, n2, n1), dtype=torch.complex128,
+                      device="cuda")
+    g.orbitals_realspace(psi)
+    torch.cuda.synchronize()
+    ref = rpa.orbitals_realspace(s.a, s.fft, s.miller, s.coeff)
+    got = psi.cpu().numpy().transpose(0, 3, 2, 1)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    _log(f"orbitals rel err {err:.2e}")
+    assert err < 1e-13
+    g.close()
+
+
+@pytest.mark.parametrize("scaled", [True, False])
+def test_pair_matrix(env, scaled):
+    torch, ssrpa, ctx = env
+    from oracle import rpa
+    s = ragged_system()
+    g = ssrpa.System.from_synthetic(ctx, s)
+    idx = label_index(g.gvectors())
+    mo = rpa.chi_gvectors(s.a, s.ecut_chi)
+    perm = np.array([idx[tuple(int(x) for x in m)] for m in mo])
+    out = torch.empty((s.n_v * s.n_c, len(mo)), dtype=torch.complex128,
+                      device="cuda")
+    _log(f"pair matrix ragged scaled={scaled}")
+    g.pair_matrix(0, s.n_v, out, scaled=scaled)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()[:, perm]
+    psi = rpa.orbitals_realspace(s.a, s.fft, s.miller, s.coeff)
+    m = rpa.pair_matrix_fft(s.a, s.fft, psi[: s.n_v], psi[s.n_v:], mo)
+    ref = rpa.scaled_pair_matrix(s.a, m, mo) if scaled else \
+        m.reshape(s.n_v * s.n_c, -1)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    _log(f"pair matrix rel err {err:.2e}")
+    assert err < 1e-12
+    # a sub-block of valence bands lands at the same rows
+    out2 = torch.empty((2 * s.n_c, len(mo)), dtype=torch.complex128,
+                       device="cuda")
+    g.pair_matrix(2, 2, out2, scaled=scaled)
+    torch.cuda.synchronize()
+    got2 = out2.cpu().numpy()[:, perm]
+    assert np.max(np.abs(got2 - ref[2 * s.n_c: 4 * s.n_c])) <= \
+        1e-12 * np.max(np.abs(ref))
+    g.close()
+
+
+def _chi0_check(g, s, torch, symmetrized, vb=0):
+    from oracle import rpa
+    idx = label_index(g.gvectors())
+    mo = rpa.chi_gvectors(s.a, s.ecut_chi)
+    perm = np.array([idx[tuple(int(x) for x in m)] for m in mo])
+    n = len(mo)
+    out = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+    g.chi0_static("fp64", valence_block=vb, out_dev=out,
+                  symmetrized=symmetrized)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()[np.ix_(perm, perm)]
+    psi = rpa.orbitals_realspace(s.a, s.fft, s.miller, s.coeff)
+    m = rpa.pair_matrix_fft(s.a, s.fft, psi[: s.n_v], psi[s.n_v:], mo)
+    dvc = rpa.energy_factor(s.energy[: s.n_v], s.energy[s.n_v:], 0.0)
+    ref = rpa.chi0(s.a, m, dvc)
+    if symmetrized:
+        ref = rpa.symmetrize_chi0(s.a, ref, mo)
+    return np.max(np.abs(got - ref)) / np.max(np.abs(ref)), got
+
+
+@pytest.mark.parametrize("symmetrized", [True, False])
+def test_chi0_static_ragged(env, symmetrized):
+    torch, ssrpa, ctx = env
+    s = ragged_system()
+    g = ssrpa.System.from_synthetic(ctx, s)
+    _log(f"chi0 ragged symmetrized={symmetrized}")
+    err, got = _chi0_check(g, s, torch, symmetrized)
+    _log(f"chi0 rel err {err:.2e}")
+    assert err < 1e-10
+    assert np.max(np.abs(got - got.conj().T)) == 0.0   # exactly Hermitian
+    g.close()
+
+
+def test_chi0_valence_block_invariance(env):
+    torch, ssrpa, ctx = env
+    s = ragged_system()
+    g = ssrpa.System.from_synthetic(ctx, s)
+    _log("chi0 ragged valence blocks 2 (ragged last block)")
+    err, a = _chi0_check(g, s, torch, True, vb=2)
+    assert err < 1e-10
+    g.close()
+
+
+def test_trace_log_against_numpy(env):
+    torch, ssrpa, ctx = env
+    rng = np.random.default_rng(5)
+    for n, nm in ((1, 3), (7, 2), (75, 4), (130, 3)):
+        _log(f"trace_log n={n} batch={nm}")
+        xs = []
+        for _ in range(nm):
+            a = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+            h = -(a @ a.conj().T) / (n * 2.0)   # negative semidefinite
+            xs.append(h)
+        x = np.stack(xs)
+        xd = torch.from_numpy(x).to("cuda")
+        f = ctx.trace_log(xd, n, nm, 1.0)
+        for j in range(nm):
+            mu = np.linalg.eigvalsh(x[j])
+            ref = float(np.sum(np.log1p(-mu) + mu))
+            assert abs(f[j] - ref) <= 1e-11 * max(1.0, abs(ref)), (n, j)
+        # coupling scales the matrix
+        f2 = ctx.trace_log(xd, n, nm, 0.5)
+        mu = np.linalg.eigvalsh(x[0])
+        ref = float(np.sum(np.log1p(-0.5 * mu) + 0.5 * mu))
+        assert abs(f2[0] - ref) <= 1e-11 * max(1.0, abs(ref))
+
+
+def test_trace_log_rejects_non_positive(env):
+    torch, ssrpa, ctx = env
+    x = np.zeros((1, 4, 4), dtype=np.complex128)
+    x[0, 2, 2] = 2.0   # I - X has a negative pivot
+    xd = torch.from_numpy(x).to("cuda")
+    with pytest.raises(ssrpa.SsrpaError) as e:
+        ctx.trace_log(xd, 4, 1, 1.0)
+    assert e.value.status == ssrpa.ERR_NUMERIC
+
+
+def test_subspace_and_energy_ragged(env):
+    torch, ssrpa, ctx = env
+    from oracle import rpa
+    from synth import systems as sy
+    s = ragged_system()
+    om, wt = sy.frequency_grid(16)
+    g = ssrpa.System.from_synthetic(ctx, s)
+    g.chi0_static("fp64")
+    ng = g.n_g
+    idx = label_index(g.gvectors())
+    mo = rpa.chi_gvectors(s.a, s.ecut_chi)
+    perm = np.array([idx[tuple(int(x) for x in m)] for m in mo])
+    for n_eig in (1, 12, 64, 65, ng):
+        _log(f"subspace ragged n_eig={n_eig}")
+        ref = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                                     s.n_v, s.ecut_chi, n_eig, om, wt)
+        if n_eig < ng:
+            basis = torch.empty((ng, n_eig), dtype=torch.complex128,
+                                device="cuda")
+            lam = g.subspace(n_eig, basis)
+            torch.cuda.synchronize()
+            assert np.max(np.abs(lam - ref["eigval"][:n_eig])) < \
+                1e-10 * abs(ref["eigval"][0])
+            c = basis.cpu().numpy()[perm]
+            assert np.max(np.abs(c.conj().T @ c - np.eye(n_eig))) < 1e-12
+            cb0 = ref["chibar0"]
+            lr, vr = np.linalg.eigh(cb0)
+            pr = vr[:, :n_eig] @ vr[:, :n_eig].conj().T
+            pg = c @ c.conj().T
+            gap = (lr[n_eig] - lr[n_eig - 1]) / abs(lr[0])
+            _log(f"  projector err {np.max(np.abs(pg - pr)):.2e} gap {gap:.2e}")
+            assert np.max(np.abs(pg - pr)) < 1e-8
+        ec, f = g.correlation_energy(n_eig, om, wt, "fp64")
+        rel = abs(ec - ref["ec"]) / abs(ref["ec"])
+        _log(f"  E_c gpu {ec!r} oracle {ref['ec']!r} rel {rel:.2e}")
+        assert rel < 1e-10
+        assert np.max(np.abs(f - ref["integrand"])) < \
+            1e-10 * np.max(np.abs(ref["integrand"]))
+    g.close()
+
+
+def test_energy_valence_block_invariance_and_state(env):
+    torch, ssrpa, ctx = env
+    from synth import systems as sy
+    s = ragged_system()
+    om, wt = sy.frequency_grid(16)
+    g = ssrpa.System.from_synthetic(ctx, s)
+    with pytest.raises(ssrpa.SsrpaError) as e:
+        g.subspace(5)
+    assert e.value.status == ssrpa.ERR_STATE
+    g.chi0_static("fp64", valence_block=5)
+    g.subspace(10)
+    with pytest.raises(ssrpa.SsrpaError) as e:
+        g.correlation_energy(11, om, wt)
+    assert e.value.status == ssrpa.ERR_STATE
+    e1, _ = g.correlation_energy(10, om, wt, valence_block=5)
+    e2, _ = g.correlation_energy(10, om, wt, valence_block=2)
+    assert abs(e1 - e2) < 1e-12 * abs(e1)
+    g.close()
+
+
+def test_tiny_workload_against_golden(env):
+    """Tiny workload (N_G = 304, 16 x 240 pairs): N_eig = 75 and full RPA."""
+    torch, ssrpa, ctx = env
+    from synth import systems as sy
+    gold = json.load(open(os.path.join(HERE, "golden", "tiny.json")))
+    s = sy.make_system(sy.TINY, gold["seed"])
+    om, wt = sy.frequency_grid(gold["n_freq"])
+    _log("tiny workload")
+    g = ssrpa.System.from_synthetic(ctx, s)
+    ng = g.n_g
+    assert ng == gold["n_g"] == 304
+    idx = label_index(g.gvectors())
+    out = torch.empty((ng, ng), dtype=torch.complex128, device="cuda")
+    g.chi0_static("fp64", out_dev=out, symmetrized=True)
+    torch.cuda.synchronize()
+    chi = out.cpu().numpy()
+    err = 0.0
+    for row in gold["chibar0_samples"]:
+        i = idx[tuple(row[0:3])]
+        j = idx[tuple(row[3:6])]
+        err = max(err, abs(chi[i, j] - complex(row[6], row[7])))
+    err /= gold["chibar0_maxabs"]
+    _log(f"tiny chi0 sample err {err:.2e}")
+    assert err < 1e-10
+    for key in ("n_eig_75", "n_eig_150"):
+        r = gold["results"][key]
+        lam = g.subspace(r["n_eig"])
+        assert np.max(np.abs(lam - np.array(r["eigval"]))) < \
+            1e-10 * abs(r["eigval"][0])
+        ec, f = g.correlation_energy(r["n_eig"], om, wt)
+        rel = abs(ec - r["ec"]) / abs(r["ec"])
+        _log(f"tiny {key}: E_c {ec!r} golden {r['ec']!r} rel {rel:.2e}")
+        assert rel < 1e-10
+    r = gold["results"]["full"]
+    ec, f = g.correlation_energy(ng, om, wt)
+    rel = abs(ec - r["ec"]) / abs(r["ec"])
+    _log(f"tiny full: E_c {ec!r} golden {r['ec']!r} rel {rel:.2e}")
+    assert rel < 1e-10
+    g.close()
+
+
+@pytest.mark.timeout(300)
+def test_medium_workload_against_golden(env):
+    """Medium workload (N_G = 3958, 128 x 2048 pairs, N_eig = 400)."""
+    torch, ssrpa, ctx = env
+    from synth import systems as sy
+    path = os.path.join(HERE, "golden", "medium.json")
+    if not os.path.exists(path):
+        pytest.skip("medium golden values not generated")
+    gold = json.load(open(path))
+    if "n_eig_400" not in gold["results"]:
+        pytest.skip("medium golden values incomplete")
+    _log("medium workload: generating inputs")
+    s = sy.make_system(sy.MEDIUM, gold["seed"])
+    om, wt = sy.frequency_grid(gold["n_freq"])
+    _log("medium workload: system create")
+    g = ssrpa.System.from_synthetic(ctx, s)
+    ng = g.n_g
+    assert ng == gold["n_g"]
+    idx = label_index(g.gvectors())
+    # pair matrix samples
+    vs = sorted({row[0] for row in gold["w_samples"]})[:4]
+    werr = 0.0
+    wmax = 0.0
+    for v in vs:
+        out = torch.empty((s.n_c, ng), dtype=torch.complex128, device="cuda")
+        g.pair_matrix(v, 1, out, scaled=True)
+        torch.cuda.synchronize()
+        w = out.cpu().numpy()
+        for row in gold["w_samples"]:
+            if row[0] != v:
+                continue
+            val = w[row[1], idx[tuple(row[2:5])]]
+            ref = complex(row[5], row[6])
+            werr = max(werr, abs(val - ref))
+            wmax = max(wmax, abs(ref))
+    _log(f"medium W sample err {werr:.2e} (max {wmax:.2e})")
+    assert werr < 1e-12 * max(wmax, 1e-3) * 10
+    _log("medium workload: chi0")
+    out = torch.empty((ng, ng), dtype=torch.complex128, device="cuda")
+    g.chi0_static("fp64", out_dev=out, symmetrized=True)
+    torch.cuda.synchronize()
+    chi = out.cpu().numpy()
+    del out
+    err = 0.0
+    for row in gold["chibar0_samples"]:
+        i = idx[tuple(row[0:3])]
+        j = idx[tuple(row[3:6])]
+        err = max(err, abs(chi[i, j] - complex(row[6], row[7])))
+    err /= gold["chibar0_maxabs"]
+    _log(f"medium chi0 sample err {err:.2e}")
+    assert err < 1e-10
+    r = gold["results"]["n_eig_400"]
+    _log("medium workload: subspace 400")
+    lam = g.subspace(400)
+    lerr = np.max(np.abs(lam - np.array(r["eigval"]))) / abs(r["eigval"][0])
+    _log(f"medium eigval err {lerr:.2e}")
+    assert lerr < 1e-10
+    ec, f = g.correlation_energy(400, om, wt)
+    rel = abs(ec - r["ec"]) / abs(r["ec"])
+    _log(f"medium n_eig=400: E_c {ec!r} golden {r['ec']!r} rel {rel:.2e}")
+    assert rel < 1e-10
+    g.close()
