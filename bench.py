@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Benchmark of the static-subspace RPA hot path on one MI355X.
+
+One step = one whole correlation-energy solve of the medium synthetic
+workload (20 bohr cubic cell, 48^3 grid, 128 valence x 2048 conduction
+bands = 262144 pairs, N_G = 3958, N_eig = 400, 16 frequencies), starting
+from orbital coefficients already resident in HBM:
+  system creation (orbital FFTs) -> pair-density FFTs -> static chi0 HERK
+  -> FP64 eigensolver -> projection GEMM -> per-frequency HERK -> Cholesky
+  log-determinants -> quadrature.
+
+Reported value: the chi0 GEMM rate in TFLOP/s, i.e. the algorithmic flops
+of the static contraction (4 N_G^2 K real flops, one triangle, complex
+multiply-add = 8 flops) divided by the duration of that kernel measured with
+HIP events recorded on the solve's own stream.  ms_per_step is the
+time-to-E_c per system.  The CPU baseline times the FP64 oracle on a bounded
+sample of the same workload (see --help).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("χ0 GEMM TFLOP/s + time-to-E_c per system; p50/p99 E_c "
+          "latency, mixed stream")
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="medium",
+                    choices=["tiny", "medium", "large"])
+    ap.add_argument("--precision", default="fp64",
+                    choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--n-eig", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-bands", type=int, default=4,
+                    help="valence bands in the oracle's timed sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(s, n_vb):
+    """Time the FP64 oracle's chi0 contraction on a bounded pair sample."""
+    import numpy as np
+    from oracle import rpa
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()]
+                      or [os.cpu_count()])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count()
+    t0 = time.perf_counter()
+    w, mchi = rpa.w_matrix(s.a, s.fft, s.miller, s.coeff, s.n_v, s.ecut_chi,
+                           v_range=(0, n_vb))
+    t1 = time.perf_counter()
+    d = rpa.pair_weights(s.energy, s.n_v, 0.0)[: w.shape[0]]
+    t2 = time.perf_counter()
+    cb = rpa.chibar(s.a, w, d)
+    t3 = time.perf_counter()
+    ng = w.shape[1]
+    flops = 4.0 * ng * ng * w.shape[0]
+    del cb
+    return {"value": flops / (t3 - t2) / 1e12, "unit": "TFLOP/s",
+            "cores": int(threads), "kind": "oracle",
+            "sample": (f"chi0 contraction of the oracle on {w.shape[0]} of "
+                       f"{s.n_v * s.n_c} pairs (valence bands 0-{n_vb - 1} x "
+                       f"{s.n_c} conduction), W from the oracle's FFT path "
+                       f"({t1 - t0:.1f} s, not in the rate); contraction "
+                       f"{t3 - t2:.2f} s"),
+            "host_cpus": os.cpu_count()}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; "
+                          "--gpus N > 1 is not supported (the multi-GPU "
+                          "sharding is described in the design notes)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2405_20258_amd import ssrpa
+    from synth import systems as sy
+
+    spec = {"tiny": sy.TINY, "medium": sy.MEDIUM,
+            "large": sy.LARGE_SHARE}[args.workload]
+    seed = sy.CONFIG_SEED_BASE[spec.name]
+    n_eig = args.n_eig or spec.n_eig
+    prec = args.precision
+    print(f"# generating {spec.name} (seed {seed})", file=sys.stderr,
+          flush=True)
+    s = sy.make_system(spec, seed)
+    om, wt = ssrpa.frequency_grid(spec.n_freq)
+    coeff_d = torch.from_numpy(s.coeff).to("cuda")   # inputs resident in HBM
+    torch.cuda.synchronize()
+    ctx = ssrpa.Context(0)
+    stream = torch.cuda.current_stream()
+    vb = spec.valence_block or s.n_v
+
+    def step():
+        g = ssrpa.System(ctx, s.a, s.fft, s.miller, coeff_d, s.energy, s.n_v,
+                         s.ecut_chi, stream)
+        g.stage_times(True)
+        g.chi0_static(prec, valence_block=vb)
+        g.subspace(n_eig)
+        ec, f = g.correlation_energy(n_eig, om, wt, prec, valence_block=vb)
+        st = g.stage_times(False)
+        n_g = g.n_g
+        g.close()
+        return ec, st, n_g
+
+    for i in range(args.warmup):
+        ec, st, n_g = step()
+        print(f"# warmup {i}: E_c = {ec!r}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stage = {k: [0.0, 0] for k in ssrpa.STAGES}
+    for i in range(args.steps):
+        ec, st, n_g = step()
+        for k, (ms, n) in st.items():
+            stage[k][0] += ms
+            stage[k][1] += n
+        print(f"# step {i}: E_c = {ec!r}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    pairs = s.n_v * s.n_c
+    herk_flops_step = 4.0 * n_g * n_g * pairs
+    herk_ms, herk_launches = stage["chi0_herk"]
+    value = herk_flops_step * args.steps / (herk_ms * 1e-3) / 1e12
+    per_launch_flops = herk_flops_step * args.steps / herk_launches
+    avg_launch_s = herk_ms * 1e-3 / herk_launches
+    achieved = per_launch_flops / avg_launch_s / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[prec],
+        "data": "synthetic",
+        "config": {"workload": spec.name, "n_g": n_g, "pairs": pairs,
+                   "n_eig": n_eig, "n_freq": spec.n_freq,
+                   "valence_block": vb, "precision": prec,
+                   "fft": list(s.fft)},
+        "time_to_ec_ms": round(ms_per_step, 3),
+        "ec": ec,
+        "stage_ms_per_step": {k: round(v[0] / args.steps, 3)
+                              for k, v in stage.items()},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
+                     "peak": PEAK[prec], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK[prec], 4),
+                     "traffic": None,
+                     "kernel": "herk_f64_kernel (static chi0)",
+                     "flops_per_launch": per_launch_flops,
+                     "avg_launch_ms": round(avg_launch_s * 1e3, 4)},
+    }
+    if not args.no_cpu_baseline:
+        print("# timing the oracle on a bounded sample", file=sys.stderr,
+              flush=True)
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_sample_bands)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -116,6 +116,8 @@ SSRPA_API const char *ssrpa_version(void);
 SSRPA_API ssrpa_status ssrpa_context_create(int hip_device,
                                             size_t hbm_budget_bytes,
                                             ssrpa_context **out);
+/* Destroy a context; SSRPA_ERR_STATE (and nothing freed) while systems
+ * created on it are still alive. */
 SSRPA_API ssrpa_status ssrpa_context_destroy(ssrpa_context *ctx);
 
 /* Device bytes currently held and the high-water mark of this context. */
@@ -222,6 +224,28 @@ SSRPA_API ssrpa_status ssrpa_trace_log(ssrpa_context *ctx, const double *x,
  * w = omega0 (1 + x)/(1 - x), weight 2 omega0 w_x / (1 - x)^2 (host). */
 SSRPA_API ssrpa_status ssrpa_frequency_grid(int n, double omega0,
                                             double *omega, double *weight);
+
+/* ---- stage timing ------------------------------------------------------- */
+
+/* Stages of the path after system creation, timed with HIP events recorded
+ * on the caller's stream around the kernels of each stage. */
+typedef enum ssrpa_stage {
+  SSRPA_STAGE_PAIR_FFT = 0,     /* pair densities -> M (Eq. 3), per block     */
+  SSRPA_STAGE_CHI0_HERK = 1,    /* static chi0 contraction kernel (Eq. 6)     */
+  SSRPA_STAGE_EIGEN = 2,        /* static subspace eigensolver                */
+  SSRPA_STAGE_PROJECTION = 3,   /* M_s = M C_s (Eq. 7), per block             */
+  SSRPA_STAGE_FREQ_HERK = 4,    /* per-frequency subspace contraction (Eq. 8) */
+  SSRPA_STAGE_TRACE_LOG = 5,    /* log-determinants and quadrature            */
+  SSRPA_N_STAGES = 6
+} ssrpa_stage;
+
+/* enable = 1 starts (and resets) event timing on this system, 0 stops it.
+ * ms and launches (host, SSRPA_N_STAGES each, nullable) receive the time and
+ * number of timed launches per stage accumulated since the last reset; the
+ * call waits for the recorded events.  Timing adds one event pair per
+ * launch and is off by default. */
+SSRPA_API ssrpa_status ssrpa_stage_times(ssrpa_system *sys, int enable,
+                                         double *ms, int *launches);
 
 /* ---- serving: the same solve, enqueued without blocking the caller ------ */
 

@@ -57,6 +57,27 @@ void Context::release(void *p, size_t bytes) {
   in_use -= bytes == 0 ? 8 : bytes;
 }
 
+int StageTimer::start(int stage, hipStream_t s) {
+  Rec r{stage, nullptr, nullptr};
+  SSRPA_HIP(hipEventCreate(&r.a));
+  SSRPA_HIP(hipEventCreate(&r.b));
+  SSRPA_HIP(hipEventRecord(r.a, s));
+  recs.push_back(r);
+  return (int)recs.size() - 1;
+}
+
+void StageTimer::stop(int idx, hipStream_t s) {
+  (void)hipEventRecord(recs[idx].b, s);
+}
+
+void StageTimer::clear() {
+  for (auto &r : recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  recs.clear();
+}
+
 DevBuf::DevBuf(Context *ctx, size_t bytes) : ctx_(ctx), bytes_(bytes) {
   ptr_ = ctx->alloc(bytes);
 }
@@ -266,7 +287,10 @@ const double *block_pairs(System &sys, int v0, int nvb, DevBuf &scratch,
   if (single && sys.w_cache_valid) return sys.w_cache.as<double>();
   DevBuf &dst = single ? sys.w_cache : scratch;
   dst.ensure(sys.ctx, bytes);
-  launch_pair_matrix(sys, v0, nvb, true, dst.as<double>(), s);
+  {
+    StageScope sc(sys.timer, SSRPA_STAGE_PAIR_FFT, s);
+    launch_pair_matrix(sys, v0, nvb, true, dst.as<double>(), s);
+  }
   if (single) sys.w_cache_valid = true;
   return dst.as<double>();
 }
@@ -296,6 +320,8 @@ void static_chi0(System &sys, ssrpa_precision prec, int vb, hipStream_t s) {
     h.omega = om.as<double>();
     h.n_omega = 1;
     h.wscale = 1.0 / g.volume;
+    h.timer = &sys.timer;
+    h.stage = SSRPA_STAGE_CHI0_HERK;
     herk(ctx, h, prec, sys.chibar0.as<double>(), 0, v0 > 0 ? 1 : 0, ws, s);
   }
   SSRPA_HIP(hipStreamSynchronize(s));
@@ -315,6 +341,7 @@ void compute_subspace(System &sys, int n_eig, hipStream_t s) {
   sub.ld_e = round_up(n_eig, 64);
   sub.basis = DevBuf(ctx, sizeof(double) * 2 * (size_t)g.ld_g * sub.ld_e);
   DevBuf ev(ctx, sizeof(double) * n_eig);
+  StageScope sc(sys.timer, SSRPA_STAGE_EIGEN, s);
   eig_lowest(ctx, sys.chibar0.as<double>(), g.n_g, n_eig, ev.as<double>(),
              sub.basis.as<double>(), sub.ld_e, sys.dev_flag.as<int>(), s);
   sub.eigval.resize(n_eig);
@@ -384,6 +411,7 @@ EcResult energy(System &sys, int n_eig, int n_freq, const double *omega,
       gm.c = wsub.as<double>(); gm.ldc = 2L * ld; gm.c_im = ld;
       gm.m = rows; gm.n = ld; gm.k = g.ld_g;
       gm.alpha = 1.0; gm.beta = 0.0;
+      StageScope sc(sys.timer, SSRPA_STAGE_PROJECTION, s);
       gemm(ctx, gm, prec, s);
       h.a = wsub.as<double>();
       h.lda = 2L * ld;
@@ -396,11 +424,16 @@ EcResult energy(System &sys, int n_eig, int n_freq, const double *omega,
     h.omega = om_d;
     h.n_omega = n_freq;
     h.wscale = 1.0 / g.volume;
+    h.timer = &sys.timer;
+    h.stage = SSRPA_STAGE_FREQ_HERK;
     herk(ctx, h, prec, chis, 2L * n * n, v0 > 0 ? 1 : 0, ws, s);
   }
   fill_zero(sys.dev_flag.as(), sizeof(int), s);
-  trace_log(ctx, chis, n, n_freq, coupling, f_d, sys.dev_flag.as<int>(), s);
-  quadrature(w_d, f_d, n_freq, ec_d, s);
+  {
+    StageScope sc(sys.timer, SSRPA_STAGE_TRACE_LOG, s);
+    trace_log(ctx, chis, n, n_freq, coupling, f_d, sys.dev_flag.as<int>(), s);
+    quadrature(w_d, f_d, n_freq, ec_d, s);
+  }
   EcResult r;
   r.f.resize(n_freq);
   int flag = 0;
@@ -478,6 +511,13 @@ ssrpa_status ssrpa_context_create(int hip_device, size_t hbm_budget_bytes,
 
 ssrpa_status ssrpa_context_destroy(ssrpa_context *ctx) {
   if (!ctx) return SSRPA_ERR_ARG;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (ctx->live_systems > 0) {
+      ctx->last_error = "systems still alive on this context";
+      return SSRPA_ERR_STATE;
+    }
+  }
   delete ctx;
   return SSRPA_OK;
 }
@@ -619,15 +659,22 @@ ssrpa_status ssrpa_system_create(ssrpa_context *ctx, const ssrpa_system_desc *de
     delete sys;
     return st;
   }
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->live_systems += 1;
+  }
   *out = sys;
   return SSRPA_OK;
 }
 
 ssrpa_status ssrpa_system_destroy(ssrpa_system *sys) {
   if (!sys) return SSRPA_ERR_ARG;
-  (void)hipSetDevice(sys->ctx->device);
+  Context *ctx = sys->ctx;
+  (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   delete sys;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->live_systems -= 1;
   return SSRPA_OK;
 }
 
@@ -797,6 +844,33 @@ ssrpa_status ssrpa_frequency_grid(int n, double omega0, double *omega,
     weight[o] = (double)(2.0L * omega0 * wx / ((1.0L - x) * (1.0L - x)));
   }
   return SSRPA_OK;
+}
+
+ssrpa_status ssrpa_stage_times(ssrpa_system *sys, int enable, double *ms,
+                               int *launches) {
+  if (!sys) return SSRPA_ERR_ARG;
+  return guarded(sys->ctx, [&] {
+    set_device(sys->ctx);
+    if (ms || launches) {
+      double acc[SSRPA_N_STAGES] = {0};
+      int cnt[SSRPA_N_STAGES] = {0};
+      for (auto &r : sys->timer.recs) {
+        SSRPA_HIP(hipEventSynchronize(r.b));
+        float t = 0.f;
+        SSRPA_HIP(hipEventElapsedTime(&t, r.a, r.b));
+        if (r.stage >= 0 && r.stage < SSRPA_N_STAGES) {
+          acc[r.stage] += t;
+          cnt[r.stage] += 1;
+        }
+      }
+      for (int i = 0; i < SSRPA_N_STAGES; ++i) {
+        if (ms) ms[i] = acc[i];
+        if (launches) launches[i] = cnt[i];
+      }
+    }
+    sys->timer.clear();
+    sys->timer.on = enable != 0;
+  });
 }
 
 ssrpa_status ssrpa_correlation_energy_enqueue(ssrpa_system *sys, int n_eig,

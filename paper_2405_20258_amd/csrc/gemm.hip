@@ -40,8 +40,8 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
 }
 
 // Output element (row, col) held by lane `l` in accumulator slot e of a
-// 16 x 16 f64 MFMA tile: 16-lane groups hold 4 consecutive rows.
-__device__ __forceinline__ int acc_row(int l, int e) { return 4 * (l >> 4) + e; }
+// 16 x 16 f64 MFMA tile: slot e of lane l holds row l/16 + 4e, column l%16.
+__device__ __forceinline__ int acc_row(int l, int e) { return (l >> 4) + 4 * e; }
 __device__ __forceinline__ int acc_col(int l) { return l & 15; }
 
 // Spread consecutive block ids over the 8 XCDs so that neighbouring tiles
@@ -317,28 +317,41 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g, int m_tiles,
 
 }  // namespace
 
+// reduced-precision launchers (gemm_mixed.hip)
+int herk_mixed_kstage(ssrpa_precision prec);
+void herk_mixed_launch(const HerkArgs &h, ssrpa_precision prec, int n_tiles,
+                       long nsplit, long kchunk, double *partial, hipStream_t s);
+void gemm_mixed_launch(const GemmArgs &g, ssrpa_precision prec, int m_tiles,
+                       int n_tiles, hipStream_t s);
+
 void herk(Context *ctx, const HerkArgs &h, ssrpa_precision prec, double *out,
           long out_stride, int beta, DevBuf &ws, hipStream_t s) {
-  (void)prec;  // reduced-precision paths are dispatched in gemm_mixed.hip
   SSRPA_REQUIRE(h.ld % kT == 0 && h.ncol <= h.ld, SSRPA_ERR_ARG,
                 "herk: bad padding");
   const int T = h.ld / kT;
   const int n_tiles = T * (T + 1) / 2;
   // split K so that there are at least ~2 blocks per CU
-  const long kr = (h.k + kKc - 1) / kKc;
+  const int kst = prec == SSRPA_FP64 ? kKc : herk_mixed_kstage(prec);
+  const long kr = (h.k + kst - 1) / kst;
   long nsplit = (512 + (long)n_tiles * h.n_omega - 1) / ((long)n_tiles * h.n_omega);
   nsplit = std::max(1L, std::min(nsplit, std::max(1L, kr / 8)));
-  long kchunk = ((kr + nsplit - 1) / nsplit) * kKc;
+  long kchunk = ((kr + nsplit - 1) / nsplit) * kst;
   nsplit = (h.k + kchunk - 1) / kchunk;
   if (nsplit < 1) nsplit = 1;
   const size_t need = sizeof(double) * 2L * kT * kT * n_tiles * nsplit * h.n_omega;
   ws.ensure(ctx, need);
   DevBuf *wsb = &ws;
   if (h.k > 0) {
-    hipLaunchKernelGGL(herk_f64_kernel, dim3(n_tiles, (unsigned)nsplit, h.n_omega),
-                       dim3(256), 0, s, h, n_tiles, kchunk,
-                       wsb->as<double>());
-    SSRPA_HIP(hipGetLastError());
+    const int ti = (h.timer && h.timer->on) ? h.timer->start(h.stage, s) : -1;
+    if (prec == SSRPA_FP64) {
+      hipLaunchKernelGGL(herk_f64_kernel, dim3(n_tiles, (unsigned)nsplit, h.n_omega),
+                         dim3(256), 0, s, h, n_tiles, kchunk,
+                         wsb->as<double>());
+      SSRPA_HIP(hipGetLastError());
+    } else {
+      herk_mixed_launch(h, prec, n_tiles, nsplit, kchunk, wsb->as<double>(), s);
+    }
+    if (ti >= 0) h.timer->stop(ti, s);
   } else {
     fill_zero(wsb->as(), need, s);
   }
@@ -350,13 +363,16 @@ void herk(Context *ctx, const HerkArgs &h, ssrpa_precision prec, double *out,
 
 void gemm(Context *ctx, const GemmArgs &g, ssrpa_precision prec, hipStream_t s) {
   (void)ctx;
-  (void)prec;
   SSRPA_REQUIRE(g.k % kT == 0 && g.n % kT == 0, SSRPA_ERR_ARG,
                 "gemm: k and n must be padded to 64");
   if (g.m <= 0) return;
   const long m_tiles = (g.m + kT - 1) / kT;
   const int n_tiles = g.n / kT;
   SSRPA_REQUIRE(m_tiles * n_tiles < (1L << 31), SSRPA_ERR_ARG, "gemm too large");
+  if (prec != SSRPA_FP64) {
+    gemm_mixed_launch(g, prec, (int)m_tiles, n_tiles, s);
+    return;
+  }
   hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)(m_tiles * n_tiles)),
                      dim3(256), 0, s, g, (int)m_tiles, n_tiles);
   SSRPA_HIP(hipGetLastError());

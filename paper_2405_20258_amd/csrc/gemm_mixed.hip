@@ -1,0 +1,614 @@
+// Reduced-precision forms of the complex contractions (same operands,
+// layouts and output as gemm.hip; the precision is a property of the MFMA
+// products only, every result leaves in FP64):
+//
+//  * FP32:   operands rounded to FP32 while staged; v_mfma_f32_16x16x4f32.
+//  * BF16x3: each real operand x is split as hi = bf16(x), lo = bf16(x - hi)
+//            while staged; a product is hi*hi' + hi*lo' + lo*hi' (the lo*lo'
+//            term, ~2^-16 relative, is dropped) on v_mfma_f32_16x16x32_bf16.
+//
+// Accumulation is FP32 inside a K chunk of kFlush rows and FP64 across
+// chunks (and across split-K partials and valence blocks), which keeps the
+// FP32 rounding walk short.
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace ssrpa {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4m __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int kT = 64;
+constexpr int kFlush = 1024;   // K rows accumulated in FP32 before flushing
+
+// 16 x 16 f32 accumulator layout of the 16x16xK f32-output MFMAs: slot e of
+// lane l holds row 4 (l/16) + e, column l % 16.
+__device__ __forceinline__ int accf_row(int l, int e) { return 4 * (l >> 4) + e; }
+__device__ __forceinline__ int accf_col(int l) { return l & 15; }
+
+__device__ __forceinline__ int xcd_remap_m(int b, int total) {
+  const int per = total / 8;
+  if (b >= per * 8) return b;
+  return (b & 7) * per + (b >> 3);
+}
+
+__device__ __forceinline__ int2 tri_tile_m(int t) {
+  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while (I * (I + 1) / 2 > t) --I;
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  return make_int2(I, t - I * (I + 1) / 2);
+}
+
+__device__ __forceinline__ double weight_m(const HerkArgs &h, long p, double om) {
+  if (h.unit_weight) return 1.0;
+  const double de = h.de[p];
+  return -4.0 * de / (de * de + om * om) * h.wscale;
+}
+
+// round-to-nearest-even float -> bf16 bits (finite inputs)
+__device__ __forceinline__ unsigned short f2bf(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) {
+  return __uint_as_float(((unsigned)h) << 16);
+}
+__device__ __forceinline__ void split_bf16(double x, unsigned short &hi,
+                                           unsigned short &lo) {
+  hi = f2bf((float)x);
+  lo = f2bf((float)(x - (double)bf2f(hi)));
+}
+
+__device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfmabf(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf8 load_bf8(const unsigned short *p) {
+  const uint4 v = *reinterpret_cast<const uint4 *>(p);
+  return __builtin_bit_cast(bf8, v);
+}
+__device__ __forceinline__ bf8 neg_bf8(bf8 a) {
+  uint4 v = __builtin_bit_cast(uint4, a);
+  v.x ^= 0x80008000u; v.y ^= 0x80008000u; v.z ^= 0x80008000u; v.w ^= 0x80008000u;
+  return __builtin_bit_cast(bf8, v);
+}
+
+// ------------------------------------------------------------- HERK FP32
+
+constexpr int kKc32 = 16;
+
+__global__ __launch_bounds__(256) void herk_f32_kernel(
+    HerkArgs h, int n_tiles, long kchunk, double *__restrict__ partial) {
+  __shared__ float As[2][kKc32][kT + 4];
+  __shared__ float Bs[2][kKc32][kT + 4];
+  __shared__ double wk[kKc32];
+  const int tile_id = xcd_remap_m(blockIdx.x, n_tiles);
+  const int split = blockIdx.y;
+  const int om_i = blockIdx.z;
+  const int2 tile = tri_tile_m(tile_id);
+  const int I0 = tile.x * kT, J0 = tile.y * kT;
+  const double om = h.unit_weight ? 0.0 : h.omega[om_i];
+  const long kbeg = split * kchunk;
+  const long kend = min(h.k, kbeg + kchunk);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  f4 re[2][2], im[2][2];
+  d4m Re[2][2], Im[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      re[i][j] = f4{0, 0, 0, 0}; im[i][j] = f4{0, 0, 0, 0};
+      Re[i][j] = d4m{0, 0, 0, 0}; Im[i][j] = d4m{0, 0, 0, 0};
+    }
+  int since = 0;
+  for (long k0 = kbeg; k0 < kend; k0 += kKc32) {
+    if (threadIdx.x < kKc32) {
+      const long p = k0 + threadIdx.x;
+      wk[threadIdx.x] = p < kend ? weight_m(h, p, om) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int idx = threadIdx.x + it * 256;
+      const int op = idx >> 9, part = (idx >> 8) & 1;
+      const int r = (idx >> 4) & 15, c2 = (idx & 15) * 2;
+      const long p = k0 + r;
+      const int col0 = op ? J0 : I0;
+      double2 v = make_double2(0.0, 0.0), u = make_double2(0.0, 0.0);
+      if (p < kend) {
+        const double *src = h.a + p * h.lda + part * h.im_off + col0;
+        v = *reinterpret_cast<const double2 *>(src + c2);
+        u = *reinterpret_cast<const double2 *>(src + c2 + 32);
+      }
+      const double sc = op ? wk[r] : 1.0;
+      float *dst = op ? &Bs[part][r][0] : &As[part][r][0];
+      dst[c2] = (float)(v.x * sc);
+      dst[c2 + 1] = (float)(v.y * sc);
+      dst[c2 + 32] = (float)(u.x * sc);
+      dst[c2 + 33] = (float)(u.y * sc);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kKc32; ks += 4) {
+      const int kr = ks + (lane >> 4), cl = lane & 15;
+      float ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ar[i] = As[0][kr][wr + i * 16 + cl];
+        ai[i] = As[1][kr][wr + i * 16 + cl];
+        br[i] = Bs[0][kr][wc + i * 16 + cl];
+        bi[i] = Bs[1][kr][wc + i * 16 + cl];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          re[i][j] = mfma32(ar[i], br[j], re[i][j]);
+          re[i][j] = mfma32(ai[i], bi[j], re[i][j]);
+          im[i][j] = mfma32(ar[i], bi[j], im[i][j]);
+          im[i][j] = mfma32(-ai[i], br[j], im[i][j]);
+        }
+    }
+    __syncthreads();
+    since += kKc32;
+    if (since >= kFlush) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            Re[i][j][e] += (double)re[i][j][e];
+            Im[i][j][e] += (double)im[i][j][e];
+            re[i][j][e] = 0.f;
+            im[i][j][e] = 0.f;
+          }
+      since = 0;
+    }
+  }
+  double *out = partial + (((long)om_i * gridDim.y + split) * n_tiles + tile_id) *
+                              2L * kT * kT;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = wr + i * 16 + accf_row(lane, e);
+        const int c = wc + j * 16 + accf_col(lane);
+        out[r * kT + c] = Re[i][j][e] + (double)re[i][j][e];
+        out[kT * kT + r * kT + c] = Im[i][j][e] + (double)im[i][j][e];
+      }
+}
+
+// ----------------------------------------------------------- HERK BF16x3
+
+constexpr int kKb = 32;         // K rows per stage = one bf16 MFMA
+constexpr int kKbP = kKb + 8;   // LDS row length (bf16), 16-byte aligned
+
+// LDS operand tile: [part re/im][hi/lo][column 0..63][k 0..31]
+struct alignas(16) BfTile {
+  unsigned short v[2][2][kT][kKbP];
+};
+
+__device__ __forceinline__ void stage_bf16(BfTile &t, const HerkArgs &h,
+                                           long k0, long kend, int col0,
+                                           const double *wk, bool weighted) {
+  // 2 parts x 32 rows x 64 columns = 4096 values; 256 threads x 8 (2 x 4)
+#pragma unroll
+  for (int it = 0; it < 8; ++it) {
+    const int idx = threadIdx.x + it * 256;   // 0..2047 (pairs of columns)
+    const int part = idx >> 10;
+    const int r = (idx >> 5) & 31;
+    const int c2 = (idx & 31) * 2;
+    const long p = k0 + r;
+    double2 v = make_double2(0.0, 0.0);
+    if (p < kend)
+      v = *reinterpret_cast<const double2 *>(h.a + p * h.lda + part * h.im_off +
+                                             col0 + c2);
+    const double sc = weighted ? wk[r] : 1.0;
+    unsigned short hi, lo;
+    split_bf16(v.x * sc, hi, lo);
+    t.v[part][0][c2][r] = hi;
+    t.v[part][1][c2][r] = lo;
+    split_bf16(v.y * sc, hi, lo);
+    t.v[part][0][c2 + 1][r] = hi;
+    t.v[part][1][c2 + 1][r] = lo;
+  }
+}
+
+__global__ __launch_bounds__(256) void herk_bf16x3_kernel(
+    HerkArgs h, int n_tiles, long kchunk, double *__restrict__ partial) {
+  __shared__ BfTile At, Bt;
+  __shared__ double wk[kKb];
+  const int tile_id = xcd_remap_m(blockIdx.x, n_tiles);
+  const int split = blockIdx.y;
+  const int om_i = blockIdx.z;
+  const int2 tile = tri_tile_m(tile_id);
+  const int I0 = tile.x * kT, J0 = tile.y * kT;
+  const double om = h.unit_weight ? 0.0 : h.omega[om_i];
+  const long kbeg = split * kchunk;
+  const long kend = min(h.k, kbeg + kchunk);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int ko = 8 * (lane >> 4), cl = lane & 15;
+  f4 re[2][2], im[2][2];
+  d4m Re[2][2], Im[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      re[i][j] = f4{0, 0, 0, 0}; im[i][j] = f4{0, 0, 0, 0};
+      Re[i][j] = d4m{0, 0, 0, 0}; Im[i][j] = d4m{0, 0, 0, 0};
+    }
+  int since = 0;
+  for (long k0 = kbeg; k0 < kend; k0 += kKb) {
+    if (threadIdx.x < kKb) {
+      const long p = k0 + threadIdx.x;
+      wk[threadIdx.x] = p < kend ? weight_m(h, p, om) : 0.0;
+    }
+    __syncthreads();
+    stage_bf16(At, h, k0, kend, I0, wk, false);
+    stage_bf16(Bt, h, k0, kend, J0, wk, true);
+    __syncthreads();
+    bf8 arh[2], arl[2], aih[2], ail[2], brh[2], brl[2], bih[2], bil[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int ma = wr + i * 16 + cl, mb = wc + i * 16 + cl;
+      arh[i] = load_bf8(&At.v[0][0][ma][ko]);
+      arl[i] = load_bf8(&At.v[0][1][ma][ko]);
+      aih[i] = load_bf8(&At.v[1][0][ma][ko]);
+      ail[i] = load_bf8(&At.v[1][1][ma][ko]);
+      brh[i] = load_bf8(&Bt.v[0][0][mb][ko]);
+      brl[i] = load_bf8(&Bt.v[0][1][mb][ko]);
+      bih[i] = load_bf8(&Bt.v[1][0][mb][ko]);
+      bil[i] = load_bf8(&Bt.v[1][1][mb][ko]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const bf8 naih = neg_bf8(aih[i]), nail = neg_bf8(ail[i]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        // Re += ar br + ai bi
+        re[i][j] = mfmabf(arh[i], brh[j], re[i][j]);
+        re[i][j] = mfmabf(arh[i], brl[j], re[i][j]);
+        re[i][j] = mfmabf(arl[i], brh[j], re[i][j]);
+        re[i][j] = mfmabf(aih[i], bih[j], re[i][j]);
+        re[i][j] = mfmabf(aih[i], bil[j], re[i][j]);
+        re[i][j] = mfmabf(ail[i], bih[j], re[i][j]);
+        // Im += ar bi - ai br
+        im[i][j] = mfmabf(arh[i], bih[j], im[i][j]);
+        im[i][j] = mfmabf(arh[i], bil[j], im[i][j]);
+        im[i][j] = mfmabf(arl[i], bih[j], im[i][j]);
+        im[i][j] = mfmabf(naih, brh[j], im[i][j]);
+        im[i][j] = mfmabf(naih, brl[j], im[i][j]);
+        im[i][j] = mfmabf(nail, brh[j], im[i][j]);
+      }
+    }
+    __syncthreads();
+    since += kKb;
+    if (since >= kFlush) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            Re[i][j][e] += (double)re[i][j][e];
+            Im[i][j][e] += (double)im[i][j][e];
+            re[i][j][e] = 0.f;
+            im[i][j][e] = 0.f;
+          }
+      since = 0;
+    }
+  }
+  double *out = partial + (((long)om_i * gridDim.y + split) * n_tiles + tile_id) *
+                              2L * kT * kT;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = wr + i * 16 + accf_row(lane, e);
+        const int c = wc + j * 16 + accf_col(lane);
+        out[r * kT + c] = Re[i][j][e] + (double)re[i][j][e];
+        out[kT * kT + r * kT + c] = Im[i][j][e] + (double)im[i][j][e];
+      }
+}
+
+// ------------------------------------------------------------- GEMM FP32
+
+__global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g, int m_tiles,
+                                                      int n_tiles) {
+  __shared__ float As[2][16][kT + 4];   // [part][k][m]
+  __shared__ float Bs[2][16][kT + 4];   // [part][k][n]
+  const int total = m_tiles * n_tiles;
+  const int b = xcd_remap_m(blockIdx.x, total);
+  const int mt = b / n_tiles, nt = b % n_tiles;
+  const long M0 = (long)mt * kT;
+  const int N0 = nt * kT;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  f4 re[2][2], im[2][2];
+  d4m Re[2][2], Im[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      re[i][j] = f4{0, 0, 0, 0}; im[i][j] = f4{0, 0, 0, 0};
+      Re[i][j] = d4m{0, 0, 0, 0}; Im[i][j] = d4m{0, 0, 0, 0};
+    }
+  int since = 0;
+  for (int k0 = 0; k0 < g.k; k0 += 16) {
+    {
+      const int row = threadIdx.x >> 2, part = (threadIdx.x >> 1) & 1;
+      const int kq = (threadIdx.x & 1) * 8;
+      const long m = M0 + row;
+      double v[8];
+      if (m < g.m) {
+        const double *src = g.a + m * g.lda + part * g.a_im + k0 + kq;
+#pragma unroll
+        for (int x = 0; x < 8; x += 2) {
+          const double2 t = *reinterpret_cast<const double2 *>(src + x);
+          v[x] = t.x; v[x + 1] = t.y;
+        }
+      } else {
+#pragma unroll
+        for (int x = 0; x < 8; ++x) v[x] = 0.0;
+      }
+#pragma unroll
+      for (int x = 0; x < 8; ++x) As[part][kq + x][row] = (float)v[x];
+    }
+    {
+      const int kr = threadIdx.x >> 4, part = (threadIdx.x >> 3) & 1;
+      const int cq = (threadIdx.x & 7) * 8;
+      const double *src = g.b + (long)(k0 + kr) * g.ldb + part * g.b_im + N0 + cq;
+#pragma unroll
+      for (int x = 0; x < 8; x += 2) {
+        const double2 t = *reinterpret_cast<const double2 *>(src + x);
+        Bs[part][kr][cq + x] = (float)t.x;
+        Bs[part][kr][cq + x + 1] = (float)t.y;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 16; ks += 4) {
+      const int kr = ks + (lane >> 4), cl = lane & 15;
+      float ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ar[i] = As[0][kr][wr + i * 16 + cl];
+        ai[i] = As[1][kr][wr + i * 16 + cl];
+        br[i] = Bs[0][kr][wc + i * 16 + cl];
+        bi[i] = Bs[1][kr][wc + i * 16 + cl];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          re[i][j] = mfma32(ar[i], br[j], re[i][j]);
+          re[i][j] = mfma32(-ai[i], bi[j], re[i][j]);
+          im[i][j] = mfma32(ar[i], bi[j], im[i][j]);
+          im[i][j] = mfma32(ai[i], br[j], im[i][j]);
+        }
+    }
+    __syncthreads();
+    since += 16;
+    if (since >= kFlush) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            Re[i][j][e] += (double)re[i][j][e];
+            Im[i][j][e] += (double)im[i][j][e];
+            re[i][j][e] = 0.f;
+            im[i][j][e] = 0.f;
+          }
+      since = 0;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const long m = M0 + wr + i * 16 + accf_row(lane, e);
+        const int n = N0 + wc + j * 16 + accf_col(lane);
+        if (m >= g.m) continue;
+        double *cr = g.c + m * g.ldc + n;
+        double *ci = cr + g.c_im;
+        const double vr = g.alpha * (Re[i][j][e] + (double)re[i][j][e]);
+        const double vi = g.alpha * (Im[i][j][e] + (double)im[i][j][e]);
+        if (g.beta != 0.0) {
+          *cr = vr + g.beta * *cr;
+          *ci = vi + g.beta * *ci;
+        } else {
+          *cr = vr;
+          *ci = vi;
+        }
+      }
+}
+
+// ----------------------------------------------------------- GEMM BF16x3
+
+__global__ __launch_bounds__(256) void gemm_bf16x3_kernel(GemmArgs g,
+                                                         int m_tiles,
+                                                         int n_tiles) {
+  __shared__ BfTile At, Bt;   // At: [part][hl][m][k], Bt: [part][hl][n][k]
+  const int total = m_tiles * n_tiles;
+  const int b = xcd_remap_m(blockIdx.x, total);
+  const int mt = b / n_tiles, nt = b % n_tiles;
+  const long M0 = (long)mt * kT;
+  const int N0 = nt * kT;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int ko = 8 * (lane >> 4), cl = lane & 15;
+  f4 re[2][2], im[2][2];
+  d4m Re[2][2], Im[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      re[i][j] = f4{0, 0, 0, 0}; im[i][j] = f4{0, 0, 0, 0};
+      Re[i][j] = d4m{0, 0, 0, 0}; Im[i][j] = d4m{0, 0, 0, 0};
+    }
+  int since = 0;
+  for (int k0 = 0; k0 < g.k; k0 += kKb) {
+    // A: 64 rows x 32 k x 2 parts; k is contiguous in memory
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int idx = threadIdx.x + it * 256;   // 0..1023
+      const int part = idx >> 9, row = (idx >> 3) & 63, kq = (idx & 7) * 4;
+      const long m = M0 + row;
+      double v[4] = {0.0, 0.0, 0.0, 0.0};
+      if (m < g.m) {
+        const double *src = g.a + m * g.lda + part * g.a_im + k0 + kq;
+        const double2 t0 = *reinterpret_cast<const double2 *>(src);
+        const double2 t1 = *reinterpret_cast<const double2 *>(src + 2);
+        v[0] = t0.x; v[1] = t0.y; v[2] = t1.x; v[3] = t1.y;
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        unsigned short hi, lo;
+        split_bf16(v[x], hi, lo);
+        At.v[part][0][row][kq + x] = hi;
+        At.v[part][1][row][kq + x] = lo;
+      }
+    }
+    // B: 32 k rows x 64 columns x 2 parts; transposed into [n][k]
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int idx = threadIdx.x + it * 256;
+      const int part = idx >> 9, kr = (idx >> 4) & 31, cq = (idx & 15) * 4;
+      const double *src = g.b + (long)(k0 + kr) * g.ldb + part * g.b_im + N0 + cq;
+      const double2 t0 = *reinterpret_cast<const double2 *>(src);
+      const double2 t1 = *reinterpret_cast<const double2 *>(src + 2);
+      const double v[4] = {t0.x, t0.y, t1.x, t1.y};
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        unsigned short hi, lo;
+        split_bf16(v[x], hi, lo);
+        Bt.v[part][0][cq + x][kr] = hi;
+        Bt.v[part][1][cq + x][kr] = lo;
+      }
+    }
+    __syncthreads();
+    bf8 arh[2], arl[2], aih[2], ail[2], brh[2], brl[2], bih[2], bil[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int ma = wr + i * 16 + cl, mb = wc + i * 16 + cl;
+      arh[i] = load_bf8(&At.v[0][0][ma][ko]);
+      arl[i] = load_bf8(&At.v[0][1][ma][ko]);
+      aih[i] = load_bf8(&At.v[1][0][ma][ko]);
+      ail[i] = load_bf8(&At.v[1][1][ma][ko]);
+      brh[i] = load_bf8(&Bt.v[0][0][mb][ko]);
+      brl[i] = load_bf8(&Bt.v[0][1][mb][ko]);
+      bih[i] = load_bf8(&Bt.v[1][0][mb][ko]);
+      bil[i] = load_bf8(&Bt.v[1][1][mb][ko]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const bf8 naih = neg_bf8(aih[i]), nail = neg_bf8(ail[i]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        // Re += ar br - ai bi
+        re[i][j] = mfmabf(arh[i], brh[j], re[i][j]);
+        re[i][j] = mfmabf(arh[i], brl[j], re[i][j]);
+        re[i][j] = mfmabf(arl[i], brh[j], re[i][j]);
+        re[i][j] = mfmabf(naih, bih[j], re[i][j]);
+        re[i][j] = mfmabf(naih, bil[j], re[i][j]);
+        re[i][j] = mfmabf(nail, bih[j], re[i][j]);
+        // Im += ar bi + ai br
+        im[i][j] = mfmabf(arh[i], bih[j], im[i][j]);
+        im[i][j] = mfmabf(arh[i], bil[j], im[i][j]);
+        im[i][j] = mfmabf(arl[i], bih[j], im[i][j]);
+        im[i][j] = mfmabf(aih[i], brh[j], im[i][j]);
+        im[i][j] = mfmabf(aih[i], brl[j], im[i][j]);
+        im[i][j] = mfmabf(ail[i], brh[j], im[i][j]);
+      }
+    }
+    __syncthreads();
+    since += kKb;
+    if (since >= kFlush) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            Re[i][j][e] += (double)re[i][j][e];
+            Im[i][j][e] += (double)im[i][j][e];
+            re[i][j][e] = 0.f;
+            im[i][j][e] = 0.f;
+          }
+      since = 0;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const long m = M0 + wr + i * 16 + accf_row(lane, e);
+        const int n = N0 + wc + j * 16 + accf_col(lane);
+        if (m >= g.m) continue;
+        double *cr = g.c + m * g.ldc + n;
+        double *ci = cr + g.c_im;
+        const double vr = g.alpha * (Re[i][j][e] + (double)re[i][j][e]);
+        const double vi = g.alpha * (Im[i][j][e] + (double)im[i][j][e]);
+        if (g.beta != 0.0) {
+          *cr = vr + g.beta * *cr;
+          *ci = vi + g.beta * *ci;
+        } else {
+          *cr = vr;
+          *ci = vi;
+        }
+      }
+}
+
+}  // namespace
+
+// K rows per stage of the reduced-precision HERK kernels.
+int herk_mixed_kstage(ssrpa_precision prec) {
+  return prec == SSRPA_BF16X3 ? kKb : kKc32;
+}
+
+void herk_mixed_launch(const HerkArgs &h, ssrpa_precision prec, int n_tiles,
+                       long nsplit, long kchunk, double *partial,
+                       hipStream_t s) {
+  const dim3 grid(n_tiles, (unsigned)nsplit, h.n_omega);
+  if (prec == SSRPA_FP32)
+    hipLaunchKernelGGL(herk_f32_kernel, grid, dim3(256), 0, s, h, n_tiles,
+                       kchunk, partial);
+  else
+    hipLaunchKernelGGL(herk_bf16x3_kernel, grid, dim3(256), 0, s, h, n_tiles,
+                       kchunk, partial);
+  SSRPA_HIP(hipGetLastError());
+}
+
+void gemm_mixed_launch(const GemmArgs &g, ssrpa_precision prec, int m_tiles,
+                       int n_tiles, hipStream_t s) {
+  const dim3 grid((unsigned)(m_tiles * n_tiles));
+  if (prec == SSRPA_FP32)
+    hipLaunchKernelGGL(gemm_f32_kernel, grid, dim3(256), 0, s, g, m_tiles,
+                       n_tiles);
+  else
+    hipLaunchKernelGGL(gemm_bf16x3_kernel, grid, dim3(256), 0, s, g, m_tiles,
+                       n_tiles);
+  SSRPA_HIP(hipGetLastError());
+}
+
+}  // namespace ssrpa

@@ -82,6 +82,7 @@ struct Context {
   size_t in_use = 0;
   size_t high_water = 0;
   std::string last_error;
+  int live_systems = 0;  // systems created on this context and not destroyed
   std::mutex mu;  // guards the byte accounting (serving threads share it)
   void *alloc(size_t bytes);
   void release(void *p, size_t bytes);
@@ -98,6 +99,28 @@ struct Geometry {
   int ld_g;          // n_g rounded up to a multiple of 64 (zero padded)
   std::vector<int32_t> miller_chi;  // n_g x 3
   std::vector<double> sqrt_v;       // v(G)^1/2 per chi0 vector
+};
+
+// Event timing of the stages (ssrpa_stage_times).
+struct StageTimer {
+  bool on = false;
+  struct Rec { int stage; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  // record the start of a stage on stream s; returns an index for stop()
+  int start(int stage, hipStream_t s);
+  void stop(int idx, hipStream_t s);
+  void clear();
+  ~StageTimer() { clear(); }
+};
+
+// RAII stage scope: records events only when the timer is on.
+struct StageScope {
+  StageTimer *t;
+  hipStream_t s;
+  int idx;
+  StageScope(StageTimer &tm, int stage, hipStream_t st)
+      : t(&tm), s(st), idx(tm.on ? tm.start(stage, st) : -1) {}
+  ~StageScope() { if (idx >= 0) t->stop(idx, s); }
 };
 
 // Resident subspace state after ssrpa_subspace.
@@ -128,6 +151,7 @@ struct System {
   bool w_cache_valid = false;
   // Device-side error flag (non-positive pivot, etc.): int.
   DevBuf dev_flag;
+  StageTimer timer;
 };
 
 // ---------------------------------------------------------------------------
@@ -160,6 +184,8 @@ struct HerkArgs {
   int n_omega;
   double wscale;       // multiplies Delta (1/Omega)
   int unit_weight;     // 1: weights all 1 (Gram matrices), ignore de/omega
+  StageTimer *timer = nullptr;  // optional: time the contraction kernel
+  int stage = 0;
 };
 // out_j (+)= A^H diag(d_j) A for every j, written as full Hermitian
 // ncol x ncol interleaved complex matrices at out + j * out_stride (doubles).

@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -86,6 +87,9 @@ ssrpa_correlation_energy = _sig("ssrpa_correlation_energy", _i,
                                  _p, _p])
 ssrpa_trace_log = _sig("ssrpa_trace_log", _i, [_p, _p, _i, _i, _d, _dp, _p])
 ssrpa_frequency_grid = _sig("ssrpa_frequency_grid", _i, [_i, _d, _dp, _dp])
+ssrpa_stage_times = _sig("ssrpa_stage_times", _i, [_p, _i, _dp, _ip])
+STAGES = ["pair_fft", "chi0_herk", "eigen", "projection", "freq_herk",
+          "trace_log"]
 ssrpa_correlation_energy_enqueue = _sig(
     "ssrpa_correlation_energy_enqueue", _i,
     [_p, _i, _i, _dp, _dp, _i, _i, _p, ctypes.POINTER(_p)])
@@ -173,10 +177,14 @@ class Context:
         h = _p()
         _check(ssrpa_context_create(device, hbm_budget, ctypes.byref(h)))
         self.handle = h
+        self._systems = weakref.WeakSet()
 
     def close(self):
+        """Destroy the context, closing its remaining systems first."""
         if self.handle:
-            ssrpa_context_destroy(self.handle)
+            for s in list(self._systems):
+                s.close()
+            _check(ssrpa_context_destroy(self.handle), self.handle)
             self.handle = None
 
     def memory(self):
@@ -213,6 +221,7 @@ class System:
                                    _stream(stream), ctypes.byref(h)),
                ctx.handle)
         self.handle = h
+        ctx._systems.add(self)
         self.n_v = int(n_v)
         self.n_c = int(len(energy) - n_v)
         self.fft = tuple(int(x) for x in fft)
@@ -224,7 +233,8 @@ class System:
 
     def close(self):
         if getattr(self, "handle", None):
-            ssrpa_system_destroy(self.handle)
+            if self.ctx.handle:
+                ssrpa_system_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -284,6 +294,13 @@ class System:
             PRECISIONS[precision], valence_block, coupling, ctypes.byref(ec),
             _dptr(f), _addr(chi_sub_dev), _stream(stream)))
         return ec.value, f
+
+    def stage_times(self, enable: bool = True):
+        """{stage: (ms, launches)} since the last call; (re)starts timing."""
+        ms = np.zeros(len(STAGES))
+        n = (ctypes.c_int * len(STAGES))()
+        self._chk(ssrpa_stage_times(self.handle, int(enable), _dptr(ms), n))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(STAGES)}
 
     def enqueue(self, n_eig: int, omega, weight, precision="fp64",
                 valence_block: int = 0, stream=None):

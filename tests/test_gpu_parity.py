@@ -7,7 +7,13 @@ CPU (or its stored outputs in tests/golden/ are read).
 Tolerances (FP64 path): pair matrix elements 1e-12 relative to the largest
 element; chi0 1e-10 in max-norm relative; eigenvalues 1e-10 relative to the
 largest |eigenvalue|; subspace projector 1e-8 absolute; per-frequency F_j
-and E_c 1e-10 relative.  Eigenvectors are compared through the projector
+and E_c 1e-10 relative.  On the small ragged system (E_c ~ 3e-3) E_c also
+gets an absolute floor of 1e-12: F_j = ln det(I - X_j) + Tr X_j cancels to
+second order in X_j, so at the high-frequency nodes of the mapped rule
+(weights up to ~500) the FP64 rounding of the log-determinant of a
+near-identity matrix (~n eps per node) leaves ~5e-13 in E_c on both sides;
+the oracle's rank-one pin shows the same floor.  The workload tests keep
+the plain 1e-10 relative bound.  Eigenvectors are compared through the projector
 C_s C_s^H because each vector is defined only up to a phase.
 """
 import json
@@ -214,7 +220,7 @@ def test_subspace_and_energy_ragged(env):
         ec, f = g.correlation_energy(n_eig, om, wt, "fp64")
         rel = abs(ec - ref["ec"]) / abs(ref["ec"])
         _log(f"  E_c gpu {ec!r} oracle {ref['ec']!r} rel {rel:.2e}")
-        assert rel < 1e-10
+        assert abs(ec - ref["ec"]) < 1e-10 * abs(ref["ec"]) + 1e-12
         assert np.max(np.abs(f - ref["integrand"])) < \
             1e-10 * np.max(np.abs(ref["integrand"]))
     g.close()
@@ -342,4 +348,43 @@ def test_medium_workload_against_golden(env):
     rel = abs(ec - r["ec"]) / abs(r["ec"])
     _log(f"medium n_eig=400: E_c {ec!r} golden {r['ec']!r} rel {rel:.2e}")
     assert rel < 1e-10
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_precision_modes_tiny(env, prec):
+    """Reduced-precision contractions: E_c within 1e-5 of the FP64 oracle.
+
+    The static eigendecomposition and the log-determinants stay FP64; only
+    the chi0, projection and per-frequency contractions change arithmetic.
+    The result must differ from the FP64 path (the reduced arithmetic really
+    ran) and stay within the mixed-precision bound.
+    """
+    torch, ssrpa, ctx = env
+    from synth import systems as sy
+    gold = json.load(open(os.path.join(HERE, "golden", "tiny.json")))
+    s = sy.make_system(sy.TINY, gold["seed"])
+    om, wt = sy.frequency_grid(gold["n_freq"])
+    r = gold["results"]["n_eig_75"]
+    _log(f"tiny precision {prec}")
+    g = ssrpa.System.from_synthetic(ctx, s)
+    ng = g.n_g
+    idx = label_index(g.gvectors())
+    out = torch.empty((ng, ng), dtype=torch.complex128, device="cuda")
+    g.chi0_static(prec, out_dev=out, symmetrized=True)
+    torch.cuda.synchronize()
+    chi = out.cpu().numpy()
+    err = 0.0
+    for row in gold["chibar0_samples"]:
+        i = idx[tuple(row[0:3])]
+        j = idx[tuple(row[3:6])]
+        err = max(err, abs(chi[i, j] - complex(row[6], row[7])))
+    err /= gold["chibar0_maxabs"]
+    lam = g.subspace(75)
+    ec, f = g.correlation_energy(75, om, wt, prec)
+    rel = abs(ec - r["ec"]) / abs(r["ec"])
+    _log(f"{prec}: chi0 sample err {err:.2e}  E_c {ec!r} rel {rel:.2e}")
+    assert rel < 1e-5
+    assert err < 1e-5
+    assert rel > 1e-13 or err > 1e-13, "reduced precision path did not run"
     g.close()
