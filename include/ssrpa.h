@@ -45,7 +45,9 @@
  * A failed call leaves the system usable, except after SSRPA_ERR_HIP (a HIP
  * runtime error), after which the context should be destroyed.  The text of
  * the last error of a context is available from ssrpa_last_error.
- * One context per host thread; a context is not thread safe.
+ * A context may be shared by threads that work on different systems (the
+ * memory accounting is locked); one system must not be used by two threads
+ * at once.
  */
 #ifndef SSRPA_H
 #define SSRPA_H
@@ -104,7 +106,8 @@ typedef struct ssrpa_system_desc {
 /* Human-readable name of a status code (static string). */
 SSRPA_API const char *ssrpa_status_string(ssrpa_status s);
 
-/* Text of the most recent error on this context ("" if none). */
+/* Text of the most recent error of a call on this context made by the
+ * calling thread ("" if that call succeeded). */
 SSRPA_API const char *ssrpa_last_error(const ssrpa_context *ctx);
 
 /* Library version string, e.g. "0.1.0 gfx950". */
@@ -120,7 +123,8 @@ SSRPA_API ssrpa_status ssrpa_context_create(int hip_device,
  * created on it are still alive. */
 SSRPA_API ssrpa_status ssrpa_context_destroy(ssrpa_context *ctx);
 
-/* Device bytes currently held and the high-water mark of this context. */
+/* Device bytes held by this context (live plus cached blocks) and the
+ * high-water mark of live allocations. */
 SSRPA_API ssrpa_status ssrpa_context_memory(const ssrpa_context *ctx,
                                             size_t *in_use, size_t *high_water);
 
@@ -265,6 +269,60 @@ SSRPA_API ssrpa_status ssrpa_ticket_query(ssrpa_ticket *t, int *done);
  * integrand values; free the ticket.  Returns the solve's status. */
 SSRPA_API ssrpa_status ssrpa_ticket_wait(ssrpa_ticket *t, double *ec,
                                          double *integrand);
+
+/* ---- serving: a request loop with admission by HBM footprint ---------- */
+
+typedef struct ssrpa_server ssrpa_server;
+
+/* Request states reported by ssrpa_server_poll. */
+enum { SSRPA_REQ_QUEUED = 0, SSRPA_REQ_RUNNING = 1, SSRPA_REQ_DONE = 2,
+       SSRPA_REQ_FAILED = 3 };
+
+/* A server owns a dispatcher thread over `ctx`.  Submitted requests wait in
+ * arrival order; the dispatcher admits the first waiting request whose
+ * ssrpa_footprint fits the memory not yet reserved (budget minus the
+ * footprints of running requests), up to `max_running` at once, and runs
+ * each admitted request (system creation, static chi0, subspace, E_c) on a
+ * worker thread with its own HIP stream, so the device work of different
+ * requests overlaps.  A request that has waited longer than
+ * `max_bypass_s` seconds is not overtaken by later ones.  Each result is
+ * independent of the mix: kernels and reduction orders depend only on the
+ * request's own sizes. */
+SSRPA_API ssrpa_status ssrpa_server_create(ssrpa_context *ctx, int max_running,
+                                           double max_bypass_s,
+                                           ssrpa_server **out);
+
+/* Queue one E_c solve.  The description's arrays, `omega` and `weight` are
+ * copied (host memory only: coeff_on_device must be 0); n_eig >= N_G asks for
+ * the full basis.  valence_block 0 picks the largest block that fits the
+ * request's reservation.  *request_id identifies it for polling.
+ * SSRPA_ERR_NOMEM if the request could never fit the context budget. */
+SSRPA_API ssrpa_status ssrpa_server_submit(ssrpa_server *srv,
+                                           const ssrpa_system_desc *desc,
+                                           int n_eig, int n_freq,
+                                           const double *omega,
+                                           const double *weight,
+                                           ssrpa_precision precision,
+                                           uint64_t *request_id);
+
+/* State of a request; when done, *ec and the times in seconds since the
+ * server's creation (submit, admission to the device, completion).
+ * Any output pointer may be NULL.  `status` receives the solve's status. */
+SSRPA_API ssrpa_status ssrpa_server_poll(ssrpa_server *srv, uint64_t request_id,
+                                         int *state, ssrpa_status *status,
+                                         double *ec, double *t_submit,
+                                         double *t_start, double *t_done);
+
+/* Block until every submitted request has finished. */
+SSRPA_API ssrpa_status ssrpa_server_drain(ssrpa_server *srv);
+
+/* Peak device memory reserved by admitted requests (bytes), and the
+ * context's measured high-water mark. */
+SSRPA_API ssrpa_status ssrpa_server_memory(ssrpa_server *srv, size_t *reserved_peak,
+                                           size_t *high_water);
+
+/* Drain and destroy. */
+SSRPA_API ssrpa_status ssrpa_server_destroy(ssrpa_server *srv);
 
 #ifdef __cplusplus
 }

@@ -29,32 +29,93 @@ void fail(ssrpa_status code, const char *fmt, ...) {
   throw Error(code, buf);
 }
 
-void *Context::alloc(size_t bytes) {
-  if (bytes == 0) bytes = 8;
-  {
-    std::lock_guard<std::mutex> g(mu);
-    if (in_use + bytes > budget)
-      fail(SSRPA_ERR_NOMEM, "HBM budget exceeded: %zu in use + %zu requested > %zu",
-           in_use, bytes, budget);
-    in_use += bytes;
-    high_water = std::max(high_water, in_use);
+// Allocation granularity: sizes are rounded up so that cached blocks are
+// reusable across slightly different requests.
+static size_t round_alloc(size_t bytes) {
+  const size_t g = bytes >= (64u << 20) ? (8u << 20) : (bytes >= (1u << 20) ? (1u << 20) : 4096);
+  return (bytes + g - 1) / g * g;
+}
+
+void Context::trim_locked(size_t need) {
+  // largest cached blocks first
+  while (!free_blocks.empty() && in_use + cached + need > budget) {
+    auto it = std::prev(free_blocks.end());
+    (void)hipFree(it->second);
+    cached -= it->first;
+    free_blocks.erase(it);
   }
+}
+
+void *Context::alloc(size_t bytes) {
+  bytes = round_alloc(bytes == 0 ? 8 : bytes);
+  std::lock_guard<std::mutex> g(mu);
+  // reuse a cached block of at least `bytes` and at most 1.25x larger
+  auto it = free_blocks.lower_bound(bytes);
+  if (it != free_blocks.end() && it->first <= bytes + bytes / 4) {
+    void *p = it->second;
+    const size_t sz = it->first;
+    free_blocks.erase(it);
+    cached -= sz;
+    in_use += sz;
+    high_water = std::max(high_water, in_use);
+    // record the actual block size for release
+    sizes_[p] = sz;
+    return p;
+  }
+  trim_locked(bytes);
+  if (in_use + cached + bytes > budget)
+    fail(SSRPA_ERR_NOMEM, "HBM budget exceeded: %zu in use + %zu requested > %zu",
+         in_use, bytes, budget);
   void *p = nullptr;
   hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    std::lock_guard<std::mutex> g(mu);
-    in_use -= bytes;
-    fail(SSRPA_ERR_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    // give every cached block back and retry once
+    for (auto &fb : free_blocks) (void)hipFree(fb.second);
+    free_blocks.clear();
+    cached = 0;
+    e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(SSRPA_ERR_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
   }
+  in_use += bytes;
+  high_water = std::max(high_water, in_use);
+  sizes_[p] = bytes;
   return p;
 }
 
-void Context::release(void *p, size_t bytes) {
+void Context::release(void *p, size_t) {
   if (!p) return;
-  (void)hipFree(p);
   std::lock_guard<std::mutex> g(mu);
-  in_use -= bytes == 0 ? 8 : bytes;
+  auto it = sizes_.find(p);
+  if (it == sizes_.end()) return;
+  const size_t sz = it->second;
+  sizes_.erase(it);
+  in_use -= sz;
+  free_blocks.emplace(sz, p);
+  cached += sz;
+}
+
+// Error text is kept per calling thread and context, so concurrent callers
+// (e.g. serving workers) do not overwrite each other's message.
+static std::map<const Context *, std::string> &thread_errors() {
+  static thread_local std::map<const Context *, std::string> m;
+  return m;
+}
+
+void Context::set_error(const std::string &m) { thread_errors()[this] = m; }
+
+std::string Context::error() {
+  auto &m = thread_errors();
+  auto it = m.find(this);
+  return it == m.end() ? std::string() : it->second;
+}
+
+Context::~Context() {
+  for (auto &fb : free_blocks) (void)hipFree(fb.second);
+  for (auto &kv : sizes_) (void)hipFree(kv.first);
 }
 
 int StageTimer::start(int stage, hipStream_t s) {
@@ -230,16 +291,16 @@ ssrpa_status finish(Context *ctx, const std::exception_ptr &ep) {
   try {
     std::rethrow_exception(ep);
   } catch (const Error &e) {
-    if (ctx) ctx->last_error = e.what();
+    if (ctx) ctx->set_error(e.what());
     return e.code;
   } catch (const std::bad_alloc &) {
-    if (ctx) ctx->last_error = "host allocation failed";
+    if (ctx) ctx->set_error("host allocation failed");
     return SSRPA_ERR_NOMEM;
   } catch (const std::exception &e) {
-    if (ctx) ctx->last_error = e.what();
+    if (ctx) ctx->set_error(e.what());
     return SSRPA_ERR_ARG;
   } catch (...) {
-    if (ctx) ctx->last_error = "unknown error";
+    if (ctx) ctx->set_error("unknown error");
     return SSRPA_ERR_ARG;
   }
 }
@@ -247,7 +308,7 @@ ssrpa_status finish(Context *ctx, const std::exception_ptr &ep) {
 template <class F>
 ssrpa_status guarded(Context *ctx, F &&f) {
   try {
-    if (ctx) ctx->last_error.clear();
+    if (ctx) ctx->set_error("");
     f();
     return SSRPA_OK;
   } catch (...) {
@@ -479,7 +540,9 @@ const char *ssrpa_status_string(ssrpa_status s) {
 }
 
 const char *ssrpa_last_error(const ssrpa_context *ctx) {
-  return ctx ? ctx->last_error.c_str() : "";
+  static thread_local std::string copy;
+  copy = ctx ? const_cast<ssrpa_context *>(ctx)->error() : std::string();
+  return copy.c_str();
 }
 
 const char *ssrpa_version(void) { return "0.1.0 gfx950"; }
@@ -514,7 +577,7 @@ ssrpa_status ssrpa_context_destroy(ssrpa_context *ctx) {
   {
     std::lock_guard<std::mutex> g(ctx->mu);
     if (ctx->live_systems > 0) {
-      ctx->last_error = "systems still alive on this context";
+      ctx->set_error("systems still alive on this context");
       return SSRPA_ERR_STATE;
     }
   }
@@ -527,7 +590,7 @@ ssrpa_status ssrpa_context_memory(const ssrpa_context *ctx, size_t *in_use,
   if (!ctx) return SSRPA_ERR_ARG;
   auto *c = const_cast<ssrpa_context *>(ctx);
   std::lock_guard<std::mutex> g(c->mu);
-  if (in_use) *in_use = c->in_use;
+  if (in_use) *in_use = c->in_use + c->cached;
   if (high_water) *high_water = c->high_water;
   return SSRPA_OK;
 }

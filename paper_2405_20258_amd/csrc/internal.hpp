@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <stdexcept>
@@ -76,16 +77,27 @@ class DevBuf {
   size_t bytes_ = 0;
 };
 
+// A context owns the device memory budget.  Freed blocks are cached (every
+// library call synchronizes its stream before its buffers go out of scope,
+// so a returned block is idle) and reused by later allocations; this keeps
+// hipFree, which synchronizes the whole device, out of the steady state
+// where several requests run concurrently.  budget caps live + cached bytes.
 struct Context {
   int device = 0;
   size_t budget = 0;
-  size_t in_use = 0;
-  size_t high_water = 0;
-  std::string last_error;
-  int live_systems = 0;  // systems created on this context and not destroyed
-  std::mutex mu;  // guards the byte accounting (serving threads share it)
+  size_t in_use = 0;       // bytes in live allocations
+  size_t cached = 0;       // bytes in cached free blocks
+  size_t high_water = 0;   // peak of in_use
+  int live_systems = 0;    // systems created on this context and not destroyed
+  std::multimap<size_t, void *> free_blocks;
+  std::mutex mu;           // guards everything above
   void *alloc(size_t bytes);
   void release(void *p, size_t bytes);
+  void set_error(const std::string &m);
+  std::string error();
+  void trim_locked(size_t need);   // free cached blocks until `need` fits
+  ~Context();
+  std::map<void *, size_t> sizes_;  // live allocations and their block sizes
 };
 
 // Geometry of the real-space grid and the chi0 G set, derived once per system.
