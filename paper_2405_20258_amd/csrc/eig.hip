@@ -378,50 +378,182 @@ __global__ void phase_apply_kernel(const double *__restrict__ z, int ldz,
   }
 }
 
-// Apply H_{n-2} ... H_0 (in that order, H_0 last) to columns [c0, c0+16).
-__global__ __launch_bounds__(256) void apply_reflectors_kernel(
-    const double2 *__restrict__ a, const double *__restrict__ tau, int n,
-    double *__restrict__ c, int ld_e, int n_eig) {
-  __shared__ double sr[16][17], si[16][17];
-  const int col = blockIdx.x * 16 + (threadIdx.x & 15);
-  const int rs = threadIdx.x >> 4;
-  const bool active = col < n_eig;
-  const long ldc = 2L * ld_e;
-  for (int k = n - 2; k >= 0; --k) {
-    const double tk = tau[k];
-    if (tk == 0.0) continue;
-    const int m = n - k - 1;
-    const double2 *u = a + (long)k * n + k + 1;
-    double dr = 0.0, di = 0.0;
-    if (active) {
-      for (int i = rs; i < m; i += 16) {
-        const double2 ui = u[i];
-        const double *cr = c + (long)(k + 1 + i) * ldc + col;
-        const double xr = cr[0], xi = cr[ld_e];
-        dr += ui.x * xr + ui.y * xi;   // conj(u) x
-        di += ui.x * xi - ui.y * xr;
-      }
-    }
-    sr[rs][threadIdx.x & 15] = dr;
-    si[rs][threadIdx.x & 15] = di;
+// Blocked back-transformation.  Reflectors k0 .. k0+nb-1 are combined as
+// H_k0 H_k0+1 ... H_k0+nb-1 = I - V T V^H with T upper triangular:
+// T_jj = tau_j, T_{0:j,j} = -tau_j T_{0:j,0:j} (V_{:,0:j}^H v_j).  Column j of
+// V is reflector k0+j: zero in rows <= k0+j, u (stored in row k0+j of the
+// work matrix) below.  Blocks are applied last block first, since
+// Q = Q_0 Q_1 ... Q_last acts on C from the left.
+constexpr int kWy = 32;   // reflectors per block
+
+__device__ __forceinline__ double2 vref(const double2 *a, int n, int k, int r) {
+  return r > k ? a[(long)k * n + r] : make_double2(0.0, 0.0);
+}
+
+// One block per reflector block: S = V^H V (strict upper part), then T.
+__global__ __launch_bounds__(256) void wy_t_kernel(const double2 *__restrict__ a,
+                                                   const double *__restrict__ tau,
+                                                   int n, double2 *__restrict__ t_all) {
+  __shared__ double2 vs[64][kWy + 1];
+  __shared__ double2 S[kWy][kWy + 1];
+  __shared__ double2 T[kWy][kWy + 1];
+  const int b = blockIdx.x;
+  const int k0 = b * kWy;
+  const int nb = min(kWy, (n - 1) - k0);
+  // each thread owns up to 2 (i < j) pairs of the 32 x 32 strict upper part
+  double2 acc[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+  int pi[2], pj[2];
+  for (int q = 0; q < 2; ++q) {
+    const int id = threadIdx.x + q * 256;   // 0..511 covers 496 pairs
+    // decode (i, j) by rows of the upper triangle: row i has kWy - 1 - i pairs
+    int ii = 0, rem = id;
+    while (ii < kWy - 1 && rem >= kWy - 1 - ii) { rem -= kWy - 1 - ii; ++ii; }
+    pi[q] = ii;
+    pj[q] = ii + 1 + rem;
+  }
+  for (int r0 = k0 + 1; r0 < n; r0 += 64) {
     __syncthreads();
-    double tr = 0.0, ti = 0.0;
-    for (int s = 0; s < 16; ++s) {
-      tr += sr[s][threadIdx.x & 15];
-      ti += si[s][threadIdx.x & 15];
+    for (int idx = threadIdx.x; idx < 64 * kWy; idx += 256) {
+      const int j = idx / 64, rr = idx % 64;
+      const int r = r0 + rr;
+      vs[rr][j] = (j < nb && r < n) ? vref(a, n, k0 + j, r) : make_double2(0.0, 0.0);
     }
-    tr *= tk;
-    ti *= tk;
-    if (active) {
-      for (int i = rs; i < m; i += 16) {
-        const double2 ui = u[i];
-        double *cr = c + (long)(k + 1 + i) * ldc + col;
-        cr[0] -= ui.x * tr - ui.y * ti;
-        cr[ld_e] -= ui.x * ti + ui.y * tr;
+    __syncthreads();
+    for (int q = 0; q < 2; ++q) {
+      if (pi[q] >= kWy - 1 || pj[q] >= kWy) continue;
+      for (int rr = 0; rr < 64; ++rr) {
+        const double2 x = vs[rr][pi[q]], y = vs[rr][pj[q]];
+        acc[q].x += x.x * y.x + x.y * y.y;   // conj(x) y
+        acc[q].y += x.x * y.y - x.y * y.x;
       }
     }
+  }
+  __syncthreads();
+  for (int q = 0; q < 2; ++q)
+    if (pi[q] < kWy - 1 && pj[q] < kWy) S[pi[q]][pj[q]] = acc[q];
+  for (int idx = threadIdx.x; idx < kWy * kWy; idx += 256)
+    T[idx / kWy][idx % kWy] = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    const double tj = tau[k0 + j];
+    double2 val = make_double2(0.0, 0.0);
+    const int i = threadIdx.x;
+    if (i < j) {
+      // -tau_j sum_{l=i}^{j-1} T[i][l] S[l][j]
+      for (int l = i; l < j; ++l) {
+        const double2 tl = T[i][l], sl = S[l][j];
+        val.x += tl.x * sl.x - tl.y * sl.y;
+        val.y += tl.x * sl.y + tl.y * sl.x;
+      }
+      val.x *= -tj;
+      val.y *= -tj;
+    }
+    __syncthreads();
+    if (i < j) T[i][j] = val;
+    if (i == j) T[j][j] = make_double2(tj, 0.0);
     __syncthreads();
   }
+  double2 *out = t_all + (long)b * kWy * kWy;
+  for (int idx = threadIdx.x; idx < kWy * kWy; idx += 256)
+    out[idx] = T[idx / kWy][idx % kWy];
+}
+
+// Partial W1 = V^H C over a chunk of rows: part[chunk][j][e].
+constexpr int kWyRows = 128;
+__global__ __launch_bounds__(256) void wy_vhc_kernel(const double2 *__restrict__ a,
+                                                     int n, int k0, int nb,
+                                                     const double *__restrict__ c,
+                                                     int ld_e, int n_eig,
+                                                     double2 *__restrict__ part) {
+  const int e = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int jg = threadIdx.x >> 6;           // 0..3, 8 reflectors each
+  const int chunk = blockIdx.y;
+  const int r0 = k0 + 1 + chunk * kWyRows;
+  const int r1 = min(n, r0 + kWyRows);
+  double2 acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
+  if (e < n_eig) {
+    for (int r = r0; r < r1; ++r) {
+      const double cr = c[(long)r * 2 * ld_e + e];
+      const double ci = c[(long)r * 2 * ld_e + ld_e + e];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int j = jg * 8 + q;
+        if (j < nb) {
+          const double2 v = vref(a, n, k0 + j, r);
+          acc[q].x += v.x * cr + v.y * ci;   // conj(v) c
+          acc[q].y += v.x * ci - v.y * cr;
+        }
+      }
+    }
+  }
+  double2 *p = part + (long)chunk * kWy * ld_e;
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    if (e < ld_e) p[(long)(jg * 8 + q) * ld_e + e] = acc[q];
+}
+
+// W2 = T (sum over chunks of the partials): w2[j][e].
+__global__ __launch_bounds__(256) void wy_tw_kernel(const double2 *__restrict__ part,
+                                                    int n_chunks,
+                                                    const double2 *__restrict__ t,
+                                                    int nb, int ld_e, int n_eig,
+                                                    double2 *__restrict__ w2) {
+  __shared__ double2 w1[kWy][64];
+  const int el = threadIdx.x & 63;
+  const int e = blockIdx.x * 64 + el;
+  const int jg = threadIdx.x >> 6;
+  for (int q = 0; q < 8; ++q) {
+    const int j = jg * 8 + q;
+    double2 s = make_double2(0.0, 0.0);
+    if (e < n_eig)
+      for (int ch = 0; ch < n_chunks; ++ch) {
+        const double2 v = part[((long)ch * kWy + j) * ld_e + e];
+        s.x += v.x;
+        s.y += v.y;
+      }
+    w1[j][el] = s;
+  }
+  __syncthreads();
+  for (int q = 0; q < 8; ++q) {
+    const int j = jg * 8 + q;
+    double2 s = make_double2(0.0, 0.0);
+    if (j < nb)
+      for (int l = j; l < nb; ++l) {
+        const double2 tv = t[j * kWy + l], x = w1[l][el];
+        s.x += tv.x * x.x - tv.y * x.y;
+        s.y += tv.x * x.y + tv.y * x.x;
+      }
+    if (e < ld_e) w2[(long)j * ld_e + e] = s;
+  }
+}
+
+// C[r][e] -= sum_j v_j[r] W2[j][e] for rows r > k0.
+__global__ __launch_bounds__(256) void wy_update_kernel(const double2 *__restrict__ a,
+                                                        int n, int k0, int nb,
+                                                        const double2 *__restrict__ w2,
+                                                        double *__restrict__ c,
+                                                        int ld_e, int n_eig) {
+  __shared__ double2 vs[4][kWy];
+  const int e = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int rl = threadIdx.x >> 6;
+  const int r = k0 + 1 + blockIdx.y * 4 + rl;
+  if (threadIdx.x < 4 * kWy) {
+    const int rr = threadIdx.x / kWy, j = threadIdx.x % kWy;
+    const int row = k0 + 1 + blockIdx.y * 4 + rr;
+    vs[rr][j] = (j < nb && row < n) ? vref(a, n, k0 + j, row) : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  if (r >= n || e >= n_eig) return;
+  double sr = 0.0, si = 0.0;
+  for (int j = 0; j < nb; ++j) {
+    const double2 v = vs[rl][j], w = w2[(long)j * ld_e + e];
+    sr += v.x * w.x - v.y * w.y;
+    si += v.x * w.y + v.y * w.x;
+  }
+  c[(long)r * 2 * ld_e + e] -= sr;
+  c[(long)r * 2 * ld_e + ld_e + e] -= si;
 }
 
 // B = 1.5 I - 0.5 G  (G interleaved n_eig x n_eig) into planar ld_e x ld_e
@@ -517,9 +649,34 @@ void eig_lowest(Context *ctx, const double *a_in, int n, int n_eig,
                      dim3((unsigned)std::min<long>((tot + 255) / 256, 65536)),
                      dim3(256), 0, s, q.z, ldz, (const double2 *)phase, n, n_eig,
                      basis, ld_e, rows_pad);
-  hipLaunchKernelGGL(apply_reflectors_kernel, dim3((n_eig + 15) / 16), dim3(256),
-                     0, s, (const double2 *)t.a, t.tau, n, basis, ld_e, n_eig);
-  SSRPA_HIP(hipGetLastError());
+  if (n > 1) {
+    const int nblk = (n - 1 + kWy - 1) / kWy;
+    const int max_chunks = (n + kWyRows - 1) / kWyRows;
+    DevBuf tw(ctx, sizeof(double2) * (size_t)nblk * kWy * kWy);
+    DevBuf part(ctx, sizeof(double2) * (size_t)max_chunks * kWy * ld_e);
+    DevBuf w2(ctx, sizeof(double2) * (size_t)kWy * ld_e);
+    hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(256), 0, s,
+                       (const double2 *)t.a, t.tau, n, tw.as<double2>());
+    const int ctiles = ld_e / 64;
+    for (int b = nblk - 1; b >= 0; --b) {
+      const int k0 = b * kWy;
+      const int nb = std::min(kWy, (n - 1) - k0);
+      const int rows = n - k0 - 1;
+      const int chunks = (rows + kWyRows - 1) / kWyRows;
+      hipLaunchKernelGGL(wy_vhc_kernel, dim3(ctiles, chunks), dim3(256), 0, s,
+                         (const double2 *)t.a, n, k0, nb, (const double *)basis,
+                         ld_e, n_eig, part.as<double2>());
+      hipLaunchKernelGGL(wy_tw_kernel, dim3(ctiles), dim3(256), 0, s,
+                         (const double2 *)part.as<double2>(), chunks,
+                         (const double2 *)tw.as<double2>() + (long)b * kWy * kWy,
+                         nb, ld_e, n_eig, w2.as<double2>());
+      hipLaunchKernelGGL(wy_update_kernel, dim3(ctiles, (rows + 3) / 4), dim3(256),
+                         0, s, (const double2 *)t.a, n, k0, nb,
+                         (const double2 *)w2.as<double2>(), basis, ld_e, n_eig);
+    }
+    SSRPA_HIP(hipGetLastError());
+    SSRPA_HIP(hipStreamSynchronize(s));
+  }
 
   // Newton-Schulz: C <- C (1.5 I - 0.5 C^H C)
   DevBuf gram(ctx, sizeof(double2) * (size_t)n_eig * n_eig);

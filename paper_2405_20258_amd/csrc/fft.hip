@@ -47,6 +47,32 @@ __device__ __forceinline__ double2 cmuli(double2 a) {
   return make_double2(-a.y, a.x);
 }
 
+// In-register radix-R DFT, y_k = sum_j v_j e^{+2 pi i jk / R}.
+template <int R>
+__device__ __forceinline__ void radix_dft(const double2 *v, double2 *y) {
+  if constexpr (R == 2) {
+    y[0] = cadd(v[0], v[1]);
+    y[1] = csub(v[0], v[1]);
+  } else if constexpr (R == 4) {
+    const double2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    const double2 s13 = cadd(v[1], v[3]), d13 = cmuli(csub(v[1], v[3]));
+    y[0] = cadd(s02, s13);
+    y[2] = csub(s02, s13);
+    y[1] = cadd(d02, d13);
+    y[3] = csub(d02, d13);
+  } else {  // R == 3, w = e^{2 pi i / 3}
+    const double c = -0.5;
+    const double sq = 0.86602540378443864676;  // sqrt(3)/2
+    const double2 t1 = cadd(v[1], v[2]);
+    const double2 t2 = csub(v[1], v[2]);
+    const double2 m = make_double2(v[0].x + c * t1.x, v[0].y + c * t1.y);
+    const double2 r = make_double2(-sq * t2.y, sq * t2.x);  // i sq t2
+    y[0] = cadd(v[0], t1);
+    y[1] = cadd(m, r);
+    y[2] = csub(m, r);
+  }
+}
+
 // One Stockham pass of radix R over `nlines` lines of length N (line stride
 // ls) from `in` to `out`; Ns = product of the radices of earlier passes.
 // X[k] = sum_j x[j] e^{+2 pi i jk / N}.
@@ -71,30 +97,73 @@ __device__ __forceinline__ void stockham_pass(const double2 *in, double2 *out,
       v[i] = cmul(v[i], tw[t]);
     }
     double2 y[R];
-    if constexpr (R == 2) {
-      y[0] = cadd(v[0], v[1]);
-      y[1] = csub(v[0], v[1]);
-    } else if constexpr (R == 4) {
-      const double2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
-      const double2 s13 = cadd(v[1], v[3]), d13 = cmuli(csub(v[1], v[3]));
-      y[0] = cadd(s02, s13);
-      y[2] = csub(s02, s13);
-      y[1] = cadd(d02, d13);
-      y[3] = csub(d02, d13);
-    } else {  // R == 3, w = e^{2 pi i / 3}
-      const double c = -0.5;
-      const double sq = 0.86602540378443864676;  // sqrt(3)/2
-      const double2 t1 = cadd(v[1], v[2]);
-      const double2 t2 = csub(v[1], v[2]);
-      const double2 m = make_double2(v[0].x + c * t1.x, v[0].y + c * t1.y);
-      const double2 r = make_double2(-sq * t2.y, sq * t2.x);  // i sq t2
-      y[0] = cadd(v[0], t1);
-      y[1] = cadd(m, r);
-      y[2] = csub(m, r);
-    }
+    radix_dft<R>(v, y);
     double2 *dst = out + line * ls + (j / Ns) * Ns * R + k;
 #pragma unroll
     for (int i = 0; i < R; ++i) dst[i * Ns] = y[i];
+  }
+}
+
+// Compile-time radix schedule (4s, then 2s, then 3s) of a length N.
+template <int N>
+struct Plan {
+  static constexpr int count() {
+    int m = N, c = 0;
+    while (m % 4 == 0) { m /= 4; ++c; }
+    while (m % 2 == 0) { m /= 2; ++c; }
+    while (m % 3 == 0) { m /= 3; ++c; }
+    return c;
+  }
+  static constexpr int radix(int s) {
+    int m = N, c = 0;
+    while (m % 4 == 0) { if (c == s) return 4; m /= 4; ++c; }
+    while (m % 2 == 0) { if (c == s) return 2; m /= 2; ++c; }
+    while (m % 3 == 0) { if (c == s) return 3; m /= 3; ++c; }
+    return 1;
+  }
+  static constexpr int ns(int s) {
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= radix(i);
+    return p;
+  }
+};
+
+// The same pass with N, R and Ns known at compile time (line stride N), so
+// the index arithmetic reduces to shifts and multiplications.
+template <int N, int R, int NS>
+__device__ __forceinline__ void stockham_pass_t(const double2 *in, double2 *out,
+                                                int nlines, const double2 *tw) {
+  constexpr int nb = N / R;
+  constexpr int stride = N / (NS * R);
+  const int total = nlines * nb;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int line = idx / nb;
+    const int j = idx - line * nb;
+    const int k = j % NS;
+    const double2 *src = in + line * N + j;
+    double2 v[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = src[i * nb];
+#pragma unroll
+    for (int i = 1; i < R; ++i) v[i] = cmul(v[i], tw[(k * i * stride) % N]);
+    double2 y[R];
+    radix_dft<R>(v, y);
+    double2 *dst = out + line * N + (j / NS) * NS * R + k;
+#pragma unroll
+    for (int i = 0; i < R; ++i) dst[i * NS] = y[i];
+  }
+}
+
+template <int N, int S = 0>
+__device__ __forceinline__ double2 *lds_fft_t(double2 *a, double2 *b, int nlines,
+                                              const double2 *tw) {
+  if constexpr (S == Plan<N>::count()) {
+    __syncthreads();
+    return a;
+  } else {
+    __syncthreads();
+    stockham_pass_t<N, Plan<N>::radix(S), Plan<N>::ns(S)>(a, b, nlines, tw);
+    return lds_fft_t<N, S + 1>(b, a, nlines, tw);
   }
 }
 
@@ -209,14 +278,15 @@ struct PairGeo {
 // plane, x transforms (in batches of lx lines) pruned to |n1| <= m1, y
 // transforms of those columns, then the z sum for the chi0 G vectors is
 // accumulated in registers: acc(G) += Y(n1, n2; j3) e^{2 pi i n3 j3 / N3}.
-template <int GPT>
+template <int GPT, int N>
 __global__ __launch_bounds__(kPairThreads) void pair_fft_kernel(
     const double2 *__restrict__ psi, PairGeo geo, int v0, int nvb, int n_v,
     int n_c, const int *__restrict__ gcol, const double *__restrict__ gscale,
     int n_g, int ld_g, const double2 *__restrict__ tw_g,
     double *__restrict__ w) {
   extern __shared__ double2 smem[];
-  const int n1 = geo.n1, n2 = geo.n2, n3 = geo.n3, m1 = geo.m1, lx = geo.lx;
+  const int n1 = N > 0 ? N : geo.n1, n2 = N > 0 ? N : geo.n2;
+  const int n3 = geo.n3, m1 = geo.m1, lx = geo.lx;
   const int ny = 2 * m1 + 1;
   double2 *tw1 = smem;
   double2 *tw2 = tw1 + n1;
@@ -224,6 +294,7 @@ __global__ __launch_bounds__(kPairThreads) void pair_fft_kernel(
   double2 *xa = tw3 + n3;          // lx * n1  (also y ping-pong buffer)
   double2 *xb = xa + lx * n1;      // lx * n1
   double2 *yb = xb + lx * n1;      // ny * n2
+  double2 *pz = yb + ny * n2;      // n3: e^{2 pi i k3 j3 / N3} of this plane
   for (int t = threadIdx.x; t < n1 + n2 + n3; t += blockDim.x) smem[t] = tw_g[t];
 
   // pair of this block: tiles of kTileV valence x kTileC conduction bands
@@ -253,13 +324,19 @@ __global__ __launch_bounds__(kPairThreads) void pair_fft_kernel(
     for (int g0 = 0; g0 < n2; g0 += lx) {
       const int nl = min(lx, n2 - g0);
       __syncthreads();
+      if (g0 == 0)
+        for (int t = threadIdx.x; t < n3; t += blockDim.x) pz[t] = tw3[(t * j3) % n3];
       for (int idx = threadIdx.x; idx < nl * n1; idx += blockDim.x) {
         const double2 a = sv[(long)g0 * n1 + idx];
         const double2 b = sc[(long)g0 * n1 + idx];
         // conj(a) * b
         xa[idx] = make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
       }
-      const double2 *r = lds_fft(xa, xb, nl, n1, n1, geo.r1, tw1);
+      const double2 *r;
+      if constexpr (N > 0)
+        r = lds_fft_t<N>(xa, xb, nl, tw1);
+      else
+        r = lds_fft(xa, xb, nl, n1, n1, geo.r1, tw1);
       for (int idx = threadIdx.x; idx < nl * ny; idx += blockDim.x) {
         const int line = idx / ny, qq = idx - line * ny;
         int k1 = qq - m1;
@@ -267,7 +344,11 @@ __global__ __launch_bounds__(kPairThreads) void pair_fft_kernel(
         yb[qq * n2 + g0 + line] = r[line * n1 + k1];
       }
     }
-    const double2 *ry = lds_fft(yb, xa, ny, n2, n2, geo.r2, tw2);
+    const double2 *ry;
+    if constexpr (N > 0)
+      ry = lds_fft_t<N>(yb, xa, ny, tw2);
+    else
+      ry = lds_fft(yb, xa, ny, n2, n2, geo.r2, tw2);
 #pragma unroll
     for (int i = 0; i < GPT; ++i) {
       const int g = threadIdx.x + i * kPairThreads;
@@ -275,7 +356,7 @@ __global__ __launch_bounds__(kPairThreads) void pair_fft_kernel(
         const int col = code[i] & 0xFFFFF;
         const int k3 = code[i] >> 20;
         const double2 val = ry[col];
-        const double2 t = tw3[(k3 * j3) % n3];
+        const double2 t = pz[k3];
         acc[i].x += val.x * t.x - val.y * t.y;
         acc[i].y += val.x * t.y + val.y * t.x;
       }
@@ -354,7 +435,7 @@ void launch_pair_matrix(System &sys, int v0, int nvb, bool scaled, double *w,
   pg.lx = std::max(16, (ny * g.n2 + 2 * g.n1 - 1) / (2 * g.n1));
   pg.lx = std::min(pg.lx, g.n2);
   if (2 * pg.lx * g.n1 < ny * g.n2) pg.lx = g.n2;  // y ping-pong must fit
-  const size_t shmem = sizeof(double2) * (g.n1 + g.n2 + g.n3 +
+  const size_t shmem = sizeof(double2) * (g.n1 + g.n2 + 2 * g.n3 +
                                           2 * pg.lx * g.n1 + ny * g.n2);
   SSRPA_REQUIRE(shmem <= 160 * 1024, SSRPA_ERR_ARG,
                 "pair FFT needs %zu bytes of LDS", shmem);
@@ -368,15 +449,27 @@ void launch_pair_matrix(System &sys, int v0, int nvb, bool scaled, double *w,
   const double2 *psi = sys.psi_r.as<double2>();
   const int *gcol = sys.gcol.as<int>();
   const double2 *tw = sys.fft_tw.as<double2>();
-#define SSRPA_PAIR(G)                                                        \
+#define SSRPA_PAIR_N(G, NN)                                                  \
   do {                                                                       \
     if (shmem > 64 * 1024)                                                   \
       SSRPA_HIP(hipFuncSetAttribute(                                         \
-          reinterpret_cast<const void *>(&pair_fft_kernel<G>),               \
+          reinterpret_cast<const void *>(&pair_fft_kernel<G, NN>),           \
           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));          \
-    hipLaunchKernelGGL(pair_fft_kernel<G>, dim3((unsigned)blocks),          \
+    hipLaunchKernelGGL((pair_fft_kernel<G, NN>), dim3((unsigned)blocks),     \
                        dim3(kPairThreads), shmem, s, psi, pg, v0, nvb,       \
                        sys.n_v, sys.n_c, gcol, gscale, g.n_g, g.ld_g, tw, w); \
+  } while (0)
+  // grid lengths with a compile-time schedule (x = y); others run generic
+#define SSRPA_PAIR(G)                                                        \
+  do {                                                                       \
+    const int nn = g.n1 == g.n2 ? g.n1 : 0;                                  \
+    if (nn == 24) SSRPA_PAIR_N(G, 24);                                       \
+    else if (nn == 32) SSRPA_PAIR_N(G, 32);                                  \
+    else if (nn == 36) SSRPA_PAIR_N(G, 36);                                  \
+    else if (nn == 48) SSRPA_PAIR_N(G, 48);                                  \
+    else if (nn == 64) SSRPA_PAIR_N(G, 64);                                  \
+    else if (nn == 72) SSRPA_PAIR_N(G, 72);                                  \
+    else SSRPA_PAIR_N(G, 0);                                                 \
   } while (0)
   if (gpt <= 2) SSRPA_PAIR(2);
   else if (gpt <= 4) SSRPA_PAIR(4);
@@ -386,6 +479,7 @@ void launch_pair_matrix(System &sys, int v0, int nvb, bool scaled, double *w,
   else if (gpt <= 64) SSRPA_PAIR(64);
   else fail(SSRPA_ERR_ARG, "chi0 basis of %d vectors is too large", g.n_g);
 #undef SSRPA_PAIR
+#undef SSRPA_PAIR_N
   SSRPA_HIP(hipGetLastError());
 }
 

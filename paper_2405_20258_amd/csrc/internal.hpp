@@ -249,3 +249,7 @@ void copy_interleaved(const double *src, double *dst, size_t n_complex,
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
 }  // namespace ssrpa
+
+// The opaque handles of the C ABI are the runtime objects themselves.
+struct ssrpa_context : ssrpa::Context {};
+struct ssrpa_system : ssrpa::System {};

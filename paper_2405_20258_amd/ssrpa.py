@@ -96,6 +96,19 @@ ssrpa_correlation_energy_enqueue = _sig(
 ssrpa_ticket_query = _sig("ssrpa_ticket_query", _i, [_p, _ip])
 ssrpa_ticket_wait = _sig("ssrpa_ticket_wait", _i, [_p, _dp, _dp])
 
+ssrpa_server_create = _sig("ssrpa_server_create", _i,
+                           [_p, _i, _d, ctypes.POINTER(_p)])
+ssrpa_server_submit = _sig("ssrpa_server_submit", _i,
+                           [_p, ctypes.POINTER(ssrpa_system_desc), _i, _i, _dp,
+                            _dp, _i, ctypes.POINTER(ctypes.c_uint64)])
+ssrpa_server_poll = _sig("ssrpa_server_poll", _i,
+                         [_p, ctypes.c_uint64, _ip, _ip, _dp, _dp, _dp, _dp])
+ssrpa_server_drain = _sig("ssrpa_server_drain", _i, [_p])
+ssrpa_server_memory = _sig("ssrpa_server_memory", _i,
+                           [_p, ctypes.POINTER(_sz), ctypes.POINTER(_sz)])
+ssrpa_server_destroy = _sig("ssrpa_server_destroy", _i, [_p])
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = range(4)
+
 EXPORTED = [n for n in dir() if n.startswith("ssrpa_") and
             n != "ssrpa_system_desc"]
 
@@ -331,3 +344,60 @@ class Ticket:
         self.handle = None
         _check(st)
         return ec.value, f
+
+
+class Server:
+    """Request loop over a context: admission by HBM footprint, overlapping
+    solves on separate streams (ssrpa_server_* in the C ABI)."""
+
+    def __init__(self, ctx: Context, max_running: int = 4,
+                 max_bypass_s: float = 2.0):
+        h = _p()
+        _check(ssrpa_server_create(ctx.handle, max_running, max_bypass_s,
+                                   ctypes.byref(h)), ctx.handle)
+        self.handle = h
+        self.ctx = ctx
+
+    def submit(self, s, n_eig: int, omega, weight, precision="fp64") -> int:
+        """Queue a synthetic system `s` (host arrays); returns the request id."""
+        keep = []
+        d = make_desc(s.a, s.fft, s.miller, s.coeff, s.energy, s.n_v,
+                      s.ecut_chi, keep)
+        om = np.ascontiguousarray(omega, dtype=np.float64)
+        wt = np.ascontiguousarray(weight, dtype=np.float64)
+        rid = ctypes.c_uint64()
+        _check(ssrpa_server_submit(self.handle, ctypes.byref(d), n_eig,
+                                   len(om), _dptr(om), _dptr(wt),
+                                   PRECISIONS[precision], ctypes.byref(rid)),
+               self.ctx.handle)
+        return rid.value
+
+    def poll(self, rid: int) -> dict:
+        st, status = ctypes.c_int(), ctypes.c_int()
+        ec, t0, t1, t2 = (ctypes.c_double() for _ in range(4))
+        _check(ssrpa_server_poll(self.handle, rid, ctypes.byref(st),
+                                 ctypes.byref(status), ctypes.byref(ec),
+                                 ctypes.byref(t0), ctypes.byref(t1),
+                                 ctypes.byref(t2)))
+        return dict(state=st.value, status=status.value, ec=ec.value,
+                    t_submit=t0.value, t_start=t1.value, t_done=t2.value)
+
+    def drain(self):
+        _check(ssrpa_server_drain(self.handle))
+
+    def memory(self):
+        a, b = _sz(), _sz()
+        _check(ssrpa_server_memory(self.handle, ctypes.byref(a),
+                                   ctypes.byref(b)))
+        return a.value, b.value
+
+    def close(self):
+        if self.handle:
+            ssrpa_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

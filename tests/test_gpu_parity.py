@@ -348,7 +348,52 @@ def test_medium_workload_against_golden(env):
     rel = abs(ec - r["ec"]) / abs(r["ec"])
     _log(f"medium n_eig=400: E_c {ec!r} golden {r['ec']!r} rel {rel:.2e}")
     assert rel < 1e-10
+    if "full" in gold["results"]:
+        rf = gold["results"]["full"]
+        _log("medium workload: full RPA (N_eig = N_G)")
+        ec, f = g.correlation_energy(ng, om, wt)
+        rel = abs(ec - rf["ec"]) / abs(rf["ec"])
+        _log(f"medium full: E_c {ec!r} golden {rf['ec']!r} rel {rel:.2e}")
+        assert rel < 1e-10
     g.close()
+
+
+@pytest.mark.timeout(300)
+def test_medium_mixed_precision_sweep():
+    """Mixed precision on the medium inputs: BF16x3 contractions (FP64
+    eigensolver and log-dets) at N_eig = 198, 400, 792 (5/10/20% of N_G).
+    Error against the FP64 oracle at the same N_eig <= 1e-5 relative; the
+    error against FP64 full RPA (which includes the subspace truncation) is
+    reported."""
+    import torch
+    from paper_2405_20258_amd import ssrpa
+    from synth import systems as sy
+    path = os.path.join(HERE, "golden", "medium.json")
+    if not os.path.exists(path):
+        pytest.skip("medium golden values not generated")
+    gold = json.load(open(path))
+    need = ["n_eig_198", "n_eig_400", "n_eig_792", "full"]
+    if not all(k in gold["results"] for k in need):
+        pytest.skip("medium golden values incomplete")
+    s = sy.make_system(sy.MEDIUM, gold["seed"])
+    om, wt = sy.frequency_grid(gold["n_freq"])
+    ctx = ssrpa.Context(0)
+    g = ssrpa.System.from_synthetic(ctx, s)
+    full = gold["results"]["full"]["ec"]
+    for prec in ("bf16x3", "fp32"):
+        _log(f"medium {prec}: chi0")
+        g.chi0_static(prec)
+        for key in ("n_eig_198", "n_eig_400", "n_eig_792"):
+            r = gold["results"][key]
+            g.subspace(r["n_eig"])
+            ec, f = g.correlation_energy(r["n_eig"], om, wt, prec)
+            dprec = abs(ec - r["ec"]) / abs(r["ec"])
+            dtot = abs(ec - full) / abs(full)
+            _log(f"medium {prec} n_eig={r['n_eig']}: E_c {ec!r} "
+                 f"|dE_prec| {dprec:.2e} |dE_total| {dtot:.2e}")
+            assert dprec < 1e-5
+    g.close()
+    ctx.close()
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
