@@ -30,6 +30,9 @@ METRIC = ("χ0 GEMM TFLOP/s + time-to-E_c per system; p50/p99 E_c "
           "latency, mixed stream")
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
+HERK_KERNEL = {"fp64": "herk_f64_pipe_kernel (static chi0)",
+               "fp32": "herk_f32_kernel (static chi0)",
+               "bf16x3": "herk_bf16x3_kernel (static chi0)"}
 
 
 def parse():
@@ -46,6 +49,19 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-bands", type=int, default=4,
                     help="valence bands in the oracle's timed sample")
+    ap.add_argument("--serve", action="store_true",
+                    help="also replay the mixed serving stream (64 requests, "
+                         "Poisson 4/s) and report p50/p99 latency")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-rate", type=float, default=4.0)
+    ap.add_argument("--serve-max-running", type=int, default=4)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB "
+                         "(reference dispatch for the FETCH_SIZE/WRITE_SIZE "
+                         "counter scale)")
+    ap.add_argument("--traffic-json", default="",
+                    help="counter summary (profiles/*.json) whose scaled "
+                         "FETCH+WRITE bytes per launch fill roofline.traffic")
     return ap.parse_args()
 
 
@@ -80,6 +96,47 @@ def cpu_baseline(s, n_vb):
             "host_cpus": os.cpu_count()}
 
 
+def serve_stream(ssrpa, ctx, n_req, rate, max_running):
+    """Replay the Poisson request stream through the native server."""
+    import numpy as np
+    from synth import systems as sy
+    reqs = sy.serving_stream(n_req, rate)
+    print(f"# generating {n_req} serving systems", file=sys.stderr, flush=True)
+    systems = []
+    for r in reqs:
+        s, n_eig = sy.serving_system(r, qr="torch")
+        systems.append((r, s, n_eig))
+    om, wt = ssrpa.frequency_grid(16)
+    srv = ssrpa.Server(ctx, max_running=max_running, max_bypass_s=2.0)
+    ids = []
+    t0 = time.perf_counter()
+    for k in range(len(systems)):
+        r, s, n_eig = systems[k]
+        systems[k] = None          # the server keeps its own copy
+        delay = r["arrival"] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        ids.append((r, srv.submit(s, n_eig, om, wt, r["precision"])))
+        del s
+    srv.drain()
+    res = [(r, srv.poll(i)) for r, i in ids]
+    reserved_peak, high = srv.memory()
+    srv.close()
+    lat = np.array([p["t_done"] - p["t_submit"] for _, p in res])
+    ok = sum(p["state"] == ssrpa.REQ_DONE for _, p in res)
+    span = max(p["t_done"] for _, p in res) - min(p["t_submit"] for _, p in res)
+    return {"requests": n_req, "completed": int(ok),
+            "arrival_rate_per_s": rate, "max_running": max_running,
+            "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
+            "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
+            "systems_per_s": round(n_req / span, 3),
+            "makespan_s": round(span, 3),
+            "reserved_peak_gb": round(reserved_peak / 1e9, 2),
+            "hbm_high_water_gb": round(high / 1e9, 2),
+            "mix": {"fp64": sum(r["precision"] == "fp64" for r, _ in res),
+                    "bf16x3": sum(r["precision"] == "bf16x3" for r, _ in res)}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -100,7 +157,9 @@ def main():
     prec = args.precision
     print(f"# generating {spec.name} (seed {seed})", file=sys.stderr,
           flush=True)
-    s = sy.make_system(spec, seed)
+    # the large share's 40651 x 8704 orthonormalization runs on the GPU
+    s = sy.make_system(spec, seed, qr="torch" if args.workload == "large"
+                       else "numpy")
     om, wt = ssrpa.frequency_grid(spec.n_freq)
     coeff_d = torch.from_numpy(s.coeff).to("cuda")   # inputs resident in HBM
     torch.cuda.synchronize()
@@ -167,10 +226,27 @@ def main():
                      "peak": PEAK[prec], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK[prec], 4),
                      "traffic": None,
-                     "kernel": "herk_f64_kernel (static chi0)",
+                     "kernel": HERK_KERNEL[prec],
                      "flops_per_launch": per_launch_flops,
                      "avg_launch_ms": round(avg_launch_s * 1e3, 4)},
     }
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 2 * n * 8
+        del src, dst
+    if args.traffic_json and os.path.exists(args.traffic_json):
+        tj = json.load(open(args.traffic_json))
+        if tj.get("kernel_signature") == out["roofline"]["kernel"]:
+            out["roofline"]["traffic"] = tj["bytes_per_launch"]
+            out["roofline"]["traffic_note"] = tj.get("note", "")
+    if args.serve:
+        out["serving"] = serve_stream(ssrpa, ctx, args.serve_requests,
+                                      args.serve_rate, args.serve_max_running)
     if not args.no_cpu_baseline:
         print("# timing the oracle on a bounded sample", file=sys.stderr,
               flush=True)

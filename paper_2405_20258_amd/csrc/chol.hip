@@ -8,6 +8,12 @@
 // so a Cholesky factor is used: ln det = sum_k ln p_k with p_k the pivots of
 // the outer-product elimination B <- B - b_k b_k^H / p_k.
 // Then E_c = (1/2 pi) sum_j w_j F_j  (Eq. 1).
+//
+// At high frequency X_j is small, the pivots are 1 + O(|X|) and ln det and
+// l Tr X cancel to second order.  The elimination therefore works on
+// B - I: the diagonal holds delta_k = p_k - 1 without the rounding of
+// 1 + delta, and F = sum_k [log1p(delta_k) + l X_kk], whose terms are each
+// accurate to rounding of their own size.
 #include <cmath>
 
 #include "internal.hpp"
@@ -16,32 +22,32 @@ namespace ssrpa {
 
 namespace {
 
-// B_j = I - c X_j   (interleaved n x n per matrix)
+// D_j = B_j - I = -c X_j   (interleaved n x n per matrix)
 __global__ void build_b_kernel(const double *__restrict__ x, double c, int n,
                                long n_mat, double *__restrict__ b) {
   const long per = (long)n * n;
   const long total = per * n_mat;
   for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
        idx += (long)gridDim.x * blockDim.x) {
-    const long e = idx % per;
-    const int r = (int)(e / n), cc = (int)(e % n);
-    b[2 * idx] = (r == cc ? 1.0 : 0.0) - c * x[2 * idx];
+    b[2 * idx] = -c * x[2 * idx];
     b[2 * idx + 1] = -c * x[2 * idx + 1];
   }
 }
 
-// One elimination step k for every matrix: B[i][j] -= conj(B[k][i]) B[k][j] /
-// B[k][k] for k < i, j (upper form, row k holds the pivot row).  Block
-// (tile, matrix); block 0 of each matrix records the pivot.
+// One elimination step k for every matrix on D = B - I:
+// D[i][j] -= conj(D[k][i]) D[k][j] / (1 + D[k][k]) for k < i <= j (upper
+// form, row k holds the pivot row; off the diagonal D and B agree).  Block
+// (tile, matrix); block 0 of each matrix records delta_k = D[k][k].
 __global__ __launch_bounds__(256) void chol_step_kernel(double *__restrict__ b,
                                                         int n, int k,
                                                         double *__restrict__ piv,
                                                         int *__restrict__ flag) {
   const int j_mat = blockIdx.y;
   double2 *B = reinterpret_cast<double2 *>(b) + (long)j_mat * n * n;
-  const double p = B[(long)k * n + k].x;
+  const double dk = B[(long)k * n + k].x;
+  const double p = 1.0 + dk;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    piv[(long)j_mat * n + k] = p;
+    piv[(long)j_mat * n + k] = dk;
     if (!(p > 0.0)) *flag = 1;  // every writer stores the same value
   }
   const int m = n - k - 1;
@@ -70,22 +76,17 @@ __global__ void logdet_finish_kernel(const double *__restrict__ piv,
                                      int n, int n_mat, double *__restrict__ f) {
   const int j = blockIdx.x;
   if (j >= n_mat) return;
-  __shared__ double red[2][256];
-  double ld = 0.0, tr = 0.0;
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    ld += log(piv[(long)j * n + k]);
-    tr += x[2 * ((long)j * n * n + (long)k * n + k)];
-  }
-  red[0][threadIdx.x] = ld;
-  red[1][threadIdx.x] = tr;
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x)
+    // log(1 + delta_k) + c X_kk, with delta_k = p_k - 1 carried exactly
+    acc += log1p(piv[(long)j * n + k]) + c * x[2 * ((long)j * n * n + (long)k * n + k)];
+  red[threadIdx.x] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double a = 0.0, t = 0.0;
-    for (int i = 0; i < (int)blockDim.x; ++i) {
-      a += red[0][i];
-      t += red[1][i];
-    }
-    f[j] = a + c * t;
+    double a = 0.0;
+    for (int i = 0; i < (int)blockDim.x; ++i) a += red[i];
+    f[j] = a;
   }
 }
 

@@ -165,6 +165,116 @@ __global__ __launch_bounds__(256) void hh_her2_kernel(TriWork t, int n, int k) {
   *x = v;
 }
 
+// Fused reduction step, part A (one block).  Finishes step k-1
+// (w_{k-1} = p - (tau/2)(u^H p) u), applies the pending rank-two update of
+// step k-1 to row k, and builds reflector k from that row.
+__global__ __launch_bounds__(1024) void hh_step_a_kernel(TriWork t, int n, int k) {
+  __shared__ double red[16];
+  const int m = n - k - 1;
+  double2 *row = t.a + (long)k * n + k;       // row k from the diagonal on
+  if (k > 0) {
+    const int mp = m + 1;                      // length of step k-1 vectors
+    const double taup = t.tau[k - 1];
+    const double2 *up = t.a + (long)(k - 1) * n + k;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < mp; i += blockDim.x) s += cmulc(up[i], t.p[i]).x;
+    const double K = 0.5 * taup * block_sum(s, red);
+    for (int i = threadIdx.x; i < mp; i += blockDim.x) {
+      const double2 pi = t.p[i], ui = up[i];
+      t.w[i] = make_double2(pi.x - K * ui.x, pi.y - K * ui.y);
+    }
+    __syncthreads();
+    if (taup != 0.0) {
+      const double2 u0 = up[0], w0 = t.w[0];
+      for (int j = threadIdx.x; j < mp; j += blockDim.x) {
+        const double2 a = cmulc(t.w[j], u0);   // u_k conj(w_j)
+        const double2 b = cmulc(up[j], w0);    // w_k conj(u_j)
+        double2 v = row[j];
+        v.x -= a.x + b.x;
+        v.y -= a.y + b.y;
+        row[j] = v;
+      }
+    }
+    __syncthreads();
+  }
+  double2 *x = row + 1;                        // conj of column k below diag
+  double s = 0.0;
+  for (int i = threadIdx.x + 1; i < m; i += blockDim.x) {
+    const double2 v = x[i];
+    s += v.x * v.x + v.y * v.y;
+  }
+  const double rest = block_sum(s, red);
+  const double2 a0c = x[0];
+  const double2 x0 = make_double2(a0c.x, -a0c.y);
+  const double ax0 = hypot(x0.x, x0.y);
+  const double nrm2 = rest + ax0 * ax0;
+  __syncthreads();
+  if (m == 1 || rest == 0.0) {
+    if (threadIdx.x == 0) {
+      t.tau[k] = 0.0;
+      t.e[k] = x0;
+      t.d[k] = row[0].x;
+    }
+    return;
+  }
+  const double nrm = sqrt(nrm2);
+  const double2 ph = ax0 > 0.0 ? make_double2(x0.x / ax0, x0.y / ax0)
+                               : make_double2(1.0, 0.0);
+  const double2 beta = make_double2(-ph.x * nrm, -ph.y * nrm);
+  const double tau = 1.0 / (nrm * (nrm + ax0));
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const double2 v = x[i];
+    double2 u = make_double2(v.x, -v.y);
+    if (i == 0) u = make_double2(x0.x - beta.x, x0.y - beta.y);
+    x[i] = u;
+  }
+  if (threadIdx.x == 0) {
+    t.tau[k] = tau;
+    t.e[k] = beta;
+    t.d[k] = row[0].x;
+  }
+}
+
+// Fused reduction step, part B (one wave per trailing row i > k): apply the
+// pending rank-two update of step k-1 to the row and, in the same pass,
+// p_i = tau_k sum_j A[i][j] u_k[j].  One read and one write of the trailing
+// matrix per step.
+__global__ __launch_bounds__(256) void hh_step_b_kernel(TriWork t, int n, int k) {
+  const int m = n - k - 1;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= m) return;
+  const double tau = t.tau[k];
+  const double2 *u = t.a + (long)k * n + k + 1;
+  double2 *ar = t.a + (long)(k + 1 + i) * n + k + 1;
+  const bool pend = k > 0 && t.tau[k - 1] != 0.0;
+  // step k-1 vectors start at index k: offset 1 for row/col k+1+i
+  const double2 *up = t.a + (long)(k - 1) * n + k + 1;
+  const double2 *wp = t.w + 1;
+  double2 ui = make_double2(0.0, 0.0), wi = make_double2(0.0, 0.0);
+  if (pend) {
+    ui = up[i];
+    wi = wp[i];
+  }
+  double sr = 0.0, si = 0.0;
+  for (int j = lane; j < m; j += 64) {
+    double2 a = ar[j];
+    if (pend) {
+      const double2 x = cmulc(wp[j], ui);   // u_i conj(w_j)
+      const double2 y = cmulc(up[j], wi);   // w_i conj(u_j)
+      a.x -= x.x + y.x;
+      a.y -= x.y + y.y;
+      ar[j] = a;
+    }
+    const double2 b = u[j];
+    sr += a.x * b.x - a.y * b.y;
+    si += a.x * b.y + a.y * b.x;
+  }
+  sr = wave_sum(sr);
+  si = wave_sum(si);
+  if (lane == 0) t.p[i] = make_double2(tau * sr, tau * si);
+}
+
 __global__ void hh_last_kernel(TriWork t, int n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) t.d[n - 1] = t.a[(long)(n - 1) * n + n - 1].x;
 }
@@ -598,14 +708,9 @@ void eig_lowest(Context *ctx, const double *a_in, int n, int n_eig,
   double2 *phase = t.w + n;
   for (int k = 0; k < n - 1; ++k) {
     const int m = n - k - 1;
-    hipLaunchKernelGGL(hh_make_kernel, dim3(1), dim3(256), 0, s, t, n, k);
-    if (m > 1) {
-      hipLaunchKernelGGL(hh_hemv_kernel, dim3((m + 3) / 4), dim3(256), 0, s, t,
-                         n, k);
-      hipLaunchKernelGGL(hh_w_kernel, dim3(1), dim3(256), 0, s, t, n, k);
-      hipLaunchKernelGGL(hh_her2_kernel, dim3((m + 255) / 256, m), dim3(256), 0,
-                         s, t, n, k);
-    }
+    hipLaunchKernelGGL(hh_step_a_kernel, dim3(1), dim3(1024), 0, s, t, n, k);
+    hipLaunchKernelGGL(hh_step_b_kernel, dim3((m + 3) / 4), dim3(256), 0, s, t,
+                       n, k);
   }
   hipLaunchKernelGGL(hh_last_kernel, dim3(1), dim3(64), 0, s, t, n);
   SSRPA_HIP(hipGetLastError());

@@ -108,6 +108,7 @@ __device__ __forceinline__ void stockham_pass(const double2 *in, double2 *out,
 template <int N>
 struct Plan {
   static constexpr int count() {
+    if (N <= 0) return 0;
     int m = N, c = 0;
     while (m % 4 == 0) { m /= 4; ++c; }
     while (m % 2 == 0) { m /= 2; ++c; }
@@ -115,6 +116,7 @@ struct Plan {
     return c;
   }
   static constexpr int radix(int s) {
+    if (N <= 0) return 1;
     int m = N, c = 0;
     while (m % 4 == 0) { if (c == s) return 4; m /= 4; ++c; }
     while (m % 2 == 0) { if (c == s) return 2; m /= 2; ++c; }
@@ -378,6 +380,181 @@ __global__ __launch_bounds__(kPairThreads) void pair_fft_kernel(
   }
 }
 
+// ---------------------------------------------- wave-synchronous pair FFT
+
+// LDS ordering between lanes of one wave: a wavefront-scope fence pair
+// around a wave barrier (no block-wide barrier needed).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Stockham pass executed by the 64 lanes of one wave (line stride N).
+template <int N, int R, int NS>
+__device__ __forceinline__ void stockham_pass_wave(const double2 *in, double2 *out,
+                                                   int nlines, const double2 *tw,
+                                                   int lane) {
+  constexpr int nb = N / R;
+  constexpr int stride = N / (NS * R);
+  const int total = nlines * nb;
+  for (int idx = lane; idx < total; idx += 64) {
+    const int line = idx / nb;
+    const int j = idx - line * nb;
+    const int k = j % NS;
+    const double2 *src = in + line * N + j;
+    double2 v[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = src[i * nb];
+#pragma unroll
+    for (int i = 1; i < R; ++i) v[i] = cmul(v[i], tw[(k * i * stride) % N]);
+    double2 y[R];
+    radix_dft<R>(v, y);
+    double2 *dst = out + line * N + (j / NS) * NS * R + k;
+#pragma unroll
+    for (int i = 0; i < R; ++i) dst[i * NS] = y[i];
+  }
+}
+
+// Whole transform of `nlines` lines by one wave: pass 0 reads `in0`, the
+// last pass writes `outF`, passes in between alternate between bufA (after
+// even passes) and bufB (after odd passes).  outF must differ from the
+// source of the last pass.
+template <int N, int S>
+__device__ __forceinline__ void wave_fft(const double2 *in0, double2 *bufA,
+                                         double2 *bufB, double2 *outF,
+                                         int nlines, const double2 *tw, int lane) {
+  constexpr int C = Plan<N>::count();
+  const double2 *src = S == 0 ? in0 : ((S - 1) % 2 == 0 ? bufA : bufB);
+  double2 *dst = S == C - 1 ? outF : (S % 2 == 0 ? bufA : bufB);
+  stockham_pass_wave<N, Plan<N>::radix(S), Plan<N>::ns(S)>(src, dst, nlines, tw,
+                                                          lane);
+  wave_lds_sync();
+  if constexpr (S + 1 < C) wave_fft<N, S + 1>(in0, bufA, bufB, outF, nlines, tw, lane);
+}
+
+// buffer that is not the source of the last pass of wave_fft<N>
+template <int N>
+__device__ __forceinline__ double2 *wave_fft_out(double2 *in0, double2 *bufA,
+                                                 double2 *bufB, double2 *spare) {
+  constexpr int C = Plan<N>::count();
+  if constexpr (C == 1) return bufA;
+  const double2 *last_src = (C - 2) % 2 == 0 ? bufA : bufB;
+  if (last_src == bufA) return bufB == in0 ? spare : bufB;
+  return bufA == in0 ? spare : bufA;
+}
+
+template <int N>
+constexpr int wave_lines() { return N <= 24 ? 8 : 4; }
+
+// Same result as pair_fft_kernel for N1 = N2 = N: per z-plane, each wave
+// transforms its own batches of x lines (private LDS, wave-level ordering
+// only), writes the |n1| <= m1 outputs to a shared buffer, then the waves
+// transform the y lines the same way; two block barriers per plane.
+template <int GPT, int N>
+__global__ __launch_bounds__(kPairThreads) void pair_fft_wave_kernel(
+    const double2 *__restrict__ psi, PairGeo geo, int v0, int nvb, int n_v,
+    int n_c, const int *__restrict__ gcol, const double *__restrict__ gscale,
+    int n_g, int ld_g, const double2 *__restrict__ tw_g,
+    double *__restrict__ w) {
+  constexpr int LW = wave_lines<N>();
+  extern __shared__ double2 smem[];
+  const int n3 = geo.n3, m1 = geo.m1;
+  const int ny = 2 * m1 + 1;
+  double2 *tw1 = smem;                 // N   (x and y lengths are equal)
+  double2 *tw3 = tw1 + N;              // n3
+  double2 *pz = tw3 + n3;              // n3
+  double2 *yb = pz + n3;               // ny * N: x outputs, [n1][j2]
+  double2 *ry = yb + ny * N;           // ny * N: y outputs, [n1][k2]
+  double2 *priv = ry + ny * N;         // 4 waves x 3 x LW x N
+  for (int t = threadIdx.x; t < N; t += blockDim.x) tw1[t] = tw_g[t];
+  for (int t = threadIdx.x; t < n3; t += blockDim.x) tw3[t] = tw_g[geo.n1 + geo.n2 + t];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double2 *pa = priv + wave * 3 * LW * N;
+  double2 *pb = pa + LW * N;
+  double2 *pc = pb + LW * N;
+
+  const int tiles_c = (n_c + kTileC - 1) / kTileC;
+  const int tile = blockIdx.x / (kTileV * kTileC);
+  const int q = blockIdx.x % (kTileV * kTileC);
+  const int vl = (tile / tiles_c) * kTileV + q / kTileC;
+  const int c = (tile % tiles_c) * kTileC + q % kTileC;
+  if (vl >= nvb || c >= n_c) return;
+  const long plane = (long)N * N;
+  const long box = plane * n3;
+  const double2 *pv = psi + (long)(v0 + vl) * box;
+  const double2 *pcs = psi + (long)(n_v + c) * box;
+
+  int code[GPT];
+  double2 acc[GPT];
+#pragma unroll
+  for (int i = 0; i < GPT; ++i) {
+    const int g = threadIdx.x + i * kPairThreads;
+    code[i] = g < n_g ? gcol[g] : 0;
+    acc[i] = make_double2(0.0, 0.0);
+  }
+  constexpr int nbx = (N + LW - 1) / LW;
+  const int nby = (ny + LW - 1) / LW;
+  __syncthreads();
+  for (int j3 = 0; j3 < n3; ++j3) {
+    const double2 *sv = pv + j3 * plane;
+    const double2 *sc = pcs + j3 * plane;
+    // x lines: pair density, transform, keep |n1| <= m1
+    for (int b = wave; b < nbx; b += 4) {
+      const int l0 = b * LW;
+      const int nl = min(LW, N - l0);
+      for (int idx = lane; idx < nl * N; idx += 64) {
+        const double2 a = sv[(long)l0 * N + idx];
+        const double2 d = sc[(long)l0 * N + idx];
+        pa[idx] = make_double2(a.x * d.x + a.y * d.y, a.x * d.y - a.y * d.x);
+      }
+      wave_lds_sync();
+      double2 *res = wave_fft_out<N>(pa, pb, pc, pc);
+      wave_fft<N, 0>(pa, pb, pc, res, nl, tw1, lane);
+      for (int idx = lane; idx < nl * ny; idx += 64) {
+        const int line = idx / ny, qq = idx - line * ny;
+        int k1 = qq - m1;
+        if (k1 < 0) k1 += N;
+        yb[qq * N + l0 + line] = res[line * N + k1];
+      }
+      wave_lds_sync();
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < n3; t += blockDim.x) pz[t] = tw3[(t * j3) % n3];
+    // y lines (one per kept n1): transform from yb straight into ry
+    for (int b = wave; b < nby; b += 4) {
+      const int q0 = b * LW;
+      const int nl = min(LW, ny - q0);
+      wave_fft<N, 0>(yb + q0 * N, pa, pb, ry + q0 * N, nl, tw1, lane);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < GPT; ++i) {
+      const int g = threadIdx.x + i * kPairThreads;
+      if (g < n_g) {
+        const double2 val = ry[code[i] & 0xFFFFF];
+        const double2 t = pz[code[i] >> 20];
+        acc[i].x += val.x * t.x - val.y * t.y;
+        acc[i].y += val.x * t.y + val.y * t.x;
+      }
+    }
+  }
+  double *row = w + ((long)vl * n_c + c) * 2L * ld_g;
+#pragma unroll
+  for (int i = 0; i < GPT; ++i) {
+    const int g = threadIdx.x + i * kPairThreads;
+    if (g < n_g) {
+      const double scl = gscale[g];
+      row[g] = acc[i].x * scl;
+      row[ld_g + g] = acc[i].y * scl;
+    }
+  }
+  for (int g = n_g + threadIdx.x; g < ld_g; g += blockDim.x) {
+    row[g] = 0.0;
+    row[ld_g + g] = 0.0;
+  }
+}
+
 }  // namespace
 
 void upload_twiddles(System &sys) {
@@ -451,13 +628,28 @@ void launch_pair_matrix(System &sys, int v0, int nvb, bool scaled, double *w,
   const double2 *tw = sys.fft_tw.as<double2>();
 #define SSRPA_PAIR_N(G, NN)                                                  \
   do {                                                                       \
-    if (shmem > 64 * 1024)                                                   \
-      SSRPA_HIP(hipFuncSetAttribute(                                         \
-          reinterpret_cast<const void *>(&pair_fft_kernel<G, NN>),           \
-          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));          \
-    hipLaunchKernelGGL((pair_fft_kernel<G, NN>), dim3((unsigned)blocks),     \
-                       dim3(kPairThreads), shmem, s, psi, pg, v0, nvb,       \
-                       sys.n_v, sys.n_c, gcol, gscale, g.n_g, g.ld_g, tw, w); \
+    if constexpr (NN > 0) {                                                  \
+      const size_t shw = sizeof(double2) *                                   \
+          (NN + 2 * g.n3 + 2 * ny * NN + 4 * 3 * wave_lines<NN>() * NN);     \
+      SSRPA_REQUIRE(shw <= 160 * 1024, SSRPA_ERR_ARG, "pair FFT LDS");      \
+      if (shw > 64 * 1024)                                                   \
+        SSRPA_HIP(hipFuncSetAttribute(                                       \
+            reinterpret_cast<const void *>(&pair_fft_wave_kernel<G, NN>),    \
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shw));          \
+      hipLaunchKernelGGL((pair_fft_wave_kernel<G, NN>),                      \
+                         dim3((unsigned)blocks), dim3(kPairThreads), shw, s, \
+                         psi, pg, v0, nvb, sys.n_v, sys.n_c, gcol, gscale,   \
+                         g.n_g, g.ld_g, tw, w);                              \
+    } else {                                                                 \
+      if (shmem > 64 * 1024)                                                 \
+        SSRPA_HIP(hipFuncSetAttribute(                                       \
+            reinterpret_cast<const void *>(&pair_fft_kernel<G, NN>),         \
+            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));        \
+      hipLaunchKernelGGL((pair_fft_kernel<G, NN>), dim3((unsigned)blocks),   \
+                         dim3(kPairThreads), shmem, s, psi, pg, v0, nvb,     \
+                         sys.n_v, sys.n_c, gcol, gscale, g.n_g, g.ld_g, tw,  \
+                         w);                                                 \
+    }                                                                        \
   } while (0)
   // grid lengths with a compile-time schedule (x = y); others run generic
 #define SSRPA_PAIR(G)                                                        \

@@ -69,7 +69,7 @@ __device__ __forceinline__ double pair_weight(const HerkArgs &h, long p,
 
 // ---------------------------------------------------------------- HERK f64
 
-__global__ __launch_bounds__(256) void herk_f64_kernel(
+__global__ __launch_bounds__(256, 4) void herk_f64_kernel(
     HerkArgs h, int n_tiles, long kchunk, double *__restrict__ partial) {
   __shared__ double As[2][kKc][kT + kPad];
   __shared__ double Bs[2][kKc][kT + kPad];
@@ -345,8 +345,7 @@ void herk(Context *ctx, const HerkArgs &h, ssrpa_precision prec, double *out,
     const int ti = (h.timer && h.timer->on) ? h.timer->start(h.stage, s) : -1;
     if (prec == SSRPA_FP64) {
       hipLaunchKernelGGL(herk_f64_kernel, dim3(n_tiles, (unsigned)nsplit, h.n_omega),
-                         dim3(256), 0, s, h, n_tiles, kchunk,
-                         wsb->as<double>());
+                         dim3(256), 0, s, h, n_tiles, kchunk, wsb->as<double>());
       SSRPA_HIP(hipGetLastError());
     } else {
       herk_mixed_launch(h, prec, n_tiles, nsplit, kchunk, wsb->as<double>(), s);

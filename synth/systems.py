@@ -114,8 +114,13 @@ class System:
 
 
 def make_system(spec: SystemSpec, seed: int, n_v: Optional[int] = None,
-                n_c: Optional[int] = None) -> System:
-    """Draw one seeded synthetic system of the given shape."""
+                n_c: Optional[int] = None, qr: str = "numpy") -> System:
+    """Draw one seeded synthetic system of the given shape.
+
+    qr="torch" orthonormalizes on the GPU (torch.linalg.qr) for large inputs;
+    the random numbers are the same, the orbitals agree with the numpy QR up
+    to rounding and per-band phases.
+    """
     n_v = spec.n_v if n_v is None else n_v
     n_c = spec.n_c if n_c is None else n_c
     nb = n_v + n_c
@@ -133,8 +138,14 @@ def make_system(spec: SystemSpec, seed: int, n_v: Optional[int] = None,
     u = rng.uniform(0.0, 1.0, n_c)
     eps_c = np.sort(0.1 + 4.9 * u ** (2.0 / 3.0))
     z = (xr + 1j * xi) * envelope[:, None]
-    q, _ = np.linalg.qr(z, mode="reduced")
-    coeff = np.ascontiguousarray(q.T)  # (nb, n_pw): one band per row
+    if qr == "torch":
+        import torch
+        q = torch.linalg.qr(torch.from_numpy(z).to("cuda"), mode="reduced")[0]
+        coeff = np.ascontiguousarray(q.T.cpu().numpy())
+        del q
+    else:
+        q, _ = np.linalg.qr(z, mode="reduced")
+        coeff = np.ascontiguousarray(q.T)  # (nb, n_pw): one band per row
     energy = np.concatenate([eps_v, eps_c]).astype(np.float64)
     return System(spec=spec, seed=seed, a=spec.a, fft=(spec.fft,) * 3,
                   miller=miller, coeff=coeff, energy=energy, n_v=n_v,
@@ -228,7 +239,7 @@ def _shell_counts(nmax: int):
     return _SHELLS
 
 
-def serving_system(req: dict) -> tuple:
+def serving_system(req: dict, qr: str = "numpy") -> tuple:
     """Concrete (System, n_eig) for one serving request."""
     a = req["a"]
     spec = SystemSpec(f"serve_{req['index']}", a=a, fft=8, n_v=req["n_v"],
@@ -237,7 +248,7 @@ def serving_system(req: dict) -> tuple:
     miller = sphere_miller(a, spec.e_psi)
     grid = alias_free_grid(miller, spec.nsq_chi)
     spec = dataclasses.replace(spec, fft=grid)
-    sysm = make_system(spec, req["seed"])
+    sysm = make_system(spec, req["seed"], qr=qr)
     n_g = int(_shell_counts(120)[spec.nsq_chi])
     n_eig = max(1, int(round(req["eig_frac"] * n_g)))
     return sysm, n_eig
