@@ -30,7 +30,7 @@ METRIC = ("χ0 GEMM TFLOP/s + time-to-E_c per system; p50/p99 E_c "
           "latency, mixed stream")
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
-HERK_KERNEL = {"fp64": "herk_f64_pipe_kernel (static chi0)",
+HERK_KERNEL = {"fp64": "herk_f64_kernel (static chi0)",
                "fp32": "herk_f32_kernel (static chi0)",
                "bf16x3": "herk_bf16x3_kernel (static chi0)"}
 
@@ -103,9 +103,12 @@ def serve_stream(ssrpa, ctx, n_req, rate, max_running):
     reqs = sy.serving_stream(n_req, rate)
     print(f"# generating {n_req} serving systems", file=sys.stderr, flush=True)
     systems = []
-    for r in reqs:
+    for k, r in enumerate(reqs):
         s, n_eig = sy.serving_system(r, qr="torch")
         systems.append((r, s, n_eig))
+        if k % 8 == 7:
+            print(f"# generated {k + 1}/{len(reqs)}", file=sys.stderr,
+                  flush=True)
     om, wt = ssrpa.frequency_grid(16)
     srv = ssrpa.Server(ctx, max_running=max_running, max_bypass_s=2.0)
     ids = []
@@ -118,6 +121,16 @@ def serve_stream(ssrpa, ctx, n_req, rate, max_running):
             time.sleep(delay)
         ids.append((r, srv.submit(s, n_eig, om, wt, r["precision"])))
         del s
+    done = set()
+    while len(done) < len(ids):
+        for r, i in ids:
+            if i not in done and srv.poll(i)["state"] >= ssrpa.REQ_DONE:
+                done.add(i)
+                p = srv.poll(i)
+                print(f"# request {r['index']} done: {p['t_done'] - p['t_submit']:.2f} s"
+                      f" (N_v {r['n_v']}, {r['precision']})", file=sys.stderr,
+                      flush=True)
+        time.sleep(0.05)
     srv.drain()
     res = [(r, srv.poll(i)) for r, i in ids]
     reserved_peak, high = srv.memory()
@@ -235,7 +248,7 @@ def main():
         src = torch.ones(n, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)     # one streaming read + write kernel
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = 2 * n * 8
         del src, dst

@@ -13,6 +13,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstring>
 #include <thread>
 
@@ -323,6 +324,24 @@ ssrpa_status guarded(Context *ctx, F &&f) {
 
 void set_device(Context *ctx) { SSRPA_HIP(hipSetDevice(ctx->device)); }
 
+// SSRPA_VERBOSE=1: one line on stderr per finished valence block (the block
+// is synchronized first), for long solves.
+bool verbose() {
+  static const bool v = [] {
+    const char *e = getenv("SSRPA_VERBOSE");
+    return e && e[0] == '1';
+  }();
+  return v;
+}
+
+void block_done(const char *stage, int v0, int nvb, int n_v, hipStream_t s) {
+  if (!verbose()) return;
+  SSRPA_HIP(hipStreamSynchronize(s));
+  fprintf(stderr, "ssrpa: %s: valence bands %d-%d of %d done\n", stage, v0,
+          v0 + nvb - 1, n_v);
+  fflush(stderr);
+}
+
 int resolve_block(System &sys, int requested, int n_eig, int n_freq) {
   if (requested > 0) return std::min(requested, sys.n_v);
   // largest block whose pair matrices fit in the remaining budget
@@ -389,6 +408,7 @@ void static_chi0(System &sys, ssrpa_precision prec, int vb, hipStream_t s) {
     h.timer = &sys.timer;
     h.stage = SSRPA_STAGE_CHI0_HERK;
     herk(ctx, h, prec, sys.chibar0.as<double>(), 0, v0 > 0 ? 1 : 0, ws, s);
+    block_done("static chi0", v0, nvb, sys.n_v, s);
   }
   SSRPA_HIP(hipStreamSynchronize(s));
   sys.have_chi0 = true;
@@ -493,6 +513,7 @@ EcResult energy(System &sys, int n_eig, int n_freq, const double *omega,
     h.timer = &sys.timer;
     h.stage = SSRPA_STAGE_FREQ_HERK;
     herk(ctx, h, prec, chis, 2L * n * n, v0 > 0 ? 1 : 0, ws, s);
+    block_done("subspace chi0(iw)", v0, nvb, sys.n_v, s);
   }
   fill_zero(sys.dev_flag.as(), sizeof(int), s);
   {

@@ -52,12 +52,37 @@ __device__ __forceinline__ int xcd_remap(int b, int total) {
   return (b & 7) * per + (b >> 3);
 }
 
-// Lower-triangle tile t -> (I, J), I >= J, t = I (I + 1) / 2 + J.
-__device__ __forceinline__ int2 tri_tile(int t) {
-  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while (I * (I + 1) / 2 > t) --I;
-  while ((I + 1) * (I + 2) / 2 <= t) ++I;
-  return make_int2(I, t - I * (I + 1) / 2);
+// Lower-triangle tile t -> (I, J) in blocks of kSB x kSB tiles: blocks in
+// lower-triangle order, tiles row by row inside a block.  Consecutive tile
+// ids (which the XCD remap keeps on one XCD) then share few operand panels,
+// so they hit in that XCD's L2.  T = tiles per side.
+constexpr int kSB = 8;
+__device__ __forceinline__ int2 tri_tile_blocked(int t, int T) {
+  const int nb = (T + kSB - 1) / kSB;
+  int acc = 0;
+  for (int bI = 0; bI < nb; ++bI) {
+    const int rI = min(kSB, T - bI * kSB);
+    for (int bJ = 0; bJ <= bI; ++bJ) {
+      const int cJ = min(kSB, T - bJ * kSB);
+      const int cnt = bJ < bI ? rI * cJ : rI * (rI + 1) / 2;
+      if (t < acc + cnt) {
+        const int l = t - acc;
+        int i, j;
+        if (bJ < bI) {
+          i = l / cJ;
+          j = l - i * cJ;
+        } else {
+          i = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
+          while (i * (i + 1) / 2 > l) --i;
+          while ((i + 1) * (i + 2) / 2 <= l) ++i;
+          j = l - i * (i + 1) / 2;
+        }
+        return make_int2(bI * kSB + i, bJ * kSB + j);
+      }
+      acc += cnt;
+    }
+  }
+  return make_int2(0, 0);  // not reached for t < T (T + 1) / 2
 }
 
 __device__ __forceinline__ double pair_weight(const HerkArgs &h, long p,
@@ -77,7 +102,7 @@ __global__ __launch_bounds__(256, 4) void herk_f64_kernel(
   const int tile_id = xcd_remap(blockIdx.x, n_tiles);
   const int split = blockIdx.y;
   const int om_i = blockIdx.z;
-  const int2 tile = tri_tile(tile_id);
+  const int2 tile = tri_tile_blocked(tile_id, h.ld / kT);
   const int I0 = tile.x * kT, J0 = tile.y * kT;
   const double om = h.unit_weight ? 0.0 : h.omega[om_i];
   const long kbeg = split * kchunk;
@@ -168,12 +193,12 @@ __global__ __launch_bounds__(256, 4) void herk_f64_kernel(
 
 // Sum split partials in order and write the Hermitian matrix (both halves).
 __global__ void herk_reduce_kernel(const double *__restrict__ partial,
-                                   int n_tiles,
+                                   int n_tiles, int T,
                                    int nsplit, int ncol, double *__restrict__ out,
                                    long out_stride, int beta) {
   const int tile_id = blockIdx.x;
   const int om_i = blockIdx.y;
-  const int2 tile = tri_tile(tile_id);
+  const int2 tile = tri_tile_blocked(tile_id, T);
   const int I0 = tile.x * kT, J0 = tile.y * kT;
   double *o = out + om_i * out_stride;
   for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
@@ -355,7 +380,7 @@ void herk(Context *ctx, const HerkArgs &h, ssrpa_precision prec, double *out,
     fill_zero(wsb->as(), need, s);
   }
   hipLaunchKernelGGL(herk_reduce_kernel, dim3(n_tiles, h.n_omega), dim3(256), 0,
-                     s, wsb->as<double>(), n_tiles, (int)nsplit, h.ncol,
+                     s, wsb->as<double>(), n_tiles, T, (int)nsplit, h.ncol,
                      out, out_stride, beta);
   SSRPA_HIP(hipGetLastError());
 }

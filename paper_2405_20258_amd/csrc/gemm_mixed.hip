@@ -36,11 +36,35 @@ __device__ __forceinline__ int xcd_remap_m(int b, int total) {
   return (b & 7) * per + (b >> 3);
 }
 
-__device__ __forceinline__ int2 tri_tile_m(int t) {
-  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while (I * (I + 1) / 2 > t) --I;
-  while ((I + 1) * (I + 2) / 2 <= t) ++I;
-  return make_int2(I, t - I * (I + 1) / 2);
+// Same blocked lower-triangle tile order as the FP64 HERK (the reduction
+// kernel decodes tile ids with it).
+constexpr int kSBm = 8;
+__device__ __forceinline__ int2 tri_tile_m(int t, int T) {
+  const int nb = (T + kSBm - 1) / kSBm;
+  int acc = 0;
+  for (int bI = 0; bI < nb; ++bI) {
+    const int rI = min(kSBm, T - bI * kSBm);
+    for (int bJ = 0; bJ <= bI; ++bJ) {
+      const int cJ = min(kSBm, T - bJ * kSBm);
+      const int cnt = bJ < bI ? rI * cJ : rI * (rI + 1) / 2;
+      if (t < acc + cnt) {
+        const int l = t - acc;
+        int i, j;
+        if (bJ < bI) {
+          i = l / cJ;
+          j = l - i * cJ;
+        } else {
+          i = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
+          while (i * (i + 1) / 2 > l) --i;
+          while ((i + 1) * (i + 2) / 2 <= l) ++i;
+          j = l - i * (i + 1) / 2;
+        }
+        return make_int2(bI * kSBm + i, bJ * kSBm + j);
+      }
+      acc += cnt;
+    }
+  }
+  return make_int2(0, 0);
 }
 
 __device__ __forceinline__ double weight_m(const HerkArgs &h, long p, double om) {
@@ -92,7 +116,7 @@ __global__ __launch_bounds__(256) void herk_f32_kernel(
   const int tile_id = xcd_remap_m(blockIdx.x, n_tiles);
   const int split = blockIdx.y;
   const int om_i = blockIdx.z;
-  const int2 tile = tri_tile_m(tile_id);
+  const int2 tile = tri_tile_m(tile_id, h.ld / kT);
   const int I0 = tile.x * kT, J0 = tile.y * kT;
   const double om = h.unit_weight ? 0.0 : h.omega[om_i];
   const long kbeg = split * kchunk;
@@ -232,7 +256,7 @@ __global__ __launch_bounds__(256) void herk_bf16x3_kernel(
   const int tile_id = xcd_remap_m(blockIdx.x, n_tiles);
   const int split = blockIdx.y;
   const int om_i = blockIdx.z;
-  const int2 tile = tri_tile_m(tile_id);
+  const int2 tile = tri_tile_m(tile_id, h.ld / kT);
   const int I0 = tile.x * kT, J0 = tile.y * kT;
   const double om = h.unit_weight ? 0.0 : h.omega[om_i];
   const long kbeg = split * kchunk;
