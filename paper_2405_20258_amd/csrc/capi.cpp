@@ -250,6 +250,23 @@ Geometry make_geometry(const ssrpa_system_desc *d) {
                   d->fft[i], i, 2 * mp[i] + mc[i] + 1);
   SSRPA_REQUIRE((long)(2 * g.m1 + 1) * g.n2 < (1 << 20), SSRPA_ERR_ARG,
                 "grid too large");
+  // columns (n1, n2) of the chi0 set; the set is lexicographic in (n1, n2, n3)
+  const int ny2 = 2 * g.m2 + 1;
+  g.cmap.assign((size_t)(2 * g.m1 + 1) * ny2, -1);
+  g.zcode.resize(g.n_g);
+  for (int i = 0; i < g.n_g; ++i) {
+    const int a = g.miller_chi[3 * i], b = g.miller_chi[3 * i + 1],
+              c = g.miller_chi[3 * i + 2];
+    int &col = g.cmap[(size_t)(a + g.m1) * ny2 + b + g.m2];
+    if (col < 0) {
+      col = g.ncol++;
+      // the (0, 0) column skips n3 = 0 (G = 0 is not in the set)
+      g.zcol.insert(g.zcol.end(), {i, c, c, (a == 0 && b == 0) ? 1 : 0});
+    }
+    g.zcol[4 * col + 2] = c;  // n3 ascends within a column
+    g.zcode[i] = col | ((((c % g.n3) + g.n3) % g.n3) << 20);
+  }
+  g.ldy = round_up(g.ncol, 8);
   return g;
 }
 
@@ -274,6 +291,10 @@ Footprint footprint_of(const ssrpa_system_desc *d, const Geometry &g, int n_eig,
   f.resident = bytes_c(nb * box) + bytes_c(ng * ng) + 64 * ldg +
                bytes_c(nb * (size_t)d->n_pw);
   f.block = pairs * (2 * ldg * 8 + 8);
+  if (staged_grid(g)) {
+    const size_t ypp = stage_bytes_per_pair(g);
+    f.block += (size_t)vb * stage_chunk_c(vb, d->n_c, ypp) * ypp;
+  }
   f.subspace = full ? 0 : pairs * 2 * lde * 8 + bytes_c(ldg * lde);
   const size_t tiles = (lde / 64) * (lde / 64 + 1) / 2;
   f.freq = 2 * bytes_c(ne * ne) * n_freq + tiles * 64 * 64 * 16 * (size_t)n_freq * 2;
@@ -356,7 +377,14 @@ int resolve_block(System &sys, int requested, int n_eig, int n_freq) {
   const size_t per_band = (size_t)sys.n_c * (2 * sys.geo.ld_g * 8 + 8 + 2 * lde * 8);
   const size_t reserve = (size_t)1 << 30;
   const size_t avail = free_b > reserve ? free_b - reserve : 0;
-  int vb = (int)std::min<size_t>(sys.n_v, avail / std::max<size_t>(per_band, 1));
+  // the pair transform's stage: n_c * ypp per band, at most kStageBytes
+  const size_t stage_band = staged_grid(sys.geo)
+                                ? (size_t)sys.n_c * stage_bytes_per_pair(sys.geo)
+                                : 0;
+  size_t nb = avail / std::max<size_t>(per_band + stage_band, 1);
+  if (nb * stage_band > kStageBytes)
+    nb = avail > kStageBytes ? (avail - kStageBytes) / std::max<size_t>(per_band, 1) : 0;
+  int vb = (int)std::min<size_t>(sys.n_v, nb);
   SSRPA_REQUIRE(vb >= 1, SSRPA_ERR_NOMEM,
                 "one valence band of pair matrices (%zu bytes) exceeds the budget",
                 per_band);
@@ -710,6 +738,15 @@ ssrpa_status ssrpa_system_create(ssrpa_context *ctx, const ssrpa_system_desc *de
     SSRPA_HIP(hipMemcpyAsync(sys->sqrtv_d.as<double>() + 2 * (size_t)gg.ld_g,
                              gg.sqrt_v.data(), sizeof(double) * gg.n_g,
                              hipMemcpyHostToDevice, s));
+    sys->zcode = DevBuf(ctx, sizeof(int) * gg.n_g);
+    sys->cmap = DevBuf(ctx, sizeof(int) * gg.cmap.size());
+    SSRPA_HIP(hipMemcpyAsync(sys->zcode.as(), gg.zcode.data(), sizeof(int) * gg.n_g,
+                             hipMemcpyHostToDevice, s));
+    SSRPA_HIP(hipMemcpyAsync(sys->cmap.as(), gg.cmap.data(),
+                             sizeof(int) * gg.cmap.size(), hipMemcpyHostToDevice, s));
+    sys->zcol = DevBuf(ctx, sizeof(int) * gg.zcol.size());
+    SSRPA_HIP(hipMemcpyAsync(sys->zcol.as(), gg.zcol.data(),
+                             sizeof(int) * gg.zcol.size(), hipMemcpyHostToDevice, s));
     sys->dev_flag = DevBuf(ctx, 64);
     fill_zero(sys->dev_flag.as(), 64, s);
     upload_twiddles(*sys);

@@ -104,71 +104,6 @@ __device__ __forceinline__ void stockham_pass(const double2 *in, double2 *out,
   }
 }
 
-// Compile-time radix schedule (4s, then 2s, then 3s) of a length N.
-template <int N>
-struct Plan {
-  static constexpr int count() {
-    if (N <= 0) return 0;
-    int m = N, c = 0;
-    while (m % 4 == 0) { m /= 4; ++c; }
-    while (m % 2 == 0) { m /= 2; ++c; }
-    while (m % 3 == 0) { m /= 3; ++c; }
-    return c;
-  }
-  static constexpr int radix(int s) {
-    if (N <= 0) return 1;
-    int m = N, c = 0;
-    while (m % 4 == 0) { if (c == s) return 4; m /= 4; ++c; }
-    while (m % 2 == 0) { if (c == s) return 2; m /= 2; ++c; }
-    while (m % 3 == 0) { if (c == s) return 3; m /= 3; ++c; }
-    return 1;
-  }
-  static constexpr int ns(int s) {
-    int p = 1;
-    for (int i = 0; i < s; ++i) p *= radix(i);
-    return p;
-  }
-};
-
-// The same pass with N, R and Ns known at compile time (line stride N), so
-// the index arithmetic reduces to shifts and multiplications.
-template <int N, int R, int NS>
-__device__ __forceinline__ void stockham_pass_t(const double2 *in, double2 *out,
-                                                int nlines, const double2 *tw) {
-  constexpr int nb = N / R;
-  constexpr int stride = N / (NS * R);
-  const int total = nlines * nb;
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    const int line = idx / nb;
-    const int j = idx - line * nb;
-    const int k = j % NS;
-    const double2 *src = in + line * N + j;
-    double2 v[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) v[i] = src[i * nb];
-#pragma unroll
-    for (int i = 1; i < R; ++i) v[i] = cmul(v[i], tw[(k * i * stride) % N]);
-    double2 y[R];
-    radix_dft<R>(v, y);
-    double2 *dst = out + line * N + (j / NS) * NS * R + k;
-#pragma unroll
-    for (int i = 0; i < R; ++i) dst[i * NS] = y[i];
-  }
-}
-
-template <int N, int S = 0>
-__device__ __forceinline__ double2 *lds_fft_t(double2 *a, double2 *b, int nlines,
-                                              const double2 *tw) {
-  if constexpr (S == Plan<N>::count()) {
-    __syncthreads();
-    return a;
-  } else {
-    __syncthreads();
-    stockham_pass_t<N, Plan<N>::radix(S), Plan<N>::ns(S)>(a, b, nlines, tw);
-    return lds_fft_t<N, S + 1>(b, a, nlines, tw);
-  }
-}
-
 // Transform the lines in `a` (ping-pong with `b`); returns the buffer that
 // holds the result.  Synchronizes the block before and after each pass.
 __device__ double2 *lds_fft(double2 *a, double2 *b, int nlines, int ls, int N,
@@ -276,18 +211,20 @@ struct PairGeo {
   Radices r1, r2;
 };
 
-// One block per (v, c) pair.  For every z-plane j3: pair density of the
-// plane, x transforms (in batches of lx lines) pruned to |n1| <= m1, y
-// transforms of those columns, then the z sum for the chi0 G vectors is
-// accumulated in registers: acc(G) += Y(n1, n2; j3) e^{2 pi i n3 j3 / N3}.
-template <int GPT, int N>
+// Generic fused kernel for grids without a compile-time schedule (N1 != N2,
+// or a length outside the staged set): one block per (v, c) pair.  For every
+// z-plane j3: pair density of the plane, x transforms (in batches of lx
+// lines) pruned to |n1| <= m1, y transforms of those columns, then the z sum
+// for the chi0 G vectors is accumulated in registers:
+// acc(G) += Y(n1, n2; j3) e^{2 pi i n3 j3 / N3}.
+template <int GPT>
 __global__ __launch_bounds__(kPairThreads) void pair_fft_kernel(
     const double2 *__restrict__ psi, PairGeo geo, int v0, int nvb, int n_v,
     int n_c, const int *__restrict__ gcol, const double *__restrict__ gscale,
     int n_g, int ld_g, const double2 *__restrict__ tw_g,
     double *__restrict__ w) {
   extern __shared__ double2 smem[];
-  const int n1 = N > 0 ? N : geo.n1, n2 = N > 0 ? N : geo.n2;
+  const int n1 = geo.n1, n2 = geo.n2;
   const int n3 = geo.n3, m1 = geo.m1, lx = geo.lx;
   const int ny = 2 * m1 + 1;
   double2 *tw1 = smem;
@@ -334,11 +271,7 @@ __global__ __launch_bounds__(kPairThreads) void pair_fft_kernel(
         // conj(a) * b
         xa[idx] = make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
       }
-      const double2 *r;
-      if constexpr (N > 0)
-        r = lds_fft_t<N>(xa, xb, nl, tw1);
-      else
-        r = lds_fft(xa, xb, nl, n1, n1, geo.r1, tw1);
+      const double2 *r = lds_fft(xa, xb, nl, n1, n1, geo.r1, tw1);
       for (int idx = threadIdx.x; idx < nl * ny; idx += blockDim.x) {
         const int line = idx / ny, qq = idx - line * ny;
         int k1 = qq - m1;
@@ -346,11 +279,7 @@ __global__ __launch_bounds__(kPairThreads) void pair_fft_kernel(
         yb[qq * n2 + g0 + line] = r[line * n1 + k1];
       }
     }
-    const double2 *ry;
-    if constexpr (N > 0)
-      ry = lds_fft_t<N>(yb, xa, ny, tw2);
-    else
-      ry = lds_fft(yb, xa, ny, n2, n2, geo.r2, tw2);
+    const double2 *ry = lds_fft(yb, xa, ny, n2, n2, geo.r2, tw2);
 #pragma unroll
     for (int i = 0; i < GPT; ++i) {
       const int g = threadIdx.x + i * kPairThreads;
@@ -380,8 +309,6 @@ __global__ __launch_bounds__(kPairThreads) void pair_fft_kernel(
   }
 }
 
-// ---------------------------------------------- wave-synchronous pair FFT
-
 // LDS ordering between lanes of one wave: a wavefront-scope fence pair
 // around a wave barrier (no block-wide barrier needed).
 __device__ __forceinline__ void wave_lds_sync() {
@@ -390,171 +317,357 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Stockham pass executed by the 64 lanes of one wave (line stride N).
-template <int N, int R, int NS>
-__device__ __forceinline__ void stockham_pass_wave(const double2 *in, double2 *out,
-                                                   int nlines, const double2 *tw,
-                                                   int lane) {
-  constexpr int nb = N / R;
-  constexpr int stride = N / (NS * R);
-  const int total = nlines * nb;
-  for (int idx = lane; idx < total; idx += 64) {
-    const int line = idx / nb;
-    const int j = idx - line * nb;
-    const int k = j % NS;
-    const double2 *src = in + line * N + j;
-    double2 v[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) v[i] = src[i * nb];
-#pragma unroll
-    for (int i = 1; i < R; ++i) v[i] = cmul(v[i], tw[(k * i * stride) % N]);
+// ------------------------------------------------- staged pair transform
+//
+// Two kernels per chunk of pairs (same result as pair_fft_kernel):
+//  * pair_plane_kernel forms the pair density conj(psi_v) psi_c of one
+//    z-plane at a time and transforms it along x, then along y.  Each line of
+//    length N = R1 R2 is split into an R1-point step and an R2-point step
+//    computed in registers with one LDS exchange in between (decimation in
+//    time: X[ka + R1 kb] = sum_b e^{2 pi i b kb / R2} e^{2 pi i b ka / N}
+//    sum_a x[R2 a + b] e^{2 pi i a ka / R1}).  Only |n1| <= m1 survives the x
+//    step and only the (n1, n2) columns that hold chi0 vectors are written,
+//    to a stage Y[pair][j3][column] in HBM.
+//  * pair_z_kernel forms, for every chi0 vector G = (n1, n2, n3),
+//    sum_j3 Y[col(G)][j3] e^{2 pi i n3 j3 / N3}, scales it and writes W.
+
+// cos and sin of 2 pi t / R for the register transforms (R divides 16, 12
+// or 9); the arguments are compile-time constants after unrolling.
+__host__ __device__ constexpr double tw_cos(int R, int t) {
+  constexpr double c16[16] = {1.0, 0.9238795325112867, 0.7071067811865476,
+                              0.3826834323650898, 0.0, -0.3826834323650898,
+                              -0.7071067811865476, -0.9238795325112867, -1.0,
+                              -0.9238795325112867, -0.7071067811865476,
+                              -0.3826834323650898, 0.0, 0.3826834323650898,
+                              0.7071067811865476, 0.9238795325112867};
+  constexpr double c12[12] = {1.0, 0.8660254037844386, 0.5, 0.0, -0.5,
+                              -0.8660254037844386, -1.0, -0.8660254037844386,
+                              -0.5, 0.0, 0.5, 0.8660254037844386};
+  constexpr double c9[9] = {1.0, 0.766044443118978, 0.17364817766693036, -0.5,
+                            -0.9396926207859084, -0.9396926207859084, -0.5,
+                            0.17364817766693036, 0.766044443118978};
+  return 16 % R == 0 ? c16[t * (16 / R)]
+                     : (12 % R == 0 ? c12[t * (12 / R)] : c9[t * (9 / R)]);
+}
+__host__ __device__ constexpr double tw_sin(int R, int t) {
+  // sin(2 pi t / R) = cos(2 pi (t - R/4) / R), written out for R = 9
+  constexpr double s9[9] = {0.0, 0.6427876096865394, 0.984807753012208,
+                            0.8660254037844386, 0.3420201433256687,
+                            -0.3420201433256687, -0.8660254037844386,
+                            -0.984807753012208, -0.6427876096865394};
+  return R % 4 == 0 ? tw_cos(R, (t + 3 * (R / 4)) % R)
+                    : (12 % R == 0 ? tw_cos(12, ((t * (12 / R)) + 9) % 12)
+                                   : s9[t * (9 / R)]);
+}
+
+// v e^{2 pi i t / R}, 0 <= t < R; exact for the multiples of pi/2 and pi/4.
+template <int R>
+__device__ __forceinline__ double2 rot(double2 v, int t) {
+  constexpr double h = 0.70710678118654752440;
+  if (t == 0) return v;
+  if (2 * t == R) return make_double2(-v.x, -v.y);
+  if (4 * t == R) return make_double2(-v.y, v.x);
+  if (4 * t == 3 * R) return make_double2(v.y, -v.x);
+  if (8 * t == R) return make_double2(h * (v.x - v.y), h * (v.x + v.y));
+  if (8 * t == 3 * R) return make_double2(-h * (v.x + v.y), h * (v.x - v.y));
+  if (8 * t == 5 * R) return make_double2(h * (v.y - v.x), -h * (v.x + v.y));
+  if (8 * t == 7 * R) return make_double2(h * (v.x + v.y), h * (v.y - v.x));
+  const double c = tw_cos(R, t), s = tw_sin(R, t);
+  return make_double2(v.x * c - v.y * s, v.x * s + v.y * c);
+}
+
+// In-register DFT of length R in place, y_k = sum_j v_j e^{+2 pi i jk / R};
+// R = A B with A, B <= 4 by one Cooley-Tukey split.
+template <int R>
+__device__ __forceinline__ void dft(double2 *v) {
+  if constexpr (R == 2 || R == 3 || R == 4) {
     double2 y[R];
     radix_dft<R>(v, y);
-    double2 *dst = out + line * N + (j / NS) * NS * R + k;
 #pragma unroll
-    for (int i = 0; i < R; ++i) dst[i * NS] = y[i];
+    for (int i = 0; i < R; ++i) v[i] = y[i];
+  } else if constexpr (R > 4) {
+    constexpr int A = R % 4 == 0 ? 4 : (R % 3 == 0 ? 3 : 2);
+    constexpr int B = R / A;
+    static_assert(A * B == R && B <= 4, "register DFT length");
+    double2 t[R];  // t[ka * B + b]
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      double2 u[A];
+#pragma unroll
+      for (int a = 0; a < A; ++a) u[a] = v[B * a + b];
+      dft<A>(u);
+#pragma unroll
+      for (int ka = 0; ka < A; ++ka) t[ka * B + b] = rot<R>(u[ka], b * ka);
+    }
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) {
+      double2 u[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) u[b] = t[ka * B + b];
+      dft<B>(u);
+#pragma unroll
+      for (int kb = 0; kb < B; ++kb) v[ka + A * kb] = u[kb];
+    }
   }
 }
 
-// Whole transform of `nlines` lines by one wave: pass 0 reads `in0`, the
-// last pass writes `outF`, passes in between alternate between bufA (after
-// even passes) and bufB (after odd passes).  outF must differ from the
-// source of the last pass.
-template <int N, int S>
-__device__ __forceinline__ void wave_fft(const double2 *in0, double2 *bufA,
-                                         double2 *bufB, double2 *outF,
-                                         int nlines, const double2 *tw, int lane) {
-  constexpr int C = Plan<N>::count();
-  const double2 *src = S == 0 ? in0 : ((S - 1) % 2 == 0 ? bufA : bufB);
-  double2 *dst = S == C - 1 ? outF : (S % 2 == 0 ? bufA : bufB);
-  stockham_pass_wave<N, Plan<N>::radix(S), Plan<N>::ns(S)>(src, dst, nlines, tw,
-                                                          lane);
+constexpr int kPlaneWaves = 8;
+constexpr int kPlaneThreads = 64 * kPlaneWaves;
+
+// Lines per wave batch: fewest issue slots per line over the two steps
+// (step 1 has R2 items per line, step 2 has R1).
+constexpr int pick_lines(int r1, int r2) {
+  int best = 1, bn = 1, bd = 1;  // best cost bn / bd
+  for (int L = 1; L <= 16; ++L) {
+    const int n = (L * r2 + 63) / 64 + (L * r1 + 63) / 64;
+    if (n * bd < bn * L || L == 1) { best = L; bn = n; bd = L; }
+  }
+  return best;
+}
+
+template <int R1_, int R2_>
+struct LineSplit {
+  static constexpr int R1 = R1_, R2 = R2_, N = R1 * R2;
+  static constexpr int SB = R2 | 1;      // odd stride between ka rows
+  static constexpr int SL = R1 * SB;     // scratch per line
+  static constexpr int XS = N | 1;       // odd row stride of the x output
+  static constexpr int L = pick_lines(R1, R2);
+  static constexpr bool kHoist = L * R2 <= 64;  // one step-1 item per lane
+};
+
+// LDS bytes of pair_plane_kernel (tw, column map, nxo x outputs, scratch).
+template <class S>
+size_t plane_lds_bytes(int ny1, int ny2, int nxo) {
+  const size_t cm = ((size_t)ny1 * ny2 * sizeof(int) + 15) / 16 * 16;
+  return sizeof(double2) * (S::N + (size_t)nxo * ny1 * S::XS +
+                            (size_t)kPlaneWaves * S::L * S::SL) + cm;
+}
+
+// Work-group b -> pair (vl, cl) of a chunk of nvb x ncc pairs.  Work-groups
+// are dealt round-robin to the eight XCDs; on each XCD consecutive ones walk
+// an 8 x 8 tile of pairs, so the groups resident on one XCD share eight
+// valence and eight conduction orbitals through its L2.
+__device__ __forceinline__ bool chunk_pair(int b, int nvb, int ncc, int &vl,
+                                           int &cl) {
+  const int tiles_c = (ncc + 7) >> 3;
+  const int xcd = b & 7, s = b >> 3;
+  const int tile = (s >> 6) * 8 + xcd;
+  const int q = s & 63;
+  const int tv = tile / tiles_c, tc = tile - tv * tiles_c;
+  vl = tv * 8 + (q >> 3);
+  cl = tc * 8 + (q & 7);
+  return vl < nvb && cl < ncc;
+}
+
+// Step 1 of a batch of nl lines: item (line, b) loads x[R2 a + b] through
+// `load`, transforms over a, twists by e^{2 pi i b ka / N} and stores to
+// scr[line][ka][b].  Step 2: item (line, ka) transforms over b and hands
+// X[ka + R1 kb] to `store`.
+// With kLineFast the step-1 items run line-fastest (it = b * nl + line), so
+// that lanes next to each other load neighbouring lines; the twiddles then
+// come from the table.
+template <class S, bool kLineFast = false, class Load, class Store>
+__device__ __forceinline__ void line_batch(int nl, Load load, Store store,
+                                           double2 *scr, const double2 *tw,
+                                           const double2 *twh, int lane) {
+  for (int it = lane; it < nl * S::R2; it += 64) {
+    int line, b;
+    if constexpr (kLineFast) {
+      b = it / nl;
+      line = it - b * nl;
+    } else {
+      line = it / S::R2;
+      b = it - line * S::R2;
+    }
+    double2 x[S::R1];
+#pragma unroll
+    for (int a = 0; a < S::R1; ++a) x[a] = load(line, S::R2 * a + b);
+    dft<S::R1>(x);
+    double2 *d = scr + line * S::SL + b;
+    d[0] = x[0];
+#pragma unroll
+    for (int ka = 1; ka < S::R1; ++ka)
+      d[ka * S::SB] =
+          cmul(x[ka], (S::kHoist && !kLineFast) ? twh[ka - 1] : tw[b * ka]);
+  }
   wave_lds_sync();
-  if constexpr (S + 1 < C) wave_fft<N, S + 1>(in0, bufA, bufB, outF, nlines, tw, lane);
+  for (int it = lane; it < nl * S::R1; it += 64) {
+    const int line = it / S::R1, ka = it - line * S::R1;
+    double2 y[S::R2];
+    const double2 *s = scr + line * S::SL + ka * S::SB;
+#pragma unroll
+    for (int b = 0; b < S::R2; ++b) y[b] = s[b];
+    dft<S::R2>(y);
+#pragma unroll
+    for (int kb = 0; kb < S::R2; ++kb) store(line, ka + S::R1 * kb, y[kb]);
+  }
+  wave_lds_sync();
 }
 
-// buffer that is not the source of the last pass of wave_fft<N>
-template <int N>
-__device__ __forceinline__ double2 *wave_fft_out(double2 *in0, double2 *bufA,
-                                                 double2 *bufB, double2 *spare) {
-  constexpr int C = Plan<N>::count();
-  if constexpr (C == 1) return bufA;
-  const double2 *last_src = (C - 2) % 2 == 0 ? bufA : bufB;
-  if (last_src == bufA) return bufB == in0 ? spare : bufB;
-  return bufA == in0 ? spare : bufA;
-}
-
-template <int N>
-constexpr int wave_lines() { return N <= 24 ? 8 : 4; }
-
-// Same result as pair_fft_kernel for N1 = N2 = N: per z-plane, each wave
-// transforms its own batches of x lines (private LDS, wave-level ordering
-// only), writes the |n1| <= m1 outputs to a shared buffer, then the waves
-// transform the y lines the same way; two block barriers per plane.
-template <int GPT, int N>
-__global__ __launch_bounds__(kPairThreads) void pair_fft_wave_kernel(
-    const double2 *__restrict__ psi, PairGeo geo, int v0, int nvb, int n_v,
-    int n_c, const int *__restrict__ gcol, const double *__restrict__ gscale,
-    int n_g, int ld_g, const double2 *__restrict__ tw_g,
-    double *__restrict__ w) {
-  constexpr int LW = wave_lines<N>();
+// One work-group per pair of the chunk; it walks the n3 planes.  With
+// nxo = 2 the x outputs alternate between two buffers and one block barrier
+// per plane suffices; with nxo = 1 a second barrier guards the buffer.
+template <int R1, int R2>
+__global__ __launch_bounds__(kPlaneThreads) void pair_plane_kernel(
+    const double2 *__restrict__ psi, int v0, int nvb, int n_v, int c0,
+    int ncc, int n3, int m1, int m2, int nxo, const int *__restrict__ cmap_g,
+    int ldy, const double2 *__restrict__ tw_g, double2 *__restrict__ yst) {
+  using S = LineSplit<R1, R2>;
+  constexpr int N = S::N;
   extern __shared__ double2 smem[];
-  const int n3 = geo.n3, m1 = geo.m1;
-  const int ny = 2 * m1 + 1;
-  double2 *tw1 = smem;                 // N   (x and y lengths are equal)
-  double2 *tw3 = tw1 + N;              // n3
-  double2 *pz = tw3 + n3;              // n3
-  double2 *yb = pz + n3;               // ny * N: x outputs, [n1][j2]
-  double2 *ry = yb + ny * N;           // ny * N: y outputs, [n1][k2]
-  double2 *priv = ry + ny * N;         // 4 waves x 3 x LW x N
-  for (int t = threadIdx.x; t < N; t += blockDim.x) tw1[t] = tw_g[t];
-  for (int t = threadIdx.x; t < n3; t += blockDim.x) tw3[t] = tw_g[geo.n1 + geo.n2 + t];
+  const int ny1 = 2 * m1 + 1, ny2 = 2 * m2 + 1;
+  double2 *tw = smem;
+  double2 *xo0 = tw + N;
+  double2 *scr_all = xo0 + nxo * ny1 * S::XS;
+  int *cmap = reinterpret_cast<int *>(scr_all + kPlaneWaves * S::L * S::SL);
+  int vl, cl;
+  if (!chunk_pair(blockIdx.x, nvb, ncc, vl, cl)) return;
+  for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t] = tw_g[t];
+  for (int t = threadIdx.x; t < ny1 * ny2; t += blockDim.x) cmap[t] = cmap_g[t];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double2 *pa = priv + wave * 3 * LW * N;
-  double2 *pb = pa + LW * N;
-  double2 *pc = pb + LW * N;
-
-  const int tiles_c = (n_c + kTileC - 1) / kTileC;
-  const int tile = blockIdx.x / (kTileV * kTileC);
-  const int q = blockIdx.x % (kTileV * kTileC);
-  const int vl = (tile / tiles_c) * kTileV + q / kTileC;
-  const int c = (tile % tiles_c) * kTileC + q % kTileC;
-  if (vl >= nvb || c >= n_c) return;
+  double2 *scr = scr_all + wave * S::L * S::SL;
+  // twiddles of this lane's step-1 item, when each lane has one
+  double2 twh[S::R1 > 1 ? S::R1 - 1 : 1];
+  if constexpr (S::kHoist) {
+    const int b = lane % S::R2;
+#pragma unroll
+    for (int ka = 1; ka < S::R1; ++ka) twh[ka - 1] = tw_g[b * ka];
+  }
   const long plane = (long)N * N;
   const long box = plane * n3;
   const double2 *pv = psi + (long)(v0 + vl) * box;
-  const double2 *pcs = psi + (long)(n_v + c) * box;
-
-  int code[GPT];
-  double2 acc[GPT];
-#pragma unroll
-  for (int i = 0; i < GPT; ++i) {
-    const int g = threadIdx.x + i * kPairThreads;
-    code[i] = g < n_g ? gcol[g] : 0;
-    acc[i] = make_double2(0.0, 0.0);
-  }
-  constexpr int nbx = (N + LW - 1) / LW;
-  const int nby = (ny + LW - 1) / LW;
+  const double2 *pc = psi + (long)(n_v + c0 + cl) * box;
+  double2 *yp = yst + ((long)vl * ncc + cl) * n3 * (long)ldy;
+  constexpr int nbx = (N + S::L - 1) / S::L;
+  const int nby = (ny1 + S::L - 1) / S::L;
   __syncthreads();
   for (int j3 = 0; j3 < n3; ++j3) {
+    double2 *xo = xo0 + (nxo == 2 ? (j3 & 1) : 0) * ny1 * S::XS;
     const double2 *sv = pv + j3 * plane;
-    const double2 *sc = pcs + j3 * plane;
-    // x lines: pair density, transform, keep |n1| <= m1
-    for (int b = wave; b < nbx; b += 4) {
-      const int l0 = b * LW;
-      const int nl = min(LW, N - l0);
-      for (int idx = lane; idx < nl * N; idx += 64) {
-        const double2 a = sv[(long)l0 * N + idx];
-        const double2 d = sc[(long)l0 * N + idx];
-        pa[idx] = make_double2(a.x * d.x + a.y * d.y, a.x * d.y - a.y * d.x);
-      }
-      wave_lds_sync();
-      double2 *res = wave_fft_out<N>(pa, pb, pc, pc);
-      wave_fft<N, 0>(pa, pb, pc, res, nl, tw1, lane);
-      for (int idx = lane; idx < nl * ny; idx += 64) {
-        const int line = idx / ny, qq = idx - line * ny;
-        int k1 = qq - m1;
-        if (k1 < 0) k1 += N;
-        yb[qq * N + l0 + line] = res[line * N + k1];
-      }
-      wave_lds_sync();
+    const double2 *sc = pc + j3 * plane;
+    for (int bt = wave; bt < nbx; bt += kPlaneWaves) {
+      const int l0 = bt * S::L;
+      const int nl = min(S::L, N - l0);
+      line_batch<S>(
+          nl,
+          [&](int line, int j) {
+            const long o = (long)(l0 + line) * N + j;
+            const double2 a = sv[o], d = sc[o];
+            return make_double2(a.x * d.x + a.y * d.y, a.x * d.y - a.y * d.x);
+          },
+          [&](int line, int k, double2 v) {
+            int kk = k + m1;
+            if (kk >= N) kk -= N;
+            if (kk < ny1) xo[kk * S::XS + l0 + line] = v;
+          },
+          scr, tw, twh, lane);
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < n3; t += blockDim.x) pz[t] = tw3[(t * j3) % n3];
-    // y lines (one per kept n1): transform from yb straight into ry
-    for (int b = wave; b < nby; b += 4) {
-      const int q0 = b * LW;
-      const int nl = min(LW, ny - q0);
-      wave_fft<N, 0>(yb + q0 * N, pa, pb, ry + q0 * N, nl, tw1, lane);
+    double2 *yo = yp + (long)j3 * ldy;
+    for (int bt = wave; bt < nby; bt += kPlaneWaves) {
+      const int r0 = bt * S::L;
+      const int nl = min(S::L, ny1 - r0);
+      line_batch<S>(
+          nl, [&](int line, int j) { return xo[(r0 + line) * S::XS + j]; },
+          [&](int line, int k, double2 v) {
+            int kk = k + m2;
+            if (kk >= N) kk -= N;
+            if (kk < ny2) {
+              const int col = cmap[(r0 + line) * ny2 + kk];
+              if (col >= 0) yo[col] = v;
+            }
+          },
+          scr, tw, twh, lane);
     }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < GPT; ++i) {
-      const int g = threadIdx.x + i * kPairThreads;
-      if (g < n_g) {
-        const double2 val = ry[code[i] & 0xFFFFF];
-        const double2 t = pz[code[i] >> 20];
-        acc[i].x += val.x * t.x - val.y * t.y;
-        acc[i].y += val.x * t.y + val.y * t.x;
-      }
-    }
+    if (nxo == 1) __syncthreads();
   }
-  double *row = w + ((long)vl * n_c + c) * 2L * ld_g;
-#pragma unroll
-  for (int i = 0; i < GPT; ++i) {
-    const int g = threadIdx.x + i * kPairThreads;
-    if (g < n_g) {
-      const double scl = gscale[g];
-      row[g] = acc[i].x * scl;
-      row[ld_g + g] = acc[i].y * scl;
+}
+
+// z transform of the stage for N3 = R1 R2: each wave takes L neighbouring
+// columns of one pair (four waves per work-group), transforms them along j3
+// and writes the chi0 vectors of each column, zcol[col] = (first G, lowest
+// n3, highest n3, gap): G = first + n3 - lowest, less one above n3 = 0 in
+// the (0, 0) column (gap = 1), which has no G = 0.
+constexpr int kZWaves = 4;
+template <int R1, int R2>
+__global__ __launch_bounds__(64 * kZWaves) void pair_zfft_kernel(
+    const double2 *__restrict__ yst, int ncc, int c0, int n_c, int ncol,
+    int ldy, int nblk, const int4 *__restrict__ zcol,
+    const double *__restrict__ gscale, int n_g, int ld_g,
+    const double2 *__restrict__ tw3_g, double *__restrict__ w) {
+  using S = LineSplit<R1, R2>;
+  constexpr int N = S::N;
+  extern __shared__ double2 zsm[];
+  double2 *tw = zsm;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double2 *scr = zsm + N + wave * S::L * S::SL;
+  for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t] = tw3_g[t];
+  const int q = blockIdx.x / nblk, blk = blockIdx.x - q * nblk;
+  const int vl = q / ncc, cl = q - vl * ncc;
+  const double2 *yp = yst + (long)q * N * ldy;
+  double *row = w + ((long)vl * n_c + c0 + cl) * 2L * ld_g;
+  if (blk == 0)
+    for (int g = n_g + threadIdx.x; g < ld_g; g += blockDim.x) {
+      row[g] = 0.0;
+      row[ld_g + g] = 0.0;
     }
+  __syncthreads();
+  const int cb = (blk * kZWaves + wave) * S::L;
+  if (cb >= ncol) return;
+  const int nl = min(S::L, ncol - cb);
+  const int half = N / 2;
+  line_batch<S, true>(
+      nl, [&](int line, int j) { return yp[(long)j * ldy + cb + line]; },
+      [&](int line, int k, double2 v) {
+        const int4 zc = zcol[cb + line];
+        const int n3 = k <= half ? k : k - N;
+        if (n3 >= zc.y && n3 <= zc.z && !(zc.w && n3 == 0)) {
+          const int g = zc.x + n3 - zc.y - (zc.w && n3 > 0 ? 1 : 0);
+          const double s = gscale[g];
+          row[g] = v.x * s;
+          row[ld_g + g] = v.y * s;
+        }
+      },
+      scr, tw, nullptr, lane);
+}
+
+// One work-group per pair of the chunk: the z sums of its chi0 vectors
+// (direct sum, for N3 without a staged split).
+__global__ __launch_bounds__(256) void pair_z_kernel(
+    const double2 *__restrict__ yst, int ncc, int c0, int n_c, int n3, int ldy,
+    const int *__restrict__ zcode, const double *__restrict__ gscale, int n_g,
+    int ld_g, const double2 *__restrict__ tw3_g, double *__restrict__ w) {
+  extern __shared__ double2 tw3[];
+  for (int t = threadIdx.x; t < n3; t += blockDim.x) tw3[t] = tw3_g[t];
+  __syncthreads();
+  const int q = blockIdx.x;
+  const int vl = q / ncc, cl = q - vl * ncc;
+  const double2 *yp = yst + (long)q * n3 * ldy;
+  double *row = w + ((long)vl * n_c + c0 + cl) * 2L * ld_g;
+  for (int g = threadIdx.x; g < n_g; g += blockDim.x) {
+    const int code = zcode[g];
+    const int col = code & 0xFFFFF, k3 = code >> 20;
+    const double2 *src = yp + col;
+    double2 acc = make_double2(0.0, 0.0);
+    int t = 0;
+#pragma unroll 8
+    for (int j3 = 0; j3 < n3; ++j3) {
+      const double2 v = src[(long)j3 * ldy];
+      const double2 p = tw3[t];
+      acc.x += v.x * p.x - v.y * p.y;
+      acc.y += v.x * p.y + v.y * p.x;
+      t += k3;
+      if (t >= n3) t -= n3;
+    }
+    const double s = gscale[g];
+    row[g] = acc.x * s;
+    row[ld_g + g] = acc.y * s;
   }
   for (int g = n_g + threadIdx.x; g < ld_g; g += blockDim.x) {
     row[g] = 0.0;
     row[ld_g + g] = 0.0;
   }
 }
-
 }  // namespace
 
 void upload_twiddles(System &sys) {
@@ -598,9 +711,104 @@ void launch_orbital_fft(System &sys, const double *coeff_dev,
             1.0 / std::sqrt(g.volume), s);
 }
 
+namespace {
+
+// Staged transform of one valence block: chunks of nvb x ncc pairs.
+template <int R1, int R2>
+void staged_pairs(System &sys, int v0, int nvb, const double *gscale,
+                  double *w, hipStream_t s) {
+  using S = LineSplit<R1, R2>;
+  const Geometry &g = sys.geo;
+  const int ny1 = 2 * g.m1 + 1, ny2 = 2 * g.m2 + 1;
+  const size_t ypp = stage_bytes_per_pair(g);
+  const int ncc_max = stage_chunk_c(nvb, sys.n_c, ypp);
+  sys.ystage.ensure(sys.ctx, (size_t)nvb * ncc_max * ypp);
+  // double-buffer the x outputs when that costs no work-groups per CU
+  const size_t l1 = plane_lds_bytes<S>(ny1, ny2, 1);
+  const size_t l2 = plane_lds_bytes<S>(ny1, ny2, 2);
+  const size_t cu = 160 * 1024;
+  SSRPA_REQUIRE(l1 <= cu, SSRPA_ERR_ARG, "pair transform needs %zu bytes of LDS", l1);
+  const int nxo = (l2 <= cu && cu / l2 >= cu / l1) ? 2 : 1;
+  const size_t lds = nxo == 2 ? l2 : l1;
+  auto kern = &pair_plane_kernel<R1, R2>;
+  if (lds > 64 * 1024)
+    SSRPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds));
+  const double2 *psi = sys.psi_r.as<double2>();
+  const double2 *tw = sys.fft_tw.as<double2>();
+  double2 *yst = sys.ystage.as<double2>();
+  // z: transform the columns when N3 has the same split, else direct sums
+  const bool zfft = g.n3 == S::N && 2 * g.m3 + 1 <= g.n3;
+  const int nblk = (g.ncol + kZWaves * S::L - 1) / (kZWaves * S::L);
+  const size_t zlds = sizeof(double2) * (S::N + (size_t)kZWaves * S::L * S::SL);
+  for (int c0 = 0; c0 < sys.n_c; c0 += ncc_max) {
+    const int ncc = std::min(ncc_max, sys.n_c - c0);
+    const long tiles = (long)((nvb + 7) / 8) * ((ncc + 7) / 8);
+    const long blocks = (tiles + 7) / 8 * 8 * 64;
+    SSRPA_REQUIRE(blocks < (1L << 31), SSRPA_ERR_ARG, "pair grid too large");
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kPlaneThreads), lds, s,
+                       psi, v0, nvb, sys.n_v, c0, ncc, g.n3, g.m1, g.m2, nxo,
+                       sys.cmap.as<int>(), g.ldy, tw, yst);
+    SSRPA_HIP(hipGetLastError());
+    if (zfft) {
+      const long zb = (long)nvb * ncc * nblk;
+      SSRPA_REQUIRE(zb < (1L << 31), SSRPA_ERR_ARG, "pair grid too large");
+      hipLaunchKernelGGL((pair_zfft_kernel<R1, R2>), dim3((unsigned)zb),
+                         dim3(64 * kZWaves), zlds, s, yst, ncc, c0, sys.n_c,
+                         g.ncol, g.ldy, nblk, sys.zcol.as<int4>(), gscale,
+                         g.n_g, g.ld_g, tw + g.n1 + g.n2, w);
+    } else {
+      hipLaunchKernelGGL(pair_z_kernel, dim3((unsigned)(nvb * ncc)), dim3(256),
+                         sizeof(double2) * g.n3, s, yst, ncc, c0, sys.n_c, g.n3,
+                         g.ldy, sys.zcode.as<int>(), gscale, g.n_g, g.ld_g,
+                         tw + g.n1 + g.n2, w);
+    }
+    SSRPA_HIP(hipGetLastError());
+  }
+}
+
+template <int A, int B>
+struct Split { static constexpr int r1 = A, r2 = B; };
+
+// Grid lengths with a staged schedule (N1 = N2 = R1 R2).
+template <class F>
+bool staged_dispatch(int n, F &&f) {
+  switch (n) {
+    case 18: f(Split<6, 3>{}); return true;
+    case 24: f(Split<4, 6>{}); return true;
+    case 27: f(Split<9, 3>{}); return true;
+    case 32: f(Split<4, 8>{}); return true;
+    case 36: f(Split<6, 6>{}); return true;
+    case 48: f(Split<6, 8>{}); return true;
+    case 54: f(Split<9, 6>{}); return true;
+    case 64: f(Split<8, 8>{}); return true;
+    case 72: f(Split<8, 9>{}); return true;
+    case 96: f(Split<12, 8>{}); return true;
+    default: return false;
+  }
+}
+
+}  // namespace
+
+bool staged_grid(const Geometry &g) {
+  // the x outputs and the y columns must not wrap around the grid
+  return g.n1 == g.n2 && 2 * g.m1 + 1 <= g.n1 && 2 * g.m2 + 1 <= g.n2 &&
+         staged_dispatch(g.n1, [](auto) {});
+}
+
 void launch_pair_matrix(System &sys, int v0, int nvb, bool scaled, double *w,
                         hipStream_t s) {
   const Geometry &g = sys.geo;
+  const double *gscale = sys.sqrtv_d.as<double>();
+  if (!scaled) gscale += g.ld_g;  // second half holds Omega/N only
+  if (staged_grid(g)) {
+    staged_dispatch(g.n1, [&](auto sp) {
+      using T = decltype(sp);
+      staged_pairs<T::r1, T::r2>(sys, v0, nvb, gscale, w, s);
+    });
+    return;
+  }
   PairGeo pg{};
   pg.n1 = g.n1;
   pg.n2 = g.n2;
@@ -616,8 +824,6 @@ void launch_pair_matrix(System &sys, int v0, int nvb, bool scaled, double *w,
                                           2 * pg.lx * g.n1 + ny * g.n2);
   SSRPA_REQUIRE(shmem <= 160 * 1024, SSRPA_ERR_ARG,
                 "pair FFT needs %zu bytes of LDS", shmem);
-  const double *gscale = sys.sqrtv_d.as<double>();
-  if (!scaled) gscale += g.ld_g;  // second half holds Omega/N only
   const int tiles_c = (sys.n_c + kTileC - 1) / kTileC;
   const int tiles_v = (nvb + kTileV - 1) / kTileV;
   const long blocks = (long)tiles_v * tiles_c * kTileV * kTileC;
@@ -626,42 +832,15 @@ void launch_pair_matrix(System &sys, int v0, int nvb, bool scaled, double *w,
   const double2 *psi = sys.psi_r.as<double2>();
   const int *gcol = sys.gcol.as<int>();
   const double2 *tw = sys.fft_tw.as<double2>();
-#define SSRPA_PAIR_N(G, NN)                                                  \
-  do {                                                                       \
-    if constexpr (NN > 0) {                                                  \
-      const size_t shw = sizeof(double2) *                                   \
-          (NN + 2 * g.n3 + 2 * ny * NN + 4 * 3 * wave_lines<NN>() * NN);     \
-      SSRPA_REQUIRE(shw <= 160 * 1024, SSRPA_ERR_ARG, "pair FFT LDS");      \
-      if (shw > 64 * 1024)                                                   \
-        SSRPA_HIP(hipFuncSetAttribute(                                       \
-            reinterpret_cast<const void *>(&pair_fft_wave_kernel<G, NN>),    \
-            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shw));          \
-      hipLaunchKernelGGL((pair_fft_wave_kernel<G, NN>),                      \
-                         dim3((unsigned)blocks), dim3(kPairThreads), shw, s, \
-                         psi, pg, v0, nvb, sys.n_v, sys.n_c, gcol, gscale,   \
-                         g.n_g, g.ld_g, tw, w);                              \
-    } else {                                                                 \
-      if (shmem > 64 * 1024)                                                 \
-        SSRPA_HIP(hipFuncSetAttribute(                                       \
-            reinterpret_cast<const void *>(&pair_fft_kernel<G, NN>),         \
-            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));        \
-      hipLaunchKernelGGL((pair_fft_kernel<G, NN>), dim3((unsigned)blocks),   \
-                         dim3(kPairThreads), shmem, s, psi, pg, v0, nvb,     \
-                         sys.n_v, sys.n_c, gcol, gscale, g.n_g, g.ld_g, tw,  \
-                         w);                                                 \
-    }                                                                        \
-  } while (0)
-  // grid lengths with a compile-time schedule (x = y); others run generic
-#define SSRPA_PAIR(G)                                                        \
-  do {                                                                       \
-    const int nn = g.n1 == g.n2 ? g.n1 : 0;                                  \
-    if (nn == 24) SSRPA_PAIR_N(G, 24);                                       \
-    else if (nn == 32) SSRPA_PAIR_N(G, 32);                                  \
-    else if (nn == 36) SSRPA_PAIR_N(G, 36);                                  \
-    else if (nn == 48) SSRPA_PAIR_N(G, 48);                                  \
-    else if (nn == 64) SSRPA_PAIR_N(G, 64);                                  \
-    else if (nn == 72) SSRPA_PAIR_N(G, 72);                                  \
-    else SSRPA_PAIR_N(G, 0);                                                 \
+#define SSRPA_PAIR(G)                                                         \
+  do {                                                                        \
+    if (shmem > 64 * 1024)                                                    \
+      SSRPA_HIP(hipFuncSetAttribute(                                          \
+          reinterpret_cast<const void *>(&pair_fft_kernel<G>),                \
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));           \
+    hipLaunchKernelGGL((pair_fft_kernel<G>), dim3((unsigned)blocks),          \
+                       dim3(kPairThreads), shmem, s, psi, pg, v0, nvb,        \
+                       sys.n_v, sys.n_c, gcol, gscale, g.n_g, g.ld_g, tw, w); \
   } while (0)
   if (gpt <= 2) SSRPA_PAIR(2);
   else if (gpt <= 4) SSRPA_PAIR(4);
@@ -671,7 +850,6 @@ void launch_pair_matrix(System &sys, int v0, int nvb, bool scaled, double *w,
   else if (gpt <= 64) SSRPA_PAIR(64);
   else fail(SSRPA_ERR_ARG, "chi0 basis of %d vectors is too large", g.n_g);
 #undef SSRPA_PAIR
-#undef SSRPA_PAIR_N
   SSRPA_HIP(hipGetLastError());
 }
 

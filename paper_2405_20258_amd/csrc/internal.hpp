@@ -111,7 +111,32 @@ struct Geometry {
   int ld_g;          // n_g rounded up to a multiple of 64 (zero padded)
   std::vector<int32_t> miller_chi;  // n_g x 3
   std::vector<double> sqrt_v;       // v(G)^1/2 per chi0 vector
+  // Columns (n1, n2) that hold chi0 vectors, in order of first appearance:
+  // cmap[(n1 + m1) * (2 m2 + 1) + n2 + m2] = column or -1; per G,
+  // zcode = column | (n3 mod N3) << 20.  ldy = ncol rounded up to 8.
+  // zcol[4 col ..] = (first G of the column, lowest n3, highest n3, 1 for
+  // the (0, 0) column, whose n3 = 0 member G = 0 is left out, else 0).
+  int ncol = 0, ldy = 0;
+  std::vector<int> cmap, zcode, zcol;
 };
+
+// Staged pair transform (fft.hip): the pair x-y stage holds n3 * ldy complex
+// values per pair and is processed in chunks of at most kStageBytes.
+constexpr size_t kStageBytes = size_t(4) << 30;
+inline size_t stage_bytes_per_pair(const Geometry &g) {
+  return (size_t)g.n3 * g.ldy * 16;
+}
+// Conduction bands per chunk of a block of nvb valence bands.
+inline int stage_chunk_c(int nvb, int n_c, size_t ypp) {
+  const size_t per_c = (size_t)nvb * ypp;
+  size_t c = kStageBytes / (per_c ? per_c : 1);
+  if (c >= (size_t)n_c) return n_c;
+  c = c >= 8 ? c / 8 * 8 : (c ? c : 1);
+  return (int)c;
+}
+// true when the staged kernels cover the grid (N1 = N2 with a compiled
+// split); other grids use the fused generic kernel, which needs no stage.
+bool staged_grid(const Geometry &g);
 
 // Event timing of the stages (ssrpa_stage_times).
 struct StageTimer {
@@ -151,6 +176,8 @@ struct System {
   DevBuf energy_d;               // n_b doubles
   DevBuf psi_r;                  // n_b x N3 x N2 x N1 complex (interleaved)
   DevBuf gcol;                   // per G: int (column index | n3 mod N3 << 20)
+  DevBuf zcode, cmap, zcol;      // Geometry::zcode / cmap / zcol on the device
+  DevBuf ystage;                 // x-y stage of the staged pair transform
   DevBuf sqrtv_d;                // per G: v(G)^1/2 * Omega / N
   DevBuf fft_tw;                 // twiddle tables for N1, N2, N3
   DevBuf chibar0;                // n_g x n_g complex (interleaved), symmetrized
