@@ -28,11 +28,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("χ0 GEMM TFLOP/s + time-to-E_c per system; p50/p99 E_c "
           "latency, mixed stream")
-PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+# Dense MFMA peaks of MI355X in the flops the contraction is counted in
+# (4 N_G^2 K, a complex MAC = 8 flops).  BF16x3 spends three bf16 products
+# per real product, so its peak in those flops is the bf16 peak / 3.
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": round(2500.0 / 3.0, 1)}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
 HERK_KERNEL = {"fp64": "herk_f64_kernel (static chi0)",
                "fp32": "herk_f32_kernel (static chi0)",
-               "bf16x3": "herk_bf16x3_kernel (static chi0)"}
+               "bf16x3": "split_rows_bf16_kernel + gram_bf16x3_kernel "
+                         "(static chi0)"}
 
 
 def parse():

@@ -277,7 +277,7 @@ struct Footprint {
 };
 
 Footprint footprint_of(const ssrpa_system_desc *d, const Geometry &g, int n_eig,
-                       int n_freq, int vb) {
+                       int n_freq, int vb, ssrpa_precision prec) {
   Footprint f{};
   const size_t nb = (size_t)d->n_v + d->n_c;
   const size_t box = (size_t)g.n1 * g.n2 * g.n3;
@@ -301,7 +301,16 @@ Footprint footprint_of(const ssrpa_system_desc *d, const Geometry &g, int n_eig,
   f.eig = full ? 0 : bytes_c(ng * ng) + 6 * ng * lde * 8 + 3 * bytes_c(ldg * lde);
   // the static pass: chi0 partial tiles
   const size_t gt = (ldg / 64) * (ldg / 64 + 1) / 2;
-  const size_t stat = gt * 64 * 64 * 16 * 2;
+  size_t stat = gt * 64 * 64 * 16 * 2;
+  if (prec == SSRPA_BF16X3) {
+    // split rows and 128 x 128 partial tiles of the Gram path
+    HerkArgs h{};
+    h.ncol = g.n_g;
+    h.k = (long)pairs;
+    stat = std::max(stat, herk_bf16x3_workspace(h));
+    h.ncol = (int)ne;
+    f.freq += herk_bf16x3_workspace(h);
+  }
   // the caching allocator rounds blocks up (<= 12.5%) and reuses blocks up to
   // 25% larger than asked: budget for that slack
   const size_t live = f.resident + f.block + std::max(stat, f.subspace + f.freq + f.eig);
@@ -650,20 +659,18 @@ ssrpa_status ssrpa_context_memory(const ssrpa_context *ctx, size_t *in_use,
 ssrpa_status ssrpa_footprint(const ssrpa_system_desc *desc, int n_eig,
                              int n_freq, ssrpa_precision precision,
                              int valence_block, size_t *bytes) {
-  (void)precision;
   if (!bytes) return SSRPA_ERR_ARG;
   return guarded(nullptr, [&] {
     const Geometry g = make_geometry(desc);
     SSRPA_REQUIRE(n_eig >= 1 && n_freq >= 1, SSRPA_ERR_ARG, "bad n_eig/n_freq");
     const int vb = valence_block > 0 ? std::min(valence_block, desc->n_v) : desc->n_v;
-    *bytes = footprint_of(desc, g, n_eig, n_freq, vb).total;
+    *bytes = footprint_of(desc, g, n_eig, n_freq, vb, precision).total;
   });
 }
 
 ssrpa_status ssrpa_plan_valence_block(const ssrpa_system_desc *desc, int n_eig,
                                       int n_freq, ssrpa_precision precision,
                                       size_t budget_bytes, int *valence_block) {
-  (void)precision;
   if (!valence_block) return SSRPA_ERR_ARG;
   *valence_block = 0;
   return guarded(nullptr, [&] {
@@ -672,7 +679,7 @@ ssrpa_status ssrpa_plan_valence_block(const ssrpa_system_desc *desc, int n_eig,
     int lo = 1, hi = desc->n_v, best = 0;
     while (lo <= hi) {
       const int mid = (lo + hi) / 2;
-      if (footprint_of(desc, g, n_eig, n_freq, mid).total <= budget_bytes) {
+      if (footprint_of(desc, g, n_eig, n_freq, mid, precision).total <= budget_bytes) {
         best = mid;
         lo = mid + 1;
       } else {

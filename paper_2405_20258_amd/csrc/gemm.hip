@@ -353,6 +353,10 @@ void herk(Context *ctx, const HerkArgs &h, ssrpa_precision prec, double *out,
           long out_stride, int beta, DevBuf &ws, hipStream_t s) {
   SSRPA_REQUIRE(h.ld % kT == 0 && h.ncol <= h.ld, SSRPA_ERR_ARG,
                 "herk: bad padding");
+  if (prec == SSRPA_BF16X3) {
+    herk_bf16x3_gram(ctx, h, out, out_stride, beta, ws, s);
+    return;
+  }
   const int T = h.ld / kT;
   const int n_tiles = T * (T + 1) / 2;
   // split K so that there are at least ~2 blocks per CU

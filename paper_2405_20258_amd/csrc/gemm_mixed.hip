@@ -603,7 +603,295 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(GemmArgs g,
       }
 }
 
+// ---------------------------------------------- BF16x3 Gram contraction
+//
+// The BF16x3 HERK runs as two passes per K chunk.  split_rows_bf16_kernel
+// scales row p by sqrt|d_p| (the row weights d_p of one HERK all have one
+// sign) and splits each real component into hi + lo bf16, in a K-blocked
+// layout wb[kb][part][col][32 rows] (part = re hi, re lo, im hi, im lo), so
+// that a lane's MFMA operand, 8 consecutive rows of one column, is a single
+// 16-byte load.  gram_bf16x3_kernel then forms sum_p conj(x_p[I]) x_p[J]
+// over 128 x 128 tiles of the lower triangle; its FP32 accumulators are
+// added into the block's own FP64 partial tile every kGFlushSteps K steps,
+// and gram_reduce_kernel sums the split-K partials in order, restores the
+// sign of the weights (and the J-side factor) and mirrors the Hermitian half.
+
+constexpr int kGT = 128;          // Gram tile side
+constexpr int kGFlushSteps = 32;  // K steps of 32 rows between FP64 flushes
+constexpr int kGColStride = 5;    // uint4 per column in LDS (4 + 1 pad)
+constexpr size_t kGChunkBytes = size_t(1) << 30;  // per copy
+constexpr size_t kGLds = 2 * 4 * kGT * kGColStride * sizeof(uint4);
+
+// Writes two split copies of the chunk: wb (the I operand) from s_p x and
+// wb + half (the J operand) from kGJScale s_p x.  With one copy, lo_I lo_J
+// on the diagonal would be lo^2 >= 0 for every row and the dropped lo*lo'
+// term would bias the diagonal by ~2^-16/3 relative; splitting the J side
+// from 3x rounds it independently, so the dropped terms average out.
+constexpr double kGJScale = 3.0;
+
+__global__ __launch_bounds__(256) void split_rows_bf16_kernel(
+    HerkArgs h, long k0, int nrows, int ldb, int om_i, uint4 *__restrict__ wb,
+    long half) {
+  const int col = blockIdx.x * 256 + threadIdx.x;
+  const int kb = blockIdx.y;
+  if (col >= ldb) return;
+  const double om = h.unit_weight ? 0.0 : h.omega[om_i];
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const double f = side ? kGJScale : 1.0;
+    unsigned pk[4][16];  // [part][row pair]: two bf16 per word, even row low
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+      const int r = kb * 32 + t;
+      double xr = 0.0, xi = 0.0;
+      if (r < nrows && col < h.ncol) {
+        const long p = k0 + r;
+        const double sc = f * (h.unit_weight ? 1.0 : sqrt(-weight_m(h, p, om)));
+        const double *src = h.a + p * h.lda + col;
+        xr = src[0] * sc;
+        xi = src[h.im_off] * sc;
+      }
+      unsigned short v[4];
+      split_bf16(xr, v[0], v[1]);
+      split_bf16(xi, v[2], v[3]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (t & 1)
+          pk[q][t >> 1] |= (unsigned)v[q] << 16;
+        else
+          pk[q][t >> 1] = v[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint4 *dst = wb + side * half + (((long)kb * 4 + q) * ldb + col) * 4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        dst[u] = make_uint4(pk[q][4 * u], pk[q][4 * u + 1], pk[q][4 * u + 2],
+                            pk[q][4 * u + 3]);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(
+    const uint4 *__restrict__ wb, int ldb, int nkb, int T, int n_tiles,
+    int kb_per_split, long half, double *__restrict__ partial) {
+  extern __shared__ uint4 gsm[];
+  uint4 *As = gsm;                          // [part][col][kGColStride]
+  uint4 *Bs = gsm + 4 * kGT * kGColStride;
+  const int tile_id = xcd_remap_m(blockIdx.x, n_tiles);
+  const int split = blockIdx.y;
+  const int2 tile = tri_tile_m(tile_id, T);
+  const int I0 = tile.x * kGT, J0 = tile.y * kGT;
+  const int kb0 = split * kb_per_split;
+  const int kb1 = min(nkb, kb0 + kb_per_split);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  const int q = lane >> 4, cl = lane & 15;
+  double *pt = partial + ((long)split * n_tiles + tile_id) * 2L * kGT * kGT;
+  f4 re[4][4], im[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      re[i][j] = f4{0, 0, 0, 0};
+      im[i][j] = f4{0, 0, 0, 0};
+    }
+  // partial tiles start zeroed (a fill before the first chunk): every flush
+  // adds, so the code has no per-element branches
+  // Per-lane offsets; the empty asm statements mark them as redefined on
+  // every use, so the compiler rebuilds the 64 flush addresses and the 16
+  // staging addresses from them instead of hoisting (and spilling) them.
+  int foff = (wr + accf_row(lane, 0)) * kGT + wc + accf_col(lane);
+  int soff = (threadIdx.x >> 2) * 4 + (threadIdx.x & 3);
+  auto flush = [&]() __attribute__((always_inline)) {
+    asm volatile("" : "+v"(foff));
+    double *pl = pt + foff;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          double *p0 = pl + (i * 16 + e) * kGT + j * 16;
+          p0[0] += (double)re[i][j][e];
+          p0[kGT * kGT] += (double)im[i][j][e];
+          re[i][j][e] = 0.f;
+          im[i][j][e] = 0.f;
+        }
+  };
+  int steps = 0;
+  for (int kb = kb0; kb < kb1; ++kb) {
+    __syncthreads();
+    asm volatile("" : "+v"(soff));
+    const uint4 *src = wb + (long)kb * 16 * ldb + soff;
+    // item it: operand it / 8 (the J operand from the second copy), part
+    // (it / 2) % 4, columns + 64 (it % 2)
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+      const int op = it >> 3, part = (it >> 1) & 3, hc = it & 1;
+      const uint4 v =
+          src[op * half + (part * ldb + (op ? J0 : I0) + 64 * hc) * 4];
+      const int col = (soff >> 2) + 64 * hc;
+      (op ? Bs : As)[(part * kGT + col) * kGColStride + (soff & 3)] = v;
+    }
+    __syncthreads();
+    bf8 a[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp)
+        a[i][pp] = __builtin_bit_cast(
+            bf8, As[(pp * kGT + wr + i * 16 + cl) * kGColStride + q]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bf8 b[4];
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp)
+        b[pp] = __builtin_bit_cast(
+            bf8, Bs[(pp * kGT + wc + j * 16 + cl) * kGColStride + q]);
+      const bf8 nbh = neg_bf8(b[0]), nbl = neg_bf8(b[1]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        // Re += ar br + ai bi;  Im += ar bi - ai br  (hi*hi + hi*lo + lo*hi)
+        re[i][j] = mfmabf(a[i][0], b[0], re[i][j]);
+        re[i][j] = mfmabf(a[i][0], b[1], re[i][j]);
+        re[i][j] = mfmabf(a[i][1], b[0], re[i][j]);
+        re[i][j] = mfmabf(a[i][2], b[2], re[i][j]);
+        re[i][j] = mfmabf(a[i][2], b[3], re[i][j]);
+        re[i][j] = mfmabf(a[i][3], b[2], re[i][j]);
+        im[i][j] = mfmabf(a[i][0], b[2], im[i][j]);
+        im[i][j] = mfmabf(a[i][0], b[3], im[i][j]);
+        im[i][j] = mfmabf(a[i][1], b[2], im[i][j]);
+        im[i][j] = mfmabf(a[i][2], nbh, im[i][j]);
+        im[i][j] = mfmabf(a[i][2], nbl, im[i][j]);
+        im[i][j] = mfmabf(a[i][3], nbh, im[i][j]);
+      }
+    }
+    if (++steps == kGFlushSteps || kb + 1 == kb1) {
+      flush();
+      steps = 0;
+    }
+  }
+}
+
+__global__ void gram_reduce_kernel(const double *__restrict__ partial,
+                                   int n_tiles, int T, int nsplit, int ncol,
+                                   double sign, double *__restrict__ out,
+                                   int beta) {
+  const int tile_id = blockIdx.x;
+  const int2 tile = tri_tile_m(tile_id, T);
+  const int I0 = tile.x * kGT, J0 = tile.y * kGT;
+  for (int e = threadIdx.x; e < kGT * kGT; e += blockDim.x) {
+    const int r = e / kGT, c = e % kGT;
+    const int g = I0 + r, gp = J0 + c;
+    if (g >= ncol || gp >= ncol) continue;
+    if (tile.x == tile.y && r < c) continue;
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < nsplit; ++s) {
+      const double *p = partial + ((long)s * n_tiles + tile_id) * 2L * kGT * kGT;
+      sr += p[e];
+      si += p[kGT * kGT + e];
+    }
+    sr *= sign;
+    si *= sign;
+    if (g == gp) si = 0.0;  // the diagonal of a Gram matrix is real
+    double *d1 = out + 2L * ((long)g * ncol + gp);
+    double *d2 = out + 2L * ((long)gp * ncol + g);
+    if (beta) {
+      d1[0] += sr;
+      d1[1] += si;
+      if (g != gp) {
+        d2[0] += sr;
+        d2[1] -= si;
+      }
+    } else {
+      d1[0] = sr;
+      d1[1] = si;
+      if (g != gp) {
+        d2[0] = sr;
+        d2[1] = -si;
+      }
+    }
+  }
+}
+
 }  // namespace
+
+// Work space of the BF16x3 Gram path: split-K partials and one K chunk of
+// split rows.
+struct GramPlan {
+  int ldb, T, n_tiles, nsplit, kb_per_split;
+  long kc, nchunks;
+  size_t partial_bytes, wb_bytes;
+};
+
+static GramPlan gram_plan(const HerkArgs &h) {
+  GramPlan p{};
+  p.ldb = round_up(std::max(h.ncol, 1), kGT);
+  p.T = p.ldb / kGT;
+  p.n_tiles = p.T * (p.T + 1) / 2;
+  const size_t row_bytes = (size_t)p.ldb * 8;  // 4 parts x 2 B per column
+  const long kmax = std::max<long>(32, (long)(kGChunkBytes / row_bytes) / 32 * 32);
+  const long k32 = std::max<long>(32, (h.k + 31) / 32 * 32);
+  p.kc = std::min(kmax, k32);
+  p.nchunks = std::max<long>(1, (h.k + p.kc - 1) / p.kc);
+  const int nkb = (int)(p.kc / 32);
+  // about two blocks per CU over the tiles and splits of one frequency
+  int nsplit = std::max(1, std::min(nkb, (512 + p.n_tiles - 1) / p.n_tiles));
+  p.kb_per_split = (nkb + nsplit - 1) / nsplit;
+  p.nsplit = (nkb + p.kb_per_split - 1) / p.kb_per_split;
+  p.partial_bytes = sizeof(double) * 2L * kGT * kGT * p.n_tiles * p.nsplit;
+  p.wb_bytes = 2 * (size_t)p.kc * row_bytes;  // I and J copies
+  return p;
+}
+
+size_t herk_bf16x3_workspace(const HerkArgs &h) {
+  const GramPlan p = gram_plan(h);
+  return p.partial_bytes + p.wb_bytes;
+}
+
+void herk_bf16x3_gram(Context *ctx, const HerkArgs &h, double *out,
+                      long out_stride, int beta, DevBuf &ws, hipStream_t s) {
+  const GramPlan p = gram_plan(h);
+  ws.ensure(ctx, p.partial_bytes + p.wb_bytes);
+  double *partial = ws.as<double>();
+  uint4 *wb = reinterpret_cast<uint4 *>(ws.as<char>() + p.partial_bytes);
+  const long half = (long)(p.wb_bytes / 2 / sizeof(uint4));
+  static bool attr = [] {
+    SSRPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&gram_bf16x3_kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)kGLds));
+    return true;
+  }();
+  (void)attr;
+  const int ti = (h.timer && h.timer->on) ? h.timer->start(h.stage, s) : -1;
+  for (int om = 0; om < h.n_omega; ++om) {
+    fill_zero(partial, p.partial_bytes, s);
+    for (long c = 0; c < p.nchunks; ++c) {
+      const long k0 = c * p.kc;
+      const int nrows = (int)std::max<long>(0, std::min(p.kc, h.k - k0));
+      const int nkb = (nrows + 31) / 32;
+      if (nkb > 0) {
+        hipLaunchKernelGGL(split_rows_bf16_kernel,
+                           dim3((unsigned)((p.ldb + 255) / 256), (unsigned)nkb),
+                           dim3(256), 0, s, h, k0, nrows, p.ldb, om, wb, half);
+        SSRPA_HIP(hipGetLastError());
+      }
+      hipLaunchKernelGGL(gram_bf16x3_kernel,
+                         dim3((unsigned)p.n_tiles, (unsigned)p.nsplit), dim3(256),
+                         kGLds, s, wb, p.ldb, nkb, p.T, p.n_tiles, p.kb_per_split,
+                         half, partial);
+      SSRPA_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)p.n_tiles), dim3(256), 0,
+                       s, partial, p.n_tiles, p.T, p.nsplit, h.ncol,
+                       (h.unit_weight ? 1.0 : -1.0) / kGJScale,
+                       out + om * out_stride, beta);
+    SSRPA_HIP(hipGetLastError());
+  }
+  if (ti >= 0) h.timer->stop(ti, s);
+}
 
 // K rows per stage of the reduced-precision HERK kernels.
 int herk_mixed_kstage(ssrpa_precision prec) {

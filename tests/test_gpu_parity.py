@@ -170,6 +170,28 @@ def test_chi0_static_ragged(env, symmetrized):
     g.close()
 
 
+@pytest.mark.parametrize("prec,tol", [("bf16x3", 2e-5), ("fp32", 2e-5)])
+def test_chi0_reduced_precision_ragged(env, prec, tol):
+    """The reduced-precision chi0 contraction against the FP64 one, element
+    by element (max-norm relative), and exactly Hermitian."""
+    torch, ssrpa, ctx = env
+    s = ragged_system()
+    g = ssrpa.System.from_synthetic(ctx, s)
+    n = g.n_g
+    ref = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+    out = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+    _log(f"chi0 ragged {prec}")
+    g.chi0_static("fp64", out_dev=ref, symmetrized=True)
+    g.chi0_static(prec, out_dev=out, symmetrized=True)
+    torch.cuda.synchronize()
+    a, b = out.cpu().numpy(), ref.cpu().numpy()
+    err = np.max(np.abs(a - b)) / np.max(np.abs(b))
+    _log(f"chi0 {prec} vs fp64 rel err {err:.2e}")
+    assert 0.0 < err < tol
+    assert np.max(np.abs(a - a.conj().T)) == 0.0
+    g.close()
+
+
 def test_chi0_valence_block_invariance(env):
     torch, ssrpa, ctx = env
     s = ragged_system()
