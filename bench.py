@@ -34,7 +34,7 @@ METRIC = ("χ0 GEMM TFLOP/s + time-to-E_c per system; p50/p99 E_c "
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": round(2500.0 / 3.0, 1)}
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
 HERK_KERNEL = {"fp64": "herk_f64_kernel (static chi0)",
-               "fp32": "herk_f32_kernel (static chi0)",
+               "fp32": "split_rows_f32_kernel + gram_f32_kernel (static chi0)",
                "bf16x3": "split_rows_bf16_kernel + gram_bf16x3_kernel "
                          "(static chi0)"}
 
@@ -63,9 +63,12 @@ def parse():
                     help="also run one plain device copy of this many MiB "
                          "(reference dispatch for the FETCH_SIZE/WRITE_SIZE "
                          "counter scale)")
-    ap.add_argument("--traffic-json", default="",
+    ap.add_argument("--traffic-json",
+                    default=os.path.join(ROOT, "profiles",
+                                         "herk_f64_medium_traffic.json"),
                     help="counter summary (profiles/*.json) whose scaled "
-                         "FETCH+WRITE bytes per launch fill roofline.traffic")
+                         "FETCH+WRITE bytes per launch fill roofline.traffic "
+                         "when its kernel and workload match this run")
     return ap.parse_args()
 
 
@@ -258,7 +261,8 @@ def main():
         del src, dst
     if args.traffic_json and os.path.exists(args.traffic_json):
         tj = json.load(open(args.traffic_json))
-        if tj.get("kernel_signature") == out["roofline"]["kernel"]:
+        if (tj.get("kernel_signature") == out["roofline"]["kernel"] and
+                tj.get("workload") == out["config"]["workload"]):
             out["roofline"]["traffic"] = tj["bytes_per_launch"]
             out["roofline"]["traffic_note"] = tj.get("note", "")
     if args.serve:

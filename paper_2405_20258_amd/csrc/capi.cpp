@@ -302,14 +302,16 @@ Footprint footprint_of(const ssrpa_system_desc *d, const Geometry &g, int n_eig,
   // the static pass: chi0 partial tiles
   const size_t gt = (ldg / 64) * (ldg / 64 + 1) / 2;
   size_t stat = gt * 64 * 64 * 16 * 2;
-  if (prec == SSRPA_BF16X3) {
-    // split rows and 128 x 128 partial tiles of the Gram path
+  if (prec != SSRPA_FP64) {
+    // converted rows and 128 x 128 partial tiles of the Gram path
     HerkArgs h{};
     h.ncol = g.n_g;
     h.k = (long)pairs;
-    stat = std::max(stat, herk_bf16x3_workspace(h));
+    h.n_omega = 1;
+    stat = std::max(stat, herk_gram_workspace(h, prec));
     h.ncol = (int)ne;
-    f.freq += herk_bf16x3_workspace(h);
+    h.n_omega = n_freq;
+    f.freq += herk_gram_workspace(h, prec);
   }
   // the caching allocator rounds blocks up (<= 12.5%) and reuses blocks up to
   // 25% larger than asked: budget for that slack

@@ -343,9 +343,6 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g, int m_tiles,
 }  // namespace
 
 // reduced-precision launchers (gemm_mixed.hip)
-int herk_mixed_kstage(ssrpa_precision prec);
-void herk_mixed_launch(const HerkArgs &h, ssrpa_precision prec, int n_tiles,
-                       long nsplit, long kchunk, double *partial, hipStream_t s);
 void gemm_mixed_launch(const GemmArgs &g, ssrpa_precision prec, int m_tiles,
                        int n_tiles, hipStream_t s);
 
@@ -353,14 +350,14 @@ void herk(Context *ctx, const HerkArgs &h, ssrpa_precision prec, double *out,
           long out_stride, int beta, DevBuf &ws, hipStream_t s) {
   SSRPA_REQUIRE(h.ld % kT == 0 && h.ncol <= h.ld, SSRPA_ERR_ARG,
                 "herk: bad padding");
-  if (prec == SSRPA_BF16X3) {
-    herk_bf16x3_gram(ctx, h, out, out_stride, beta, ws, s);
+  if (prec != SSRPA_FP64) {
+    herk_gram(ctx, h, prec, out, out_stride, beta, ws, s);
     return;
   }
   const int T = h.ld / kT;
   const int n_tiles = T * (T + 1) / 2;
   // split K so that there are at least ~2 blocks per CU
-  const int kst = prec == SSRPA_FP64 ? kKc : herk_mixed_kstage(prec);
+  const int kst = kKc;
   const long kr = (h.k + kst - 1) / kst;
   long nsplit = (512 + (long)n_tiles * h.n_omega - 1) / ((long)n_tiles * h.n_omega);
   nsplit = std::max(1L, std::min(nsplit, std::max(1L, kr / 8)));
@@ -372,13 +369,9 @@ void herk(Context *ctx, const HerkArgs &h, ssrpa_precision prec, double *out,
   DevBuf *wsb = &ws;
   if (h.k > 0) {
     const int ti = (h.timer && h.timer->on) ? h.timer->start(h.stage, s) : -1;
-    if (prec == SSRPA_FP64) {
-      hipLaunchKernelGGL(herk_f64_kernel, dim3(n_tiles, (unsigned)nsplit, h.n_omega),
-                         dim3(256), 0, s, h, n_tiles, kchunk, wsb->as<double>());
-      SSRPA_HIP(hipGetLastError());
-    } else {
-      herk_mixed_launch(h, prec, n_tiles, nsplit, kchunk, wsb->as<double>(), s);
-    }
+    hipLaunchKernelGGL(herk_f64_kernel, dim3(n_tiles, (unsigned)nsplit, h.n_omega),
+                       dim3(256), 0, s, h, n_tiles, kchunk, wsb->as<double>());
+    SSRPA_HIP(hipGetLastError());
     if (ti >= 0) h.timer->stop(ti, s);
   } else {
     fill_zero(wsb->as(), need, s);

@@ -104,116 +104,7 @@ __device__ __forceinline__ bf8 neg_bf8(bf8 a) {
   return __builtin_bit_cast(bf8, v);
 }
 
-// ------------------------------------------------------------- HERK FP32
-
-constexpr int kKc32 = 16;
-
-__global__ __launch_bounds__(256) void herk_f32_kernel(
-    HerkArgs h, int n_tiles, long kchunk, double *__restrict__ partial) {
-  __shared__ float As[2][kKc32][kT + 4];
-  __shared__ float Bs[2][kKc32][kT + 4];
-  __shared__ double wk[kKc32];
-  const int tile_id = xcd_remap_m(blockIdx.x, n_tiles);
-  const int split = blockIdx.y;
-  const int om_i = blockIdx.z;
-  const int2 tile = tri_tile_m(tile_id, h.ld / kT);
-  const int I0 = tile.x * kT, J0 = tile.y * kT;
-  const double om = h.unit_weight ? 0.0 : h.omega[om_i];
-  const long kbeg = split * kchunk;
-  const long kend = min(h.k, kbeg + kchunk);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  f4 re[2][2], im[2][2];
-  d4m Re[2][2], Im[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      re[i][j] = f4{0, 0, 0, 0}; im[i][j] = f4{0, 0, 0, 0};
-      Re[i][j] = d4m{0, 0, 0, 0}; Im[i][j] = d4m{0, 0, 0, 0};
-    }
-  int since = 0;
-  for (long k0 = kbeg; k0 < kend; k0 += kKc32) {
-    if (threadIdx.x < kKc32) {
-      const long p = k0 + threadIdx.x;
-      wk[threadIdx.x] = p < kend ? weight_m(h, p, om) : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int idx = threadIdx.x + it * 256;
-      const int op = idx >> 9, part = (idx >> 8) & 1;
-      const int r = (idx >> 4) & 15, c2 = (idx & 15) * 2;
-      const long p = k0 + r;
-      const int col0 = op ? J0 : I0;
-      double2 v = make_double2(0.0, 0.0), u = make_double2(0.0, 0.0);
-      if (p < kend) {
-        const double *src = h.a + p * h.lda + part * h.im_off + col0;
-        v = *reinterpret_cast<const double2 *>(src + c2);
-        u = *reinterpret_cast<const double2 *>(src + c2 + 32);
-      }
-      const double sc = op ? wk[r] : 1.0;
-      float *dst = op ? &Bs[part][r][0] : &As[part][r][0];
-      dst[c2] = (float)(v.x * sc);
-      dst[c2 + 1] = (float)(v.y * sc);
-      dst[c2 + 32] = (float)(u.x * sc);
-      dst[c2 + 33] = (float)(u.y * sc);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < kKc32; ks += 4) {
-      const int kr = ks + (lane >> 4), cl = lane & 15;
-      float ar[2], ai[2], br[2], bi[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        ar[i] = As[0][kr][wr + i * 16 + cl];
-        ai[i] = As[1][kr][wr + i * 16 + cl];
-        br[i] = Bs[0][kr][wc + i * 16 + cl];
-        bi[i] = Bs[1][kr][wc + i * 16 + cl];
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          re[i][j] = mfma32(ar[i], br[j], re[i][j]);
-          re[i][j] = mfma32(ai[i], bi[j], re[i][j]);
-          im[i][j] = mfma32(ar[i], bi[j], im[i][j]);
-          im[i][j] = mfma32(-ai[i], br[j], im[i][j]);
-        }
-    }
-    __syncthreads();
-    since += kKc32;
-    if (since >= kFlush) {
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            Re[i][j][e] += (double)re[i][j][e];
-            Im[i][j][e] += (double)im[i][j][e];
-            re[i][j][e] = 0.f;
-            im[i][j][e] = 0.f;
-          }
-      since = 0;
-    }
-  }
-  double *out = partial + (((long)om_i * gridDim.y + split) * n_tiles + tile_id) *
-                              2L * kT * kT;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = wr + i * 16 + accf_row(lane, e);
-        const int c = wc + j * 16 + accf_col(lane);
-        out[r * kT + c] = Re[i][j][e] + (double)re[i][j][e];
-        out[kT * kT + r * kT + c] = Im[i][j][e] + (double)im[i][j][e];
-      }
-}
-
-// ----------------------------------------------------------- HERK BF16x3
+// ------------------------------------------------- BF16x3 operand staging
 
 constexpr int kKb = 32;         // K rows per stage = one bf16 MFMA
 constexpr int kKbP = kKb + 8;   // LDS row length (bf16), 16-byte aligned
@@ -223,131 +114,6 @@ struct alignas(16) BfTile {
   unsigned short v[2][2][kT][kKbP];
 };
 
-__device__ __forceinline__ void stage_bf16(BfTile &t, const HerkArgs &h,
-                                           long k0, long kend, int col0,
-                                           const double *wk, bool weighted) {
-  // 2 parts x 32 rows x 64 columns = 4096 values; 256 threads x 8 (2 x 4)
-#pragma unroll
-  for (int it = 0; it < 8; ++it) {
-    const int idx = threadIdx.x + it * 256;   // 0..2047 (pairs of columns)
-    const int part = idx >> 10;
-    const int r = (idx >> 5) & 31;
-    const int c2 = (idx & 31) * 2;
-    const long p = k0 + r;
-    double2 v = make_double2(0.0, 0.0);
-    if (p < kend)
-      v = *reinterpret_cast<const double2 *>(h.a + p * h.lda + part * h.im_off +
-                                             col0 + c2);
-    const double sc = weighted ? wk[r] : 1.0;
-    unsigned short hi, lo;
-    split_bf16(v.x * sc, hi, lo);
-    t.v[part][0][c2][r] = hi;
-    t.v[part][1][c2][r] = lo;
-    split_bf16(v.y * sc, hi, lo);
-    t.v[part][0][c2 + 1][r] = hi;
-    t.v[part][1][c2 + 1][r] = lo;
-  }
-}
-
-__global__ __launch_bounds__(256) void herk_bf16x3_kernel(
-    HerkArgs h, int n_tiles, long kchunk, double *__restrict__ partial) {
-  __shared__ BfTile At, Bt;
-  __shared__ double wk[kKb];
-  const int tile_id = xcd_remap_m(blockIdx.x, n_tiles);
-  const int split = blockIdx.y;
-  const int om_i = blockIdx.z;
-  const int2 tile = tri_tile_m(tile_id, h.ld / kT);
-  const int I0 = tile.x * kT, J0 = tile.y * kT;
-  const double om = h.unit_weight ? 0.0 : h.omega[om_i];
-  const long kbeg = split * kchunk;
-  const long kend = min(h.k, kbeg + kchunk);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  const int ko = 8 * (lane >> 4), cl = lane & 15;
-  f4 re[2][2], im[2][2];
-  d4m Re[2][2], Im[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      re[i][j] = f4{0, 0, 0, 0}; im[i][j] = f4{0, 0, 0, 0};
-      Re[i][j] = d4m{0, 0, 0, 0}; Im[i][j] = d4m{0, 0, 0, 0};
-    }
-  int since = 0;
-  for (long k0 = kbeg; k0 < kend; k0 += kKb) {
-    if (threadIdx.x < kKb) {
-      const long p = k0 + threadIdx.x;
-      wk[threadIdx.x] = p < kend ? weight_m(h, p, om) : 0.0;
-    }
-    __syncthreads();
-    stage_bf16(At, h, k0, kend, I0, wk, false);
-    stage_bf16(Bt, h, k0, kend, J0, wk, true);
-    __syncthreads();
-    bf8 arh[2], arl[2], aih[2], ail[2], brh[2], brl[2], bih[2], bil[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int ma = wr + i * 16 + cl, mb = wc + i * 16 + cl;
-      arh[i] = load_bf8(&At.v[0][0][ma][ko]);
-      arl[i] = load_bf8(&At.v[0][1][ma][ko]);
-      aih[i] = load_bf8(&At.v[1][0][ma][ko]);
-      ail[i] = load_bf8(&At.v[1][1][ma][ko]);
-      brh[i] = load_bf8(&Bt.v[0][0][mb][ko]);
-      brl[i] = load_bf8(&Bt.v[0][1][mb][ko]);
-      bih[i] = load_bf8(&Bt.v[1][0][mb][ko]);
-      bil[i] = load_bf8(&Bt.v[1][1][mb][ko]);
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const bf8 naih = neg_bf8(aih[i]), nail = neg_bf8(ail[i]);
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        // Re += ar br + ai bi
-        re[i][j] = mfmabf(arh[i], brh[j], re[i][j]);
-        re[i][j] = mfmabf(arh[i], brl[j], re[i][j]);
-        re[i][j] = mfmabf(arl[i], brh[j], re[i][j]);
-        re[i][j] = mfmabf(aih[i], bih[j], re[i][j]);
-        re[i][j] = mfmabf(aih[i], bil[j], re[i][j]);
-        re[i][j] = mfmabf(ail[i], bih[j], re[i][j]);
-        // Im += ar bi - ai br
-        im[i][j] = mfmabf(arh[i], bih[j], im[i][j]);
-        im[i][j] = mfmabf(arh[i], bil[j], im[i][j]);
-        im[i][j] = mfmabf(arl[i], bih[j], im[i][j]);
-        im[i][j] = mfmabf(naih, brh[j], im[i][j]);
-        im[i][j] = mfmabf(naih, brl[j], im[i][j]);
-        im[i][j] = mfmabf(nail, brh[j], im[i][j]);
-      }
-    }
-    __syncthreads();
-    since += kKb;
-    if (since >= kFlush) {
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            Re[i][j][e] += (double)re[i][j][e];
-            Im[i][j][e] += (double)im[i][j][e];
-            re[i][j][e] = 0.f;
-            im[i][j][e] = 0.f;
-          }
-      since = 0;
-    }
-  }
-  double *out = partial + (((long)om_i * gridDim.y + split) * n_tiles + tile_id) *
-                              2L * kT * kT;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = wr + i * 16 + accf_row(lane, e);
-        const int c = wc + j * 16 + accf_col(lane);
-        out[r * kT + c] = Re[i][j][e] + (double)re[i][j][e];
-        out[kT * kT + r * kT + c] = Im[i][j][e] + (double)im[i][j][e];
-      }
-}
 
 // ------------------------------------------------------------- GEMM FP32
 
@@ -603,18 +369,22 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(GemmArgs g,
       }
 }
 
-// ---------------------------------------------- BF16x3 Gram contraction
+// ------------------------------------------ reduced-precision contractions
 //
-// The BF16x3 HERK runs as two passes per K chunk.  split_rows_bf16_kernel
-// scales row p by sqrt|d_p| (the row weights d_p of one HERK all have one
-// sign) and splits each real component into hi + lo bf16, in a K-blocked
-// layout wb[kb][part][col][32 rows] (part = re hi, re lo, im hi, im lo), so
-// that a lane's MFMA operand, 8 consecutive rows of one column, is a single
-// 16-byte load.  gram_bf16x3_kernel then forms sum_p conj(x_p[I]) x_p[J]
-// over 128 x 128 tiles of the lower triangle; its FP32 accumulators are
-// added into the block's own FP64 partial tile every kGFlushSteps K steps,
-// and gram_reduce_kernel sums the split-K partials in order, restores the
-// sign of the weights (and the J-side factor) and mirrors the Hermitian half.
+// The FP32 and BF16x3 HERKs convert each row once per K chunk into a
+// K-blocked layout [kb][part][col][rows of the block] with the rows of one
+// column contiguous (64 B), so that a lane's MFMA operand (consecutive rows
+// of one column) is a single 16-byte load; a Gram kernel then forms
+// sum_p conj(a_p[I]) b_p[J] over 128 x 128 tiles of the lower triangle.
+// FP32 accumulators are added into the block's own FP64 partial tile every
+// 1024 rows, and gram_reduce_kernel sums the split-K partials in order and
+// mirrors the Hermitian half (deterministic).
+//  * BF16x3: the I operand is the rows as they are, the J operand the rows
+//    times d_p; each real part is split hi + lo (bf16) and a product is
+//    hi hi' + hi lo' + lo hi'.  For several frequencies the I copy of the
+//    whole K range is split once and reused.
+//  * FP32: one copy of the rows times sqrt|d_p| (the d_p of one HERK have
+//    one sign, restored by the reduction), rounded to FP32.
 
 constexpr int kGT = 128;          // Gram tile side
 constexpr int kGFlushSteps = 32;  // K steps of 32 rows between FP64 flushes
@@ -622,60 +392,58 @@ constexpr int kGColStride = 5;    // uint4 per column in LDS (4 + 1 pad)
 constexpr size_t kGChunkBytes = size_t(1) << 30;  // per copy
 constexpr size_t kGLds = 2 * 4 * kGT * kGColStride * sizeof(uint4);
 
-// Writes two split copies of the chunk: wb (the I operand) from s_p x and
-// wb + half (the J operand) from kGJScale s_p x.  With one copy, lo_I lo_J
-// on the diagonal would be lo^2 >= 0 for every row and the dropped lo*lo'
-// term would bias the diagonal by ~2^-16/3 relative; splitting the J side
-// from 3x rounds it independently, so the dropped terms average out.
+// Splits one copy of a K chunk: the I operand from the rows as they are
+// (weighted = 0), the J operand from d_p x (weighted = 1; kGJScale x for a
+// unit-weight Gram matrix).  The J copy is rounded independently of the I
+// copy, so the dropped lo_I lo_J' products average out; with one copy for
+// both they would be lo^2 >= 0 on the diagonal and bias it by ~2^-16/3.
 constexpr double kGJScale = 3.0;
 
 __global__ __launch_bounds__(256) void split_rows_bf16_kernel(
-    HerkArgs h, long k0, int nrows, int ldb, int om_i, uint4 *__restrict__ wb,
-    long half) {
+    HerkArgs h, long k0, int nrows, int ldb, int om_i, int weighted,
+    uint4 *__restrict__ wb) {
   const int col = blockIdx.x * 256 + threadIdx.x;
   const int kb = blockIdx.y;
   if (col >= ldb) return;
   const double om = h.unit_weight ? 0.0 : h.omega[om_i];
+  unsigned pk[4][16];  // [part][row pair]: two bf16 per word, even row low
 #pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    const double f = side ? kGJScale : 1.0;
-    unsigned pk[4][16];  // [part][row pair]: two bf16 per word, even row low
-#pragma unroll
-    for (int t = 0; t < 32; ++t) {
-      const int r = kb * 32 + t;
-      double xr = 0.0, xi = 0.0;
-      if (r < nrows && col < h.ncol) {
-        const long p = k0 + r;
-        const double sc = f * (h.unit_weight ? 1.0 : sqrt(-weight_m(h, p, om)));
-        const double *src = h.a + p * h.lda + col;
-        xr = src[0] * sc;
-        xi = src[h.im_off] * sc;
-      }
-      unsigned short v[4];
-      split_bf16(xr, v[0], v[1]);
-      split_bf16(xi, v[2], v[3]);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (t & 1)
-          pk[q][t >> 1] |= (unsigned)v[q] << 16;
-        else
-          pk[q][t >> 1] = v[q];
-      }
+  for (int t = 0; t < 32; ++t) {
+    const int r = kb * 32 + t;
+    double xr = 0.0, xi = 0.0;
+    if (r < nrows && col < h.ncol) {
+      const long p = k0 + r;
+      const double sc = !weighted ? 1.0
+                        : (h.unit_weight ? kGJScale : weight_m(h, p, om));
+      const double *src = h.a + p * h.lda + col;
+      xr = src[0] * sc;
+      xi = src[h.im_off] * sc;
     }
+    unsigned short v[4];
+    split_bf16(xr, v[0], v[1]);
+    split_bf16(xi, v[2], v[3]);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      uint4 *dst = wb + side * half + (((long)kb * 4 + q) * ldb + col) * 4;
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        dst[u] = make_uint4(pk[q][4 * u], pk[q][4 * u + 1], pk[q][4 * u + 2],
-                            pk[q][4 * u + 3]);
+      if (t & 1)
+        pk[q][t >> 1] |= (unsigned)v[q] << 16;
+      else
+        pk[q][t >> 1] = v[q];
     }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    uint4 *dst = wb + (((long)kb * 4 + q) * ldb + col) * 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      dst[u] = make_uint4(pk[q][4 * u], pk[q][4 * u + 1], pk[q][4 * u + 2],
+                          pk[q][4 * u + 3]);
   }
 }
 
 __global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(
-    const uint4 *__restrict__ wb, int ldb, int nkb, int T, int n_tiles,
-    int kb_per_split, long half, double *__restrict__ partial) {
+    const uint4 *__restrict__ wi, const uint4 *__restrict__ wj, int ldb,
+    int nkb, int T, int n_tiles, int kb_per_split,
+    double *__restrict__ partial) {
   extern __shared__ uint4 gsm[];
   uint4 *As = gsm;                          // [part][col][kGColStride]
   uint4 *Bs = gsm + 4 * kGT * kGColStride;
@@ -724,14 +492,15 @@ __global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(
   for (int kb = kb0; kb < kb1; ++kb) {
     __syncthreads();
     asm volatile("" : "+v"(soff));
-    const uint4 *src = wb + (long)kb * 16 * ldb + soff;
-    // item it: operand it / 8 (the J operand from the second copy), part
-    // (it / 2) % 4, columns + 64 (it % 2)
+    const uint4 *si = wi + (long)kb * 16 * ldb + soff;
+    const uint4 *sj = wj + (long)kb * 16 * ldb + soff;
+    // item it: operand it / 8 (I, then J), part (it / 2) % 4, columns
+    // + 64 (it % 2)
 #pragma unroll
     for (int it = 0; it < 16; ++it) {
       const int op = it >> 3, part = (it >> 1) & 3, hc = it & 1;
       const uint4 v =
-          src[op * half + (part * ldb + (op ? J0 : I0) + 64 * hc) * 4];
+          (op ? sj : si)[(part * ldb + (op ? J0 : I0) + 64 * hc) * 4];
       const int col = (soff >> 2) + 64 * hc;
       (op ? Bs : As)[(part * kGT + col) * kGColStride + (soff & 3)] = v;
     }
@@ -775,6 +544,143 @@ __global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(
   }
 }
 
+// FP32 form of the Gram pass: one copy wf[kb][part][col][16 floats] (part =
+// re, im) of the scaled rows rounded to FP32 (no split, so no bias term);
+// in each 16-row block position 4q + s holds row 4s + q, so that lane q's
+// 16-byte load carries its rows for the four 16x16x4 MFMA steps.
+constexpr int kFFlushSteps = 64;  // 16-row steps between FP64 flushes
+constexpr size_t kFLds = 2 * 2 * kGT * kGColStride * sizeof(uint4);
+
+__global__ __launch_bounds__(256) void split_rows_f32_kernel(
+    HerkArgs h, long k0, int nrows, int ldb, int om_i, uint4 *__restrict__ wf) {
+  const int col = blockIdx.x * 256 + threadIdx.x;
+  const int kb = blockIdx.y;
+  if (col >= ldb) return;
+  const double om = h.unit_weight ? 0.0 : h.omega[om_i];
+  float v[2][16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int r = kb * 16 + t;
+    double xr = 0.0, xi = 0.0;
+    if (r < nrows && col < h.ncol) {
+      const long p = k0 + r;
+      const double sc = h.unit_weight ? 1.0 : sqrt(-weight_m(h, p, om));
+      const double *src = h.a + p * h.lda + col;
+      xr = src[0] * sc;
+      xi = src[h.im_off] * sc;
+    }
+    const int pos = 4 * (t & 3) + (t >> 2);  // row t = 4 s + q -> 4 q + s
+    v[0][pos] = (float)xr;
+    v[1][pos] = (float)xi;
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    uint4 *dst = wf + (((long)kb * 2 + q) * ldb + col) * 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      dst[u] = make_uint4(__float_as_uint(v[q][4 * u]), __float_as_uint(v[q][4 * u + 1]),
+                          __float_as_uint(v[q][4 * u + 2]),
+                          __float_as_uint(v[q][4 * u + 3]));
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void gram_f32_kernel(
+    const uint4 *__restrict__ wf, int ldb, int nkb, int T, int n_tiles,
+    int kb_per_split, double *__restrict__ partial) {
+  extern __shared__ uint4 fsm[];
+  uint4 *As = fsm;                          // [part][col][kGColStride]
+  uint4 *Bs = fsm + 2 * kGT * kGColStride;
+  const int tile_id = xcd_remap_m(blockIdx.x, n_tiles);
+  const int split = blockIdx.y;
+  const int2 tile = tri_tile_m(tile_id, T);
+  const int I0 = tile.x * kGT, J0 = tile.y * kGT;
+  const int kb0 = split * kb_per_split;
+  const int kb1 = min(nkb, kb0 + kb_per_split);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  const int q = lane >> 4, cl = lane & 15;
+  double *pt = partial + ((long)split * n_tiles + tile_id) * 2L * kGT * kGT;
+  f4 re[4][4], im[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      re[i][j] = f4{0, 0, 0, 0};
+      im[i][j] = f4{0, 0, 0, 0};
+    }
+  int foff = (wr + accf_row(lane, 0)) * kGT + wc + accf_col(lane);
+  int soff = (threadIdx.x >> 2) * 4 + (threadIdx.x & 3);
+  auto flush = [&]() __attribute__((always_inline)) {
+    asm volatile("" : "+v"(foff));
+    double *pl = pt + foff;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          double *p0 = pl + (i * 16 + e) * kGT + j * 16;
+          p0[0] += (double)re[i][j][e];
+          p0[kGT * kGT] += (double)im[i][j][e];
+          re[i][j][e] = 0.f;
+          im[i][j][e] = 0.f;
+        }
+  };
+  int steps = 0;
+  for (int kb = kb0; kb < kb1; ++kb) {
+    __syncthreads();
+    asm volatile("" : "+v"(soff));
+    const uint4 *src = wf + (long)kb * 8 * ldb + soff;
+    // item it: operand it / 4, part (it / 2) % 2, columns + 64 (it % 2)
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int op = it >> 2, part = (it >> 1) & 1, hc = it & 1;
+      const uint4 v = src[(part * ldb + (op ? J0 : I0) + 64 * hc) * 4];
+      const int col = (soff >> 2) + 64 * hc;
+      (op ? Bs : As)[(part * kGT + col) * kGColStride + (soff & 3)] = v;
+    }
+    __syncthreads();
+    uint4 a[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp)
+        a[i][pp] = As[(pp * kGT + wr + i * 16 + cl) * kGColStride + q];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint4 b[2];
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp)
+        b[pp] = Bs[(pp * kGT + wc + j * 16 + cl) * kGColStride + q];
+      const float br[4] = {__uint_as_float(b[0].x), __uint_as_float(b[0].y),
+                           __uint_as_float(b[0].z), __uint_as_float(b[0].w)};
+      const float bi[4] = {__uint_as_float(b[1].x), __uint_as_float(b[1].y),
+                           __uint_as_float(b[1].z), __uint_as_float(b[1].w)};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float ar[4] = {__uint_as_float(a[i][0].x), __uint_as_float(a[i][0].y),
+                             __uint_as_float(a[i][0].z), __uint_as_float(a[i][0].w)};
+        const float ai[4] = {__uint_as_float(a[i][1].x), __uint_as_float(a[i][1].y),
+                             __uint_as_float(a[i][1].z), __uint_as_float(a[i][1].w)};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          // Re += ar br + ai bi;  Im += ar bi - ai br
+          re[i][j] = mfma32(ar[s], br[s], re[i][j]);
+          re[i][j] = mfma32(ai[s], bi[s], re[i][j]);
+          im[i][j] = mfma32(ar[s], bi[s], im[i][j]);
+          im[i][j] = mfma32(ai[s], -br[s], im[i][j]);
+        }
+      }
+    }
+    if (++steps == kFFlushSteps || kb + 1 == kb1) {
+      flush();
+      steps = 0;
+    }
+  }
+}
+
+// One block per (tile, 1/kGRedParts of its elements).
+constexpr int kGRedParts = 16;
 __global__ void gram_reduce_kernel(const double *__restrict__ partial,
                                    int n_tiles, int T, int nsplit, int ncol,
                                    double sign, double *__restrict__ out,
@@ -782,7 +688,9 @@ __global__ void gram_reduce_kernel(const double *__restrict__ partial,
   const int tile_id = blockIdx.x;
   const int2 tile = tri_tile_m(tile_id, T);
   const int I0 = tile.x * kGT, J0 = tile.y * kGT;
-  for (int e = threadIdx.x; e < kGT * kGT; e += blockDim.x) {
+  constexpr int per = kGT * kGT / kGRedParts;
+  const int e0 = blockIdx.y * per;
+  for (int e = e0 + threadIdx.x; e < e0 + per; e += blockDim.x) {
     const int r = e / kGT, c = e % kGT;
     const int g = I0 + r, gp = J0 + c;
     if (g >= ncol || gp >= ncol) continue;
@@ -795,7 +703,7 @@ __global__ void gram_reduce_kernel(const double *__restrict__ partial,
     }
     sr *= sign;
     si *= sign;
-    if (g == gp) si = 0.0;  // the diagonal of a Gram matrix is real
+    if (g == gp) si = 0.0;  // the diagonal of A^H D A is real
     double *d1 = out + 2L * ((long)g * ncol + gp);
     double *d2 = out + 2L * ((long)gp * ncol + g);
     if (beta) {
@@ -818,46 +726,60 @@ __global__ void gram_reduce_kernel(const double *__restrict__ partial,
 
 }  // namespace
 
-// Work space of the BF16x3 Gram path: split-K partials and one K chunk of
-// split rows.
+// Work space of the Gram paths: split-K partials and converted rows.
+//  * FP32: one copy of a K chunk.
+//  * BF16x3, one matrix: an I and a J copy of a K chunk.
+//  * BF16x3, several frequencies: the I copy of the whole K range (split
+//    once) and a J copy of a K chunk per frequency.
 struct GramPlan {
-  int ldb, T, n_tiles, nsplit, kb_per_split;
+  int ldb, T, n_tiles, nsplit, kb_per_split, rows_step;
+  bool resident_i;
   long kc, nchunks;
-  size_t partial_bytes, wb_bytes;
+  size_t partial_bytes, i_bytes, j_bytes;
 };
 
-static GramPlan gram_plan(const HerkArgs &h) {
+static GramPlan gram_plan(const HerkArgs &h, ssrpa_precision prec) {
   GramPlan p{};
+  const bool bf = prec == SSRPA_BF16X3;
+  p.rows_step = bf ? 32 : 16;
   p.ldb = round_up(std::max(h.ncol, 1), kGT);
   p.T = p.ldb / kGT;
   p.n_tiles = p.T * (p.T + 1) / 2;
-  const size_t row_bytes = (size_t)p.ldb * 8;  // 4 parts x 2 B per column
+  // 8 bytes per column and row in both forms (4 bf16 parts or 2 floats)
+  const size_t row_bytes = (size_t)p.ldb * 8;
   const long kmax = std::max<long>(32, (long)(kGChunkBytes / row_bytes) / 32 * 32);
   const long k32 = std::max<long>(32, (h.k + 31) / 32 * 32);
   p.kc = std::min(kmax, k32);
   p.nchunks = std::max<long>(1, (h.k + p.kc - 1) / p.kc);
-  const int nkb = (int)(p.kc / 32);
+  const int nkb = (int)(p.kc / p.rows_step);
   // about two blocks per CU over the tiles and splits of one frequency
   int nsplit = std::max(1, std::min(nkb, (512 + p.n_tiles - 1) / p.n_tiles));
   p.kb_per_split = (nkb + nsplit - 1) / nsplit;
   p.nsplit = (nkb + p.kb_per_split - 1) / p.kb_per_split;
   p.partial_bytes = sizeof(double) * 2L * kGT * kGT * p.n_tiles * p.nsplit;
-  p.wb_bytes = 2 * (size_t)p.kc * row_bytes;  // I and J copies
+  p.resident_i = bf && h.n_omega > 1;
+  p.i_bytes = p.resident_i ? (size_t)(p.nchunks * p.kc) * row_bytes
+                           : (size_t)p.kc * row_bytes;
+  p.j_bytes = bf ? (size_t)p.kc * row_bytes : 0;
   return p;
 }
 
-size_t herk_bf16x3_workspace(const HerkArgs &h) {
-  const GramPlan p = gram_plan(h);
-  return p.partial_bytes + p.wb_bytes;
+size_t herk_gram_workspace(const HerkArgs &h, ssrpa_precision prec) {
+  const GramPlan p = gram_plan(h, prec);
+  return p.partial_bytes + p.i_bytes + p.j_bytes;
 }
 
-void herk_bf16x3_gram(Context *ctx, const HerkArgs &h, double *out,
-                      long out_stride, int beta, DevBuf &ws, hipStream_t s) {
-  const GramPlan p = gram_plan(h);
-  ws.ensure(ctx, p.partial_bytes + p.wb_bytes);
+void herk_gram(Context *ctx, const HerkArgs &h, ssrpa_precision prec,
+               double *out, long out_stride, int beta, DevBuf &ws,
+               hipStream_t s) {
+  SSRPA_REQUIRE(prec == SSRPA_FP32 || prec == SSRPA_BF16X3, SSRPA_ERR_ARG,
+                "herk_gram: FP32 or BF16x3 only");
+  const bool bf = prec == SSRPA_BF16X3;
+  const GramPlan p = gram_plan(h, prec);
+  ws.ensure(ctx, p.partial_bytes + p.i_bytes + p.j_bytes);
   double *partial = ws.as<double>();
-  uint4 *wb = reinterpret_cast<uint4 *>(ws.as<char>() + p.partial_bytes);
-  const long half = (long)(p.wb_bytes / 2 / sizeof(uint4));
+  uint4 *wi = reinterpret_cast<uint4 *>(ws.as<char>() + p.partial_bytes);
+  uint4 *wj = reinterpret_cast<uint4 *>(ws.as<char>() + p.partial_bytes + p.i_bytes);
   static bool attr = [] {
     SSRPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&gram_bf16x3_kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -865,50 +787,63 @@ void herk_bf16x3_gram(Context *ctx, const HerkArgs &h, double *out,
     return true;
   }();
   (void)attr;
+  const dim3 gg((unsigned)p.n_tiles, (unsigned)p.nsplit);
+  const long blk_stride = 16L * p.ldb;  // uint4 per row block (both forms)
+  auto chunk_rows = [&](long c) {
+    return (int)std::max<long>(0, std::min(p.kc, h.k - c * p.kc));
+  };
+  auto split_grid = [&](int nkb) {
+    return dim3((unsigned)((p.ldb + 255) / 256), (unsigned)nkb);
+  };
   const int ti = (h.timer && h.timer->on) ? h.timer->start(h.stage, s) : -1;
+  if (p.resident_i) {
+    for (long c = 0; c < p.nchunks; ++c) {
+      const int nkb = (chunk_rows(c) + 31) / 32;
+      if (nkb > 0)
+        hipLaunchKernelGGL(split_rows_bf16_kernel, split_grid(nkb), dim3(256), 0,
+                           s, h, c * p.kc, chunk_rows(c), p.ldb, 0, 0,
+                           wi + c * (p.kc / 32) * blk_stride);
+    }
+    SSRPA_HIP(hipGetLastError());
+  }
   for (int om = 0; om < h.n_omega; ++om) {
     fill_zero(partial, p.partial_bytes, s);
     for (long c = 0; c < p.nchunks; ++c) {
       const long k0 = c * p.kc;
-      const int nrows = (int)std::max<long>(0, std::min(p.kc, h.k - k0));
-      const int nkb = (nrows + 31) / 32;
-      if (nkb > 0) {
-        hipLaunchKernelGGL(split_rows_bf16_kernel,
-                           dim3((unsigned)((p.ldb + 255) / 256), (unsigned)nkb),
-                           dim3(256), 0, s, h, k0, nrows, p.ldb, om, wb, half);
-        SSRPA_HIP(hipGetLastError());
+      const int nrows = chunk_rows(c);
+      const int nkb = (nrows + p.rows_step - 1) / p.rows_step;
+      if (bf) {
+        const uint4 *ci = wi;
+        if (p.resident_i) {
+          ci = wi + c * (p.kc / 32) * blk_stride;
+        } else if (nkb > 0) {
+          hipLaunchKernelGGL(split_rows_bf16_kernel, split_grid(nkb), dim3(256), 0,
+                             s, h, k0, nrows, p.ldb, om, 0, wi);
+        }
+        if (nkb > 0)
+          hipLaunchKernelGGL(split_rows_bf16_kernel, split_grid(nkb), dim3(256), 0,
+                             s, h, k0, nrows, p.ldb, om, 1, wj);
+        hipLaunchKernelGGL(gram_bf16x3_kernel, gg, dim3(256), kGLds, s, ci, wj,
+                           p.ldb, nkb, p.T, p.n_tiles, p.kb_per_split, partial);
+      } else {
+        if (nkb > 0)
+          hipLaunchKernelGGL(split_rows_f32_kernel, split_grid(nkb), dim3(256), 0,
+                             s, h, k0, nrows, p.ldb, om, wi);
+        hipLaunchKernelGGL(gram_f32_kernel, gg, dim3(256), kFLds, s, wi, p.ldb,
+                           nkb, p.T, p.n_tiles, p.kb_per_split, partial);
       }
-      hipLaunchKernelGGL(gram_bf16x3_kernel,
-                         dim3((unsigned)p.n_tiles, (unsigned)p.nsplit), dim3(256),
-                         kGLds, s, wb, p.ldb, nkb, p.T, p.n_tiles, p.kb_per_split,
-                         half, partial);
       SSRPA_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)p.n_tiles), dim3(256), 0,
-                       s, partial, p.n_tiles, p.T, p.nsplit, h.ncol,
-                       (h.unit_weight ? 1.0 : -1.0) / kGJScale,
-                       out + om * out_stride, beta);
+    // BF16x3 carries the sign in d_p (and a factor kGJScale for unit
+    // weights); FP32 used sqrt|d_p| on both sides
+    const double scale = bf ? (h.unit_weight ? 1.0 / kGJScale : 1.0)
+                            : (h.unit_weight ? 1.0 : -1.0);
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)p.n_tiles, kGRedParts),
+                       dim3(256), 0, s, partial, p.n_tiles, p.T, p.nsplit, h.ncol,
+                       scale, out + om * out_stride, beta);
     SSRPA_HIP(hipGetLastError());
   }
   if (ti >= 0) h.timer->stop(ti, s);
-}
-
-// K rows per stage of the reduced-precision HERK kernels.
-int herk_mixed_kstage(ssrpa_precision prec) {
-  return prec == SSRPA_BF16X3 ? kKb : kKc32;
-}
-
-void herk_mixed_launch(const HerkArgs &h, ssrpa_precision prec, int n_tiles,
-                       long nsplit, long kchunk, double *partial,
-                       hipStream_t s) {
-  const dim3 grid(n_tiles, (unsigned)nsplit, h.n_omega);
-  if (prec == SSRPA_FP32)
-    hipLaunchKernelGGL(herk_f32_kernel, grid, dim3(256), 0, s, h, n_tiles,
-                       kchunk, partial);
-  else
-    hipLaunchKernelGGL(herk_bf16x3_kernel, grid, dim3(256), 0, s, h, n_tiles,
-                       kchunk, partial);
-  SSRPA_HIP(hipGetLastError());
 }
 
 void gemm_mixed_launch(const GemmArgs &g, ssrpa_precision prec, int m_tiles,

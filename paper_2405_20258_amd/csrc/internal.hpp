@@ -232,11 +232,13 @@ struct HerkArgs {
 // ws: caller-owned workspace for split-K partial tiles (grown as needed).
 void herk(Context *ctx, const HerkArgs &h, ssrpa_precision prec, double *out,
           long out_stride, int beta, DevBuf &ws, hipStream_t s);
-// BF16x3 form of herk (gemm_mixed.hip): rows pre-split once per K chunk,
-// 128 x 128 MFMA Gram tiles; herk dispatches to it.  workspace: ws bytes.
-void herk_bf16x3_gram(Context *ctx, const HerkArgs &h, double *out,
-                      long out_stride, int beta, DevBuf &ws, hipStream_t s);
-size_t herk_bf16x3_workspace(const HerkArgs &h);
+// FP32 and BF16x3 forms of herk (gemm_mixed.hip): rows scaled by
+// sqrt|d| and converted once per K chunk, 128 x 128 MFMA Gram tiles; herk
+// dispatches to it.  herk_gram_workspace: bytes of ws it needs.
+void herk_gram(Context *ctx, const HerkArgs &h, ssrpa_precision prec,
+               double *out, long out_stride, int beta, DevBuf &ws,
+               hipStream_t s);
+size_t herk_gram_workspace(const HerkArgs &h, ssrpa_precision prec);
 // C = alpha * A * B + beta * C for complex planar operands:
 //   A: m x k rows (row stride lda, im at +a_im), B: k x n (row stride ldb,
 //   im at +b_im), C: m x n (row stride ldc, im at +c_im).  k is a multiple of
