@@ -63,6 +63,10 @@ def parse():
                     help="also run one plain device copy of this many MiB "
                          "(reference dispatch for the FETCH_SIZE/WRITE_SIZE "
                          "counter scale)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also run the mixed-precision sweep: E_c at N_eig = "
+                         "5/10/20%% of N_G in FP64, FP32 and BF16x3, with "
+                         "times and errors against FP64 and FP64 full RPA")
     ap.add_argument("--traffic-json",
                     default=os.path.join(ROOT, "profiles",
                                          "herk_f64_medium_traffic.json"),
@@ -101,6 +105,58 @@ def cpu_baseline(s, n_vb):
                        f"({t1 - t0:.1f} s, not in the rate); contraction "
                        f"{t3 - t2:.2f} s"),
             "host_cpus": os.cpu_count()}
+
+
+def precision_sweep(ssrpa, ctx, s, om, wt, coeff_d, stream):
+    """E_c of one system at N_eig = 5, 10 and 20 % of N_G in each precision.
+
+    Per precision a fresh system (pair transform), one static chi0, then per
+    N_eig the subspace and E_c; time = system + chi0 + subspace + E_c.  The
+    reference is the FP64 full-RPA E_c (N_eig = N_G) of the same system."""
+    import torch
+
+    def clock():
+        torch.cuda.synchronize()
+        return time.perf_counter()
+
+    g = ssrpa.System(ctx, s.a, s.fft, s.miller, coeff_d, s.energy, s.n_v,
+                     s.ecut_chi, stream)
+    n_g = g.n_g
+    g.chi0_static("fp64")
+    t0 = clock()
+    ec_full, _ = g.correlation_energy(n_g, om, wt, "fp64")
+    t_full = clock() - t0
+    g.close()
+    print(f"# sweep: full RPA E_c = {ec_full!r}", file=sys.stderr, flush=True)
+    n_eigs = [int(round(f * n_g)) for f in (0.05, 0.10, 0.20)]
+    rows = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        t0 = clock()
+        g = ssrpa.System(ctx, s.a, s.fft, s.miller, coeff_d, s.energy, s.n_v,
+                         s.ecut_chi, stream)
+        g.chi0_static(prec)
+        t_chi = clock() - t0
+        for n in n_eigs:
+            t1 = clock()
+            g.subspace(n)
+            ec, _ = g.correlation_energy(n, om, wt, prec)
+            t_solve = clock() - t1
+            rows[(prec, n)] = (ec, (t_chi + t_solve) * 1e3)
+            print(f"# sweep: {prec} N_eig {n}: E_c = {ec!r}", file=sys.stderr,
+                  flush=True)
+        g.close()
+    out = []
+    for n in n_eigs:
+        e64, t64 = rows[("fp64", n)]
+        for prec in ("fp64", "fp32", "bf16x3"):
+            ec, ms = rows[(prec, n)]
+            out.append({"precision": prec, "n_eig": n, "ec": ec,
+                        "time_ms": round(ms, 2),
+                        "speedup_vs_fp64": round(t64 / ms, 3),
+                        "rel_err_vs_fp64_same_n_eig": abs(ec - e64) / abs(e64),
+                        "rel_err_vs_fp64_full_rpa": abs(ec - ec_full) / abs(ec_full)})
+    return {"n_g": n_g, "ec_full_rpa_fp64": ec_full,
+            "full_rpa_freq_time_ms": round(t_full * 1e3, 2), "rows": out}
 
 
 def serve_stream(ssrpa, ctx, n_req, rate, max_running):
@@ -265,6 +321,9 @@ def main():
                 tj.get("workload") == out["config"]["workload"]):
             out["roofline"]["traffic"] = tj["bytes_per_launch"]
             out["roofline"]["traffic_note"] = tj.get("note", "")
+    if args.sweep:
+        out["precision_sweep"] = precision_sweep(ssrpa, ctx, s, om, wt,
+                                                 coeff_d, stream)
     if args.serve:
         out["serving"] = serve_stream(ssrpa, ctx, args.serve_requests,
                                       args.serve_rate, args.serve_max_running)

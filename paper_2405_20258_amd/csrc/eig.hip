@@ -13,8 +13,8 @@
 //     matrix (the part of the row that the reduction no longer needs).
 //  2. A diagonal unitary D makes T = D^H T_c D real symmetric with off-
 //     diagonal |e_k|.
-//  3. Sturm-sequence bisection for the n_eig smallest eigenvalues of T (one
-//     thread per eigenvalue).
+//  3. Sturm-sequence multisection for the n_eig smallest eigenvalues of T
+//     (one wave per eigenvalue, 64 brackets per round).
 //  4. Inverse iteration on T - lambda I with a partially pivoted tridiagonal
 //     LU (one thread per group of nearly equal eigenvalues; vectors of one
 //     group are orthogonalized against each other at every iteration).
@@ -336,22 +336,34 @@ __device__ int sturm_count(const double *d, const double *e, int n,
   return cnt;
 }
 
-__global__ void bisect_kernel(TriReal r, int n, int n_eig,
-                              double *__restrict__ lam) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Multisection: one wave per eigenvalue.  Each round evaluates the Sturm
+// count at the 63 interior points of 64 equal parts of [lo, hi], one per
+// lane, and keeps the part holding eigenvalue i (the count at its left end
+// is <= i, at its right end > i); a round narrows the bracket 64-fold
+// instead of 2-fold.  lo and hi stay uniform across the wave.
+__global__ __launch_bounds__(64) void multisect_kernel(TriReal r, int n,
+                                                       int n_eig,
+                                                       double *__restrict__ lam) {
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
   if (i >= n_eig) return;
   double lo = r.bounds[0], hi = r.bounds[1];
   const double pivmin = r.bounds[3];
-  for (int it = 0; it < 128; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
+  for (int round = 0; round < 32; ++round) {
     if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
-    if (sturm_count(r.d, r.e, n, mid, pivmin) > i)
-      hi = mid;
-    else
-      lo = mid;
+    const double h = (hi - lo) * (1.0 / 64.0);
+    const double x = lane < 63 ? lo + h * (lane + 1) : hi;
+    const bool above =
+        lane == 63 || (x > lo && sturm_count(r.d, r.e, n, x, pivmin) > i);
+    const unsigned long long mask = __ballot(above);
+    const int first = __ffsll((long long)mask) - 1;   // lane 63 is always set
+    const double nlo = first == 0 ? lo : fmin(lo + h * first, hi);
+    const double nhi = first == 63 ? hi : fmin(lo + h * (first + 1), hi);
+    if (nlo == lo && nhi == hi) break;   // no representable progress
+    lo = nlo;
+    hi = nhi;
   }
-  lam[i] = 0.5 * (lo + hi);
+  if (lane == 0) lam[i] = 0.5 * (lo + hi);
 }
 
 // ------------------------------------------------------ inverse iteration
@@ -402,22 +414,70 @@ __device__ void tri_lu(const InvIt &q, int n, int col, double lam, double tiny) 
   q.u0[o] = r0; q.u1[o] = 0.0; q.u2[o] = 0.0; q.ml[o] = 0.0; q.pv[o] = 0;
 }
 
-// x <- (T - lam I)^-1 x (x is column col of z), then normalize.
+// x <- (T - lam I)^-1 x (x is column col of z).  Both substitutions run in
+// chunks of kSolveChunk rows whose coefficients and right-hand sides are
+// loaded before the dependent recurrence, so the loads of a chunk overlap
+// instead of each waiting behind the previous step.
+constexpr int kSolveChunk = 8;
 __device__ void tri_solve(const InvIt &q, int n, int col) {
   const long ld = q.ldz;
   double *x = q.z + col;
-  for (int i = 0; i < n - 1; ++i) {
-    const long o = (long)i * ld + col;
-    double a = x[i * ld], b = x[(i + 1) * ld];
-    if (q.pv[o]) { const double t = a; a = b; b = t; }
-    x[i * ld] = a;
-    x[(i + 1) * ld] = b - q.ml[o] * a;
+  const double *ml = q.ml + col, *u0 = q.u0 + col, *u1 = q.u1 + col,
+               *u2 = q.u2 + col;
+  const unsigned char *pv = q.pv + col;
+  // forward: step i pivots rows i, i+1; a carries the updated x[i]
+  double a = x[0];
+  int i = 0;
+  for (; i + kSolveChunk < n; i += kSolveChunk) {
+    double b[kSolveChunk], m[kSolveChunk];
+    unsigned char p[kSolveChunk];
+#pragma unroll
+    for (int u = 0; u < kSolveChunk; ++u) {
+      b[u] = x[(long)(i + 1 + u) * ld];
+      m[u] = ml[(long)(i + u) * ld];
+      p[u] = pv[(long)(i + u) * ld];
+    }
+#pragma unroll
+    for (int u = 0; u < kSolveChunk; ++u) {
+      double aa = a, bb = b[u];
+      if (p[u]) { const double t = aa; aa = bb; bb = t; }
+      x[(long)(i + u) * ld] = aa;
+      a = bb - m[u] * aa;
+    }
   }
+  for (; i < n - 1; ++i) {
+    const long o = (long)i * ld;
+    double aa = a, bb = x[o + ld];
+    if (pv[o]) { const double t = aa; aa = bb; bb = t; }
+    x[o] = aa;
+    a = bb - ml[o] * aa;
+  }
+  x[(long)(n - 1) * ld] = a;
+  // backward: v_i = (x_i - u1_i v_{i+1} - u2_i v_{i+2}) / u0_i
   double xp1 = 0.0, xp2 = 0.0;
-  for (int i = n - 1; i >= 0; --i) {
-    const long o = (long)i * ld + col;
-    const double v = (x[i * ld] - q.u1[o] * xp1 - q.u2[o] * xp2) / q.u0[o];
-    x[i * ld] = v;
+  i = n - 1;
+  for (; i + 1 >= kSolveChunk; i -= kSolveChunk) {
+    double xv[kSolveChunk], c0[kSolveChunk], c1[kSolveChunk], c2[kSolveChunk];
+#pragma unroll
+    for (int u = 0; u < kSolveChunk; ++u) {
+      const long o = (long)(i - u) * ld;
+      xv[u] = x[o];
+      c0[u] = u0[o];
+      c1[u] = u1[o];
+      c2[u] = u2[o];
+    }
+#pragma unroll
+    for (int u = 0; u < kSolveChunk; ++u) {
+      const double v = (xv[u] - c1[u] * xp1 - c2[u] * xp2) / c0[u];
+      x[(long)(i - u) * ld] = v;
+      xp2 = xp1;
+      xp1 = v;
+    }
+  }
+  for (; i >= 0; --i) {
+    const long o = (long)i * ld;
+    const double v = (x[o] - u1[o] * xp1 - u2[o] * xp2) / u0[o];
+    x[o] = v;
     xp2 = xp1;
     xp1 = v;
   }
@@ -723,8 +783,8 @@ void eig_lowest(Context *ctx, const double *a_in, int n, int n_eig,
   r.bounds = rw.as<double>() + n;
   hipLaunchKernelGGL(tri_phase_kernel, dim3(1), dim3(64), 0, s,
                      (const double2 *)t.e, r, n);
-  hipLaunchKernelGGL(bisect_kernel, dim3((n_eig + 63) / 64), dim3(64), 0, s, r,
-                     n, n_eig, eigval);
+  hipLaunchKernelGGL(multisect_kernel, dim3(n_eig), dim3(64), 0, s, r, n,
+                     n_eig, eigval);
   SSRPA_HIP(hipGetLastError());
 
   // inverse iteration workspace: z, u0, u1, u2, ml (doubles) + pivots
