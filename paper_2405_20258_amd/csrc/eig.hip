@@ -628,13 +628,18 @@ __global__ __launch_bounds__(256) void wy_t_kernel(const double2 *__restrict__ a
     out[idx] = T[idx / kWy][idx % kWy];
 }
 
-// Partial W1 = V^H C over a chunk of rows: part[chunk][j][e].
+// Partial W1 = V^H C over a chunk of rows: part[chunk][j][e].  The
+// reflectors of the block are staged in LDS kWySub rows at a time (zero
+// outside their support), so the row loop reads them as broadcasts and only
+// the C loads go to memory.
 constexpr int kWyRows = 128;
+constexpr int kWySub = 64;
 __global__ __launch_bounds__(256) void wy_vhc_kernel(const double2 *__restrict__ a,
                                                      int n, int k0, int nb,
                                                      const double *__restrict__ c,
                                                      int ld_e, int n_eig,
                                                      double2 *__restrict__ part) {
+  __shared__ double2 vs[kWySub][kWy];
   const int e = blockIdx.x * 64 + (threadIdx.x & 63);
   const int jg = threadIdx.x >> 6;           // 0..3, 8 reflectors each
   const int chunk = blockIdx.y;
@@ -643,15 +648,24 @@ __global__ __launch_bounds__(256) void wy_vhc_kernel(const double2 *__restrict__
   double2 acc[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
-  if (e < n_eig) {
-    for (int r = r0; r < r1; ++r) {
-      const double cr = c[(long)r * 2 * ld_e + e];
-      const double ci = c[(long)r * 2 * ld_e + ld_e + e];
+  for (int s0 = r0; s0 < r1; s0 += kWySub) {
+    const int m = min(kWySub, r1 - s0);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kWySub * kWy; idx += blockDim.x) {
+      const int rr = idx % kWySub, j = idx / kWySub;
+      vs[rr][j] = (j < nb && rr < m) ? vref(a, n, k0 + j, s0 + rr)
+                                     : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    if (e < n_eig) {
+      const double *cr_p = c + (long)s0 * 2 * ld_e + e;
+#pragma unroll 4
+      for (int rr = 0; rr < m; ++rr) {
+        const double cr = cr_p[(long)rr * 2 * ld_e];
+        const double ci = cr_p[(long)rr * 2 * ld_e + ld_e];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int j = jg * 8 + q;
-        if (j < nb) {
-          const double2 v = vref(a, n, k0 + j, r);
+        for (int q = 0; q < 8; ++q) {
+          const double2 v = vs[rr][jg * 8 + q];
           acc[q].x += v.x * cr + v.y * ci;   // conj(v) c
           acc[q].y += v.x * ci - v.y * cr;
         }
