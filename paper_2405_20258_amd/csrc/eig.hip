@@ -678,18 +678,21 @@ __global__ __launch_bounds__(256) void wy_vhc_kernel(const double2 *__restrict__
     if (e < ld_e) p[(long)(jg * 8 + q) * ld_e + e] = acc[q];
 }
 
-// W2 = T (sum over chunks of the partials): w2[j][e].
+// W2 = T (sum over chunks of the partials): w2[j][e].  A block takes 16
+// columns e; thread (e, jq) sums the partials of reflectors 2 jq, 2 jq + 1.
+constexpr int kTwCols = 16;
 __global__ __launch_bounds__(256) void wy_tw_kernel(const double2 *__restrict__ part,
                                                     int n_chunks,
                                                     const double2 *__restrict__ t,
                                                     int nb, int ld_e, int n_eig,
                                                     double2 *__restrict__ w2) {
-  __shared__ double2 w1[kWy][64];
-  const int el = threadIdx.x & 63;
-  const int e = blockIdx.x * 64 + el;
-  const int jg = threadIdx.x >> 6;
-  for (int q = 0; q < 8; ++q) {
-    const int j = jg * 8 + q;
+  __shared__ double2 w1[kWy][kTwCols];
+  const int el = threadIdx.x % kTwCols;
+  const int jq = threadIdx.x / kTwCols;   // 0..15
+  const int e = blockIdx.x * kTwCols + el;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int j = 2 * jq + q;
     double2 s = make_double2(0.0, 0.0);
     if (e < n_eig)
       for (int ch = 0; ch < n_chunks; ++ch) {
@@ -700,8 +703,9 @@ __global__ __launch_bounds__(256) void wy_tw_kernel(const double2 *__restrict__ 
     w1[j][el] = s;
   }
   __syncthreads();
-  for (int q = 0; q < 8; ++q) {
-    const int j = jg * 8 + q;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int j = 2 * jq + q;
     double2 s = make_double2(0.0, 0.0);
     if (j < nb)
       for (int l = j; l < nb; ++l) {
@@ -845,7 +849,8 @@ void eig_lowest(Context *ctx, const double *a_in, int n, int n_eig,
       hipLaunchKernelGGL(wy_vhc_kernel, dim3(ctiles, chunks), dim3(256), 0, s,
                          (const double2 *)t.a, n, k0, nb, (const double *)basis,
                          ld_e, n_eig, part.as<double2>());
-      hipLaunchKernelGGL(wy_tw_kernel, dim3(ctiles), dim3(256), 0, s,
+      hipLaunchKernelGGL(wy_tw_kernel, dim3((ld_e + kTwCols - 1) / kTwCols),
+                         dim3(256), 0, s,
                          (const double2 *)part.as<double2>(), chunks,
                          (const double2 *)tw.as<double2>() + (long)b * kWy * kWy,
                          nb, ld_e, n_eig, w2.as<double2>());
