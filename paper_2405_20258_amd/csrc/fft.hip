@@ -411,8 +411,6 @@ __device__ __forceinline__ void dft(double2 *v) {
   }
 }
 
-constexpr int kPlaneWaves = 8;
-constexpr int kPlaneThreads = 64 * kPlaneWaves;
 
 // Lines per wave batch: fewest issue slots per line over the two steps
 // (step 1 has R2 items per line, step 2 has R1).
@@ -425,6 +423,14 @@ constexpr int pick_lines(int r1, int r2) {
   return best;
 }
 
+// Waves per plane work-group: the x-line batches of a plane should divide
+// evenly over the waves (measured: 3 waves for 6 batches at N = 48, 4 for
+// 11 at N = 72, against 8 waves: -11 % and -15 % time); small work-groups
+// also let more of them share a CU.
+constexpr int plane_waves(int n_batches) {
+  return n_batches <= 2 ? 2 : ((n_batches % 3 == 0 && n_batches % 4 != 0) ? 3 : 4);
+}
+
 template <int R1_, int R2_>
 struct LineSplit {
   static constexpr int R1 = R1_, R2 = R2_, N = R1 * R2;
@@ -433,6 +439,7 @@ struct LineSplit {
   static constexpr int XS = N | 1;       // odd row stride of the x output
   static constexpr int L = pick_lines(R1, R2);
   static constexpr bool kHoist = L * R2 <= 64;  // one step-1 item per lane
+  static constexpr int W = plane_waves((N + L - 1) / L);  // plane kernel
 };
 
 // LDS bytes of pair_plane_kernel (tw, column map, nxo x outputs, scratch).
@@ -440,7 +447,7 @@ template <class S>
 size_t plane_lds_bytes(int ny1, int ny2, int nxo) {
   const size_t cm = ((size_t)ny1 * ny2 * sizeof(int) + 15) / 16 * 16;
   return sizeof(double2) * (S::N + (size_t)nxo * ny1 * S::XS +
-                            (size_t)kPlaneWaves * S::L * S::SL) + cm;
+                            (size_t)S::W * S::L * S::SL) + cm;
 }
 
 // Work-group b -> pair (vl, cl) of a chunk of nvb x ncc pairs.  Work-groups
@@ -508,7 +515,7 @@ __device__ __forceinline__ void line_batch(int nl, Load load, Store store,
 // nxo = 2 the x outputs alternate between two buffers and one block barrier
 // per plane suffices; with nxo = 1 a second barrier guards the buffer.
 template <int R1, int R2>
-__global__ __launch_bounds__(kPlaneThreads) void pair_plane_kernel(
+__global__ __launch_bounds__((64 * LineSplit<R1, R2>::W)) void pair_plane_kernel(
     const double2 *__restrict__ psi, int v0, int nvb, int n_v, int c0,
     int ncc, int n3, int m1, int m2, int nxo, const int *__restrict__ cmap_g,
     int ldy, const double2 *__restrict__ tw_g, double2 *__restrict__ yst) {
@@ -519,7 +526,7 @@ __global__ __launch_bounds__(kPlaneThreads) void pair_plane_kernel(
   double2 *tw = smem;
   double2 *xo0 = tw + N;
   double2 *scr_all = xo0 + nxo * ny1 * S::XS;
-  int *cmap = reinterpret_cast<int *>(scr_all + kPlaneWaves * S::L * S::SL);
+  int *cmap = reinterpret_cast<int *>(scr_all + S::W * S::L * S::SL);
   int vl, cl;
   if (!chunk_pair(blockIdx.x, nvb, ncc, vl, cl)) return;
   for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t] = tw_g[t];
@@ -545,7 +552,7 @@ __global__ __launch_bounds__(kPlaneThreads) void pair_plane_kernel(
     double2 *xo = xo0 + (nxo == 2 ? (j3 & 1) : 0) * ny1 * S::XS;
     const double2 *sv = pv + j3 * plane;
     const double2 *sc = pc + j3 * plane;
-    for (int bt = wave; bt < nbx; bt += kPlaneWaves) {
+    for (int bt = wave; bt < nbx; bt += S::W) {
       const int l0 = bt * S::L;
       const int nl = min(S::L, N - l0);
       line_batch<S>(
@@ -564,7 +571,7 @@ __global__ __launch_bounds__(kPlaneThreads) void pair_plane_kernel(
     }
     __syncthreads();
     double2 *yo = yp + (long)j3 * ldy;
-    for (int bt = wave; bt < nby; bt += kPlaneWaves) {
+    for (int bt = wave; bt < nby; bt += S::W) {
       const int r0 = bt * S::L;
       const int nl = min(S::L, ny1 - r0);
       line_batch<S>(
@@ -728,6 +735,9 @@ void staged_pairs(System &sys, int v0, int nvb, const double *gscale,
   const size_t l2 = plane_lds_bytes<S>(ny1, ny2, 2);
   const size_t cu = 160 * 1024;
   SSRPA_REQUIRE(l1 <= cu, SSRPA_ERR_ARG, "pair transform needs %zu bytes of LDS", l1);
+  // a second x-output buffer saves one barrier per plane but costs LDS;
+  // measured, the extra work-groups per CU win, so it is used only when it
+  // costs none of them
   const int nxo = (l2 <= cu && cu / l2 >= cu / l1) ? 2 : 1;
   const size_t lds = nxo == 2 ? l2 : l1;
   auto kern = &pair_plane_kernel<R1, R2>;
@@ -747,7 +757,7 @@ void staged_pairs(System &sys, int v0, int nvb, const double *gscale,
     const long tiles = (long)((nvb + 7) / 8) * ((ncc + 7) / 8);
     const long blocks = (tiles + 7) / 8 * 8 * 64;
     SSRPA_REQUIRE(blocks < (1L << 31), SSRPA_ERR_ARG, "pair grid too large");
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kPlaneThreads), lds, s,
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * S::W), lds, s,
                        psi, v0, nvb, sys.n_v, c0, ncc, g.n3, g.m1, g.m2, nxo,
                        sys.cmap.as<int>(), g.ldy, tw, yst);
     SSRPA_HIP(hipGetLastError());
