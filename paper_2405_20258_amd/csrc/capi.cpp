@@ -514,7 +514,7 @@ EcResult energy(System &sys, int n_eig, int n_freq, const double *omega,
                            hipMemcpyHostToDevice, s));
   SSRPA_HIP(hipMemcpyAsync(w_d, weight, sizeof(double) * n_freq,
                            hipMemcpyHostToDevice, s));
-  DevBuf scratch, de, ws, wsub;
+  DevBuf scratch, de, ws, wsub, gws;
   for (int v0 = 0; v0 < sys.n_v; v0 += vb) {
     const int nvb = std::min(vb, sys.n_v - v0);
     const long rows = (long)nvb * sys.n_c;
@@ -537,7 +537,7 @@ EcResult energy(System &sys, int n_eig, int n_freq, const double *omega,
       gm.m = rows; gm.n = ld; gm.k = g.ld_g;
       gm.alpha = 1.0; gm.beta = 0.0;
       StageScope sc(sys.timer, SSRPA_STAGE_PROJECTION, s);
-      gemm(ctx, gm, prec, s);
+      gemm(ctx, gm, prec, gws, s);
       h.a = wsub.as<double>();
       h.lda = 2L * ld;
       h.im_off = ld;

@@ -888,7 +888,8 @@ void eig_lowest(Context *ctx, const double *a_in, int n, int n_eig,
   g.c = cnew.as<double>(); g.ldc = 2L * ld_e; g.c_im = ld_e;
   g.m = rows_pad; g.n = ld_e; g.k = ld_e;
   g.alpha = 1.0; g.beta = 0.0;
-  gemm(ctx, g, SSRPA_FP64, s);
+  DevBuf gws;
+  gemm(ctx, g, SSRPA_FP64, gws, s);
   SSRPA_HIP(hipMemcpyAsync(basis, cnew.as(), sizeof(double) * 2 * (size_t)rows_pad * ld_e,
                            hipMemcpyDeviceToDevice, s));
   SSRPA_HIP(hipStreamSynchronize(s));  // work buffers are freed on return

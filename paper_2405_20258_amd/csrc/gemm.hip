@@ -382,11 +382,19 @@ void herk(Context *ctx, const HerkArgs &h, ssrpa_precision prec, double *out,
   SSRPA_HIP(hipGetLastError());
 }
 
-void gemm(Context *ctx, const GemmArgs &g, ssrpa_precision prec, hipStream_t s) {
-  (void)ctx;
+void gemm(Context *ctx, const GemmArgs &g, ssrpa_precision prec, DevBuf &ws,
+          hipStream_t s) {
   SSRPA_REQUIRE(g.k % kT == 0 && g.n % kT == 0, SSRPA_ERR_ARG,
                 "gemm: k and n must be padded to 64");
   if (g.m <= 0) return;
+  if (prec == SSRPA_BF16X3 && g.beta == 0.0) {
+    gemm_bf16x3_wide(ctx, g, ws, s);
+    return;
+  }
+  if (prec == SSRPA_FP32 && g.beta == 0.0) {
+    gemm_f32_wide(ctx, g, ws, s);
+    return;
+  }
   const long m_tiles = (g.m + kT - 1) / kT;
   const int n_tiles = g.n / kT;
   SSRPA_REQUIRE(m_tiles * n_tiles < (1L << 31), SSRPA_ERR_ARG, "gemm too large");

@@ -679,6 +679,281 @@ __global__ __launch_bounds__(256, 2) void gram_f32_kernel(
   }
 }
 
+// BF16x3 GEMM C = A B (beta = 0) for the projection W_s = W C_s: 128 x 128
+// output tiles, 4 waves of 64 x 64.  A (FP64 planar rows, k contiguous) is
+// split into bf16 hi/lo while it is staged, once per block and K step; B is
+// split once per call into the K-blocked layout of the Gram path (the basis
+// is small).  A wide N tile reads A ld/128 times instead of ld/64.  FP32
+// accumulators are added into C (zeroed first) every kGFlushSteps steps.
+__global__ __launch_bounds__(256, 2) void gemm_bf16x3_wide_kernel(
+    GemmArgs g, const uint4 *__restrict__ bt, int ldn, int m_tiles,
+    int n_tiles) {
+  extern __shared__ uint4 wsm[];
+  uint4 *As = wsm;                          // [part][row][kGColStride]
+  uint4 *Bs = wsm + 4 * kGT * kGColStride;  // [part][col][kGColStride]
+  const int total = m_tiles * n_tiles;
+  const int t = xcd_remap_m(blockIdx.x, total);
+  const int mt = t / n_tiles, nt = t - mt * n_tiles;
+  const long M0 = (long)mt * kGT;
+  const int N0 = nt * kGT;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  const int q = lane >> 4, cl = lane & 15;
+  f4 re[4][4], im[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      re[i][j] = f4{0, 0, 0, 0};
+      im[i][j] = f4{0, 0, 0, 0};
+    }
+  // an opaque zero: the flush addresses are rebuilt at every flush instead
+  // of being hoisted out of the K loop (and spilled)
+  int zero = 0;
+  int soff = (threadIdx.x >> 2) * 4 + (threadIdx.x & 3);
+  auto flush = [&]() __attribute__((always_inline)) {
+    asm volatile("" : "+v"(zero));
+    const int n0 = N0 + wc + accf_col(lane) + zero;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const long m = M0 + wr + i * 16 + accf_row(lane, e);
+        if (m < g.m) {
+          double *cr = g.c + m * g.ldc + n0;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (n0 + j * 16 < g.n) {
+              cr[j * 16] += g.alpha * (double)re[i][j][e];
+              cr[g.c_im + j * 16] += g.alpha * (double)im[i][j][e];
+            }
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          re[i][j][e] = 0.f;
+          im[i][j][e] = 0.f;
+        }
+      }
+  };
+  const int nkb = g.k / 32;
+  int steps = 0;
+  for (int kb = 0; kb < nkb; ++kb) {
+    __syncthreads();
+    asm volatile("" : "+v"(soff));
+    // A: thread (row r = soff / 4 (+ 64), q4 = soff % 4) splits the 8 rows
+    // k = 32 kb + 8 q4 .. + 7 of its row, real and imaginary parts
+#pragma unroll
+    for (int hc = 0; hc < 2; ++hc) {
+      const int r = (soff >> 2) + 64 * hc, q4 = soff & 3;
+      const long m = M0 + r;
+      unsigned pk[4][4];
+      if (m < g.m) {
+        const double *src = g.a + m * g.lda + (long)kb * 32 + q4 * 8;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double2 xr = *reinterpret_cast<const double2 *>(src + 2 * u);
+          const double2 xi =
+              *reinterpret_cast<const double2 *>(src + g.a_im + 2 * u);
+          unsigned short h0, l0, h1, l1, h2, l2, h3, l3;
+          split_bf16(xr.x, h0, l0);
+          split_bf16(xr.y, h1, l1);
+          split_bf16(xi.x, h2, l2);
+          split_bf16(xi.y, h3, l3);
+          pk[0][u] = h0 | ((unsigned)h1 << 16);
+          pk[1][u] = l0 | ((unsigned)l1 << 16);
+          pk[2][u] = h2 | ((unsigned)h3 << 16);
+          pk[3][u] = l2 | ((unsigned)l3 << 16);
+        }
+      } else {
+#pragma unroll
+        for (int pp = 0; pp < 4; ++pp)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) pk[pp][u] = 0u;
+      }
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp)
+        As[(pp * kGT + r) * kGColStride + q4] =
+            make_uint4(pk[pp][0], pk[pp][1], pk[pp][2], pk[pp][3]);
+    }
+    // B: items it = part (it / 2), columns + 64 (it % 2)
+    const uint4 *sb = bt + (long)kb * 16 * ldn + soff;
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int part = it >> 1, hc = it & 1;
+      const uint4 v = sb[(part * ldn + N0 + 64 * hc) * 4];
+      const int col = (soff >> 2) + 64 * hc;
+      Bs[(part * kGT + col) * kGColStride + (soff & 3)] = v;
+    }
+    __syncthreads();
+    bf8 a[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp)
+        a[i][pp] = __builtin_bit_cast(
+            bf8, As[(pp * kGT + wr + i * 16 + cl) * kGColStride + q]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bf8 b[4];
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp)
+        b[pp] = __builtin_bit_cast(
+            bf8, Bs[(pp * kGT + wc + j * 16 + cl) * kGColStride + q]);
+      const bf8 nih = neg_bf8(b[2]), nil = neg_bf8(b[3]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        // Re += ar br - ai bi;  Im += ar bi + ai br  (hi*hi + hi*lo + lo*hi)
+        re[i][j] = mfmabf(a[i][0], b[0], re[i][j]);
+        re[i][j] = mfmabf(a[i][0], b[1], re[i][j]);
+        re[i][j] = mfmabf(a[i][1], b[0], re[i][j]);
+        re[i][j] = mfmabf(a[i][2], nih, re[i][j]);
+        re[i][j] = mfmabf(a[i][2], nil, re[i][j]);
+        re[i][j] = mfmabf(a[i][3], nih, re[i][j]);
+        im[i][j] = mfmabf(a[i][0], b[2], im[i][j]);
+        im[i][j] = mfmabf(a[i][0], b[3], im[i][j]);
+        im[i][j] = mfmabf(a[i][1], b[2], im[i][j]);
+        im[i][j] = mfmabf(a[i][2], b[0], im[i][j]);
+        im[i][j] = mfmabf(a[i][2], b[1], im[i][j]);
+        im[i][j] = mfmabf(a[i][3], b[0], im[i][j]);
+      }
+    }
+    if (++steps == kGFlushSteps || kb + 1 == nkb) {
+      flush();
+      steps = 0;
+    }
+  }
+}
+
+// FP32 form of the wide GEMM: A rounded to FP32 while staged (in the
+// permuted 16-row layout of split_rows_f32_kernel), B split once per call.
+__global__ __launch_bounds__(256, 2) void gemm_f32_wide_kernel(
+    GemmArgs g, const uint4 *__restrict__ bt, int ldn, int m_tiles,
+    int n_tiles) {
+  extern __shared__ uint4 fwsm[];
+  uint4 *As = fwsm;                          // [part][row][kGColStride]
+  uint4 *Bs = fwsm + 2 * kGT * kGColStride;  // [part][col][kGColStride]
+  float *Af = reinterpret_cast<float *>(As);
+  const int total = m_tiles * n_tiles;
+  const int t = xcd_remap_m(blockIdx.x, total);
+  const int mt = t / n_tiles, nt = t - mt * n_tiles;
+  const long M0 = (long)mt * kGT;
+  const int N0 = nt * kGT;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  const int q = lane >> 4, cl = lane & 15;
+  f4 re[4][4], im[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      re[i][j] = f4{0, 0, 0, 0};
+      im[i][j] = f4{0, 0, 0, 0};
+    }
+  int zero = 0;
+  int soff = (threadIdx.x >> 2) * 4 + (threadIdx.x & 3);
+  auto flush = [&]() __attribute__((always_inline)) {
+    asm volatile("" : "+v"(zero));
+    const int n0 = N0 + wc + accf_col(lane) + zero;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const long m = M0 + wr + i * 16 + accf_row(lane, e);
+        if (m < g.m) {
+          double *cr = g.c + m * g.ldc + n0;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (n0 + j * 16 < g.n) {
+              cr[j * 16] += g.alpha * (double)re[i][j][e];
+              cr[g.c_im + j * 16] += g.alpha * (double)im[i][j][e];
+            }
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          re[i][j][e] = 0.f;
+          im[i][j][e] = 0.f;
+        }
+      }
+  };
+  const int nkb = g.k / 16;
+  int steps = 0;
+  for (int kb = 0; kb < nkb; ++kb) {
+    __syncthreads();
+    asm volatile("" : "+v"(soff));
+    // A: thread (row soff / 4 (+ 64), q4 = soff % 4) rounds rows k = 16 kb +
+    // 4 q4 + c, c < 4, of its row; row 4 s + q goes to float 4 q + s
+#pragma unroll
+    for (int hc = 0; hc < 2; ++hc) {
+      const int r = (soff >> 2) + 64 * hc, q4 = soff & 3;
+      const long m = M0 + r;
+      double vr[4] = {0.0, 0.0, 0.0, 0.0}, vi[4] = {0.0, 0.0, 0.0, 0.0};
+      if (m < g.m) {
+        const double *src = g.a + m * g.lda + (long)kb * 16 + q4 * 4;
+        const double2 r0 = *reinterpret_cast<const double2 *>(src);
+        const double2 r1 = *reinterpret_cast<const double2 *>(src + 2);
+        const double2 i0 = *reinterpret_cast<const double2 *>(src + g.a_im);
+        const double2 i1 = *reinterpret_cast<const double2 *>(src + g.a_im + 2);
+        vr[0] = r0.x; vr[1] = r0.y; vr[2] = r1.x; vr[3] = r1.y;
+        vi[0] = i0.x; vi[1] = i0.y; vi[2] = i1.x; vi[3] = i1.y;
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        // k = 4 q4 + c = 4 s + q with s = q4, q = c
+        Af[((0 * kGT + r) * kGColStride) * 4 + 4 * c + q4] = (float)vr[c];
+        Af[((1 * kGT + r) * kGColStride) * 4 + 4 * c + q4] = (float)vi[c];
+      }
+    }
+    // B: items it = part (it / 2), columns + 64 (it % 2)
+    const uint4 *sb = bt + (long)kb * 8 * ldn + soff;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int part = it >> 1, hc = it & 1;
+      const uint4 v = sb[(part * ldn + N0 + 64 * hc) * 4];
+      const int col = (soff >> 2) + 64 * hc;
+      Bs[(part * kGT + col) * kGColStride + (soff & 3)] = v;
+    }
+    __syncthreads();
+    uint4 a[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp)
+        a[i][pp] = As[(pp * kGT + wr + i * 16 + cl) * kGColStride + q];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint4 b[2];
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp)
+        b[pp] = Bs[(pp * kGT + wc + j * 16 + cl) * kGColStride + q];
+      const float br[4] = {__uint_as_float(b[0].x), __uint_as_float(b[0].y),
+                           __uint_as_float(b[0].z), __uint_as_float(b[0].w)};
+      const float bi[4] = {__uint_as_float(b[1].x), __uint_as_float(b[1].y),
+                           __uint_as_float(b[1].z), __uint_as_float(b[1].w)};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float ar[4] = {__uint_as_float(a[i][0].x), __uint_as_float(a[i][0].y),
+                             __uint_as_float(a[i][0].z), __uint_as_float(a[i][0].w)};
+        const float ai[4] = {__uint_as_float(a[i][1].x), __uint_as_float(a[i][1].y),
+                             __uint_as_float(a[i][1].z), __uint_as_float(a[i][1].w)};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          // Re += ar br - ai bi;  Im += ar bi + ai br
+          re[i][j] = mfma32(ar[s], br[s], re[i][j]);
+          re[i][j] = mfma32(ai[s], -bi[s], re[i][j]);
+          im[i][j] = mfma32(ar[s], bi[s], im[i][j]);
+          im[i][j] = mfma32(ai[s], br[s], im[i][j]);
+        }
+      }
+    }
+    if (++steps == kFFlushSteps || kb + 1 == nkb) {
+      flush();
+      steps = 0;
+    }
+  }
+}
+
 // One block per (tile, 1/kGRedParts of its elements).
 constexpr int kGRedParts = 16;
 __global__ void gram_reduce_kernel(const double *__restrict__ partial,
@@ -844,6 +1119,72 @@ void herk_gram(Context *ctx, const HerkArgs &h, ssrpa_precision prec,
     SSRPA_HIP(hipGetLastError());
   }
   if (ti >= 0) h.timer->stop(ti, s);
+}
+
+size_t gemm_bf16x3_wide_workspace(const GemmArgs &g) {
+  return (size_t)g.k * round_up(g.n, kGT) * 8;
+}
+
+void gemm_bf16x3_wide(Context *ctx, const GemmArgs &g, DevBuf &ws,
+                      hipStream_t s) {
+  SSRPA_REQUIRE(g.beta == 0.0 && g.k % 32 == 0, SSRPA_ERR_ARG,
+                "gemm_bf16x3_wide: beta = 0 and k padded to 32 only");
+  const int ldn = round_up(g.n, kGT);
+  ws.ensure(ctx, gemm_bf16x3_wide_workspace(g));
+  uint4 *bt = ws.as<uint4>();
+  // B rows (k) split once into [kb][part][n][32]
+  HerkArgs hb{};
+  hb.a = g.b;
+  hb.lda = g.ldb;
+  hb.im_off = g.b_im;
+  hb.ncol = g.n;
+  hb.unit_weight = 1;
+  hipLaunchKernelGGL(split_rows_bf16_kernel,
+                     dim3((unsigned)((ldn + 255) / 256), (unsigned)(g.k / 32)),
+                     dim3(256), 0, s, hb, 0L, g.k, ldn, 0, 0, bt);
+  // C accumulates its flushes: zero the rows first
+  fill_zero(g.c, sizeof(double) * (size_t)g.m * g.ldc, s);
+  static bool attr = [] {
+    SSRPA_HIP(hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&gemm_bf16x3_wide_kernel),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGLds));
+    return true;
+  }();
+  (void)attr;
+  const long m_tiles = (g.m + kGT - 1) / kGT;
+  const int n_tiles = ldn / kGT;
+  SSRPA_REQUIRE(m_tiles * n_tiles < (1L << 31), SSRPA_ERR_ARG, "gemm too large");
+  hipLaunchKernelGGL(gemm_bf16x3_wide_kernel, dim3((unsigned)(m_tiles * n_tiles)),
+                     dim3(256), kGLds, s, g, bt, ldn, (int)m_tiles, n_tiles);
+  SSRPA_HIP(hipGetLastError());
+}
+
+size_t gemm_f32_wide_workspace(const GemmArgs &g) {
+  return (size_t)g.k * round_up(g.n, kGT) * 8;
+}
+
+void gemm_f32_wide(Context *ctx, const GemmArgs &g, DevBuf &ws, hipStream_t s) {
+  SSRPA_REQUIRE(g.beta == 0.0 && g.k % 16 == 0, SSRPA_ERR_ARG,
+                "gemm_f32_wide: beta = 0 and k padded to 16 only");
+  const int ldn = round_up(g.n, kGT);
+  ws.ensure(ctx, gemm_f32_wide_workspace(g));
+  uint4 *bt = ws.as<uint4>();
+  HerkArgs hb{};
+  hb.a = g.b;
+  hb.lda = g.ldb;
+  hb.im_off = g.b_im;
+  hb.ncol = g.n;
+  hb.unit_weight = 1;
+  hipLaunchKernelGGL(split_rows_f32_kernel,
+                     dim3((unsigned)((ldn + 255) / 256), (unsigned)(g.k / 16)),
+                     dim3(256), 0, s, hb, 0L, g.k, ldn, 0, bt);
+  fill_zero(g.c, sizeof(double) * (size_t)g.m * g.ldc, s);
+  const long m_tiles = (g.m + kGT - 1) / kGT;
+  const int n_tiles = ldn / kGT;
+  SSRPA_REQUIRE(m_tiles * n_tiles < (1L << 31), SSRPA_ERR_ARG, "gemm too large");
+  hipLaunchKernelGGL(gemm_f32_wide_kernel, dim3((unsigned)(m_tiles * n_tiles)),
+                     dim3(256), kFLds, s, g, bt, ldn, (int)m_tiles, n_tiles);
+  SSRPA_HIP(hipGetLastError());
 }
 
 void gemm_mixed_launch(const GemmArgs &g, ssrpa_precision prec, int m_tiles,

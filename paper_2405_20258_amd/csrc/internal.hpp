@@ -250,7 +250,16 @@ struct GemmArgs {
   long m; int n; int k;
   double alpha, beta;
 };
-void gemm(Context *ctx, const GemmArgs &g, ssrpa_precision prec, hipStream_t s);
+// ws: caller-owned workspace (the BF16x3 path splits B into it; kept alive
+// by the caller until the stream is synchronized).
+void gemm(Context *ctx, const GemmArgs &g, ssrpa_precision prec, DevBuf &ws,
+          hipStream_t s);
+// BF16x3 GEMM with 128 x 128 tiles (gemm_mixed.hip), beta = 0.
+void gemm_bf16x3_wide(Context *ctx, const GemmArgs &g, DevBuf &ws,
+                      hipStream_t s);
+size_t gemm_bf16x3_wide_workspace(const GemmArgs &g);
+void gemm_f32_wide(Context *ctx, const GemmArgs &g, DevBuf &ws, hipStream_t s);
+size_t gemm_f32_wide_workspace(const GemmArgs &g);
 
 // Eigensolver (eig.hip): n_eig most negative eigenpairs of a Hermitian n x n
 // interleaved matrix (not modified).  eigval: device (n_eig); basis: planar
