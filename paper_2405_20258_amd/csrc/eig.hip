@@ -55,18 +55,49 @@ __device__ double block_sum(double v, double *red) {
 }
 
 // ------------------------------------------------ Householder reduction
+//
+// Blocked over panels of kNb columns.  Inside a panel the trailing matrix
+// keeps its value A0 from the start of the panel; the current matrix is
+//   A' = A0 - sum_i (V_i W_i^H + W_i V_i^H)
+// over the panel's earlier reflectors V_i = u_i and their vectors W_i = w_i.
+// Step k (slot i = k - k0 of the panel) runs four kernels:
+//   col:  w of the previous step, w = p - (tau/2)(u^H p) u, then column k of
+//         A' from the lower triangle of A0 and the panel vectors, stored
+//         conjugated in row k;
+//   make: reflector k from that row (u stored in row k; tau, e, d);
+//   hemv: tau A0 u over the lower triangle of the trailing block, in strips
+//         of 64 x 64 tiles, and the panel products W^H u and V^H u;
+//   p:    p = tau (A0 u - V (W^H u) - W (V^H u)) from the strip partials.
+// After the panel, her2k applies its rank-2 kNb update to the lower tiles of
+// the next trailing block, which is A0 of the next panel.  Only the lower
+// triangle is read, so the trailing matrix is read (half of it) once per
+// column and rewritten once per panel.
+constexpr int kNb = 32;     // panel width; 2 kNb panel products fit 64 slots
+constexpr int kHT = 64;     // hemv and her2k tile
+constexpr int kStrip = 4;   // tiles per hemv strip
 
 struct TriWork {
-  double2 *a;     // n x n work matrix (interleaved)
+  double2 *a;     // n x n work matrix (interleaved), row-major
   double *tau;    // n
   double *d;      // n   diagonal of T
   double2 *e;     // n   complex off-diagonal of T_c (e[k] = T_c[k+1][k])
-  double2 *p;     // n   scratch vector
-  double2 *w;     // n   scratch vector
+  double2 *p;     // n   p of the current step, trailing index
+  double2 *wb;    // kNb x n: panel vectors W_i by global index
+  double2 *prow;  // strips x 64: row partials of the hemv
+  double2 *pcol;  // tile rows x ldp: column partials of the hemv
+  double2 *pdot;  // tile rows x 64: partials of W^H u (slots < i), V^H u
+  double *pup;    // per p-block partial of Re(u^H p)
+  long ldp;       // row length of pcol
 };
 
-// Reflector for column k: x = A[k+1:, k] = conj(A[k][k+1:]).
-__global__ __launch_bounds__(256) void hh_make_kernel(TriWork t, int n, int k) {
+// Strips before tile row I: row I has I + 1 tiles in I / kStrip + 1 strips.
+__host__ __device__ inline long strip_prefix(int I) {
+  const long q = I / kStrip, r = I - q * kStrip;
+  return I + kStrip * q * (q - 1) / 2 + q * r;
+}
+
+// Reflector for column k: x = A'[k+1:, k] = conj(row k beyond the diagonal).
+__global__ __launch_bounds__(1024) void hh_make_kernel(TriWork t, int n, int k) {
   __shared__ double red[16];
   const int m = n - k - 1;
   double2 *row = t.a + (long)k * n + k + 1;
@@ -109,170 +140,319 @@ __global__ __launch_bounds__(256) void hh_make_kernel(TriWork t, int n, int k) {
   }
 }
 
-// p_i = tau sum_j A[k+1+i][k+1+j] u_j, one wave per row.
-__global__ __launch_bounds__(256) void hh_hemv_kernel(TriWork t, int n, int k) {
-  const int m = n - k - 1;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (i >= m) return;
-  const double tau = t.tau[k];
-  const double2 *u = t.a + (long)k * n + k + 1;
-  const double2 *ar = t.a + (long)(k + 1 + i) * n + k + 1;
-  double sr = 0.0, si = 0.0;
-  for (int j = lane; j < m; j += 64) {
-    const double2 a = ar[j], b = u[j];
-    sr += a.x * b.x - a.y * b.y;
-    si += a.x * b.y + a.y * b.x;
-  }
-  sr = wave_sum(sr);
-  si = wave_sum(si);
-  if (lane == 0) t.p[i] = make_double2(tau * sr, tau * si);
-}
-
-// w = p - (tau/2)(u^H p) u
-__global__ __launch_bounds__(256) void hh_w_kernel(TriWork t, int n, int k) {
+// Step k, part col (one thread per c = k .. n-1).  For panel slot j > 0 it
+// first finishes w of step k-1 (slot j-1) from p and the nup partials of
+// Re(u^H p); unless finish_only it then forms A'[c][k] and stores its
+// conjugate in row k.
+__global__ __launch_bounds__(256) void hh_col_kernel(TriWork t, int n, int k,
+                                                     int k0, int j, int nup,
+                                                     int finish_only) {
   __shared__ double red[16];
-  const int m = n - k - 1;
-  const double tau = t.tau[k];
-  const double2 *u = t.a + (long)k * n + k + 1;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < m; i += blockDim.x) {
-    const double2 c = cmulc(u[i], t.p[i]);
-    s += c.x;  // u^H A u is real
-  }
-  const double K = 0.5 * tau * block_sum(s, red);
-  for (int i = threadIdx.x; i < m; i += blockDim.x) {
-    const double2 pi = t.p[i], ui = u[i];
-    t.w[i] = make_double2(pi.x - K * ui.x, pi.y - K * ui.y);
-  }
-}
-
-// A'[i][j] -= u_i conj(w_j) + w_i conj(u_j)
-__global__ __launch_bounds__(256) void hh_her2_kernel(TriWork t, int n, int k) {
-  const int m = n - k - 1;
-  const int i = blockIdx.y;
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (i >= m || j >= m) return;
-  if (t.tau[k] == 0.0) return;
-  const double2 *u = t.a + (long)k * n + k + 1;
-  const double2 ui = u[i], wi = t.w[i], uj = u[j], wj = t.w[j];
-  double2 *x = t.a + (long)(k + 1 + i) * n + k + 1 + j;
-  const double2 a = cmulc(wj, ui);  // ui conj(wj)
-  const double2 b = cmulc(uj, wi);  // wi conj(uj)
-  double2 v = *x;
-  v.x -= a.x + b.x;
-  v.y -= a.y + b.y;
-  *x = v;
-}
-
-// Fused reduction step, part A (one block).  Finishes step k-1
-// (w_{k-1} = p - (tau/2)(u^H p) u), applies the pending rank-two update of
-// step k-1 to row k, and builds reflector k from that row.
-__global__ __launch_bounds__(1024) void hh_step_a_kernel(TriWork t, int n, int k) {
-  __shared__ double red[16];
-  const int m = n - k - 1;
-  double2 *row = t.a + (long)k * n + k;       // row k from the diagonal on
-  if (k > 0) {
-    const int mp = m + 1;                      // length of step k-1 vectors
-    const double taup = t.tau[k - 1];
-    const double2 *up = t.a + (long)(k - 1) * n + k;
+  __shared__ double2 vk[kNb], wk[kNb];
+  const int c = k + blockIdx.x * 256 + threadIdx.x;
+  const bool in = c < n;
+  double2 wc = make_double2(0.0, 0.0);        // w_{j-1}[c]
+  if (j > 0) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < mp; i += blockDim.x) s += cmulc(up[i], t.p[i]).x;
-    const double K = 0.5 * taup * block_sum(s, red);
-    for (int i = threadIdx.x; i < mp; i += blockDim.x) {
-      const double2 pi = t.p[i], ui = up[i];
-      t.w[i] = make_double2(pi.x - K * ui.x, pi.y - K * ui.y);
+    for (int b = threadIdx.x; b < nup; b += 256) s += t.pup[b];
+    const double K = 0.5 * t.tau[k - 1] * block_sum(s, red);
+    const double2 *up = t.a + (long)(k - 1) * n;   // u_{k-1} by global index
+    if (in) {
+      const double2 pc = t.p[c - k], uc = up[c];
+      wc = make_double2(pc.x - K * uc.x, pc.y - K * uc.y);
+      t.wb[(long)(j - 1) * n + c] = wc;
     }
+    if (threadIdx.x == 0) {
+      const double2 p0 = t.p[0], u0 = up[k];
+      wk[j - 1] = make_double2(p0.x - K * u0.x, p0.y - K * u0.y);
+    }
+  }
+  if (finish_only) return;
+  for (int i = threadIdx.x; i < j; i += 256) {
+    vk[i] = t.a[(long)(k0 + i) * n + k];
+    if (i < j - 1) wk[i] = t.wb[(long)i * n + k];
+  }
+  __syncthreads();
+  if (!in) return;
+  double2 x = t.a[(long)c * n + k];           // A0[c][k], lower triangle
+  for (int i = 0; i < j; ++i) {
+    const double2 vc = t.a[(long)(k0 + i) * n + c];
+    const double2 wci = i == j - 1 ? wc : t.wb[(long)i * n + c];
+    const double2 p = cmulc(wk[i], vc);       // V_i[c] conj(W_i[k])
+    const double2 q = cmulc(vk[i], wci);      // W_i[c] conj(V_i[k])
+    x.x -= p.x + q.x;
+    x.y -= p.y + q.y;
+  }
+  t.a[(long)k * n + c] = make_double2(x.x, -x.y);
+}
+
+// Step k, part hemv: one work-group per strip of up to kStrip tiles of tile
+// row I of the lower triangle of the trailing block (offset o = k + 1, size
+// m).  Wave w takes rows 16 w .. 16 w + 15 of the tile row, lane l column l
+// of each tile.  Row partials sum A0[r][c] u[c] over the strip; column
+// partials sum conj(A0[r][c]) u[r] over the tile's rows (the upper triangle
+// by Hermitian symmetry; strictly below the diagonal in diagonal tiles).
+// The strip holding the diagonal tile also forms the panel products over its
+// rows: slot s < j: conj(W_s) . u, slot j + s: conj(V_s) . u.
+__global__ __launch_bounds__(256) void hh_hemv_kernel(TriWork t, int n, int k,
+                                                      int k0, int j) {
+  __shared__ double2 cs[2][4][64];
+  const int o = k + 1, m = n - o;
+  const int nt = (m + kHT - 1) / kHT;
+  const long b = blockIdx.x;
+  int lo = 0, hi = nt - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (strip_prefix(mid) <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int I = lo;
+  const int J0 = (int)(b - strip_prefix(I)) * kStrip;
+  const int J1 = min(J0 + kStrip, I + 1);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double2 *u = t.a + (long)k * n + o;
+  const double2 *blk = t.a + (long)o * n + o;
+  const int rb = I * kHT + wave * 16;
+  double2 ur[16], acc[16];
+#pragma unroll
+  for (int rr = 0; rr < 16; ++rr) {
+    ur[rr] = rb + rr < m ? u[rb + rr] : make_double2(0.0, 0.0);
+    acc[rr] = make_double2(0.0, 0.0);
+  }
+  for (int J = J0; J < J1; ++J) {
+    const int cj = J * kHT + lane;
+    const bool cok = cj < m;
+    const bool diag = J == I;
+    const double2 uc = cok ? u[cj] : make_double2(0.0, 0.0);
+    const double2 *col = blk + (cok ? cj : 0);
+    double2 v[16];
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+      const bool ld = cok && rb + rr < m && (!diag || lane <= wave * 16 + rr);
+      v[rr] = ld ? col[(long)(rb + rr) * n] : make_double2(0.0, 0.0);
+    }
+    double2 csum = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+      double2 vr = v[rr], vc = v[rr];
+      if (diag && lane == wave * 16 + rr) {
+        vr.y = 0.0;                           // real diagonal
+        vc = make_double2(0.0, 0.0);
+      }
+      acc[rr].x += vr.x * uc.x - vr.y * uc.y;
+      acc[rr].y += vr.x * uc.y + vr.y * uc.x;
+      const double2 q = cmulc(vc, ur[rr]);
+      csum.x += q.x;
+      csum.y += q.y;
+    }
+    double2 (*cb)[64] = cs[J & 1];
+    cb[wave][lane] = csum;
     __syncthreads();
-    if (taup != 0.0) {
-      const double2 u0 = up[0], w0 = t.w[0];
-      for (int j = threadIdx.x; j < mp; j += blockDim.x) {
-        const double2 a = cmulc(t.w[j], u0);   // u_k conj(w_j)
-        const double2 b = cmulc(up[j], w0);    // w_k conj(u_j)
-        double2 v = row[j];
-        v.x -= a.x + b.x;
-        v.y -= a.y + b.y;
-        row[j] = v;
+    if (wave == 0) {
+      double2 tot = cb[0][lane];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) {
+        tot.x += cb[w][lane].x;
+        tot.y += cb[w][lane].y;
+      }
+      t.pcol[(long)I * t.ldp + cj] = tot;
+    }
+  }
+  // reduce the 16 row sums over the 64 lanes: halve the values per lane at
+  // each exchange; lane l ends with row (l >> 2) & 15 over lanes l ^ {0..3}
+#pragma unroll
+  for (int h = 0; h < 8; ++h) {
+    const bool hi5 = lane & 32;
+    const double2 send = hi5 ? acc[h] : acc[h + 8];
+    const double2 keep = hi5 ? acc[h + 8] : acc[h];
+    acc[h] = make_double2(keep.x + __shfl_xor(send.x, 32), keep.y + __shfl_xor(send.y, 32));
+  }
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const bool hi4 = lane & 16;
+    const double2 send = hi4 ? acc[h] : acc[h + 4];
+    const double2 keep = hi4 ? acc[h + 4] : acc[h];
+    acc[h] = make_double2(keep.x + __shfl_xor(send.x, 16), keep.y + __shfl_xor(send.y, 16));
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const bool hi3 = lane & 8;
+    const double2 send = hi3 ? acc[h] : acc[h + 2];
+    const double2 keep = hi3 ? acc[h + 2] : acc[h];
+    acc[h] = make_double2(keep.x + __shfl_xor(send.x, 8), keep.y + __shfl_xor(send.y, 8));
+  }
+  {
+    const bool hi2 = lane & 4;
+    const double2 send = hi2 ? acc[0] : acc[1];
+    const double2 keep = hi2 ? acc[1] : acc[0];
+    acc[0] = make_double2(keep.x + __shfl_xor(send.x, 4), keep.y + __shfl_xor(send.y, 4));
+  }
+  acc[0].x += __shfl_xor(acc[0].x, 2);
+  acc[0].y += __shfl_xor(acc[0].y, 2);
+  acc[0].x += __shfl_xor(acc[0].x, 1);
+  acc[0].y += __shfl_xor(acc[0].y, 1);
+  if ((lane & 3) == 0) t.prow[b * kHT + wave * 16 + (lane >> 2)] = acc[0];
+  if (J1 == I + 1 && j > 0) {
+    // panel products over rows I*64 .. I*64+63: 4 threads per slot
+    const int slot = threadIdx.x >> 2, qt = threadIdx.x & 3;
+    double2 s = make_double2(0.0, 0.0);
+    if (slot < 2 * j) {
+      const double2 *x = slot < j ? t.wb + (long)slot * n + o
+                                  : t.a + (long)(k0 + slot - j) * n + o;
+      const int r0 = I * kHT + qt * 16;
+      for (int r = r0; r < min(r0 + 16, m); ++r) {
+        const double2 q = cmulc(x[r], u[r]);
+        s.x += q.x;
+        s.y += q.y;
       }
     }
-    __syncthreads();
-  }
-  double2 *x = row + 1;                        // conj of column k below diag
-  double s = 0.0;
-  for (int i = threadIdx.x + 1; i < m; i += blockDim.x) {
-    const double2 v = x[i];
-    s += v.x * v.x + v.y * v.y;
-  }
-  const double rest = block_sum(s, red);
-  const double2 a0c = x[0];
-  const double2 x0 = make_double2(a0c.x, -a0c.y);
-  const double ax0 = hypot(x0.x, x0.y);
-  const double nrm2 = rest + ax0 * ax0;
-  __syncthreads();
-  if (m == 1 || rest == 0.0) {
-    if (threadIdx.x == 0) {
-      t.tau[k] = 0.0;
-      t.e[k] = x0;
-      t.d[k] = row[0].x;
-    }
-    return;
-  }
-  const double nrm = sqrt(nrm2);
-  const double2 ph = ax0 > 0.0 ? make_double2(x0.x / ax0, x0.y / ax0)
-                               : make_double2(1.0, 0.0);
-  const double2 beta = make_double2(-ph.x * nrm, -ph.y * nrm);
-  const double tau = 1.0 / (nrm * (nrm + ax0));
-  for (int i = threadIdx.x; i < m; i += blockDim.x) {
-    const double2 v = x[i];
-    double2 u = make_double2(v.x, -v.y);
-    if (i == 0) u = make_double2(x0.x - beta.x, x0.y - beta.y);
-    x[i] = u;
-  }
-  if (threadIdx.x == 0) {
-    t.tau[k] = tau;
-    t.e[k] = beta;
-    t.d[k] = row[0].x;
+    s.x += __shfl_xor(s.x, 1);
+    s.y += __shfl_xor(s.y, 1);
+    s.x += __shfl_xor(s.x, 2);
+    s.y += __shfl_xor(s.y, 2);
+    if (qt == 0 && slot < 2 * j) t.pdot[(long)I * 64 + slot] = s;
   }
 }
 
-// Fused reduction step, part B (one wave per trailing row i > k): apply the
-// pending rank-two update of step k-1 to the row and, in the same pass,
-// p_i = tau_k sum_j A[i][j] u_k[j].  One read and one write of the trailing
-// matrix per step.
-__global__ __launch_bounds__(256) void hh_step_b_kernel(TriWork t, int n, int k) {
-  const int m = n - k - 1;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (i >= m) return;
-  const double tau = t.tau[k];
-  const double2 *u = t.a + (long)k * n + k + 1;
-  double2 *ar = t.a + (long)(k + 1 + i) * n + k + 1;
-  const bool pend = k > 0 && t.tau[k - 1] != 0.0;
-  // step k-1 vectors start at index k: offset 1 for row/col k+1+i
-  const double2 *up = t.a + (long)(k - 1) * n + k + 1;
-  const double2 *wp = t.w + 1;
-  double2 ui = make_double2(0.0, 0.0), wi = make_double2(0.0, 0.0);
-  if (pend) {
-    ui = up[i];
-    wi = wp[i];
-  }
-  double sr = 0.0, si = 0.0;
-  for (int j = lane; j < m; j += 64) {
-    double2 a = ar[j];
-    if (pend) {
-      const double2 x = cmulc(wp[j], ui);   // u_i conj(w_j)
-      const double2 y = cmulc(up[j], wi);   // w_i conj(u_j)
-      a.x -= x.x + y.x;
-      a.y -= x.y + y.y;
-      ar[j] = a;
+// Step k, part p (one thread per trailing row r): sums the strip row
+// partials of r's tile row and the column partials of the tiles below, and
+// subtracts the panel terms; p = tau (...).  Each work-group also leaves its
+// partial of Re(u^H p).
+__global__ __launch_bounds__(256) void hh_p_kernel(TriWork t, int n, int k,
+                                                   int k0, int j) {
+  __shared__ double red[16];
+  __shared__ double2 yq[4][64];
+  __shared__ double2 y[64];
+  const int o = k + 1, m = n - o;
+  const int nt = (m + kHT - 1) / kHT;
+  {
+    const int slot = threadIdx.x & 63, g = threadIdx.x >> 6;
+    double2 s = make_double2(0.0, 0.0);
+    if (slot < 2 * j)
+      for (int I = g; I < nt; I += 4) {
+        const double2 v = t.pdot[(long)I * 64 + slot];
+        s.x += v.x;
+        s.y += v.y;
+      }
+    yq[g][slot] = s;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const double2 a = yq[0][slot], b = yq[1][slot], c = yq[2][slot], d = yq[3][slot];
+      y[slot] = make_double2(a.x + b.x + c.x + d.x, a.y + b.y + c.y + d.y);
     }
-    const double2 b = u[j];
-    sr += a.x * b.x - a.y * b.y;
-    si += a.x * b.y + a.y * b.x;
+    __syncthreads();
   }
-  sr = wave_sum(sr);
-  si = wave_sum(si);
-  if (lane == 0) t.p[i] = make_double2(tau * sr, tau * si);
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  double up = 0.0;
+  if (r < m) {
+    const int I = r / kHT, rr = r - I * kHT;
+    double2 s0 = make_double2(0.0, 0.0), s1 = s0;
+    const long b0 = strip_prefix(I), b1 = b0 + I / kStrip + 1;
+    for (long b = b0; b < b1; ++b) {
+      const double2 v = t.prow[b * kHT + rr];
+      s0.x += v.x;
+      s0.y += v.y;
+    }
+    const double2 *pc = t.pcol + r;
+    int I2 = I;
+    for (; I2 + 1 < nt; I2 += 2) {
+      const double2 v0 = pc[(long)I2 * t.ldp], v1 = pc[(long)(I2 + 1) * t.ldp];
+      s0.x += v0.x;
+      s0.y += v0.y;
+      s1.x += v1.x;
+      s1.y += v1.y;
+    }
+    if (I2 < nt) {
+      const double2 v = pc[(long)I2 * t.ldp];
+      s0.x += v.x;
+      s0.y += v.y;
+    }
+    double2 s = make_double2(s0.x + s1.x, s0.y + s1.y);
+    for (int i = 0; i < j; ++i) {
+      const double2 v = t.a[(long)(k0 + i) * n + o + r];
+      const double2 w = t.wb[(long)i * n + o + r];
+      const double2 y1 = y[i], y2 = y[j + i];   // W_i^H u, V_i^H u
+      s.x -= v.x * y1.x - v.y * y1.y + w.x * y2.x - w.y * y2.y;
+      s.y -= v.x * y1.y + v.y * y1.x + w.x * y2.y + w.y * y2.x;
+    }
+    const double tau = t.tau[k];
+    const double2 pr = make_double2(tau * s.x, tau * s.y);
+    t.p[r] = pr;
+    const double2 ur = t.a[(long)k * n + o + r];
+    up = ur.x * pr.x + ur.y * pr.y;
+  }
+  const double tot = block_sum(up, red);
+  if (threadIdx.x == 0) t.pup[blockIdx.x] = tot;
+}
+
+// End of a panel of nbp reflectors from k0: the lower 64 x 64 tiles of the
+// trailing block at s0 = k0 + nbp (diagonal tiles whole) get
+// A0 -= sum_i V_i W_i^H + W_i V_i^H.
+__global__ __launch_bounds__(256) void hh_her2k_kernel(TriWork t, int n, int k0,
+                                                       int nbp, int s0) {
+  __shared__ double2 sv[4][8][kHT];   // V rows, W rows, V cols, W cols
+  const int m = n - s0;
+  const long b = blockIdx.x;
+  int I = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+  while ((long)(I + 1) * (I + 2) / 2 <= b) ++I;
+  while ((long)I * (I + 1) / 2 > b) --I;
+  const int J = (int)(b - (long)I * (I + 1) / 2);
+  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+  double2 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = make_double2(0.0, 0.0);
+  for (int i0 = 0; i0 < nbp; i0 += 8) {
+    for (int e = threadIdx.x; e < 4 * 8 * kHT; e += 256) {
+      const int arr = e >> 9, ii = (e >> 6) & 7, x = e & 63;
+      const int i = i0 + ii;
+      const int idx = (arr < 2 ? I : J) * kHT + x;
+      double2 v = make_double2(0.0, 0.0);
+      if (i < nbp && idx < m)
+        v = (arr & 1) ? t.wb[(long)i * n + s0 + idx]
+                      : t.a[(long)(k0 + i) * n + s0 + idx];
+      sv[arr][ii][x] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ii = 0; ii < 8; ++ii) {
+      double2 vr[4], wr[4], vc[4], wc[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        vr[a] = sv[0][ii][tr + 16 * a];
+        wr[a] = sv[1][ii][tr + 16 * a];
+        vc[a] = sv[2][ii][tc + 16 * a];
+        wc[a] = sv[3][ii][tc + 16 * a];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double2 p = cmulc(wc[c], vr[a]);   // V[r] conj(W[c])
+          const double2 q = cmulc(vc[c], wr[a]);   // W[r] conj(V[c])
+          acc[a][c].x += p.x + q.x;
+          acc[a][c].y += p.y + q.y;
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int r = I * kHT + tr + 16 * a;
+    if (r >= m) continue;
+    double2 *row = t.a + (long)(s0 + r) * n + s0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int cc = J * kHT + tc + 16 * c;
+      if (cc < m) {
+        double2 v = row[cc];
+        v.x -= acc[a][c].x;
+        v.y -= acc[a][c].y;
+        row[cc] = v;
+      }
+    }
+  }
 }
 
 __global__ void hh_last_kernel(TriWork t, int n) {
@@ -782,13 +962,44 @@ void eig_lowest(Context *ctx, const double *a_in, int n, int n_eig,
   t.d = base + n;
   t.e = reinterpret_cast<double2 *>(base + 2 * n);
   t.p = t.e + n;
-  t.w = t.p + n;
-  double2 *phase = t.w + n;
-  for (int k = 0; k < n - 1; ++k) {
-    const int m = n - k - 1;
-    hipLaunchKernelGGL(hh_step_a_kernel, dim3(1), dim3(1024), 0, s, t, n, k);
-    hipLaunchKernelGGL(hh_step_b_kernel, dim3((m + 3) / 4), dim3(256), 0, s, t,
-                       n, k);
+  double2 *phase = t.p + n;
+  // panel vectors and hemv partials, sized for the first step (m = n - 1)
+  const int nt_max = std::max(1, (n - 1 + kHT - 1) / kHT);
+  const long strips_max = strip_prefix(nt_max);
+  t.ldp = (long)nt_max * kHT;
+  const size_t n_wb = (size_t)kNb * n, n_prow = (size_t)strips_max * kHT,
+               n_pcol = (size_t)nt_max * t.ldp, n_pdot = (size_t)nt_max * 64;
+  const int nup_max = (n + 255) / 256;
+  DevBuf hw(ctx, sizeof(double2) * (n_wb + n_prow + n_pcol + n_pdot) +
+                     sizeof(double) * nup_max + 64);
+  t.wb = hw.as<double2>();
+  t.prow = t.wb + n_wb;
+  t.pcol = t.prow + n_prow;
+  t.pdot = t.pcol + n_pcol;
+  t.pup = reinterpret_cast<double *>(t.pdot + n_pdot);
+  for (int k0 = 0; k0 < n; k0 += kNb) {
+    const int kend = std::min(k0 + kNb, n);
+    int nup = 0;
+    for (int k = k0; k < kend; ++k) {
+      const int j = k - k0, m = n - k - 1;
+      hipLaunchKernelGGL(hh_col_kernel, dim3((m + 1 + 255) / 256), dim3(256), 0, s,
+                         t, n, k, k0, j, nup, 0);
+      if (m == 0) break;
+      hipLaunchKernelGGL(hh_make_kernel, dim3(1), dim3(1024), 0, s, t, n, k);
+      const int nt = (m + kHT - 1) / kHT;
+      hipLaunchKernelGGL(hh_hemv_kernel, dim3((unsigned)strip_prefix(nt)), dim3(256),
+                         0, s, t, n, k, k0, j);
+      nup = (m + 255) / 256;
+      hipLaunchKernelGGL(hh_p_kernel, dim3(nup), dim3(256), 0, s, t, n, k, k0, j);
+    }
+    if (kend < n) {
+      // finish w of the panel's last step, then update the next trailing block
+      hipLaunchKernelGGL(hh_col_kernel, dim3((n - kend + 255) / 256), dim3(256), 0,
+                         s, t, n, kend, k0, kend - k0, nup, 1);
+      const long nt = (n - kend + kHT - 1) / kHT;
+      hipLaunchKernelGGL(hh_her2k_kernel, dim3((unsigned)(nt * (nt + 1) / 2)),
+                         dim3(256), 0, s, t, n, k0, kend - k0, kend);
+    }
   }
   hipLaunchKernelGGL(hh_last_kernel, dim3(1), dim3(64), 0, s, t, n);
   SSRPA_HIP(hipGetLastError());
