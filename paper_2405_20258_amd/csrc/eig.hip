@@ -60,14 +60,17 @@ __device__ double block_sum(double v, double *red) {
 // keeps its value A0 from the start of the panel; the current matrix is
 //   A' = A0 - sum_i (V_i W_i^H + W_i V_i^H)
 // over the panel's earlier reflectors V_i = u_i and their vectors W_i = w_i.
-// Step k (slot i = k - k0 of the panel) runs four kernels:
-//   col:  w of the previous step, w = p - (tau/2)(u^H p) u, then column k of
-//         A' from the lower triangle of A0 and the panel vectors, stored
-//         conjugated in row k;
-//   make: reflector k from that row (u stored in row k; tau, e, d);
-//   hemv: tau A0 u over the lower triangle of the trailing block, in strips
-//         of 64 x 64 tiles, and the panel products W^H u and V^H u;
-//   p:    p = tau (A0 u - V (W^H u) - W (V^H u)) from the strip partials.
+// Step k (slot j = k - k0 of the panel) runs two kernels:
+//   col:  finishes step k-1: p = tau (A0 u - V (W^H u) - W (V^H u)) from the
+//         hemv partials and w = p - (tau/2)(u^H p) u, where
+//         u^H p = tau (u^H A0 u - 2 Re (V^H u)^H (W^H u)) needs no pass over
+//         p; then column k of A' from the lower triangle of A0 and the panel
+//         vectors (row k keeps its conjugate on the diagonal and x beyond it)
+//         and partials of |x|^2;
+//   hemv: reflector k from those partials (u = x except u_0 = x_0 - beta;
+//         work-group 0 stores u_0, tau, e, d), then A0 u over the lower
+//         triangle of the trailing block in strips of 64 x 64 tiles, the
+//         panel products W^H u and V^H u and partials of u^H A0 u.
 // After the panel, her2k applies its rank-2 kNb update to the lower tiles of
 // the next trailing block, which is A0 of the next panel.  Only the lower
 // triangle is read, so the trailing matrix is read (half of it) once per
@@ -75,18 +78,20 @@ __device__ double block_sum(double v, double *red) {
 constexpr int kNb = 32;     // panel width; 2 kNb panel products fit 64 slots
 constexpr int kHT = 64;     // hemv and her2k tile
 constexpr int kStrip = 4;   // tiles per hemv strip
+constexpr int kColRows = 64;  // elements per work-group of the col kernel
 
 struct TriWork {
   double2 *a;     // n x n work matrix (interleaved), row-major
   double *tau;    // n
   double *d;      // n   diagonal of T
   double2 *e;     // n   complex off-diagonal of T_c (e[k] = T_c[k+1][k])
-  double2 *p;     // n   p of the current step, trailing index
+  double2 *xs;    // n   x_0 of each step (before the reflector)
   double2 *wb;    // kNb x n: panel vectors W_i by global index
   double2 *prow;  // strips x 64: row partials of the hemv
   double2 *pcol;  // tile rows x ldp: column partials of the hemv
-  double2 *pdot;  // tile rows x 64: partials of W^H u (slots < i), V^H u
-  double *pup;    // per p-block partial of Re(u^H p)
+  double2 *pdot;  // tile rows x 64: partials of W^H u (slots < j), V^H u
+  double *puau;   // strips: partials of u^H A0 u
+  double *pnrm;   // col work-groups: partials of sum_{c > k+1} |x_c|^2
   long ldp;       // row length of pcol
 };
 
@@ -96,76 +101,101 @@ __host__ __device__ inline long strip_prefix(int I) {
   return I + kStrip * q * (q - 1) / 2 + q * r;
 }
 
-// Reflector for column k: x = A'[k+1:, k] = conj(row k beyond the diagonal).
-__global__ __launch_bounds__(1024) void hh_make_kernel(TriWork t, int n, int k) {
-  __shared__ double red[16];
-  const int m = n - k - 1;
-  double2 *row = t.a + (long)k * n + k + 1;
-  double s = 0.0;
-  for (int i = threadIdx.x + 1; i < m; i += blockDim.x) {
-    const double2 v = row[i];
-    s += v.x * v.x + v.y * v.y;
-  }
-  const double rest = block_sum(s, red);      // sum_{i>0} |x_i|^2
-  const double2 a0c = row[0];                 // conj(x0)
-  const double2 x0 = make_double2(a0c.x, -a0c.y);
-  const double ax0 = hypot(x0.x, x0.y);
-  const double nrm2 = rest + ax0 * ax0;
-  __syncthreads();
-  if (m == 1 || rest == 0.0) {
-    // already of the form e_k e_1: no reflection (H = I)
-    if (threadIdx.x == 0) {
-      t.tau[k] = 0.0;
-      t.e[k] = x0;
-      t.d[k] = t.a[(long)k * n + k].x;
-    }
-    return;
-  }
-  const double nrm = sqrt(nrm2);
-  const double2 ph = ax0 > 0.0 ? make_double2(x0.x / ax0, x0.y / ax0)
-                               : make_double2(1.0, 0.0);
-  // beta = -phase |x|; u = x - beta e_1; |u|^2 = 2 |x| (|x| + |x0|)
-  const double2 beta = make_double2(-ph.x * nrm, -ph.y * nrm);
-  const double tau = 1.0 / (nrm * (nrm + ax0));
-  for (int i = threadIdx.x; i < m; i += blockDim.x) {
-    const double2 v = row[i];
-    double2 u = make_double2(v.x, -v.y);      // x_i
-    if (i == 0) u = make_double2(x0.x - beta.x, x0.y - beta.y);
-    row[i] = u;                               // store u (not conjugated)
-  }
-  if (threadIdx.x == 0) {
-    t.tau[k] = tau;
-    t.e[k] = beta;
-    t.d[k] = t.a[(long)k * n + k].x;
-  }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
+  return make_double2(a.x + b.x, a.y + b.y);
 }
 
-// Step k, part col (one thread per c = k .. n-1).  For panel slot j > 0 it
-// first finishes w of step k-1 (slot j-1) from p and the nup partials of
-// Re(u^H p); unless finish_only it then forms A'[c][k] and stores its
-// conjugate in row k.
+// Step k, part col: 64 elements c = k + 64 b + e per work-group, four
+// threads (q = 0..3) per element sharing its sums.  With slot j > 0 it first
+// finishes step k-1 (slot j-1, trailing offset k, size n - k) and stores
+// W_{j-1}; unless finish_only it then forms x_c = A'[c][k].
 __global__ __launch_bounds__(256) void hh_col_kernel(TriWork t, int n, int k,
-                                                     int k0, int j, int nup,
+                                                     int k0, int j,
                                                      int finish_only) {
   __shared__ double red[16];
+  __shared__ double2 y[64], part[4][kColRows], wsh[kColRows];
   __shared__ double2 vk[kNb], wk[kNb];
-  const int c = k + blockIdx.x * 256 + threadIdx.x;
+  __shared__ double kk[2];
+  const int e = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int c = k + blockIdx.x * kColRows + e;
   const bool in = c < n;
-  double2 wc = make_double2(0.0, 0.0);        // w_{j-1}[c]
+  const double2 zero = make_double2(0.0, 0.0);
+  const double2 a_ck = (!finish_only && in) ? t.a[(long)c * n + k] : make_double2(0.0, 0.0);
   if (j > 0) {
+    const int jp = j - 1, mp = n - k;
+    const int ntp = (mp + kHT - 1) / kHT;
+    const double taup = t.tau[k - 1];
+    {
+      // panel products of step k-1: y[s] = W_s^H u, y[jp + s] = V_s^H u
+      double2 s = zero;
+      if (e < 2 * jp)
+        for (int I = q; I < ntp; I += 4) s = cadd(s, t.pdot[(long)I * 64 + e]);
+      part[q][e] = s;
+    }
     double s = 0.0;
-    for (int b = threadIdx.x; b < nup; b += 256) s += t.pup[b];
-    const double K = 0.5 * t.tau[k - 1] * block_sum(s, red);
-    const double2 *up = t.a + (long)(k - 1) * n;   // u_{k-1} by global index
-    if (in) {
-      const double2 pc = t.p[c - k], uc = up[c];
-      wc = make_double2(pc.x - K * uc.x, pc.y - K * uc.y);
-      t.wb[(long)(j - 1) * n + c] = wc;
-    }
+    const long nsp = strip_prefix(ntp);
+    for (long b = threadIdx.x; b < nsp; b += 256) s += t.puau[b];
+    const double uau = block_sum(s, red);   // syncs: part[] is complete
+    if (threadIdx.x < 64)
+      y[e] = cadd(cadd(part[0][e], part[1][e]), cadd(part[2][e], part[3][e]));
+    __syncthreads();
     if (threadIdx.x == 0) {
-      const double2 p0 = t.p[0], u0 = up[k];
-      wk[j - 1] = make_double2(p0.x - K * u0.x, p0.y - K * u0.y);
+      double corr = 0.0;
+      for (int i = 0; i < jp; ++i)
+        corr += y[jp + i].x * y[i].x + y[jp + i].y * y[i].y;
+      kk[0] = 0.5 * taup * taup * (uau - 2.0 * corr);
     }
+    // p of this element, r = c - k, in four interleaved parts
+    double2 ps = zero;
+    if (in) {
+      const int r = c - k, I = r / kHT, rr = r - I * kHT;
+      const long b0 = strip_prefix(I), b1 = b0 + I / kStrip + 1;
+      for (long b = b0 + q; b < b1; b += 4) ps = cadd(ps, t.prow[b * kHT + rr]);
+      for (int I2 = I + q; I2 < ntp; I2 += 4)
+        ps = cadd(ps, t.pcol[(long)I2 * t.ldp + r]);
+      for (int i = q; i < jp; i += 4) {
+        const double2 v = t.a[(long)(k0 + i) * n + c], w = t.wb[(long)i * n + c];
+        const double2 y1 = y[i], y2 = y[jp + i];
+        ps.x -= v.x * y1.x - v.y * y1.y + w.x * y2.x - w.y * y2.y;
+        ps.y -= v.x * y1.y + v.y * y1.x + w.x * y2.y + w.y * y2.x;
+      }
+    }
+    __syncthreads();
+    part[q][e] = ps;
+    // the same sums for r = 0 (w_{j-1}[k], needed by every work-group), by
+    // wave 0 when this group does not hold c = k
+    double2 p0 = zero;
+    if (q == 0 && blockIdx.x != 0) {
+      if (e == 0) p0 = t.prow[0];
+      for (int I2 = e; I2 < ntp; I2 += 64) p0 = cadd(p0, t.pcol[(long)I2 * t.ldp]);
+      if (e < jp) {
+        const double2 v = t.a[(long)(k0 + e) * n + k], w = t.wb[(long)e * n + k];
+        const double2 y1 = y[e], y2 = y[jp + e];
+        p0.x -= v.x * y1.x - v.y * y1.y + w.x * y2.x - w.y * y2.y;
+        p0.y -= v.x * y1.y + v.y * y1.x + w.x * y2.y + w.y * y2.x;
+      }
+      p0.x = wave_sum(p0.x);
+      p0.y = wave_sum(p0.y);
+    }
+    __syncthreads();
+    const double K = kk[0];
+    const double2 *up = t.a + (long)(k - 1) * n;    // u_{k-1} by global index
+    if (q == 0) {
+      const double2 tot = cadd(cadd(part[0][e], part[1][e]), cadd(part[2][e], part[3][e]));
+      double2 w = zero;
+      if (in) {
+        const double2 uc = up[c];
+        w = make_double2(taup * tot.x - K * uc.x, taup * tot.y - K * uc.y);
+        t.wb[(long)jp * n + c] = w;
+      }
+      wsh[e] = w;
+      if (blockIdx.x == 0 && e == 0) wk[jp] = w;
+      if (blockIdx.x != 0 && e == 0) {
+        const double2 u0 = up[k];
+        wk[jp] = make_double2(taup * p0.x - K * u0.x, taup * p0.y - K * u0.y);
+      }
+    }
+    __syncthreads();
   }
   if (finish_only) return;
   for (int i = threadIdx.x; i < j; i += 256) {
@@ -173,17 +203,34 @@ __global__ __launch_bounds__(256) void hh_col_kernel(TriWork t, int n, int k,
     if (i < j - 1) wk[i] = t.wb[(long)i * n + k];
   }
   __syncthreads();
-  if (!in) return;
-  double2 x = t.a[(long)c * n + k];           // A0[c][k], lower triangle
-  for (int i = 0; i < j; ++i) {
-    const double2 vc = t.a[(long)(k0 + i) * n + c];
-    const double2 wci = i == j - 1 ? wc : t.wb[(long)i * n + c];
-    const double2 p = cmulc(wk[i], vc);       // V_i[c] conj(W_i[k])
-    const double2 q = cmulc(vk[i], wci);      // W_i[c] conj(V_i[k])
-    x.x -= p.x + q.x;
-    x.y -= p.y + q.y;
+  double2 xs = zero;
+  if (in) {
+    for (int i = q; i < j; i += 4) {
+      const double2 vc = t.a[(long)(k0 + i) * n + c];
+      const double2 wci = i == j - 1 ? wsh[e] : t.wb[(long)i * n + c];
+      const double2 a = cmulc(wk[i], vc);     // V_i[c] conj(W_i[k])
+      const double2 b = cmulc(vk[i], wci);    // W_i[c] conj(V_i[k])
+      xs.x += a.x + b.x;
+      xs.y += a.y + b.y;
+    }
   }
-  t.a[(long)k * n + c] = make_double2(x.x, -x.y);
+  __syncthreads();
+  part[q][e] = xs;
+  __syncthreads();
+  double nrm = 0.0;
+  if (q == 0 && in) {
+    const double2 corr = cadd(cadd(part[0][e], part[1][e]), cadd(part[2][e], part[3][e]));
+    const double2 x = make_double2(a_ck.x - corr.x, a_ck.y - corr.y);
+    if (c == k) {
+      t.a[(long)k * n + k] = make_double2(x.x, -x.y);
+    } else {
+      t.a[(long)k * n + c] = x;
+      if (c == k + 1) t.xs[k] = x;
+      else nrm = x.x * x.x + x.y * x.y;
+    }
+  }
+  const double tot = block_sum(nrm, red);
+  if (threadIdx.x == 0) t.pnrm[blockIdx.x] = tot;
 }
 
 // Step k, part hemv: one work-group per strip of up to kStrip tiles of tile
@@ -194,11 +241,32 @@ __global__ __launch_bounds__(256) void hh_col_kernel(TriWork t, int n, int k,
 // by Hermitian symmetry; strictly below the diagonal in diagonal tiles).
 // The strip holding the diagonal tile also forms the panel products over its
 // rows: slot s < j: conj(W_s) . u, slot j + s: conj(V_s) . u.
-__global__ __launch_bounds__(256) void hh_hemv_kernel(TriWork t, int n, int k,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void hh_hemv_kernel(TriWork t, int n, int k,
                                                       int k0, int j) {
-  __shared__ double2 cs[2][4][64];
+  __shared__ double red[16];
+  __shared__ double2 cs[kStrip][4][64];
+  __shared__ double2 ur_s[kHT];
   const int o = k + 1, m = n - o;
   const int nt = (m + kHT - 1) / kHT;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double2 zero = make_double2(0.0, 0.0);
+  // reflector k: x = row k beyond the diagonal, |x|^2 from the col partials
+  double s = 0.0;
+  const int ncb = (m + 1 + kColRows - 1) / kColRows;
+  for (int b = threadIdx.x; b < ncb; b += 256) s += t.pnrm[b];
+  const double rest = block_sum(s, red);
+  const double2 x0 = t.xs[k];
+  const double ax0 = hypot(x0.x, x0.y);
+  double tau = 0.0;
+  double2 beta = x0, u0 = x0;
+  if (m > 1 && rest != 0.0) {
+    const double nrm = sqrt(rest + ax0 * ax0);
+    const double2 ph = ax0 > 0.0 ? make_double2(x0.x / ax0, x0.y / ax0)
+                                 : make_double2(1.0, 0.0);
+    beta = make_double2(-ph.x * nrm, -ph.y * nrm);
+    tau = 1.0 / (nrm * (nrm + ax0));
+    u0 = make_double2(x0.x - beta.x, x0.y - beta.y);
+  }
   const long b = blockIdx.x;
   int lo = 0, hi = nt - 1;
   while (lo < hi) {
@@ -209,180 +277,137 @@ __global__ __launch_bounds__(256) void hh_hemv_kernel(TriWork t, int n, int k,
   const int I = lo;
   const int J0 = (int)(b - strip_prefix(I)) * kStrip;
   const int J1 = min(J0 + kStrip, I + 1);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // u[0] lives in x0 until work-group 0 stores it, so it is never loaded
   const double2 *u = t.a + (long)k * n + o;
+  auto uat = [&](int r) {
+    double2 v = make_double2(0.0, 0.0);
+    if (r > 0 && r < m) v = u[r];
+    v.x = r == 0 ? u0.x : v.x;
+    v.y = r == 0 ? u0.y : v.y;
+    return v;
+  };
   const double2 *blk = t.a + (long)o * n + o;
   const int rb = I * kHT + wave * 16;
-  double2 ur[16], acc[16];
+  const int rbu = __builtin_amdgcn_readfirstlane(rb);
+  ur_s[threadIdx.x & 63] = uat(I * kHT + (threadIdx.x & 63));  // same in every wave
+  double2 acc[16];
 #pragma unroll
-  for (int rr = 0; rr < 16; ++rr) {
-    ur[rr] = rb + rr < m ? u[rb + rr] : make_double2(0.0, 0.0);
-    acc[rr] = make_double2(0.0, 0.0);
-  }
+  for (int rr = 0; rr < 16; ++rr) acc[rr] = zero;
+  __syncthreads();
+  const double2 *ur = ur_s + wave * 16;
+#pragma unroll 1
   for (int J = J0; J < J1; ++J) {
     const int cj = J * kHT + lane;
     const bool cok = cj < m;
     const bool diag = J == I;
-    const double2 uc = cok ? u[cj] : make_double2(0.0, 0.0);
-    const double2 *col = blk + (cok ? cj : 0);
+    const double2 uc = uat(cj);
+    const int cjc = cok ? cj : 0;
     double2 v[16];
 #pragma unroll
     for (int rr = 0; rr < 16; ++rr) {
-      const bool ld = cok && rb + rr < m && (!diag || lane <= wave * 16 + rr);
-      v[rr] = ld ? col[(long)(rb + rr) * n] : make_double2(0.0, 0.0);
+      // row base is wave-uniform, the lane adds its column
+      const double2 *rowp = blk + (long)(rbu + rr) * n;
+      const bool ld = cok && rbu + rr < m && (!diag || lane <= wave * 16 + rr);
+      v[rr] = ld ? rowp[cjc] : make_double2(0.0, 0.0);
     }
-    double2 csum = make_double2(0.0, 0.0);
+    double2 csum = zero;
 #pragma unroll
     for (int rr = 0; rr < 16; ++rr) {
       double2 vr = v[rr], vc = v[rr];
       if (diag && lane == wave * 16 + rr) {
         vr.y = 0.0;                           // real diagonal
-        vc = make_double2(0.0, 0.0);
+        vc = zero;
       }
       acc[rr].x += vr.x * uc.x - vr.y * uc.y;
       acc[rr].y += vr.x * uc.y + vr.y * uc.x;
-      const double2 q = cmulc(vc, ur[rr]);
-      csum.x += q.x;
-      csum.y += q.y;
+      const double2 qv = cmulc(vc, ur[rr]);
+      csum.x += qv.x;
+      csum.y += qv.y;
     }
-    double2 (*cb)[64] = cs[J & 1];
-    cb[wave][lane] = csum;
-    __syncthreads();
-    if (wave == 0) {
-      double2 tot = cb[0][lane];
-#pragma unroll
-      for (int w = 1; w < 4; ++w) {
-        tot.x += cb[w][lane].x;
-        tot.y += cb[w][lane].y;
-      }
-      t.pcol[(long)I * t.ldp + cj] = tot;
-    }
+    cs[J - J0][wave][lane] = csum;
   }
   // reduce the 16 row sums over the 64 lanes: halve the values per lane at
   // each exchange; lane l ends with row (l >> 2) & 15 over lanes l ^ {0..3}
 #pragma unroll
   for (int h = 0; h < 8; ++h) {
-    const bool hi5 = lane & 32;
-    const double2 send = hi5 ? acc[h] : acc[h + 8];
-    const double2 keep = hi5 ? acc[h + 8] : acc[h];
+    const bool hb = lane & 32;
+    const double2 send = hb ? acc[h] : acc[h + 8];
+    const double2 keep = hb ? acc[h + 8] : acc[h];
     acc[h] = make_double2(keep.x + __shfl_xor(send.x, 32), keep.y + __shfl_xor(send.y, 32));
   }
 #pragma unroll
   for (int h = 0; h < 4; ++h) {
-    const bool hi4 = lane & 16;
-    const double2 send = hi4 ? acc[h] : acc[h + 4];
-    const double2 keep = hi4 ? acc[h + 4] : acc[h];
+    const bool hb = lane & 16;
+    const double2 send = hb ? acc[h] : acc[h + 4];
+    const double2 keep = hb ? acc[h + 4] : acc[h];
     acc[h] = make_double2(keep.x + __shfl_xor(send.x, 16), keep.y + __shfl_xor(send.y, 16));
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const bool hi3 = lane & 8;
-    const double2 send = hi3 ? acc[h] : acc[h + 2];
-    const double2 keep = hi3 ? acc[h + 2] : acc[h];
+    const bool hb = lane & 8;
+    const double2 send = hb ? acc[h] : acc[h + 2];
+    const double2 keep = hb ? acc[h + 2] : acc[h];
     acc[h] = make_double2(keep.x + __shfl_xor(send.x, 8), keep.y + __shfl_xor(send.y, 8));
   }
   {
-    const bool hi2 = lane & 4;
-    const double2 send = hi2 ? acc[0] : acc[1];
-    const double2 keep = hi2 ? acc[1] : acc[0];
+    const bool hb = lane & 4;
+    const double2 send = hb ? acc[0] : acc[1];
+    const double2 keep = hb ? acc[1] : acc[0];
     acc[0] = make_double2(keep.x + __shfl_xor(send.x, 4), keep.y + __shfl_xor(send.y, 4));
   }
   acc[0].x += __shfl_xor(acc[0].x, 2);
   acc[0].y += __shfl_xor(acc[0].y, 2);
   acc[0].x += __shfl_xor(acc[0].x, 1);
   acc[0].y += __shfl_xor(acc[0].y, 1);
-  if ((lane & 3) == 0) t.prow[b * kHT + wave * 16 + (lane >> 2)] = acc[0];
+  double uau = 0.0;   // this group's share of u^H A0 u
+  if ((lane & 3) == 0) {
+    const int r = rb + (lane >> 2);
+    t.prow[b * kHT + wave * 16 + (lane >> 2)] = acc[0];
+    const double2 uv = uat(r);
+    uau += uv.x * acc[0].x + uv.y * acc[0].y;
+  }
+  __syncthreads();
+  if (J0 + wave < J1) {
+    const int J = J0 + wave, cj = J * kHT + lane;
+    const double2 tot = cadd(cadd(cs[wave][0][lane], cs[wave][1][lane]),
+                             cadd(cs[wave][2][lane], cs[wave][3][lane]));
+    t.pcol[(long)I * t.ldp + cj] = tot;
+    const double2 uv = uat(cj);
+    uau += uv.x * tot.x + uv.y * tot.y;
+  }
   if (J1 == I + 1 && j > 0) {
     // panel products over rows I*64 .. I*64+63: 4 threads per slot
     const int slot = threadIdx.x >> 2, qt = threadIdx.x & 3;
-    double2 s = make_double2(0.0, 0.0);
+    double2 sd = zero;
     if (slot < 2 * j) {
       const double2 *x = slot < j ? t.wb + (long)slot * n + o
                                   : t.a + (long)(k0 + slot - j) * n + o;
       const int r0 = I * kHT + qt * 16;
-      for (int r = r0; r < min(r0 + 16, m); ++r) {
-        const double2 q = cmulc(x[r], u[r]);
-        s.x += q.x;
-        s.y += q.y;
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) {
+        const int r = r0 + rr;
+        const double2 xv = r < m ? x[r] : make_double2(0.0, 0.0);
+        const double2 qv = cmulc(xv, ur_s[qt * 16 + rr]);
+        sd.x += qv.x;
+        sd.y += qv.y;
       }
     }
-    s.x += __shfl_xor(s.x, 1);
-    s.y += __shfl_xor(s.y, 1);
-    s.x += __shfl_xor(s.x, 2);
-    s.y += __shfl_xor(s.y, 2);
-    if (qt == 0 && slot < 2 * j) t.pdot[(long)I * 64 + slot] = s;
+    sd.x += __shfl_xor(sd.x, 1);
+    sd.y += __shfl_xor(sd.y, 1);
+    sd.x += __shfl_xor(sd.x, 2);
+    sd.y += __shfl_xor(sd.y, 2);
+    if (qt == 0 && slot < 2 * j) t.pdot[(long)I * 64 + slot] = sd;
   }
-}
-
-// Step k, part p (one thread per trailing row r): sums the strip row
-// partials of r's tile row and the column partials of the tiles below, and
-// subtracts the panel terms; p = tau (...).  Each work-group also leaves its
-// partial of Re(u^H p).
-__global__ __launch_bounds__(256) void hh_p_kernel(TriWork t, int n, int k,
-                                                   int k0, int j) {
-  __shared__ double red[16];
-  __shared__ double2 yq[4][64];
-  __shared__ double2 y[64];
-  const int o = k + 1, m = n - o;
-  const int nt = (m + kHT - 1) / kHT;
-  {
-    const int slot = threadIdx.x & 63, g = threadIdx.x >> 6;
-    double2 s = make_double2(0.0, 0.0);
-    if (slot < 2 * j)
-      for (int I = g; I < nt; I += 4) {
-        const double2 v = t.pdot[(long)I * 64 + slot];
-        s.x += v.x;
-        s.y += v.y;
-      }
-    yq[g][slot] = s;
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      const double2 a = yq[0][slot], b = yq[1][slot], c = yq[2][slot], d = yq[3][slot];
-      y[slot] = make_double2(a.x + b.x + c.x + d.x, a.y + b.y + c.y + d.y);
+  const double ut = block_sum(uau, red);
+  if (threadIdx.x == 0) {
+    t.puau[b] = ut;
+    if (b == 0) {
+      t.tau[k] = tau;
+      t.e[k] = beta;
+      t.d[k] = t.a[(long)k * n + k].x;
+      t.a[(long)k * n + o] = u0;
     }
-    __syncthreads();
   }
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  double up = 0.0;
-  if (r < m) {
-    const int I = r / kHT, rr = r - I * kHT;
-    double2 s0 = make_double2(0.0, 0.0), s1 = s0;
-    const long b0 = strip_prefix(I), b1 = b0 + I / kStrip + 1;
-    for (long b = b0; b < b1; ++b) {
-      const double2 v = t.prow[b * kHT + rr];
-      s0.x += v.x;
-      s0.y += v.y;
-    }
-    const double2 *pc = t.pcol + r;
-    int I2 = I;
-    for (; I2 + 1 < nt; I2 += 2) {
-      const double2 v0 = pc[(long)I2 * t.ldp], v1 = pc[(long)(I2 + 1) * t.ldp];
-      s0.x += v0.x;
-      s0.y += v0.y;
-      s1.x += v1.x;
-      s1.y += v1.y;
-    }
-    if (I2 < nt) {
-      const double2 v = pc[(long)I2 * t.ldp];
-      s0.x += v.x;
-      s0.y += v.y;
-    }
-    double2 s = make_double2(s0.x + s1.x, s0.y + s1.y);
-    for (int i = 0; i < j; ++i) {
-      const double2 v = t.a[(long)(k0 + i) * n + o + r];
-      const double2 w = t.wb[(long)i * n + o + r];
-      const double2 y1 = y[i], y2 = y[j + i];   // W_i^H u, V_i^H u
-      s.x -= v.x * y1.x - v.y * y1.y + w.x * y2.x - w.y * y2.y;
-      s.y -= v.x * y1.y + v.y * y1.x + w.x * y2.y + w.y * y2.x;
-    }
-    const double tau = t.tau[k];
-    const double2 pr = make_double2(tau * s.x, tau * s.y);
-    t.p[r] = pr;
-    const double2 ur = t.a[(long)k * n + o + r];
-    up = ur.x * pr.x + ur.y * pr.y;
-  }
-  const double tot = block_sum(up, red);
-  if (threadIdx.x == 0) t.pup[blockIdx.x] = tot;
 }
 
 // End of a panel of nbp reflectors from k0: the lower 64 x 64 tiles of the
@@ -961,41 +986,38 @@ void eig_lowest(Context *ctx, const double *a_in, int n, int n_eig,
   t.tau = base;
   t.d = base + n;
   t.e = reinterpret_cast<double2 *>(base + 2 * n);
-  t.p = t.e + n;
-  double2 *phase = t.p + n;
+  t.xs = t.e + n;
+  double2 *phase = t.xs + n;
   // panel vectors and hemv partials, sized for the first step (m = n - 1)
   const int nt_max = std::max(1, (n - 1 + kHT - 1) / kHT);
   const long strips_max = strip_prefix(nt_max);
   t.ldp = (long)nt_max * kHT;
   const size_t n_wb = (size_t)kNb * n, n_prow = (size_t)strips_max * kHT,
                n_pcol = (size_t)nt_max * t.ldp, n_pdot = (size_t)nt_max * 64;
-  const int nup_max = (n + 255) / 256;
+  const int ncb_max = (n + kColRows - 1) / kColRows;
   DevBuf hw(ctx, sizeof(double2) * (n_wb + n_prow + n_pcol + n_pdot) +
-                     sizeof(double) * nup_max + 64);
+                     sizeof(double) * (strips_max + ncb_max) + 64);
   t.wb = hw.as<double2>();
   t.prow = t.wb + n_wb;
   t.pcol = t.prow + n_prow;
   t.pdot = t.pcol + n_pcol;
-  t.pup = reinterpret_cast<double *>(t.pdot + n_pdot);
+  t.puau = reinterpret_cast<double *>(t.pdot + n_pdot);
+  t.pnrm = t.puau + strips_max;
   for (int k0 = 0; k0 < n; k0 += kNb) {
     const int kend = std::min(k0 + kNb, n);
-    int nup = 0;
     for (int k = k0; k < kend; ++k) {
       const int j = k - k0, m = n - k - 1;
-      hipLaunchKernelGGL(hh_col_kernel, dim3((m + 1 + 255) / 256), dim3(256), 0, s,
-                         t, n, k, k0, j, nup, 0);
+      hipLaunchKernelGGL(hh_col_kernel, dim3((m + 1 + kColRows - 1) / kColRows),
+                         dim3(256), 0, s, t, n, k, k0, j, 0);
       if (m == 0) break;
-      hipLaunchKernelGGL(hh_make_kernel, dim3(1), dim3(1024), 0, s, t, n, k);
       const int nt = (m + kHT - 1) / kHT;
       hipLaunchKernelGGL(hh_hemv_kernel, dim3((unsigned)strip_prefix(nt)), dim3(256),
                          0, s, t, n, k, k0, j);
-      nup = (m + 255) / 256;
-      hipLaunchKernelGGL(hh_p_kernel, dim3(nup), dim3(256), 0, s, t, n, k, k0, j);
     }
     if (kend < n) {
       // finish w of the panel's last step, then update the next trailing block
-      hipLaunchKernelGGL(hh_col_kernel, dim3((n - kend + 255) / 256), dim3(256), 0,
-                         s, t, n, kend, k0, kend - k0, nup, 1);
+      hipLaunchKernelGGL(hh_col_kernel, dim3((n - kend + kColRows - 1) / kColRows),
+                         dim3(256), 0, s, t, n, kend, k0, kend - k0, 1);
       const long nt = (n - kend + kHT - 1) / kHT;
       hipLaunchKernelGGL(hh_her2k_kernel, dim3((unsigned)(nt * (nt + 1) / 2)),
                          dim3(256), 0, s, t, n, k0, kend - k0, kend);
