@@ -112,6 +112,7 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
 __global__ __launch_bounds__(256) void hh_col_kernel(TriWork t, int n, int k,
                                                      int k0, int j,
                                                      int finish_only) {
+  constexpr int kPer = kNb / 4;               // panel slots per quarter
   __shared__ double red[16];
   __shared__ double2 y[64], part[4][kColRows], wsh[kColRows];
   __shared__ double2 vk[kNb], wk[kNb];
@@ -119,23 +120,57 @@ __global__ __launch_bounds__(256) void hh_col_kernel(TriWork t, int n, int k,
   const int e = threadIdx.x & 63, q = threadIdx.x >> 6;
   const int c = k + blockIdx.x * kColRows + e;
   const bool in = c < n;
-  const double2 zero = make_double2(0.0, 0.0);
-  const double2 a_ck = (!finish_only && in) ? t.a[(long)c * n + k] : make_double2(0.0, 0.0);
+  const int jp = j - 1;                       // slot of step k-1
+  // every load that depends on nothing computed here is issued first
+  double2 a_ck = make_double2(0.0, 0.0);
+  if (!finish_only && in) a_ck = t.a[(long)c * n + k];
+  double2 vc[kPer], wc[kPer];                 // V_i[c], W_i[c], i = q + 4 s
+#pragma unroll
+  for (int s = 0; s < kPer; ++s) {
+    const int i = q + 4 * s;
+    vc[s] = make_double2(0.0, 0.0);
+    wc[s] = make_double2(0.0, 0.0);
+    if (in && i < j) vc[s] = t.a[(long)(k0 + i) * n + c];
+    if (in && i < jp) wc[s] = t.wb[(long)i * n + c];
+  }
+  // V_e[k], W_e[k] for the panel slots (wave 0)
+  double2 vke = make_double2(0.0, 0.0), wke = make_double2(0.0, 0.0);
+  if (q == 0 && e < j) vke = t.a[(long)(k0 + e) * n + k];
+  if (q == 0 && e < jp) wke = t.wb[(long)e * n + k];
+  double2 w_own = make_double2(0.0, 0.0);     // w_{j-1}[c]
   if (j > 0) {
-    const int jp = j - 1, mp = n - k;
+    const int mp = n - k;
     const int ntp = (mp + kHT - 1) / kHT;
     const double taup = t.tau[k - 1];
+    const double2 *up = t.a + (long)(k - 1) * n;   // u_{k-1} by global index
+    double2 u_c = make_double2(0.0, 0.0), u_k = up[k];
+    if (in) u_c = up[c];
     {
       // panel products of step k-1: y[s] = W_s^H u, y[jp + s] = V_s^H u
-      double2 s = zero;
+      double2 sy = make_double2(0.0, 0.0);
       if (e < 2 * jp)
-        for (int I = q; I < ntp; I += 4) s = cadd(s, t.pdot[(long)I * 64 + e]);
-      part[q][e] = s;
+        for (int I = q; I < ntp; I += 4) sy = cadd(sy, t.pdot[(long)I * 64 + e]);
+      part[q][e] = sy;
+    }
+    // hemv sums of p[r], r = c - k, in four interleaved parts
+    double2 ps = make_double2(0.0, 0.0);
+    if (in) {
+      const int r = c - k, I = r / kHT, rr = r - I * kHT;
+      const long b0 = strip_prefix(I), b1 = b0 + I / kStrip + 1;
+      for (long b = b0 + q; b < b1; b += 4) ps = cadd(ps, t.prow[b * kHT + rr]);
+      for (int I2 = I + q; I2 < ntp; I2 += 4)
+        ps = cadd(ps, t.pcol[(long)I2 * t.ldp + r]);
+    }
+    // the same for r = 0 (w_{j-1}[k] is needed by every work-group)
+    double2 p0 = make_double2(0.0, 0.0);
+    if (q == 0) {
+      if (e == 0) p0 = t.prow[0];
+      for (int I2 = e; I2 < ntp; I2 += 64) p0 = cadd(p0, t.pcol[(long)I2 * t.ldp]);
     }
     double s = 0.0;
     const long nsp = strip_prefix(ntp);
     for (long b = threadIdx.x; b < nsp; b += 256) s += t.puau[b];
-    const double uau = block_sum(s, red);   // syncs: part[] is complete
+    const double uau = block_sum(s, red);     // syncs: part[] is complete
     if (threadIdx.x < 64)
       y[e] = cadd(cadd(part[0][e], part[1][e]), cadd(part[2][e], part[3][e]));
     __syncthreads();
@@ -145,76 +180,57 @@ __global__ __launch_bounds__(256) void hh_col_kernel(TriWork t, int n, int k,
         corr += y[jp + i].x * y[i].x + y[jp + i].y * y[i].y;
       kk[0] = 0.5 * taup * taup * (uau - 2.0 * corr);
     }
-    // p of this element, r = c - k, in four interleaved parts
-    double2 ps = zero;
-    if (in) {
-      const int r = c - k, I = r / kHT, rr = r - I * kHT;
-      const long b0 = strip_prefix(I), b1 = b0 + I / kStrip + 1;
-      for (long b = b0 + q; b < b1; b += 4) ps = cadd(ps, t.prow[b * kHT + rr]);
-      for (int I2 = I + q; I2 < ntp; I2 += 4)
-        ps = cadd(ps, t.pcol[(long)I2 * t.ldp + r]);
-      for (int i = q; i < jp; i += 4) {
-        const double2 v = t.a[(long)(k0 + i) * n + c], w = t.wb[(long)i * n + c];
+    // panel terms: p -= V_i (W_i^H u) + W_i (V_i^H u), i < jp
+#pragma unroll
+    for (int s2 = 0; s2 < kPer; ++s2) {
+      const int i = q + 4 * s2;
+      if (i < jp) {
         const double2 y1 = y[i], y2 = y[jp + i];
+        const double2 v = vc[s2], w = wc[s2];
         ps.x -= v.x * y1.x - v.y * y1.y + w.x * y2.x - w.y * y2.y;
         ps.y -= v.x * y1.y + v.y * y1.x + w.x * y2.y + w.y * y2.x;
       }
     }
-    __syncthreads();
     part[q][e] = ps;
-    // the same sums for r = 0 (w_{j-1}[k], needed by every work-group), by
-    // wave 0 when this group does not hold c = k
-    double2 p0 = zero;
-    if (q == 0 && blockIdx.x != 0) {
-      if (e == 0) p0 = t.prow[0];
-      for (int I2 = e; I2 < ntp; I2 += 64) p0 = cadd(p0, t.pcol[(long)I2 * t.ldp]);
+    if (q == 0) {
       if (e < jp) {
-        const double2 v = t.a[(long)(k0 + e) * n + k], w = t.wb[(long)e * n + k];
         const double2 y1 = y[e], y2 = y[jp + e];
-        p0.x -= v.x * y1.x - v.y * y1.y + w.x * y2.x - w.y * y2.y;
-        p0.y -= v.x * y1.y + v.y * y1.x + w.x * y2.y + w.y * y2.x;
+        p0.x -= vke.x * y1.x - vke.y * y1.y + wke.x * y2.x - wke.y * y2.y;
+        p0.y -= vke.x * y1.y + vke.y * y1.x + wke.x * y2.y + wke.y * y2.x;
       }
       p0.x = wave_sum(p0.x);
       p0.y = wave_sum(p0.y);
     }
     __syncthreads();
     const double K = kk[0];
-    const double2 *up = t.a + (long)(k - 1) * n;    // u_{k-1} by global index
     if (q == 0) {
       const double2 tot = cadd(cadd(part[0][e], part[1][e]), cadd(part[2][e], part[3][e]));
-      double2 w = zero;
       if (in) {
-        const double2 uc = up[c];
-        w = make_double2(taup * tot.x - K * uc.x, taup * tot.y - K * uc.y);
-        t.wb[(long)jp * n + c] = w;
+        w_own = make_double2(taup * tot.x - K * u_c.x, taup * tot.y - K * u_c.y);
+        t.wb[(long)jp * n + c] = w_own;
       }
-      wsh[e] = w;
-      if (blockIdx.x == 0 && e == 0) wk[jp] = w;
-      if (blockIdx.x != 0 && e == 0) {
-        const double2 u0 = up[k];
-        wk[jp] = make_double2(taup * p0.x - K * u0.x, taup * p0.y - K * u0.y);
-      }
+      wsh[e] = w_own;
+      if (e == 0) wk[jp] = make_double2(taup * p0.x - K * u_k.x, taup * p0.y - K * u_k.y);
     }
-    __syncthreads();
   }
   if (finish_only) return;
-  for (int i = threadIdx.x; i < j; i += 256) {
-    vk[i] = t.a[(long)(k0 + i) * n + k];
-    if (i < j - 1) wk[i] = t.wb[(long)i * n + k];
+  if (q == 0 && e < j) {
+    vk[e] = vke;
+    if (e < jp) wk[e] = wke;
   }
   __syncthreads();
-  double2 xs = zero;
-  if (in) {
-    for (int i = q; i < j; i += 4) {
-      const double2 vc = t.a[(long)(k0 + i) * n + c];
-      const double2 wci = i == j - 1 ? wsh[e] : t.wb[(long)i * n + c];
-      const double2 a = cmulc(wk[i], vc);     // V_i[c] conj(W_i[k])
-      const double2 b = cmulc(vk[i], wci);    // W_i[c] conj(V_i[k])
+  double2 xs = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int s2 = 0; s2 < kPer; ++s2) {
+    const int i = q + 4 * s2;
+    if (i < j) {
+      const double2 wci = i == jp ? wsh[e] : wc[s2];
+      const double2 a = cmulc(wk[i], vc[s2]);   // V_i[c] conj(W_i[k])
+      const double2 b = cmulc(vk[i], wci);      // W_i[c] conj(V_i[k])
       xs.x += a.x + b.x;
       xs.y += a.y + b.y;
     }
   }
-  __syncthreads();
   part[q][e] = xs;
   __syncthreads();
   double nrm = 0.0;
@@ -250,12 +266,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void h
   const int nt = (m + kHT - 1) / kHT;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const double2 zero = make_double2(0.0, 0.0);
+  const long b = blockIdx.x;
+  int lo = 0, hi = nt - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (strip_prefix(mid) <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int I = lo;
+  const int J0 = (int)(b - strip_prefix(I)) * kStrip;
+  const int J1 = min(J0 + kStrip, I + 1);
+  const double2 *u = t.a + (long)k * n + o;
+  const double2 *blk = t.a + (long)o * n + o;
+  const int rb = I * kHT + wave * 16;
+  const int rbu = __builtin_amdgcn_readfirstlane(rb);
+  // tile J of the strip: lane's column of the wave's 16 rows (the upper
+  // triangle of a diagonal tile is not loaded)
+  double2 v[16];
+  auto load_tile = [&](int J) __attribute__((always_inline)) {
+    const int cj = J * kHT + lane;
+    const bool cok = cj < m, diag = J == I;
+    const int cjc = cok ? cj : 0;
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+      // row base is wave-uniform, the lane adds its column
+      const double2 *rowp = blk + (long)(rbu + rr) * n;
+      const bool ld = cok && rbu + rr < m && (!diag || lane <= wave * 16 + rr);
+      v[rr] = ld ? rowp[cjc] : make_double2(0.0, 0.0);
+    }
+  };
+  // loads that need nothing from the reflector go first: u beyond u_0, the
+  // first tile, x_0 and the norm partials
+  const int rl = I * kHT + lane;
+  double2 url = make_double2(0.0, 0.0);
+  if (rl > 0 && rl < m) url = u[rl];
+  load_tile(J0);
+  const double2 x0 = t.xs[k];
   // reflector k: x = row k beyond the diagonal, |x|^2 from the col partials
   double s = 0.0;
   const int ncb = (m + 1 + kColRows - 1) / kColRows;
-  for (int b = threadIdx.x; b < ncb; b += 256) s += t.pnrm[b];
+  for (int bb = threadIdx.x; bb < ncb; bb += 256) s += t.pnrm[bb];
   const double rest = block_sum(s, red);
-  const double2 x0 = t.xs[k];
   const double ax0 = hypot(x0.x, x0.y);
   double tau = 0.0;
   double2 beta = x0, u0 = x0;
@@ -267,29 +318,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void h
     tau = 1.0 / (nrm * (nrm + ax0));
     u0 = make_double2(x0.x - beta.x, x0.y - beta.y);
   }
-  const long b = blockIdx.x;
-  int lo = 0, hi = nt - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (strip_prefix(mid) <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  const int I = lo;
-  const int J0 = (int)(b - strip_prefix(I)) * kStrip;
-  const int J1 = min(J0 + kStrip, I + 1);
   // u[0] lives in x0 until work-group 0 stores it, so it is never loaded
-  const double2 *u = t.a + (long)k * n + o;
   auto uat = [&](int r) {
-    double2 v = make_double2(0.0, 0.0);
-    if (r > 0 && r < m) v = u[r];
-    v.x = r == 0 ? u0.x : v.x;
-    v.y = r == 0 ? u0.y : v.y;
-    return v;
+    double2 w = make_double2(0.0, 0.0);
+    if (r > 0 && r < m) w = u[r];
+    w.x = r == 0 ? u0.x : w.x;
+    w.y = r == 0 ? u0.y : w.y;
+    return w;
   };
-  const double2 *blk = t.a + (long)o * n + o;
-  const int rb = I * kHT + wave * 16;
-  const int rbu = __builtin_amdgcn_readfirstlane(rb);
-  ur_s[threadIdx.x & 63] = uat(I * kHT + (threadIdx.x & 63));  // same in every wave
+  if (rl == 0) url = u0;
+  ur_s[lane] = url;                           // same in every wave
   double2 acc[16];
 #pragma unroll
   for (int rr = 0; rr < 16; ++rr) acc[rr] = zero;
@@ -298,18 +336,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void h
 #pragma unroll 1
   for (int J = J0; J < J1; ++J) {
     const int cj = J * kHT + lane;
-    const bool cok = cj < m;
     const bool diag = J == I;
     const double2 uc = uat(cj);
-    const int cjc = cok ? cj : 0;
-    double2 v[16];
-#pragma unroll
-    for (int rr = 0; rr < 16; ++rr) {
-      // row base is wave-uniform, the lane adds its column
-      const double2 *rowp = blk + (long)(rbu + rr) * n;
-      const bool ld = cok && rbu + rr < m && (!diag || lane <= wave * 16 + rr);
-      v[rr] = ld ? rowp[cjc] : make_double2(0.0, 0.0);
-    }
+    if (J > J0) load_tile(J);
     double2 csum = zero;
 #pragma unroll
     for (int rr = 0; rr < 16; ++rr) {
