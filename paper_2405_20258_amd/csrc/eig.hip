@@ -78,7 +78,8 @@ __device__ double block_sum(double v, double *red) {
 constexpr int kNb = 32;     // panel width; 2 kNb panel products fit 64 slots
 constexpr int kHT = 64;     // hemv and her2k tile
 constexpr int kStrip = 4;   // tiles per hemv strip
-constexpr int kColRows = 64;  // elements per work-group of the col kernel
+constexpr int kColTpe = 16;   // threads per element in the col kernel
+constexpr int kColRows = 256 / kColTpe;  // elements per col work-group
 
 struct TriWork {
   double2 *a;     // n x n work matrix (interleaved), row-major
@@ -105,38 +106,50 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
   return make_double2(a.x + b.x, a.y + b.y);
 }
 
-// Step k, part col: 64 elements c = k + 64 b + e per work-group, four
-// threads (q = 0..3) per element sharing its sums.  With slot j > 0 it first
+// Step k, part col: kColRows elements c = k + kColRows b + e per
+// work-group, kColTpe threads (q) per element sharing its sums.  With slot j > 0 it first
 // finishes step k-1 (slot j-1, trailing offset k, size n - k) and stores
 // W_{j-1}; unless finish_only it then forms x_c = A'[c][k].
 __global__ __launch_bounds__(256) void hh_col_kernel(TriWork t, int n, int k,
                                                      int k0, int j,
                                                      int finish_only) {
-  constexpr int kPer = kNb / 4;               // panel slots per quarter
+  constexpr int kPer = kNb / kColTpe;         // panel slots per thread
   __shared__ double red[16];
-  __shared__ double2 y[64], part[4][kColRows], wsh[kColRows];
+  __shared__ double2 y[64], yq[4][64], part[kColTpe][kColRows], wsh[kColRows];
   __shared__ double2 vk[kNb], wk[kNb];
   __shared__ double kk[2];
-  const int e = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int e = threadIdx.x % kColRows, q = threadIdx.x / kColRows;
   const int c = k + blockIdx.x * kColRows + e;
   const bool in = c < n;
   const int jp = j - 1;                       // slot of step k-1
+  // sum of the kColTpe parts of element e (after a barrier)
+  auto part_sum = [&](int ee) {
+    double2 s0 = part[0][ee], s1 = part[1][ee];
+#pragma unroll
+    for (int g = 2; g < kColTpe; g += 2) {
+      s0 = cadd(s0, part[g][ee]);
+      s1 = cadd(s1, part[g + 1][ee]);
+    }
+    return cadd(s0, s1);
+  };
   // every load that depends on nothing computed here is issued first
   double2 a_ck = make_double2(0.0, 0.0);
-  if (!finish_only && in) a_ck = t.a[(long)c * n + k];
-  double2 vc[kPer], wc[kPer];                 // V_i[c], W_i[c], i = q + 4 s
+  if (!finish_only && in && q == 0) a_ck = t.a[(long)c * n + k];
+  double2 vc[kPer], wc[kPer];                 // V_i[c], W_i[c], i = q + kColTpe s
 #pragma unroll
   for (int s = 0; s < kPer; ++s) {
-    const int i = q + 4 * s;
+    const int i = q + kColTpe * s;
     vc[s] = make_double2(0.0, 0.0);
     wc[s] = make_double2(0.0, 0.0);
     if (in && i < j) vc[s] = t.a[(long)(k0 + i) * n + c];
     if (in && i < jp) wc[s] = t.wb[(long)i * n + c];
   }
-  // V_e[k], W_e[k] for the panel slots (wave 0)
+  // V_l[k], W_l[k] for the panel slots l = lane of wave 0
+  const int l64 = threadIdx.x & 63;
+  const bool w0 = threadIdx.x < 64;
   double2 vke = make_double2(0.0, 0.0), wke = make_double2(0.0, 0.0);
-  if (q == 0 && e < j) vke = t.a[(long)(k0 + e) * n + k];
-  if (q == 0 && e < jp) wke = t.wb[(long)e * n + k];
+  if (w0 && l64 < j) vke = t.a[(long)(k0 + l64) * n + k];
+  if (w0 && l64 < jp) wke = t.wb[(long)l64 * n + k];
   double2 w_own = make_double2(0.0, 0.0);     // w_{j-1}[c]
   if (j > 0) {
     const int mp = n - k;
@@ -144,35 +157,51 @@ __global__ __launch_bounds__(256) void hh_col_kernel(TriWork t, int n, int k,
     const double taup = t.tau[k - 1];
     const double2 *up = t.a + (long)(k - 1) * n;   // u_{k-1} by global index
     double2 u_c = make_double2(0.0, 0.0), u_k = up[k];
-    if (in) u_c = up[c];
-    {
-      // panel products of step k-1: y[s] = W_s^H u, y[jp + s] = V_s^H u
-      double2 sy = make_double2(0.0, 0.0);
-      if (e < 2 * jp)
-        for (int I = q; I < ntp; I += 4) sy = cadd(sy, t.pdot[(long)I * 64 + e]);
-      part[q][e] = sy;
-    }
-    // hemv sums of p[r], r = c - k, in four interleaved parts
-    double2 ps = make_double2(0.0, 0.0);
+    if (in && q == 0) u_c = up[c];
+    // hemv sums of p[r], r = c - k, in kColTpe interleaved parts
+    double2 ps = make_double2(0.0, 0.0), ps1 = ps;
     if (in) {
       const int r = c - k, I = r / kHT, rr = r - I * kHT;
       const long b0 = strip_prefix(I), b1 = b0 + I / kStrip + 1;
-      for (long b = b0 + q; b < b1; b += 4) ps = cadd(ps, t.prow[b * kHT + rr]);
-      for (int I2 = I + q; I2 < ntp; I2 += 4)
+      for (long b = b0 + q; b < b1; b += kColTpe) ps = cadd(ps, t.prow[b * kHT + rr]);
+      int I2 = I + q;
+      for (; I2 + kColTpe < ntp; I2 += 2 * kColTpe) {
         ps = cadd(ps, t.pcol[(long)I2 * t.ldp + r]);
+        ps1 = cadd(ps1, t.pcol[(long)(I2 + kColTpe) * t.ldp + r]);
+      }
+      if (I2 < ntp) ps = cadd(ps, t.pcol[(long)I2 * t.ldp + r]);
+      ps = cadd(ps, ps1);
     }
     // the same for r = 0 (w_{j-1}[k] is needed by every work-group)
     double2 p0 = make_double2(0.0, 0.0);
-    if (q == 0) {
-      if (e == 0) p0 = t.prow[0];
-      for (int I2 = e; I2 < ntp; I2 += 64) p0 = cadd(p0, t.pcol[(long)I2 * t.ldp]);
+    if (w0) {
+      if (l64 == 0) p0 = t.prow[0];
+      for (int I2 = l64; I2 < ntp; I2 += 64) p0 = cadd(p0, t.pcol[(long)I2 * t.ldp]);
     }
-    double s = 0.0;
+    // panel products of step k-1, y[s] = W_s^H u, y[jp + s] = V_s^H u, in
+    // four parts; the u^H A0 u partials
+    const int slot = threadIdx.x & 63, g = threadIdx.x >> 6;
+    double2 sy = make_double2(0.0, 0.0), sy1 = sy;
+    if (slot < 2 * jp) {
+      int I = g;
+      for (; I + 4 < ntp; I += 8) {
+        sy = cadd(sy, t.pdot[(long)I * 64 + slot]);
+        sy1 = cadd(sy1, t.pdot[(long)(I + 4) * 64 + slot]);
+      }
+      if (I < ntp) sy = cadd(sy, t.pdot[(long)I * 64 + slot]);
+    }
+    double s0 = 0.0, s1 = 0.0;
     const long nsp = strip_prefix(ntp);
-    for (long b = threadIdx.x; b < nsp; b += 256) s += t.puau[b];
-    const double uau = block_sum(s, red);     // syncs: part[] is complete
+    long bq = threadIdx.x;
+    for (; bq + 256 < nsp; bq += 512) {
+      s0 += t.puau[bq];
+      s1 += t.puau[bq + 256];
+    }
+    if (bq < nsp) s0 += t.puau[bq];
+    yq[g][slot] = cadd(sy, sy1);
+    const double uau = block_sum(s0 + s1, red);   // syncs: yq[] is complete
     if (threadIdx.x < 64)
-      y[e] = cadd(cadd(part[0][e], part[1][e]), cadd(part[2][e], part[3][e]));
+      y[slot] = cadd(cadd(yq[0][slot], yq[1][slot]), cadd(yq[2][slot], yq[3][slot]));
     __syncthreads();
     if (threadIdx.x == 0) {
       double corr = 0.0;
@@ -183,7 +212,7 @@ __global__ __launch_bounds__(256) void hh_col_kernel(TriWork t, int n, int k,
     // panel terms: p -= V_i (W_i^H u) + W_i (V_i^H u), i < jp
 #pragma unroll
     for (int s2 = 0; s2 < kPer; ++s2) {
-      const int i = q + 4 * s2;
+      const int i = q + kColTpe * s2;
       if (i < jp) {
         const double2 y1 = y[i], y2 = y[jp + i];
         const double2 v = vc[s2], w = wc[s2];
@@ -191,38 +220,40 @@ __global__ __launch_bounds__(256) void hh_col_kernel(TriWork t, int n, int k,
         ps.y -= v.x * y1.y + v.y * y1.x + w.x * y2.y + w.y * y2.x;
       }
     }
-    part[q][e] = ps;
-    if (q == 0) {
-      if (e < jp) {
-        const double2 y1 = y[e], y2 = y[jp + e];
+    if (w0) {
+      if (l64 < jp) {
+        const double2 y1 = y[l64], y2 = y[jp + l64];
         p0.x -= vke.x * y1.x - vke.y * y1.y + wke.x * y2.x - wke.y * y2.y;
         p0.y -= vke.x * y1.y + vke.y * y1.x + wke.x * y2.y + wke.y * y2.x;
       }
       p0.x = wave_sum(p0.x);
       p0.y = wave_sum(p0.y);
     }
+    __syncthreads();                          // y[] reads are done
+    part[q][e] = ps;
     __syncthreads();
     const double K = kk[0];
     if (q == 0) {
-      const double2 tot = cadd(cadd(part[0][e], part[1][e]), cadd(part[2][e], part[3][e]));
+      const double2 tot = part_sum(e);
       if (in) {
         w_own = make_double2(taup * tot.x - K * u_c.x, taup * tot.y - K * u_c.y);
         t.wb[(long)jp * n + c] = w_own;
       }
       wsh[e] = w_own;
-      if (e == 0) wk[jp] = make_double2(taup * p0.x - K * u_k.x, taup * p0.y - K * u_k.y);
     }
+    if (threadIdx.x == 0)
+      wk[jp] = make_double2(taup * p0.x - K * u_k.x, taup * p0.y - K * u_k.y);
   }
   if (finish_only) return;
-  if (q == 0 && e < j) {
-    vk[e] = vke;
-    if (e < jp) wk[e] = wke;
+  if (w0 && l64 < j) {
+    vk[l64] = vke;
+    if (l64 < jp) wk[l64] = wke;
   }
   __syncthreads();
   double2 xs = make_double2(0.0, 0.0);
 #pragma unroll
   for (int s2 = 0; s2 < kPer; ++s2) {
-    const int i = q + 4 * s2;
+    const int i = q + kColTpe * s2;
     if (i < j) {
       const double2 wci = i == jp ? wsh[e] : wc[s2];
       const double2 a = cmulc(wk[i], vc[s2]);   // V_i[c] conj(W_i[k])
@@ -231,11 +262,12 @@ __global__ __launch_bounds__(256) void hh_col_kernel(TriWork t, int n, int k,
       xs.y += a.y + b.y;
     }
   }
+  __syncthreads();                            // part[] reads are done
   part[q][e] = xs;
   __syncthreads();
   double nrm = 0.0;
   if (q == 0 && in) {
-    const double2 corr = cadd(cadd(part[0][e], part[1][e]), cadd(part[2][e], part[3][e]));
+    const double2 corr = part_sum(e);
     const double2 x = make_double2(a_ck.x - corr.x, a_ck.y - corr.y);
     if (c == k) {
       t.a[(long)k * n + k] = make_double2(x.x, -x.y);
