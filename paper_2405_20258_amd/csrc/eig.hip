@@ -77,7 +77,8 @@ __device__ double block_sum(double v, double *red) {
 // column and rewritten once per panel.
 constexpr int kNb = 32;     // panel width; 2 kNb panel products fit 64 slots
 constexpr int kHT = 64;     // hemv and her2k tile
-constexpr int kStrip = 4;   // tiles per hemv strip
+constexpr int kStrip = 2;   // tiles per hemv strip (measured: 2 beats 1 and 4)
+static_assert(kStrip <= 4, "one wave per tile writes the strip's column partials");
 constexpr int kColTpe = 16;   // threads per element in the col kernel
 constexpr int kColRows = 256 / kColTpe;  // elements per col work-group
 
