@@ -94,11 +94,10 @@ __device__ __forceinline__ double pair_weight(const HerkArgs &h, long p,
 
 // ---------------------------------------------------------------- HERK f64
 
-__global__ __launch_bounds__(256, 4) void herk_f64_kernel(
+__global__ __launch_bounds__(256, 3) void herk_f64_kernel(
     HerkArgs h, int n_tiles, long kchunk, double *__restrict__ partial) {
   __shared__ double As[2][kKc][kT + kPad];
   __shared__ double Bs[2][kKc][kT + kPad];
-  __shared__ double wk[kKc];
   const int tile_id = xcd_remap(blockIdx.x, n_tiles);
   const int split = blockIdx.y;
   const int om_i = blockIdx.z;
@@ -121,36 +120,48 @@ __global__ __launch_bounds__(256, 4) void herk_f64_kernel(
     }
 
   // staging map: 256 threads x 4 loads of double2 cover 2 ops x 2 parts x
-  // 16 rows x 64 columns.
-  for (long k0 = kbeg; k0 < kend; k0 += kKc) {
-    if (threadIdx.x < kKc) {
-      const long p = k0 + threadIdx.x;
-      wk[threadIdx.x] = p < kend ? pair_weight(h, p, om) : 0.0;
-    }
-    __syncthreads();
+  // 16 rows x 64 columns.  The next chunk is fetched into registers while
+  // the current one is multiplied.
+  const int sr = (threadIdx.x >> 4) & 15;      // k row of this thread's items
+  double2 pv[4], pu[4];
+  double pde = 0.0;
+  auto fetch = [&](long k0) __attribute__((always_inline)) {
+    const long p = k0 + sr;
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
       const int idx = threadIdx.x + it * 256;   // 0..1023
       const int op = idx >> 9;                   // 0: A (rows I), 1: B (cols J)
       const int part = (idx >> 8) & 1;           // 0 re, 1 im
-      const int r = (idx >> 4) & 15;             // k row in chunk
       const int c2 = (idx & 15) * 2;             // column pair (0..30) x2 -> 64
-      const long p = k0 + r;
       const int col0 = op ? J0 : I0;
-      double2 v = make_double2(0.0, 0.0), u = make_double2(0.0, 0.0);
+      pv[it] = make_double2(0.0, 0.0);
+      pu[it] = make_double2(0.0, 0.0);
       if (p < kend) {
         const double *src = h.a + p * h.lda + part * h.im_off + col0;
-        v = *reinterpret_cast<const double2 *>(src + c2);
-        u = *reinterpret_cast<const double2 *>(src + c2 + 32);
+        pv[it] = *reinterpret_cast<const double2 *>(src + c2);
+        pu[it] = *reinterpret_cast<const double2 *>(src + c2 + 32);
       }
-      const double sc = op ? wk[r] : 1.0;
-      double *dst = op ? &Bs[part][r][0] : &As[part][r][0];
-      dst[c2] = v.x * sc;
-      dst[c2 + 1] = v.y * sc;
-      dst[c2 + 32] = u.x * sc;
-      dst[c2 + 33] = u.y * sc;
+    }
+    if (!h.unit_weight && p < kend) pde = h.de[p];
+  };
+  fetch(kbeg);
+  for (long k0 = kbeg; k0 < kend; k0 += kKc) {
+    double sc = 0.0;                             // weight of row sr (B operand)
+    if (k0 + sr < kend)
+      sc = h.unit_weight ? 1.0 : -4.0 * pde / (pde * pde + om * om) * h.wscale;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int idx = threadIdx.x + it * 256;
+      const int op = idx >> 9, part = (idx >> 8) & 1, c2 = (idx & 15) * 2;
+      const double s = op ? sc : 1.0;
+      double *dst = op ? &Bs[part][sr][0] : &As[part][sr][0];
+      dst[c2] = pv[it].x * s;
+      dst[c2 + 1] = pv[it].y * s;
+      dst[c2 + 32] = pu[it].x * s;
+      dst[c2 + 33] = pu[it].y * s;
     }
     __syncthreads();
+    if (k0 + kKc < kend) fetch(k0 + kKc);
 #pragma unroll
     for (int ks = 0; ks < kKc; ks += 4) {
       const int kr = ks + (lane >> 4);
