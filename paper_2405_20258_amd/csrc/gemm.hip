@@ -247,7 +247,7 @@ __global__ void herk_reduce_kernel(const double *__restrict__ partial,
 
 // ---------------------------------------------------------------- GEMM f64
 
-__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g, int m_tiles,
+__global__ __launch_bounds__(256, 3) void gemm_f64_kernel(GemmArgs g, int m_tiles,
                                                       int n_tiles) {
   __shared__ double As[2][kKc][kT + kPad];  // [part][k][m]
   __shared__ double Bs[2][kKc][kT + kPad];  // [part][k][n]
@@ -267,43 +267,38 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g, int m_tiles,
       re[i][j] = d4{0, 0, 0, 0};
       im[i][j] = d4{0, 0, 0, 0};
     }
-  for (int k0 = 0; k0 < g.k; k0 += kKc) {
-    // A: 64 rows x 16 k x 2 parts = 2048 doubles: thread -> (row, part, 8 k)
-    {
-      const int row = threadIdx.x >> 2;        // 0..63
-      const int part = (threadIdx.x >> 1) & 1;
-      const int kq = (threadIdx.x & 1) * 8;     // 0 or 8
-      const long m = M0 + row;
-      double v[8];
-      if (m < g.m) {
-        const double *src = g.a + m * g.lda + part * g.a_im + k0 + kq;
+  // A: 64 rows x 16 k x 2 parts = 2048 doubles: thread -> (row, part, 8 k);
+  // B: 16 k x 64 cols x 2 parts: thread -> (k, part, 8 cols).  The next K
+  // chunk is fetched into registers while the current one is multiplied.
+  const int arow = threadIdx.x >> 2, apart = (threadIdx.x >> 1) & 1;
+  const int akq = (threadIdx.x & 1) * 8;
+  const int bkr = threadIdx.x >> 4, bpart = (threadIdx.x >> 3) & 1;
+  const int bcq = (threadIdx.x & 7) * 8;
+  double2 av[4], bv[4];
+  auto fetch = [&](int k0) __attribute__((always_inline)) {
+    const long m = M0 + arow;
 #pragma unroll
-        for (int x = 0; x < 8; x += 2) {
-          const double2 t = *reinterpret_cast<const double2 *>(src + x);
-          v[x] = t.x;
-          v[x + 1] = t.y;
-        }
-      } else {
+    for (int x = 0; x < 4; ++x) av[x] = make_double2(0.0, 0.0);
+    if (m < g.m) {
+      const double *src = g.a + m * g.lda + apart * g.a_im + k0 + akq;
 #pragma unroll
-        for (int x = 0; x < 8; ++x) v[x] = 0.0;
-      }
-#pragma unroll
-      for (int x = 0; x < 8; ++x) As[part][kq + x][row] = v[x];
+      for (int x = 0; x < 4; ++x) av[x] = *reinterpret_cast<const double2 *>(src + 2 * x);
     }
-    // B: 16 k x 64 cols x 2 parts = 2048 doubles: thread -> (k, part, 8 cols)
-    {
-      const int kr = threadIdx.x >> 4;          // 0..15
-      const int part = (threadIdx.x >> 3) & 1;
-      const int cq = (threadIdx.x & 7) * 8;     // 0..56
-      const double *src = g.b + (long)(k0 + kr) * g.ldb + part * g.b_im + N0 + cq;
+    const double *srcb = g.b + (long)(k0 + bkr) * g.ldb + bpart * g.b_im + N0 + bcq;
 #pragma unroll
-      for (int x = 0; x < 8; x += 2) {
-        const double2 t = *reinterpret_cast<const double2 *>(src + x);
-        Bs[part][kr][cq + x] = t.x;
-        Bs[part][kr][cq + x + 1] = t.y;
-      }
+    for (int x = 0; x < 4; ++x) bv[x] = *reinterpret_cast<const double2 *>(srcb + 2 * x);
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < g.k; k0 += kKc) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      As[apart][akq + 2 * x][arow] = av[x].x;
+      As[apart][akq + 2 * x + 1][arow] = av[x].y;
+      Bs[bpart][bkr][bcq + 2 * x] = bv[x].x;
+      Bs[bpart][bkr][bcq + 2 * x + 1] = bv[x].y;
     }
     __syncthreads();
+    if (k0 + kKc < g.k) fetch(k0 + kKc);
 #pragma unroll
     for (int ks = 0; ks < kKc; ks += 4) {
       const int kr = ks + (lane >> 4);
