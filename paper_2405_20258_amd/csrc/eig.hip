@@ -300,6 +300,54 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void h
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const double2 zero = make_double2(0.0, 0.0);
   const long b = blockIdx.x;
+  const long nstr = strip_prefix(nt);
+  if (b >= nstr) {
+    // panel products over rows I*64 .. I*64+63 (work-groups past the
+    // strips, only for slot j > 0): 4 threads per product slot, slot s < j:
+    // conj(W_s) . u, slot j + s: conj(V_s) . u
+    const int I = (int)(b - nstr);
+    const int slot = threadIdx.x >> 2, qt = threadIdx.x & 3;
+    const int r0 = I * kHT + qt * 16;
+    const double2 *u = t.a + (long)k * n + o;
+    double2 xv[16], uv[16];
+    const double2 *x = slot < j ? t.wb + (long)slot * n + o
+                                : t.a + (long)(k0 + slot - j) * n + o;
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+      const int r = r0 + rr;
+      xv[rr] = make_double2(0.0, 0.0);
+      uv[rr] = make_double2(0.0, 0.0);
+      if (slot < 2 * j && r < m) xv[rr] = x[r];
+      if (r > 0 && r < m) uv[rr] = u[r];
+    }
+    const double2 x0 = t.xs[k];
+    double s = 0.0;
+    const int ncb = (m + 1 + kColRows - 1) / kColRows;
+    for (int bb = threadIdx.x; bb < ncb; bb += 256) s += t.pnrm[bb];
+    const double rest = block_sum(s, red);
+    double2 u0 = x0;
+    if (m > 1 && rest != 0.0) {
+      const double ax0 = hypot(x0.x, x0.y);
+      const double nrm = sqrt(rest + ax0 * ax0);
+      const double2 ph = ax0 > 0.0 ? make_double2(x0.x / ax0, x0.y / ax0)
+                                   : make_double2(1.0, 0.0);
+      u0 = make_double2(x0.x + ph.x * nrm, x0.y + ph.y * nrm);   // x0 - beta
+    }
+    if (r0 == 0) uv[0] = u0;
+    double2 sd = zero;
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+      const double2 qv = cmulc(xv[rr], uv[rr]);
+      sd.x += qv.x;
+      sd.y += qv.y;
+    }
+    sd.x += __shfl_xor(sd.x, 1);
+    sd.y += __shfl_xor(sd.y, 1);
+    sd.x += __shfl_xor(sd.x, 2);
+    sd.y += __shfl_xor(sd.y, 2);
+    if (qt == 0 && slot < 2 * j) t.pdot[(long)I * 64 + slot] = sd;
+    return;
+  }
   int lo = 0, hi = nt - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -436,29 +484,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void h
     t.pcol[(long)I * t.ldp + cj] = tot;
     const double2 uv = uat(cj);
     uau += uv.x * tot.x + uv.y * tot.y;
-  }
-  if (J1 == I + 1 && j > 0) {
-    // panel products over rows I*64 .. I*64+63: 4 threads per slot
-    const int slot = threadIdx.x >> 2, qt = threadIdx.x & 3;
-    double2 sd = zero;
-    if (slot < 2 * j) {
-      const double2 *x = slot < j ? t.wb + (long)slot * n + o
-                                  : t.a + (long)(k0 + slot - j) * n + o;
-      const int r0 = I * kHT + qt * 16;
-#pragma unroll
-      for (int rr = 0; rr < 16; ++rr) {
-        const int r = r0 + rr;
-        const double2 xv = r < m ? x[r] : make_double2(0.0, 0.0);
-        const double2 qv = cmulc(xv, ur_s[qt * 16 + rr]);
-        sd.x += qv.x;
-        sd.y += qv.y;
-      }
-    }
-    sd.x += __shfl_xor(sd.x, 1);
-    sd.y += __shfl_xor(sd.y, 1);
-    sd.x += __shfl_xor(sd.x, 2);
-    sd.y += __shfl_xor(sd.y, 2);
-    if (qt == 0 && slot < 2 * j) t.pdot[(long)I * 64 + slot] = sd;
   }
   const double ut = block_sum(uau, red);
   if (threadIdx.x == 0) {
@@ -1073,8 +1098,11 @@ void eig_lowest(Context *ctx, const double *a_in, int n, int n_eig,
                          dim3(256), 0, s, t, n, k, k0, j, 0);
       if (m == 0) break;
       const int nt = (m + kHT - 1) / kHT;
-      hipLaunchKernelGGL(hh_hemv_kernel, dim3((unsigned)strip_prefix(nt)), dim3(256),
-                         0, s, t, n, k, k0, j);
+      // strips, then (slot j > 0) one work-group per tile row for the
+      // panel products
+      hipLaunchKernelGGL(hh_hemv_kernel,
+                         dim3((unsigned)(strip_prefix(nt) + (j > 0 ? nt : 0))),
+                         dim3(256), 0, s, t, n, k, k0, j);
     }
     if (kend < n) {
       // finish w of the panel's last step, then update the next trailing block
