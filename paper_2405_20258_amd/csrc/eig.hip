@@ -77,8 +77,8 @@ __device__ double block_sum(double v, double *red) {
 // column and rewritten once per panel.
 constexpr int kNb = 32;     // panel width; 2 kNb panel products fit 64 slots
 constexpr int kHT = 64;     // hemv and her2k tile
-constexpr int kStrip = 2;   // tiles per hemv strip (measured: 2 beats 1 and 4)
-static_assert(kStrip <= 4, "one wave per tile writes the strip's column partials");
+constexpr int kStripMax = 4;   // one wave per tile writes the column partials
+constexpr int kStripWide = 32; // tile rows from which strips hold 4 tiles
 constexpr int kColTpe = 16;   // threads per element in the col kernel
 constexpr int kColRows = 256 / kColTpe;  // elements per col work-group
 
@@ -97,10 +97,17 @@ struct TriWork {
   long ldp;       // row length of pcol
 };
 
-// Strips before tile row I: row I has I + 1 tiles in I / kStrip + 1 strips.
-__host__ __device__ inline long strip_prefix(int I) {
-  const long q = I / kStrip, r = I - q * kStrip;
-  return I + kStrip * q * (q - 1) / 2 + q * r;
+// Tiles per hemv strip for a trailing block of nt tile rows: short strips
+// (more work-groups, shorter chains) while latency dominates, long ones
+// once the block is large enough to be bandwidth-bound.
+__host__ __device__ inline int strip_width(int nt) {
+  return nt >= kStripWide ? kStripMax : 2;
+}
+
+// Strips before tile row I: row I has I + 1 tiles in I / sw + 1 strips.
+__host__ __device__ inline long strip_prefix(int I, int sw) {
+  const long q = I / sw, r = I - q * sw;
+  return I + sw * q * (q - 1) / 2 + q * r;
 }
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
@@ -155,6 +162,7 @@ __global__ __launch_bounds__(256) void hh_col_kernel(TriWork t, int n, int k,
   if (j > 0) {
     const int mp = n - k;
     const int ntp = (mp + kHT - 1) / kHT;
+    const int swp = strip_width(ntp);
     const double taup = t.tau[k - 1];
     const double2 *up = t.a + (long)(k - 1) * n;   // u_{k-1} by global index
     double2 u_c = make_double2(0.0, 0.0), u_k = up[k];
@@ -163,7 +171,7 @@ __global__ __launch_bounds__(256) void hh_col_kernel(TriWork t, int n, int k,
     double2 ps = make_double2(0.0, 0.0), ps1 = ps;
     if (in) {
       const int r = c - k, I = r / kHT, rr = r - I * kHT;
-      const long b0 = strip_prefix(I), b1 = b0 + I / kStrip + 1;
+      const long b0 = strip_prefix(I, swp), b1 = b0 + I / swp + 1;
       for (long b = b0 + q; b < b1; b += kColTpe) ps = cadd(ps, t.prow[b * kHT + rr]);
       int I2 = I + q;
       for (; I2 + kColTpe < ntp; I2 += 2 * kColTpe) {
@@ -192,7 +200,7 @@ __global__ __launch_bounds__(256) void hh_col_kernel(TriWork t, int n, int k,
       if (I < ntp) sy = cadd(sy, t.pdot[(long)I * 64 + slot]);
     }
     double s0 = 0.0, s1 = 0.0;
-    const long nsp = strip_prefix(ntp);
+    const long nsp = strip_prefix(ntp, swp);
     long bq = threadIdx.x;
     for (; bq + 256 < nsp; bq += 512) {
       s0 += t.puau[bq];
@@ -282,7 +290,7 @@ __global__ __launch_bounds__(256) void hh_col_kernel(TriWork t, int n, int k,
   if (threadIdx.x == 0) t.pnrm[blockIdx.x] = tot;
 }
 
-// Step k, part hemv: one work-group per strip of up to kStrip tiles of tile
+// Step k, part hemv: one work-group per strip of up to sw tiles of tile
 // row I of the lower triangle of the trailing block (offset o = k + 1, size
 // m).  Wave w takes rows 16 w .. 16 w + 15 of the tile row, lane l column l
 // of each tile.  Row partials sum A0[r][c] u[c] over the strip; column
@@ -293,14 +301,15 @@ __global__ __launch_bounds__(256) void hh_col_kernel(TriWork t, int n, int k,
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void hh_hemv_kernel(TriWork t, int n, int k,
                                                       int k0, int j) {
   __shared__ double red[16];
-  __shared__ double2 cs[kStrip][4][64];
+  __shared__ double2 cs[kStripMax][4][64];
   __shared__ double2 ur_s[kHT];
   const int o = k + 1, m = n - o;
   const int nt = (m + kHT - 1) / kHT;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const double2 zero = make_double2(0.0, 0.0);
   const long b = blockIdx.x;
-  const long nstr = strip_prefix(nt);
+  const int sw = strip_width(nt);
+  const long nstr = strip_prefix(nt, sw);
   if (b >= nstr) {
     // panel products over rows I*64 .. I*64+63 (work-groups past the
     // strips, only for slot j > 0): 4 threads per product slot, slot s < j:
@@ -351,12 +360,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void h
   int lo = 0, hi = nt - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (strip_prefix(mid) <= b) lo = mid;
+    if (strip_prefix(mid, sw) <= b) lo = mid;
     else hi = mid - 1;
   }
   const int I = lo;
-  const int J0 = (int)(b - strip_prefix(I)) * kStrip;
-  const int J1 = min(J0 + kStrip, I + 1);
+  const int J0 = (int)(b - strip_prefix(I, sw)) * sw;
+  const int J1 = min(J0 + sw, I + 1);
   const double2 *u = t.a + (long)k * n + o;
   const double2 *blk = t.a + (long)o * n + o;
   const int rb = I * kHT + wave * 16;
@@ -1077,7 +1086,9 @@ void eig_lowest(Context *ctx, const double *a_in, int n, int n_eig,
   double2 *phase = t.xs + n;
   // panel vectors and hemv partials, sized for the first step (m = n - 1)
   const int nt_max = std::max(1, (n - 1 + kHT - 1) / kHT);
-  const long strips_max = strip_prefix(nt_max);
+  long strips_max = 0;   // the most strips of any step
+  for (int nt = 1; nt <= nt_max; ++nt)
+    strips_max = std::max(strips_max, strip_prefix(nt, strip_width(nt)));
   t.ldp = (long)nt_max * kHT;
   const size_t n_wb = (size_t)kNb * n, n_prow = (size_t)strips_max * kHT,
                n_pcol = (size_t)nt_max * t.ldp, n_pdot = (size_t)nt_max * 64;
@@ -1101,7 +1112,8 @@ void eig_lowest(Context *ctx, const double *a_in, int n, int n_eig,
       // strips, then (slot j > 0) one work-group per tile row for the
       // panel products
       hipLaunchKernelGGL(hh_hemv_kernel,
-                         dim3((unsigned)(strip_prefix(nt) + (j > 0 ? nt : 0))),
+                         dim3((unsigned)(strip_prefix(nt, strip_width(nt)) +
+                                         (j > 0 ? nt : 0))),
                          dim3(256), 0, s, t, n, k, k0, j);
     }
     if (kend < n) {
