@@ -38,7 +38,9 @@ def test_alone_equals_mixed():
     import torch  # noqa: F401  (initializes the runtime like other GPU tests)
     from paper_2405_20258_amd import ssrpa
     from synth import systems as sy
-    om, wt = sy.frequency_grid(16)
+    # 48 frequencies: each solve then lasts longer than the host needs to
+    # submit the next request, so the mix can overlap on the device
+    om, wt = sy.frequency_grid(48)
     reqs = _systems()
     ctx = ssrpa.Context(0)
     # alone: one request at a time
@@ -58,16 +60,17 @@ def test_alone_equals_mixed():
     srv.drain()
     res = [srv.poll(i) for i in ids]
     srv.close()
-    starts = sorted(r["t_start"] for r in res)
-    dones = sorted(r["t_done"] for r in res)
     _log(f"mixed: {[r['ec'] for r in res]}")
     assert all(r["state"] == ssrpa.REQ_DONE for r in res)
     for a, r in zip(alone, res):
         assert r["ec"] == a          # bitwise: independent of the mix
         assert r["ec"] < 0.0
-    # the loop really overlapped requests: a later one started before an
-    # earlier one finished
-    assert starts[1] < dones[0]
+    # the loop really overlapped requests: the run intervals of some two
+    # requests intersect
+    iv = [(r["t_start"], r["t_done"]) for r in res]
+    _log(f"intervals: {iv}")
+    assert any(iv[i][0] < iv[j][1] and iv[j][0] < iv[i][1]
+               for i in range(len(iv)) for j in range(i + 1, len(iv)))
     ctx.close()
 
 
