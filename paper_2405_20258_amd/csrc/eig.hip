@@ -79,6 +79,7 @@ constexpr int kNb = 32;     // panel width; 2 kNb panel products fit 64 slots
 constexpr int kHT = 64;     // hemv and her2k tile
 constexpr int kStripMax = 4;   // one wave per tile writes the column partials
 constexpr int kStripWide = 32; // tile rows from which strips hold 4 tiles
+constexpr int kStripNarrow = 24; // tile rows from which strips hold 2 tiles (1 below)
 constexpr int kColTpe = 16;   // threads per element in the col kernel
 constexpr int kColRows = 256 / kColTpe;  // elements per col work-group
 
@@ -101,7 +102,7 @@ struct TriWork {
 // (more work-groups, shorter chains) while latency dominates, long ones
 // once the block is large enough to be bandwidth-bound.
 __host__ __device__ inline int strip_width(int nt) {
-  return nt >= kStripWide ? kStripMax : 2;
+  return nt >= kStripWide ? kStripMax : (nt >= kStripNarrow ? 2 : 1);
 }
 
 // Strips before tile row I: row I has I + 1 tiles in I / sw + 1 strips.
