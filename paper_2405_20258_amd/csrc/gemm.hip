@@ -85,13 +85,6 @@ __device__ __forceinline__ int2 tri_tile_blocked(int t, int T) {
   return make_int2(0, 0);  // not reached for t < T (T + 1) / 2
 }
 
-__device__ __forceinline__ double pair_weight(const HerkArgs &h, long p,
-                                              double om) {
-  if (h.unit_weight) return 1.0;
-  const double de = h.de[p];
-  return -4.0 * de / (de * de + om * om) * h.wscale;
-}
-
 // ---------------------------------------------------------------- HERK f64
 
 __global__ __launch_bounds__(256, 3) void herk_f64_kernel(
@@ -146,7 +139,8 @@ __global__ __launch_bounds__(256, 3) void herk_f64_kernel(
   };
   fetch(kbeg);
   for (long k0 = kbeg; k0 < kend; k0 += kKc) {
-    double sc = 0.0;                             // weight of row sr (B operand)
+    // weight of row sr (B operand): Delta_p(i omega) = -4 de / (de^2 + omega^2)
+    double sc = 0.0;
     if (k0 + sr < kend)
       sc = h.unit_weight ? 1.0 : -4.0 * pde / (pde * pde + om * om) * h.wscale;
 #pragma unroll
