@@ -716,19 +716,21 @@ __device__ void tri_lu(const InvIt &q, int n, int col, double lam, double tiny) 
   q.u0[o] = r0; q.u1[o] = 0.0; q.u2[o] = 0.0; q.ml[o] = 0.0; q.pv[o] = 0;
 }
 
-// x <- (T - lam I)^-1 x (x is column col of z).  Both substitutions run in
-// chunks of kSolveChunk rows whose coefficients and right-hand sides are
-// loaded before the dependent recurrence, so the loads of a chunk overlap
-// instead of each waiting behind the previous step.
-constexpr int kSolveChunk = 8;
-__device__ void tri_solve(const InvIt &q, int n, int col) {
+// x <- (T - lam I)^-1 (f x) (x is column col of z); returns ||x|| of the
+// result, accumulated during the back substitution with a running scale
+// (no overflow for any finite vector).  Both substitutions run in chunks of
+// kSolveChunk rows whose coefficients and right-hand sides are loaded before
+// the dependent recurrence, so the loads of a chunk overlap instead of each
+// waiting behind the previous step.
+constexpr int kSolveChunk = 16;
+__device__ double tri_solve(const InvIt &q, int n, int col, double f) {
   const long ld = q.ldz;
   double *x = q.z + col;
   const double *ml = q.ml + col, *u0 = q.u0 + col, *u1 = q.u1 + col,
                *u2 = q.u2 + col;
   const unsigned char *pv = q.pv + col;
   // forward: step i pivots rows i, i+1; a carries the updated x[i]
-  double a = x[0];
+  double a = f * x[0];
   int i = 0;
   for (; i + kSolveChunk < n; i += kSolveChunk) {
     double b[kSolveChunk], m[kSolveChunk];
@@ -741,7 +743,7 @@ __device__ void tri_solve(const InvIt &q, int n, int col) {
     }
 #pragma unroll
     for (int u = 0; u < kSolveChunk; ++u) {
-      double aa = a, bb = b[u];
+      double aa = a, bb = f * b[u];
       if (p[u]) { const double t = aa; aa = bb; bb = t; }
       x[(long)(i + u) * ld] = aa;
       a = bb - m[u] * aa;
@@ -749,14 +751,26 @@ __device__ void tri_solve(const InvIt &q, int n, int col) {
   }
   for (; i < n - 1; ++i) {
     const long o = (long)i * ld;
-    double aa = a, bb = x[o + ld];
+    double aa = a, bb = f * x[o + ld];
     if (pv[o]) { const double t = aa; aa = bb; bb = t; }
     x[o] = aa;
     a = bb - ml[o] * aa;
   }
   x[(long)(n - 1) * ld] = a;
-  // backward: v_i = (x_i - u1_i v_{i+1} - u2_i v_{i+2}) / u0_i
-  double xp1 = 0.0, xp2 = 0.0;
+  // backward: v_i = (x_i - u1_i v_{i+1} - u2_i v_{i+2}) / u0_i, with
+  // ||v||^2 = scale^2 ssq
+  double xp1 = 0.0, xp2 = 0.0, scale = 0.0, ssq = 1.0;
+  auto acc = [&](double v) {
+    const double av = fabs(v);
+    if (av > scale) {
+      const double r = scale / av;
+      ssq = 1.0 + ssq * r * r;
+      scale = av;
+    } else if (av > 0.0) {
+      const double r = av / scale;
+      ssq += r * r;
+    }
+  };
   i = n - 1;
   for (; i + 1 >= kSolveChunk; i -= kSolveChunk) {
     double xv[kSolveChunk], c0[kSolveChunk], c1[kSolveChunk], c2[kSolveChunk];
@@ -772,6 +786,7 @@ __device__ void tri_solve(const InvIt &q, int n, int col) {
     for (int u = 0; u < kSolveChunk; ++u) {
       const double v = (xv[u] - c1[u] * xp1 - c2[u] * xp2) / c0[u];
       x[(long)(i - u) * ld] = v;
+      acc(v);
       xp2 = xp1;
       xp1 = v;
     }
@@ -780,25 +795,19 @@ __device__ void tri_solve(const InvIt &q, int n, int col) {
     const long o = (long)i * ld;
     const double v = (x[o] - u1[o] * xp1 - u2[o] * xp2) / u0[o];
     x[o] = v;
+    acc(v);
     xp2 = xp1;
     xp1 = v;
   }
+  return scale * sqrt(ssq);
 }
 
-__device__ void normalize_col(const InvIt &q, int n, int col) {
+__device__ void scale_col(const InvIt &q, int n, int col, double f) {
   const long ld = q.ldz;
-  double s = 0.0, mx = 0.0;
-  for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(q.z[i * ld + col]));
-  if (mx == 0.0) return;
-  for (int i = 0; i < n; ++i) {
-    const double v = q.z[i * ld + col] / mx;
-    s += v * v;
-  }
-  const double f = 1.0 / (mx * sqrt(s));
   for (int i = 0; i < n; ++i) q.z[i * ld + col] *= f;
 }
 
-__global__ void inverse_iteration_kernel(InvIt q, int n, int n_eig) {
+__global__ __launch_bounds__(64) void inverse_iteration_kernel(InvIt q, int n, int n_eig) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n_eig) return;
   const double tn = q.bounds[2];
@@ -814,16 +823,26 @@ __global__ void inverse_iteration_kernel(InvIt q, int n, int n_eig) {
     const double lam = q.lam[c] + (c - j) * 8.0 * tiny;
     tri_lu(q, n, c, lam, tiny);
     for (int i = 0; i < n; ++i) q.z[i * ld + c] = start_value(i, c);
+    // the normalisation of each iterate is folded into the next solve's
+    // right-hand side (the solve is linear); a group member is normalised
+    // and orthogonalised explicitly against the earlier members
+    double f = 1.0;
     for (int it = 0; it < 4; ++it) {
-      tri_solve(q, n, c);
-      // modified Gram-Schmidt against earlier vectors of the group
-      for (int o = j; o < c; ++o) {
-        double dot = 0.0;
-        for (int i = 0; i < n; ++i) dot += q.z[i * ld + o] * q.z[i * ld + c];
-        for (int i = 0; i < n; ++i) q.z[i * ld + c] -= dot * q.z[i * ld + o];
+      const double nrm = tri_solve(q, n, c, f);
+      f = nrm > 0.0 ? 1.0 / nrm : 1.0;
+      if (c > j) {
+        scale_col(q, n, c, f);
+        for (int o = j; o < c; ++o) {
+          double dot = 0.0;
+          for (int i = 0; i < n; ++i) dot += q.z[i * ld + o] * q.z[i * ld + c];
+          for (int i = 0; i < n; ++i) q.z[i * ld + c] -= dot * q.z[i * ld + o];
+        }
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += q.z[i * ld + c] * q.z[i * ld + c];
+        f = s > 0.0 ? 1.0 / sqrt(s) : 1.0;
       }
-      normalize_col(q, n, c);
     }
+    scale_col(q, n, c, f);
   }
 }
 
