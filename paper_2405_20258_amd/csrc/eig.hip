@@ -7,10 +7,13 @@
 //
 // Steps, all on the GPU:
 //  1. Householder reduction A = Q T_c Q^H to Hermitian tridiagonal form, one
-//     reflector H_k = I - tau u u^H per column (tau real); per step a matrix-
-//     vector product p = tau A' u and the rank-two update A' -= u w^H + w u^H,
-//     w = p - (tau/2)(u^H p) u.  Reflector k is stored in row k of the work
-//     matrix (the part of the row that the reduction no longer needs).
+//     reflector H_k = I - tau u u^H per column (tau real); step k needs
+//     p = tau A' u and the rank-two update A' -= u w^H + w u^H with
+//     w = p - (tau/2)(u^H p) u.  The updates are deferred over panels of
+//     columns (LAPACK's panel reduction): inside a panel A' is held as the
+//     panel-start matrix minus the panel's rank-two terms, and the matrix
+//     is updated once per panel.  Reflector k is stored in row k of the
+//     work matrix (the part of the row that the reduction no longer needs).
 //  2. A diagonal unitary D makes T = D^H T_c D real symmetric with off-
 //     diagonal |e_k|.
 //  3. Sturm-sequence multisection for the n_eig smallest eigenvalues of T
