@@ -281,6 +281,7 @@ def test_subspace_and_energy_ragged(env):
     (1, 8.0, 20, 4.0, 5),       # N_G = 6: one partial panel
     (2, 8.0, 20, 4.0, 17),      # N_G = 18
     (3, 8.0, 20, 4.0, 25),      # N_G = 26
+    (4, 8.0, 20, 4.0, 31),      # N_G = 32: exactly one full panel
     (62, 12.0, 100, 1.5, 100),  # N_G = 2102: 33 tile rows, ragged tile
 ])
 def test_eigensolver_sizes(env, nsq, a, n_c, e_psi, n_eig):
