@@ -298,7 +298,8 @@ Footprint footprint_of(const ssrpa_system_desc *d, const Geometry &g, int n_eig,
   f.subspace = full ? 0 : pairs * 2 * lde * 8 + bytes_c(ldg * lde);
   const size_t tiles = (lde / 64) * (lde / 64 + 1) / 2;
   f.freq = 2 * bytes_c(ne * ne) * n_freq + tiles * 64 * 64 * 16 * (size_t)n_freq * 2;
-  f.eig = full ? 0 : bytes_c(ng * ng) + 6 * ng * lde * 8 + 3 * bytes_c(ldg * lde);
+  f.eig = full ? 0 : bytes_c(ng * ng) + eig_workspace_bytes((int)ng) +
+                         6 * ng * lde * 8 + 3 * bytes_c(ldg * lde);
   // the static pass: chi0 partial tiles
   const size_t gt = (ldg / 64) * (ldg / 64 + 1) / 2;
   size_t stat = gt * 64 * 64 * 16 * 2;

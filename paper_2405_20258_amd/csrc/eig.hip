@@ -1087,7 +1087,36 @@ __global__ void newton_schulz_coeff_kernel(const double *__restrict__ g,
   }
 }
 
+// Layout of the Householder work buffer: panel vectors W, hemv row,
+// column and product partials, u^H A0 u and norm partials.
+struct HhSizes {
+  int nt_max;
+  long strips_max, ldp;
+  size_t n_wb, n_prow, n_pcol, n_pdot, n_dbl;
+  size_t bytes() const {
+    return sizeof(double2) * (n_wb + n_prow + n_pcol + n_pdot) +
+           sizeof(double) * n_dbl + 64;
+  }
+};
+
+HhSizes hh_sizes(int n) {
+  HhSizes z;
+  z.nt_max = std::max(1, (n - 1 + kHT - 1) / kHT);
+  z.strips_max = 0;   // the most strips of any step
+  for (int nt = 1; nt <= z.nt_max; ++nt)
+    z.strips_max = std::max(z.strips_max, strip_prefix(nt, strip_width(nt)));
+  z.ldp = (long)z.nt_max * kHT;
+  z.n_wb = (size_t)kNb * n;
+  z.n_prow = (size_t)z.strips_max * kHT;
+  z.n_pcol = (size_t)z.nt_max * z.ldp;
+  z.n_pdot = (size_t)z.nt_max * 64;
+  z.n_dbl = (size_t)z.strips_max + (n + kColRows - 1) / kColRows;
+  return z;
+}
+
 }  // namespace
+
+size_t eig_workspace_bytes(int n) { return hh_sizes(n).bytes(); }
 
 void eig_lowest(Context *ctx, const double *a_in, int n, int n_eig,
                 double *eigval, double *basis, int ld_e, int *flag,
@@ -1108,22 +1137,15 @@ void eig_lowest(Context *ctx, const double *a_in, int n, int n_eig,
   t.xs = t.e + n;
   double2 *phase = t.xs + n;
   // panel vectors and hemv partials, sized for the first step (m = n - 1)
-  const int nt_max = std::max(1, (n - 1 + kHT - 1) / kHT);
-  long strips_max = 0;   // the most strips of any step
-  for (int nt = 1; nt <= nt_max; ++nt)
-    strips_max = std::max(strips_max, strip_prefix(nt, strip_width(nt)));
-  t.ldp = (long)nt_max * kHT;
-  const size_t n_wb = (size_t)kNb * n, n_prow = (size_t)strips_max * kHT,
-               n_pcol = (size_t)nt_max * t.ldp, n_pdot = (size_t)nt_max * 64;
-  const int ncb_max = (n + kColRows - 1) / kColRows;
-  DevBuf hw(ctx, sizeof(double2) * (n_wb + n_prow + n_pcol + n_pdot) +
-                     sizeof(double) * (strips_max + ncb_max) + 64);
+  const HhSizes hz = hh_sizes(n);
+  t.ldp = hz.ldp;
+  DevBuf hw(ctx, hz.bytes());
   t.wb = hw.as<double2>();
-  t.prow = t.wb + n_wb;
-  t.pcol = t.prow + n_prow;
-  t.pdot = t.pcol + n_pcol;
-  t.puau = reinterpret_cast<double *>(t.pdot + n_pdot);
-  t.pnrm = t.puau + strips_max;
+  t.prow = t.wb + hz.n_wb;
+  t.pcol = t.prow + hz.n_prow;
+  t.pdot = t.pcol + hz.n_pcol;
+  t.puau = reinterpret_cast<double *>(t.pdot + hz.n_pdot);
+  t.pnrm = t.puau + hz.strips_max;
   for (int k0 = 0; k0 < n; k0 += kNb) {
     const int kend = std::min(k0 + kNb, n);
     for (int k = k0; k < kend; ++k) {

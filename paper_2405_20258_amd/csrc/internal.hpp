@@ -265,6 +265,9 @@ size_t gemm_f32_wide_workspace(const GemmArgs &g);
 // interleaved matrix (not modified).  eigval: device (n_eig); basis: planar
 // rows (ld_rows >= n rows, row stride 2*ld_e, im at +ld_e), padded rows/cols
 // zero.
+// Bytes of the Householder reduction's work buffer for an n x n matrix
+// (besides the n x n work copy), for the footprint model.
+size_t eig_workspace_bytes(int n);
 void eig_lowest(Context *ctx, const double *a, int n, int n_eig, double *eigval,
                 double *basis, int ld_e, int *flag, hipStream_t s);
 
