@@ -72,8 +72,9 @@ __device__ double block_sum(double v, double *red) {
 //         and partials of |x|^2;
 //   hemv: reflector k from those partials (u = x except u_0 = x_0 - beta;
 //         work-group 0 stores u_0, tau, e, d), then A0 u over the lower
-//         triangle of the trailing block in strips of 64 x 64 tiles, the
-//         panel products W^H u and V^H u and partials of u^H A0 u.
+//         triangle of the trailing block in strips of 64 x 64 tiles with
+//         partials of u^H A0 u, and (in work-groups of their own) the panel
+//         products W^H u and V^H u.
 // After the panel, her2k applies its rank-2 kNb update to the lower tiles of
 // the next trailing block, which is A0 of the next panel.  Only the lower
 // triangle is read, so the trailing matrix is read (half of it) once per
@@ -119,9 +120,9 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
 }
 
 // Step k, part col: kColRows elements c = k + kColRows b + e per
-// work-group, kColTpe threads (q) per element sharing its sums.  With slot j > 0 it first
-// finishes step k-1 (slot j-1, trailing offset k, size n - k) and stores
-// W_{j-1}; unless finish_only it then forms x_c = A'[c][k].
+// work-group, kColTpe threads (q) per element sharing its sums.  With slot
+// j > 0 it first finishes step k-1 (slot j-1, trailing offset k, size
+// n - k) and stores W_{j-1}; unless finish_only it then forms x_c = A'[c][k].
 __global__ __launch_bounds__(256) void hh_col_kernel(TriWork t, int n, int k,
                                                      int k0, int j,
                                                      int finish_only) {
