@@ -597,29 +597,34 @@ struct TriReal {
 __global__ void tri_phase_kernel(const double2 *__restrict__ ec, TriReal r,
                                  int n) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  // one thread walks the chain; e_{k-1} stays in a register and the
+  // pointers do not alias, so the loads of later rows run ahead
+  const double *__restrict__ dp = r.d;
+  double *__restrict__ ep = r.e;
+  double2 *__restrict__ php = r.phase;
   double2 ph = make_double2(1.0, 0.0);
-  r.phase[0] = ph;
-  double lo = INFINITY, hi = -INFINITY, emax2 = 0.0, tn = 0.0;
+  php[0] = ph;
+  double lo = INFINITY, hi = -INFINITY, emax2 = 0.0, tn = 0.0, ek_prev = 0.0;
   for (int k = 0; k < n; ++k) {
-    const double ek_prev = k > 0 ? r.e[k - 1] : 0.0;
     double ek = 0.0;
     if (k < n - 1) {
       const double2 c = ec[k];
       ek = hypot(c.x, c.y);
-      r.e[k] = ek;
+      ep[k] = ek;
       // phase_{k+1} = phase_k e_k / |e_k|
       double2 q = ek > 0.0 ? make_double2(c.x / ek, c.y / ek) : make_double2(1.0, 0.0);
       ph = make_double2(ph.x * q.x - ph.y * q.y, ph.x * q.y + ph.y * q.x);
       const double nr = hypot(ph.x, ph.y);
       ph.x /= nr;
       ph.y /= nr;
-      r.phase[k + 1] = ph;
+      php[k + 1] = ph;
       emax2 = fmax(emax2, ek * ek);
     }
-    const double rad = ek_prev + ek;
-    lo = fmin(lo, r.d[k] - rad);
-    hi = fmax(hi, r.d[k] + rad);
-    tn = fmax(tn, fabs(r.d[k]) + rad);
+    const double rad = ek_prev + ek, dk = dp[k];
+    lo = fmin(lo, dk - rad);
+    hi = fmax(hi, dk + rad);
+    tn = fmax(tn, fabs(dk) + rad);
+    ek_prev = ek;
   }
   const double span = fmax(hi - lo, tn) * 2.0 * DBL_EPSILON + DBL_MIN;
   r.bounds[0] = lo - span;
@@ -957,7 +962,7 @@ __global__ __launch_bounds__(256) void wy_t_kernel(const double2 *__restrict__ a
 // reflectors of the block are staged in LDS kWySub rows at a time (zero
 // outside their support), so the row loop reads them as broadcasts and only
 // the C loads go to memory.
-constexpr int kWyRows = 128;
+constexpr int kWyRows = 64;
 constexpr int kWySub = 64;
 __global__ __launch_bounds__(256) void wy_vhc_kernel(const double2 *__restrict__ a,
                                                      int n, int k0, int nb,
