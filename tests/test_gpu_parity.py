@@ -322,6 +322,30 @@ def test_eigensolver_sizes(env, nsq, a, n_c, e_psi, n_eig):
     g.close()
 
 
+@pytest.mark.parametrize("n_freq", [1, 3, 15])
+def test_energy_odd_frequency_counts(env, n_freq):
+    """E_c and every F_j against the oracle for frequency counts that leave
+    the last block of the two-frequency contraction with one frequency."""
+    torch, ssrpa, ctx = env
+    from oracle import rpa
+    from synth import systems as sy
+    s = ragged_system()
+    om, wt = sy.frequency_grid(n_freq)
+    g = ssrpa.System.from_synthetic(ctx, s)
+    g.chi0_static("fp64")
+    n_eig = 12   # a cut the ragged-system test shows to be well separated
+    g.subspace(n_eig)
+    _log(f"energy ragged n_freq={n_freq}")
+    ec, f = g.correlation_energy(n_eig, om, wt, "fp64")
+    ref = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                                 s.n_v, s.ecut_chi, n_eig, om, wt)
+    _log(f"  E_c gpu {ec!r} oracle {ref['ec']!r}")
+    assert abs(ec - ref["ec"]) < 1e-10 * abs(ref["ec"]) + 1e-12
+    assert np.max(np.abs(f - ref["integrand"])) < \
+        1e-10 * np.max(np.abs(ref["integrand"])) + 1e-13
+    g.close()
+
+
 def test_energy_valence_block_invariance_and_state(env):
     torch, ssrpa, ctx = env
     from synth import systems as sy
