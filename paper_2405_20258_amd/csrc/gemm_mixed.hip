@@ -584,9 +584,23 @@ __global__ __launch_bounds__(256) void split_rows_f32_kernel(
   }
 }
 
+// Per-row weights Delta_p(i omega) of one chunk for the FP32 Gram pass with
+// unweighted rows, in the permuted 16-row order of split_rows_f32_kernel
+// (position 4 q + s holds row 4 s + q); zero past the chunk.
+__global__ __launch_bounds__(256) void row_weights_f32_kernel(
+    HerkArgs h, long k0, int nrows, int n_pos, int om_i, float *__restrict__ wp) {
+  const int pos = blockIdx.x * 256 + threadIdx.x;
+  if (pos >= n_pos) return;
+  const int kb = pos >> 4, t = pos & 15;
+  const int r = kb * 16 + 4 * (t & 3) + (t >> 2);
+  wp[pos] = r < nrows ? (float)weight_m(h, k0 + r, h.omega[om_i]) : 0.0f;
+}
+
+template <bool kWeighted>
 __global__ __launch_bounds__(256, 2) void gram_f32_kernel(
     const uint4 *__restrict__ wf, int ldb, int nkb, int T, int n_tiles,
-    int kb_per_split, double *__restrict__ partial) {
+    int kb_per_split, const float *__restrict__ wrow,
+    double *__restrict__ partial) {
   extern __shared__ uint4 fsm[];
   uint4 *As = fsm;                          // [part][col][kGColStride]
   uint4 *Bs = fsm + 2 * kGT * kGColStride;
@@ -640,6 +654,14 @@ __global__ __launch_bounds__(256, 2) void gram_f32_kernel(
       (op ? Bs : As)[(part * kGT + col) * kGColStride + (soff & 3)] = v;
     }
     __syncthreads();
+    float wv[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+    if constexpr (kWeighted) {
+      const float4 w4 = *reinterpret_cast<const float4 *>(wrow + kb * 16 + 4 * q);
+      wv[0] = w4.x;
+      wv[1] = w4.y;
+      wv[2] = w4.z;
+      wv[3] = w4.w;
+    }
     uint4 a[4][2];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -652,10 +674,18 @@ __global__ __launch_bounds__(256, 2) void gram_f32_kernel(
 #pragma unroll
       for (int pp = 0; pp < 2; ++pp)
         b[pp] = Bs[(pp * kGT + wc + j * 16 + cl) * kGColStride + q];
-      const float br[4] = {__uint_as_float(b[0].x), __uint_as_float(b[0].y),
-                           __uint_as_float(b[0].z), __uint_as_float(b[0].w)};
-      const float bi[4] = {__uint_as_float(b[1].x), __uint_as_float(b[1].y),
-                           __uint_as_float(b[1].z), __uint_as_float(b[1].w)};
+      float br[4] = {__uint_as_float(b[0].x), __uint_as_float(b[0].y),
+                     __uint_as_float(b[0].z), __uint_as_float(b[0].w)};
+      float bi[4] = {__uint_as_float(b[1].x), __uint_as_float(b[1].y),
+                     __uint_as_float(b[1].z), __uint_as_float(b[1].w)};
+      if constexpr (kWeighted) {
+        // rows are unweighted: Delta of the lane's row of each MFMA step
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          br[s] *= wv[s];
+          bi[s] *= wv[s];
+        }
+      }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float ar[4] = {__uint_as_float(a[i][0].x), __uint_as_float(a[i][0].y),
@@ -1010,7 +1040,7 @@ struct GramPlan {
   int ldb, T, n_tiles, nsplit, kb_per_split, rows_step;
   bool resident_i;
   long kc, nchunks;
-  size_t partial_bytes, i_bytes, j_bytes;
+  size_t partial_bytes, i_bytes, j_bytes, w_bytes;
 };
 
 static GramPlan gram_plan(const HerkArgs &h, ssrpa_precision prec) {
@@ -1032,16 +1062,19 @@ static GramPlan gram_plan(const HerkArgs &h, ssrpa_precision prec) {
   p.kb_per_split = (nkb + nsplit - 1) / nsplit;
   p.nsplit = (nkb + p.kb_per_split - 1) / p.kb_per_split;
   p.partial_bytes = sizeof(double) * 2L * kGT * kGT * p.n_tiles * p.nsplit;
-  p.resident_i = bf && h.n_omega > 1;
+  // several frequencies: the I rows are converted once (BF16x3: unweighted
+  // I copy; FP32: unweighted rows, Delta applied to B in the Gram kernel)
+  p.resident_i = h.n_omega > 1 && !h.unit_weight;
   p.i_bytes = p.resident_i ? (size_t)(p.nchunks * p.kc) * row_bytes
                            : (size_t)p.kc * row_bytes;
   p.j_bytes = bf ? (size_t)p.kc * row_bytes : 0;
+  p.w_bytes = (!bf && p.resident_i) ? (size_t)p.kc * sizeof(float) : 0;
   return p;
 }
 
 size_t herk_gram_workspace(const HerkArgs &h, ssrpa_precision prec) {
   const GramPlan p = gram_plan(h, prec);
-  return p.partial_bytes + p.i_bytes + p.j_bytes;
+  return p.partial_bytes + p.i_bytes + p.j_bytes + p.w_bytes;
 }
 
 void herk_gram(Context *ctx, const HerkArgs &h, ssrpa_precision prec,
@@ -1051,10 +1084,12 @@ void herk_gram(Context *ctx, const HerkArgs &h, ssrpa_precision prec,
                 "herk_gram: FP32 or BF16x3 only");
   const bool bf = prec == SSRPA_BF16X3;
   const GramPlan p = gram_plan(h, prec);
-  ws.ensure(ctx, p.partial_bytes + p.i_bytes + p.j_bytes);
+  ws.ensure(ctx, p.partial_bytes + p.i_bytes + p.j_bytes + p.w_bytes);
   double *partial = ws.as<double>();
   uint4 *wi = reinterpret_cast<uint4 *>(ws.as<char>() + p.partial_bytes);
   uint4 *wj = reinterpret_cast<uint4 *>(ws.as<char>() + p.partial_bytes + p.i_bytes);
+  float *wrow = reinterpret_cast<float *>(ws.as<char>() + p.partial_bytes + p.i_bytes +
+                                          p.j_bytes);
   static bool attr = [] {
     SSRPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&gram_bf16x3_kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1072,11 +1107,20 @@ void herk_gram(Context *ctx, const HerkArgs &h, ssrpa_precision prec,
   };
   const int ti = (h.timer && h.timer->on) ? h.timer->start(h.stage, s) : -1;
   if (p.resident_i) {
+    // both forms hold 8 bytes per column and row, so chunk c starts at the
+    // same offset
+    HerkArgs hu = h;
+    hu.unit_weight = 1;
     for (long c = 0; c < p.nchunks; ++c) {
-      const int nkb = (chunk_rows(c) + 31) / 32;
-      if (nkb > 0)
+      const int nkb = (chunk_rows(c) + p.rows_step - 1) / p.rows_step;
+      if (nkb == 0) continue;
+      if (bf)
         hipLaunchKernelGGL(split_rows_bf16_kernel, split_grid(nkb), dim3(256), 0,
                            s, h, c * p.kc, chunk_rows(c), p.ldb, 0, 0,
+                           wi + c * (p.kc / 32) * blk_stride);
+      else
+        hipLaunchKernelGGL(split_rows_f32_kernel, split_grid(nkb), dim3(256), 0,
+                           s, hu, c * p.kc, chunk_rows(c), p.ldb, 0,
                            wi + c * (p.kc / 32) * blk_stride);
     }
     SSRPA_HIP(hipGetLastError());
@@ -1100,19 +1144,30 @@ void herk_gram(Context *ctx, const HerkArgs &h, ssrpa_precision prec,
                              s, h, k0, nrows, p.ldb, om, 1, wj);
         hipLaunchKernelGGL(gram_bf16x3_kernel, gg, dim3(256), kGLds, s, ci, wj,
                            p.ldb, nkb, p.T, p.n_tiles, p.kb_per_split, partial);
+      } else if (p.resident_i) {
+        // unweighted rows converted once; this frequency's Delta per row
+        const int n_pos = nkb * 16;
+        if (nkb > 0)
+          hipLaunchKernelGGL(row_weights_f32_kernel, dim3((n_pos + 255) / 256),
+                             dim3(256), 0, s, h, k0, nrows, n_pos, om, wrow);
+        hipLaunchKernelGGL(gram_f32_kernel<true>, gg, dim3(256), kFLds, s,
+                           wi + c * (p.kc / 32) * blk_stride, p.ldb, nkb, p.T,
+                           p.n_tiles, p.kb_per_split, wrow, partial);
       } else {
         if (nkb > 0)
           hipLaunchKernelGGL(split_rows_f32_kernel, split_grid(nkb), dim3(256), 0,
                              s, h, k0, nrows, p.ldb, om, wi);
-        hipLaunchKernelGGL(gram_f32_kernel, gg, dim3(256), kFLds, s, wi, p.ldb,
-                           nkb, p.T, p.n_tiles, p.kb_per_split, partial);
+        hipLaunchKernelGGL(gram_f32_kernel<false>, gg, dim3(256), kFLds, s, wi,
+                           p.ldb, nkb, p.T, p.n_tiles, p.kb_per_split, nullptr,
+                           partial);
       }
       SSRPA_HIP(hipGetLastError());
     }
     // BF16x3 carries the sign in d_p (and a factor kGJScale for unit
-    // weights); FP32 used sqrt|d_p| on both sides
+    // weights); FP32 used sqrt|d_p| on both sides, or (several
+    // frequencies) the signed Delta on one
     const double scale = bf ? (h.unit_weight ? 1.0 / kGJScale : 1.0)
-                            : (h.unit_weight ? 1.0 : -1.0);
+                            : (h.unit_weight || p.resident_i ? 1.0 : -1.0);
     hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)p.n_tiles, kGRedParts),
                        dim3(256), 0, s, partial, p.n_tiles, p.T, p.nsplit, h.ncol,
                        scale, out + om * out_stride, beta);
