@@ -399,25 +399,38 @@ constexpr size_t kGLds = 2 * 4 * kGT * kGColStride * sizeof(uint4);
 // both they would be lo^2 >= 0 on the diagonal and bias it by ~2^-16/3.
 constexpr double kGJScale = 3.0;
 
+// kBoth: one pass writes the unweighted copy to wb and the weighted one to
+// wb2 (the two operands of a single-frequency Gram pass), reading each
+// element of W once.
+template <bool kBoth>
 __global__ __launch_bounds__(256) void split_rows_bf16_kernel(
     HerkArgs h, long k0, int nrows, int ldb, int om_i, int weighted,
-    uint4 *__restrict__ wb) {
+    uint4 *__restrict__ wb, uint4 *__restrict__ wb2) {
   const int col = blockIdx.x * 256 + threadIdx.x;
   const int kb = blockIdx.y;
   if (col >= ldb) return;
   const double om = h.unit_weight ? 0.0 : h.omega[om_i];
-  unsigned pk[4][16];  // [part][row pair]: two bf16 per word, even row low
+  unsigned pk[4][16];   // [part][row pair]: two bf16 per word, even row low
+  unsigned pk2[4][16];  // weighted copy (kBoth)
 #pragma unroll
   for (int t = 0; t < 32; ++t) {
     const int r = kb * 32 + t;
-    double xr = 0.0, xi = 0.0;
+    // kBoth: x raw and sc the weight; otherwise x already weighted
+    double xr = 0.0, xi = 0.0, sc = 1.0;
     if (r < nrows && col < h.ncol) {
       const long p = k0 + r;
-      const double sc = !weighted ? 1.0
-                        : (h.unit_weight ? kGJScale : weight_m(h, p, om));
+      const double w = !(kBoth || weighted)
+                           ? 1.0
+                           : (h.unit_weight ? kGJScale : weight_m(h, p, om));
       const double *src = h.a + p * h.lda + col;
-      xr = src[0] * sc;
-      xi = src[h.im_off] * sc;
+      if constexpr (kBoth) {
+        sc = w;
+        xr = src[0];
+        xi = src[h.im_off];
+      } else {
+        xr = src[0] * w;
+        xi = src[h.im_off] * w;
+      }
     }
     unsigned short v[4];
     split_bf16(xr, v[0], v[1]);
@@ -429,6 +442,18 @@ __global__ __launch_bounds__(256) void split_rows_bf16_kernel(
       else
         pk[q][t >> 1] = v[q];
     }
+    if constexpr (kBoth) {
+      unsigned short w[4];
+      split_bf16(xr * sc, w[0], w[1]);
+      split_bf16(xi * sc, w[2], w[3]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (t & 1)
+          pk2[q][t >> 1] |= (unsigned)w[q] << 16;
+        else
+          pk2[q][t >> 1] = w[q];
+      }
+    }
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -437,6 +462,13 @@ __global__ __launch_bounds__(256) void split_rows_bf16_kernel(
     for (int u = 0; u < 4; ++u)
       dst[u] = make_uint4(pk[q][4 * u], pk[q][4 * u + 1], pk[q][4 * u + 2],
                           pk[q][4 * u + 3]);
+    if constexpr (kBoth) {
+      uint4 *dst2 = wb2 + (((long)kb * 4 + q) * ldb + col) * 4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        dst2[u] = make_uint4(pk2[q][4 * u], pk2[q][4 * u + 1], pk2[q][4 * u + 2],
+                             pk2[q][4 * u + 3]);
+    }
   }
 }
 
@@ -1115,9 +1147,9 @@ void herk_gram(Context *ctx, const HerkArgs &h, ssrpa_precision prec,
       const int nkb = (chunk_rows(c) + p.rows_step - 1) / p.rows_step;
       if (nkb == 0) continue;
       if (bf)
-        hipLaunchKernelGGL(split_rows_bf16_kernel, split_grid(nkb), dim3(256), 0,
-                           s, h, c * p.kc, chunk_rows(c), p.ldb, 0, 0,
-                           wi + c * (p.kc / 32) * blk_stride);
+        hipLaunchKernelGGL(split_rows_bf16_kernel<false>, split_grid(nkb), dim3(256),
+                           0, s, h, c * p.kc, chunk_rows(c), p.ldb, 0, 0,
+                           wi + c * (p.kc / 32) * blk_stride, nullptr);
       else
         hipLaunchKernelGGL(split_rows_f32_kernel, split_grid(nkb), dim3(256), 0,
                            s, hu, c * p.kc, chunk_rows(c), p.ldb, 0,
@@ -1135,13 +1167,15 @@ void herk_gram(Context *ctx, const HerkArgs &h, ssrpa_precision prec,
         const uint4 *ci = wi;
         if (p.resident_i) {
           ci = wi + c * (p.kc / 32) * blk_stride;
+          if (nkb > 0)
+            hipLaunchKernelGGL(split_rows_bf16_kernel<false>, split_grid(nkb),
+                               dim3(256), 0, s, h, k0, nrows, p.ldb, om, 1, wj,
+                               nullptr);
         } else if (nkb > 0) {
-          hipLaunchKernelGGL(split_rows_bf16_kernel, split_grid(nkb), dim3(256), 0,
-                             s, h, k0, nrows, p.ldb, om, 0, wi);
+          // both copies from one read of the rows
+          hipLaunchKernelGGL(split_rows_bf16_kernel<true>, split_grid(nkb), dim3(256),
+                             0, s, h, k0, nrows, p.ldb, om, 1, wi, wj);
         }
-        if (nkb > 0)
-          hipLaunchKernelGGL(split_rows_bf16_kernel, split_grid(nkb), dim3(256), 0,
-                             s, h, k0, nrows, p.ldb, om, 1, wj);
         hipLaunchKernelGGL(gram_bf16x3_kernel, gg, dim3(256), kGLds, s, ci, wj,
                            p.ldb, nkb, p.T, p.n_tiles, p.kb_per_split, partial);
       } else if (p.resident_i) {
@@ -1194,9 +1228,9 @@ void gemm_bf16x3_wide(Context *ctx, const GemmArgs &g, DevBuf &ws,
   hb.im_off = g.b_im;
   hb.ncol = g.n;
   hb.unit_weight = 1;
-  hipLaunchKernelGGL(split_rows_bf16_kernel,
+  hipLaunchKernelGGL(split_rows_bf16_kernel<false>,
                      dim3((unsigned)((ldn + 255) / 256), (unsigned)(g.k / 32)),
-                     dim3(256), 0, s, hb, 0L, g.k, ldn, 0, 0, bt);
+                     dim3(256), 0, s, hb, 0L, g.k, ldn, 0, 0, bt, nullptr);
   // C accumulates its flushes: zero the rows first
   fill_zero(g.c, sizeof(double) * (size_t)g.m * g.ldc, s);
   static bool attr = [] {
