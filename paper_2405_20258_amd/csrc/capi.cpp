@@ -411,7 +411,7 @@ const double *block_pairs(System &sys, int v0, int nvb, DevBuf &scratch,
   const size_t bytes = (size_t)nvb * sys.n_c * 2 * sys.geo.ld_g * sizeof(double);
   if (single && sys.w_cache_valid) return sys.w_cache.as<double>();
   DevBuf &dst = single ? sys.w_cache : scratch;
-  dst.ensure(sys.ctx, bytes);
+  dst.ensure(sys.ctx, bytes, s);
   {
     StageScope sc(sys.timer, SSRPA_STAGE_PAIR_FFT, s);
     launch_pair_matrix(sys, v0, nvb, true, dst.as<double>(), s);
@@ -431,7 +431,7 @@ void static_chi0(System &sys, ssrpa_precision prec, int vb, hipStream_t s) {
   for (int v0 = 0; v0 < sys.n_v; v0 += vb) {
     const int nvb = std::min(vb, sys.n_v - v0);
     const double *w = block_pairs(sys, v0, nvb, scratch, s);
-    de.ensure(ctx, sizeof(double) * (size_t)nvb * sys.n_c);
+    de.ensure(ctx, sizeof(double) * (size_t)nvb * sys.n_c, s);
     pair_energy_diffs(sys.energy_d.as<double>(), sys.n_v, v0, nvb, sys.n_c,
                       de.as<double>(), s);
     HerkArgs h{};
@@ -520,7 +520,7 @@ EcResult energy(System &sys, int n_eig, int n_freq, const double *omega,
     const int nvb = std::min(vb, sys.n_v - v0);
     const long rows = (long)nvb * sys.n_c;
     const double *w = block_pairs(sys, v0, nvb, scratch, s);
-    de.ensure(ctx, sizeof(double) * rows);
+    de.ensure(ctx, sizeof(double) * rows, s);
     pair_energy_diffs(sys.energy_d.as<double>(), sys.n_v, v0, nvb, sys.n_c,
                       de.as<double>(), s);
     HerkArgs h{};
@@ -530,7 +530,7 @@ EcResult energy(System &sys, int n_eig, int n_freq, const double *omega,
       h.im_off = g.ld_g;
     } else {
       // W_s = W C_s  (Eq. 7)
-      wsub.ensure(ctx, sizeof(double) * 2 * (size_t)rows * ld);
+      wsub.ensure(ctx, sizeof(double) * 2 * (size_t)rows * ld, s);
       GemmArgs gm{};
       gm.a = w; gm.lda = 2L * g.ld_g; gm.a_im = g.ld_g;
       gm.b = sys.sub.basis.as<double>(); gm.ldb = 2L * ld; gm.b_im = ld;

@@ -729,7 +729,7 @@ void staged_pairs(System &sys, int v0, int nvb, const double *gscale,
   const int ny1 = 2 * g.m1 + 1, ny2 = 2 * g.m2 + 1;
   const size_t ypp = stage_bytes_per_pair(g);
   const int ncc_max = stage_chunk_c(nvb, sys.n_c, ypp);
-  sys.ystage.ensure(sys.ctx, (size_t)nvb * ncc_max * ypp);
+  sys.ystage.ensure(sys.ctx, (size_t)nvb * ncc_max * ypp, s);
   // double-buffer the x outputs when that costs no work-groups per CU
   const size_t l1 = plane_lds_bytes<S>(ny1, ny2, 1);
   const size_t l2 = plane_lds_bytes<S>(ny1, ny2, 2);

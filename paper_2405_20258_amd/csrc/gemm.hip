@@ -485,7 +485,7 @@ void herk(Context *ctx, const HerkArgs &h, ssrpa_precision prec, double *out,
   nsplit = (h.k + kchunk - 1) / kchunk;
   if (nsplit < 1) nsplit = 1;
   const size_t need = sizeof(double) * 2L * kT * kT * n_tiles * nsplit * h.n_omega;
-  ws.ensure(ctx, need);
+  ws.ensure(ctx, need, s);
   DevBuf *wsb = &ws;
   if (h.k > 0) {
     const int ti = (h.timer && h.timer->on) ? h.timer->start(h.stage, s) : -1;

@@ -66,9 +66,15 @@ class DevBuf {
   size_t bytes() const { return bytes_; }
   bool empty() const { return ptr_ == nullptr; }
   void reset() { DevBuf t; swap(t); }
-  // Grow to at least `bytes` (contents discarded when reallocated).
-  void ensure(Context *ctx, size_t bytes) {
-    if (bytes_ < bytes || ctx_ != ctx) { reset(); *this = DevBuf(ctx, bytes); }
+  // Grow to at least `bytes` (contents discarded when reallocated).  Work
+  // queued on `s` may still use the old block, and a freed block can be
+  // handed to another request's stream at once, so `s` is drained first.
+  void ensure(Context *ctx, size_t bytes, hipStream_t s) {
+    if (bytes_ < bytes || ctx_ != ctx) {
+      if (ptr_) SSRPA_HIP(hipStreamSynchronize(s));
+      reset();
+      *this = DevBuf(ctx, bytes);
+    }
   }
 
  private:
