@@ -296,13 +296,29 @@ Footprint footprint_of(const ssrpa_system_desc *d, const Geometry &g, int n_eig,
     f.block += (size_t)vb * stage_chunk_c(vb, d->n_c, ypp) * ypp;
   }
   f.subspace = full ? 0 : pairs * 2 * lde * 8 + bytes_c(ldg * lde);
-  const size_t tiles = (lde / 64) * (lde / 64 + 1) / 2;
-  f.freq = 2 * bytes_c(ne * ne) * n_freq + tiles * 64 * 64 * 16 * (size_t)n_freq * 2;
+  // FP64 split-K partial tiles: the frequency contraction, the
+  // Newton-Schulz Gram matrix of the eigensolver and the static pass
+  HerkArgs hf{};
+  hf.ld = (int)lde;
+  hf.ncol = (int)ne;
+  hf.k = (long)pairs;
+  hf.n_omega = n_freq;
+  f.freq = 2 * bytes_c(ne * ne) * n_freq + herk_f64_workspace(hf);
+  HerkArgs hn{};
+  hn.ld = (int)lde;
+  hn.ncol = (int)ne;
+  hn.k = (long)ng;
+  hn.n_omega = 1;
+  hn.unit_weight = 1;
   f.eig = full ? 0 : bytes_c(ng * ng) + eig_workspace_bytes((int)ng) +
-                         6 * ng * lde * 8 + 3 * bytes_c(ldg * lde);
-  // the static pass: chi0 partial tiles
-  const size_t gt = (ldg / 64) * (ldg / 64 + 1) / 2;
-  size_t stat = gt * 64 * 64 * 16 * 2;
+                         6 * ng * lde * 8 + 3 * bytes_c(ldg * lde) +
+                         herk_f64_workspace(hn);
+  HerkArgs hs{};
+  hs.ld = (int)ldg;
+  hs.ncol = (int)ng;
+  hs.k = (long)pairs;
+  hs.n_omega = 1;
+  size_t stat = herk_f64_workspace(hs);
   if (prec != SSRPA_FP64) {
     // converted rows and 128 x 128 partial tiles of the Gram path
     HerkArgs h{};

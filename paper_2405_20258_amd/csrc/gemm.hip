@@ -466,6 +466,52 @@ __global__ __launch_bounds__(256, 3) void gemm_f64_kernel(GemmArgs g, int m_tile
 void gemm_mixed_launch(const GemmArgs &g, ssrpa_precision prec, int m_tiles,
                        int n_tiles, hipStream_t s);
 
+// Tiles, K split and partial-tile bytes of an FP64 HERK.  K is split so
+// that the blocks fill whole waves of the resident blocks (3 per CU for the
+// one-frequency kernel, 2 for the two-frequency one): the fewest splits
+// whose last wave is at least 95% full, else the fullest, with at least 8 K
+// chunks per split.  (Rounding 512 blocks up left 1953 medium chi0 tiles at
+// 2.5 waves, 85% full, and the 16 medium frequencies at 448 of 512.)
+struct HerkF64Plan {
+  int T, n_tiles;
+  long nsplit, kchunk;
+  size_t bytes;
+};
+
+static HerkF64Plan herk_f64_plan(const HerkArgs &h) {
+  HerkF64Plan p{};
+  p.T = h.ld / kT;
+  p.n_tiles = p.T * (p.T + 1) / 2;
+  const bool pair = h.n_omega >= 2 && !h.unit_weight;
+  const long per_split = (long)p.n_tiles * (pair ? (h.n_omega + 1) / 2 : h.n_omega);
+  const long resident = pair ? 512 : 768;
+  const int kst = kKc;
+  const long kr = std::max(1L, (h.k + kst - 1) / kst);
+  const long smax =
+      std::max(1L, std::min(kr / 8, std::max(4L, 4 * resident / std::max(1L, per_split))));
+  long nsplit = 1;
+  double best = 0.0;
+  for (long sp = 1; sp <= smax; ++sp) {
+    const long blocks = per_split * sp;
+    const long waves = (blocks + resident - 1) / resident;
+    const double fill = (double)blocks / (double)(waves * resident);
+    if (fill >= 0.95) {
+      nsplit = sp;
+      break;
+    }
+    if (fill > best + 1e-12) {
+      best = fill;
+      nsplit = sp;
+    }
+  }
+  p.kchunk = ((kr + nsplit - 1) / nsplit) * kst;
+  p.nsplit = std::max(1L, (h.k + p.kchunk - 1) / p.kchunk);
+  p.bytes = sizeof(double) * 2L * kT * kT * p.n_tiles * p.nsplit * h.n_omega;
+  return p;
+}
+
+size_t herk_f64_workspace(const HerkArgs &h) { return herk_f64_plan(h).bytes; }
+
 void herk(Context *ctx, const HerkArgs &h, ssrpa_precision prec, double *out,
           long out_stride, int beta, DevBuf &ws, hipStream_t s) {
   SSRPA_REQUIRE(h.ld % kT == 0 && h.ncol <= h.ld, SSRPA_ERR_ARG,
@@ -474,17 +520,10 @@ void herk(Context *ctx, const HerkArgs &h, ssrpa_precision prec, double *out,
     herk_gram(ctx, h, prec, out, out_stride, beta, ws, s);
     return;
   }
-  const int T = h.ld / kT;
-  const int n_tiles = T * (T + 1) / 2;
-  // split K so that there are at least ~2 blocks per CU
-  const int kst = kKc;
-  const long kr = (h.k + kst - 1) / kst;
-  long nsplit = (512 + (long)n_tiles * h.n_omega - 1) / ((long)n_tiles * h.n_omega);
-  nsplit = std::max(1L, std::min(nsplit, std::max(1L, kr / 8)));
-  long kchunk = ((kr + nsplit - 1) / nsplit) * kst;
-  nsplit = (h.k + kchunk - 1) / kchunk;
-  if (nsplit < 1) nsplit = 1;
-  const size_t need = sizeof(double) * 2L * kT * kT * n_tiles * nsplit * h.n_omega;
+  const HerkF64Plan p = herk_f64_plan(h);
+  const int T = p.T, n_tiles = p.n_tiles;
+  const long nsplit = p.nsplit, kchunk = p.kchunk;
+  const size_t need = p.bytes;
   ws.ensure(ctx, need, s);
   DevBuf *wsb = &ws;
   if (h.k > 0) {

@@ -245,6 +245,8 @@ void herk_gram(Context *ctx, const HerkArgs &h, ssrpa_precision prec,
                double *out, long out_stride, int beta, DevBuf &ws,
                hipStream_t s);
 size_t herk_gram_workspace(const HerkArgs &h, ssrpa_precision prec);
+// Bytes of ws an FP64 herk call needs (its split-K partial tiles).
+size_t herk_f64_workspace(const HerkArgs &h);
 // C = alpha * A * B + beta * C for complex planar operands:
 //   A: m x k rows (row stride lda, im at +a_im), B: k x n (row stride ldb,
 //   im at +b_im), C: m x n (row stride ldc, im at +c_im).  k is a multiple of
