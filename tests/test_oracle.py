@@ -100,6 +100,51 @@ def test_chi_gvector_count_closed_shells():
 
 # ---------------------------------------------------------- chi0 (Eq. 6)
 
+def _gaussian_shell_energy(a, coulomb_fn, s1, s2, q, nmax):
+    """(1/2 Omega) sum_{G != 0} v(G) |rho(G)|^2 for a charge +q spread as a
+    normalized Gaussian of width s1 and a charge -q of width s2, both
+    centred at the origin of a periodic cubic cell of side a.
+
+    rho(G) = q (exp(-s1^2 |G|^2 / 2) - exp(-s2^2 |G|^2 / 2)); |G|^2 is
+    formed here from the Miller indices, independently of the oracle.
+    """
+    n = np.arange(-nmax, nmax + 1)
+    m = np.stack(np.meshgrid(n, n, n, indexing="ij"), -1).reshape(-1, 3)
+    m = m[np.any(m != 0, axis=1)]
+    g2 = (2.0 * math.pi / a) ** 2 * np.sum(m.astype(np.float64) ** 2, axis=1)
+    rho = q * (np.exp(-0.5 * s1 * s1 * g2) - np.exp(-0.5 * s2 * s2 * g2))
+    return float(np.sum(coulomb_fn(a, m) * rho * rho)) / (2.0 * a ** 3)
+
+
+def test_coulomb_kernel_against_electrostatics():
+    """v(G) = 4 pi / |G|^2 pinned by Coulomb's law, not by its own formula.
+
+    A neutral charge made of two concentric Gaussians (widths s1, s2) has,
+    in free space, the energy
+        q^2 / (2 sqrt(pi) s1) + q^2 / (2 sqrt(pi) s2)
+        - q^2 sqrt(2 / pi) / sqrt(s1^2 + s2^2)
+    (two self-energies and the mutual term of Gaussian charges).  Being
+    spherical and neutral it has no multipole moments, so its periodic
+    images interact only through Gaussian tails: the reciprocal-space sum
+    of the oracle's kernel must reproduce the free-space value to rounding.
+    A constant factor on v (1.3, the Rydberg 8 pi) or another power of |G|
+    fails this.
+    """
+    q, s1, s2 = 1.0, 0.9, 1.4
+    exact = (q * q / (2.0 * math.sqrt(math.pi) * s1)
+             + q * q / (2.0 * math.sqrt(math.pi) * s2)
+             - q * q * math.sqrt(2.0 / math.pi) / math.sqrt(s1 * s1 + s2 * s2))
+    for a, nmax in ((24.0, 26), (30.0, 32)):
+        e = _gaussian_shell_energy(a, rpa.coulomb, s1, s2, q, nmax)
+        assert abs(e - exact) < 1e-12 * exact, (a, e, exact)
+    # the same sum detects a kernel off by a constant or by a power of |G|
+    for bad in (lambda a, m: 1.3 * rpa.coulomb(a, m),
+                lambda a, m: 2.0 * rpa.coulomb(a, m),
+                lambda a, m: 4.0 * math.pi / np.sqrt(rpa.gnorm2(a, m))):
+        e = _gaussian_shell_energy(24.0, bad, s1, s2, q, 26)
+        assert abs(e - exact) > 1e-3 * exact
+
+
 def test_chi0_hermitian_nsd_and_trace(small):
     s, w, mchi, d = small
     delta = rpa.pair_weights(s.energy, s.n_v, 0.0)
