@@ -1,0 +1,245 @@
+"""GPU parity of the static polarizability (Eq. 6) element by element at the
+full basis sizes of the workloads.
+
+The contraction's tile order, its super-block and XCD deal, its K split and
+the split reduction depend on N_G and on the number of pairs; these tests
+compare every element of chi0 at the workloads' own N_G (304, 3958 and
+15966) with the FP64 oracle, in max-norm relative to max|chi0|:
+
+* tiny workload, all 16 x 240 pairs (the contraction splits K 30 ways):
+  the symmetrized v^1/2 chi0 v^1/2 and the paper's chi0, 1e-10;
+* medium geometry (48^3, N_G = 3958) with 2 x 256 pairs, which gives the
+  same 3-way K split as the whole medium workload: every element of W
+  (1e-12) and of chi0 (FP64 1e-10, FP32 and BF16x3 2e-5);
+* large-share geometry (72^3, N_G = 15966, 250 tiles per side) with
+  2 x 48 pairs: every element of W (1e-12) and of chi0 (FP64 1e-10, FP32
+  and BF16x3 2e-5), compared in row blocks;
+* large-share geometry with one valence block of 32 bands and 160
+  conduction bands, which the pair transform stages in two conduction
+  chunks (144 + 16): W rows on both sides of the chunk boundary, 1e-12.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2405_20258_amd import ssrpa
+    ctx = ssrpa.Context(0)
+    yield torch, ssrpa, ctx
+    ctx.close()
+
+
+def _perm(g, s):
+    from oracle import rpa
+    idx = {tuple(int(x) for x in m): i for i, m in enumerate(g.gvectors())}
+    mo = rpa.chi_gvectors(s.a, s.ecut_chi)
+    return mo, np.array([idx[tuple(int(x) for x in m)] for m in mo])
+
+
+def _oracle_w(s, mo):
+    from oracle import rpa
+    psi = rpa.orbitals_realspace(s.a, s.fft, s.miller, s.coeff)
+    m = rpa.pair_matrix_fft(s.a, s.fft, psi[: s.n_v], psi[s.n_v:], mo)
+    del psi
+    return m, rpa.scaled_pair_matrix(s.a, m, mo)
+
+
+def _compare_blocks(torch, chi_dev, perm, w_ref, d, omega, rows=1024):
+    """max |GPU - oracle| and max |oracle| over all elements, by row blocks.
+
+    The oracle rows are (1/Omega) conj(W[:, G])^T diag(d) W (Eq. 6 with the
+    Coulomb factors folded into W); the GPU rows are gathered in the
+    oracle's G order."""
+    n = w_ref.shape[1]
+    dw = d[:, None] * w_ref
+    pt = torch.from_numpy(perm).cuda()
+    err, big = 0.0, 0.0
+    for r0 in range(0, n, rows):
+        r1 = min(n, r0 + rows)
+        ref = np.conj(w_ref[:, r0:r1]).T @ dw / omega
+        got = chi_dev[pt[r0:r1]][:, pt].cpu().numpy()
+        err = max(err, float(np.max(np.abs(got - ref))))
+        big = max(big, float(np.max(np.abs(ref))))
+    return err, big
+
+
+def test_tiny_chi0_full_matrix(env):
+    """Tiny workload: every element of both forms of chi0 at N_G = 304."""
+    torch, ssrpa, ctx = env
+    from oracle import rpa
+    from synth import systems as sy
+    s = sy.make_system(sy.TINY, 1000)
+    _log("tiny chi0 full matrix: system create")
+    g = ssrpa.System.from_synthetic(ctx, s)
+    mo, perm = _perm(g, s)
+    ng = len(mo)
+    assert ng == g.n_g == 304
+    m, w = _oracle_w(s, mo)
+    d = rpa.pair_weights(s.energy, s.n_v, 0.0)
+    ref_sym = rpa.chibar(s.a, w, d)
+    ref_paper = rpa.chi0(s.a, m, d.reshape(s.n_v, s.n_c))
+    out = torch.empty((ng, ng), dtype=torch.complex128, device="cuda")
+    for symmetrized, ref in ((True, ref_sym), (False, ref_paper)):
+        g.chi0_static("fp64", out_dev=out, symmetrized=symmetrized)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()[np.ix_(perm, perm)]
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        _log(f"tiny chi0 symmetrized={symmetrized}: max-norm rel err "
+             f"{err:.2e} over {ng * ng} elements")
+        assert err < 1e-10
+        assert np.max(np.abs(got - got.conj().T)) == 0.0
+    g.close()
+
+
+@pytest.fixture(scope="module")
+def medium_geometry(env):
+    torch, ssrpa, ctx = env
+    from oracle import rpa
+    from synth import systems as sy
+    s = sy.make_system(sy.MEDIUM, 2999, n_v=2, n_c=256)
+    _log("medium geometry (48^3, N_G = 3958, 2 x 256 pairs): system create")
+    g = ssrpa.System.from_synthetic(ctx, s)
+    mo, perm = _perm(g, s)
+    _, w = _oracle_w(s, mo)
+    d = rpa.pair_weights(s.energy, s.n_v, 0.0)
+    yield g, s, perm, w, d
+    g.close()
+
+
+def test_medium_geometry_pair_matrix_every_element(env, medium_geometry):
+    torch, ssrpa, ctx = env
+    g, s, perm, w_ref, d = medium_geometry
+    out = torch.empty((s.n_v * s.n_c, g.n_g), dtype=torch.complex128,
+                      device="cuda")
+    g.pair_matrix(0, s.n_v, out, scaled=True)
+    torch.cuda.synchronize()
+    w_gpu = out.cpu().numpy()[:, perm]
+    del out
+    werr = np.max(np.abs(w_gpu - w_ref)) / np.max(np.abs(w_ref))
+    _log(f"medium geometry: W max-norm rel err {werr:.2e}")
+    assert werr < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-5),
+                                      ("bf16x3", 2e-5)])
+def test_medium_geometry_chi0_every_element(env, medium_geometry, prec, tol):
+    torch, ssrpa, ctx = env
+    g, s, perm, w, d = medium_geometry
+    ng = g.n_g
+    assert ng == 3958
+    chi = torch.empty((ng, ng), dtype=torch.complex128, device="cuda")
+    g.chi0_static(prec, out_dev=chi, symmetrized=True)
+    torch.cuda.synchronize()
+    err, big = _compare_blocks(torch, chi, perm, w, d, s.a ** 3)
+    herm = float((chi - chi.conj().T).abs().max())
+    del chi
+    _log(f"medium geometry chi0 {prec}: max-norm rel err {err / big:.2e} "
+         f"over {ng * ng} elements")
+    assert err / big < tol
+    if prec != "fp64":
+        assert err / big > 1e-13, "reduced precision path did not run"
+    assert herm == 0.0
+
+
+@pytest.fixture(scope="module")
+def large_geometry(env):
+    torch, ssrpa, ctx = env
+    from oracle import rpa
+    from synth import systems as sy
+    s = sy.make_system(sy.LARGE_SHARE, 3999, n_v=2, n_c=48)
+    _log("large-share geometry (72^3, N_G = 15966, 2 x 48 pairs): create")
+    g = ssrpa.System.from_synthetic(ctx, s)
+    mo, perm = _perm(g, s)
+    _log("large-share geometry: oracle pair matrix")
+    _, w = _oracle_w(s, mo)
+    d = rpa.pair_weights(s.energy, s.n_v, 0.0)
+    yield g, s, perm, w, d
+    g.close()
+
+
+@pytest.mark.timeout(600)
+def test_large_geometry_pair_matrix_every_element(env, large_geometry):
+    torch, ssrpa, ctx = env
+    g, s, perm, w_ref, d = large_geometry
+    ng = g.n_g
+    assert ng == 15966
+    out = torch.empty((s.n_v * s.n_c, ng), dtype=torch.complex128,
+                      device="cuda")
+    g.pair_matrix(0, s.n_v, out, scaled=True)
+    torch.cuda.synchronize()
+    w_gpu = out.cpu().numpy()[:, perm]
+    del out
+    werr = np.max(np.abs(w_gpu - w_ref)) / np.max(np.abs(w_ref))
+    _log(f"large-share geometry: W max-norm rel err {werr:.2e}")
+    assert werr < 1e-12
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-5),
+                                      ("bf16x3", 2e-5)])
+def test_large_geometry_chi0_every_element(env, large_geometry, prec, tol):
+    torch, ssrpa, ctx = env
+    g, s, perm, w, d = large_geometry
+    ng = g.n_g
+    chi = torch.empty((ng, ng), dtype=torch.complex128, device="cuda")
+    _log(f"large-share geometry: chi0 {prec}")
+    g.chi0_static(prec, out_dev=chi, symmetrized=True)
+    torch.cuda.synchronize()
+    err, big = _compare_blocks(torch, chi, perm, w, d, s.a ** 3)
+    herm = 0.0
+    for r0 in range(0, ng, 2048):
+        blk = chi[r0:r0 + 2048]
+        herm = max(herm, float((blk - chi[:, r0:r0 + 2048].conj().T)
+                               .abs().max()))
+    del chi
+    _log(f"large-share geometry chi0 {prec}: max-norm rel err "
+         f"{err / big:.2e} over {ng * ng} elements")
+    assert err / big < tol
+    if prec != "fp64":
+        assert err / big > 1e-13, "reduced precision path did not run"
+    assert herm == 0.0
+
+
+@pytest.mark.timeout(600)
+def test_large_geometry_pair_rows_across_stage_chunks(env):
+    """One valence block of 32 bands against 160 conduction bands at 72^3:
+    the staged pair transform holds at most 4 GiB of its x-y stage, 144
+    conduction bands per chunk here, so the block runs as two chunks.  Rows
+    on both sides of the boundary match the oracle."""
+    torch, ssrpa, ctx = env
+    from oracle import rpa
+    from synth import systems as sy
+    s = sy.make_system(sy.LARGE_SHARE, 3998, n_v=32, n_c=160)
+    _log("large-share geometry, 32 x 160 pairs (two stage chunks): create")
+    g = ssrpa.System.from_synthetic(ctx, s)
+    mo, perm = _perm(g, s)
+    ng = g.n_g
+    out = torch.empty((s.n_v * s.n_c, ng), dtype=torch.complex128,
+                      device="cuda")
+    g.pair_matrix(0, s.n_v, out, scaled=True)
+    torch.cuda.synchronize()
+    vs, cs = [0, 17, 31], [0, 1, 143, 144, 145, 159]
+    rows = [v * s.n_c + c for v in vs for c in cs]
+    got = out[torch.tensor(rows, device="cuda")].cpu().numpy()[:, perm]
+    del out
+    _log("large-share geometry: oracle rows")
+    psi = rpa.orbitals_realspace(s.a, s.fft, s.miller, s.coeff)
+    m = rpa.pair_matrix_fft(s.a, s.fft, psi[vs], psi[[s.n_v + c for c in cs]],
+                            mo)
+    del psi
+    ref = rpa.scaled_pair_matrix(s.a, m, mo)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    _log(f"large-share geometry, chunked stage: W rows rel err {err:.2e}")
+    assert err < 1e-12
+    g.close()

@@ -553,52 +553,3 @@ def test_precision_modes_tiny(env, prec):
     assert err < 1e-5
     assert rel > 1e-13 or err > 1e-13, "reduced precision path did not run"
     g.close()
-
-
-@pytest.mark.timeout(600)
-def test_large_share_shape_samples(env):
-    """Large-share geometry at full size (30 bohr, 72^3 grid, N_G = 15966)
-    with few pairs (2 valence x 48 conduction bands) so that the oracle can
-    compute the pair matrix and chi0 outright: every W element and a sample
-    of chi0 elements must match (1e-12 / 1e-10 relative to the largest)."""
-    torch, ssrpa, ctx = env
-    from oracle import rpa
-    from synth import systems as sy
-    s = sy.make_system(sy.LARGE_SHARE, 3999, n_v=2, n_c=48)
-    _log("large-share shape: system create (72^3, N_G = 15966)")
-    g = ssrpa.System.from_synthetic(ctx, s)
-    ng = g.n_g
-    assert ng == 15966
-    idx = label_index(g.gvectors())
-    mo = rpa.chi_gvectors(s.a, s.ecut_chi)
-    perm = np.array([idx[tuple(int(x) for x in m)] for m in mo])
-    out = torch.empty((s.n_v * s.n_c, ng), dtype=torch.complex128, device="cuda")
-    g.pair_matrix(0, s.n_v, out, scaled=True)
-    torch.cuda.synchronize()
-    w_gpu = out.cpu().numpy()[:, perm]
-    del out
-    _log("large-share shape: oracle pair matrix")
-    psi = rpa.orbitals_realspace(s.a, s.fft, s.miller, s.coeff)
-    m = rpa.pair_matrix_fft(s.a, s.fft, psi[: s.n_v], psi[s.n_v:], mo)
-    del psi
-    w_ref = rpa.scaled_pair_matrix(s.a, m, mo)
-    werr = np.max(np.abs(w_gpu - w_ref)) / np.max(np.abs(w_ref))
-    _log(f"large-share shape: W rel err {werr:.2e}")
-    assert werr < 1e-12
-    chi = torch.empty((ng, ng), dtype=torch.complex128, device="cuda")
-    g.chi0_static("fp64", out_dev=chi, symmetrized=True)
-    torch.cuda.synchronize()
-    rng = np.random.default_rng(7)
-    gi = rng.integers(ng, size=400)
-    gj = rng.integers(ng, size=400)
-    d = rpa.pair_weights(s.energy, s.n_v, 0.0)
-    # oracle elements straight from Eq. (6) with the oracle's W
-    ref = (d[:, None] * np.conj(w_ref[:, gi]) * w_ref[:, gj]).sum(0) / s.a ** 3
-    gpu = chi[torch.from_numpy(perm[gi]).cuda(),
-              torch.from_numpy(perm[gj]).cuda()].cpu().numpy()
-    del chi
-    cmax = np.max(np.abs(d)) * np.max(np.sum(np.abs(w_ref) ** 2, axis=0)) / s.a ** 3
-    err = np.max(np.abs(gpu - ref)) / cmax
-    _log(f"large-share shape: chi0 sample err {err:.2e}")
-    assert err < 1e-10
-    g.close()
