@@ -224,6 +224,28 @@ SSRPA_API ssrpa_status ssrpa_trace_log(ssrpa_context *ctx, const double *x,
                                        int n, int n_mat, double coupling,
                                        double *f, void *hip_stream);
 
+/* Allocation-free form of ssrpa_trace_log, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same kernels and the same F_j; the work memory
+ * (the n_mat factor copies, pivots and failure marks:
+ * 16 n^2 n_mat + 8 n n_mat + 4 n_mat bytes, each part rounded up to 256)
+ * lives in a fixed 64 MiB device array per GPU, set up when a context is
+ * created on that GPU and held until the process ends.
+ *  x:    device, n_mat x n x n complex (Hermitian), not modified.
+ *  f:    device, n_mat doubles; F_j, or NaN where I - l X_j is not positive
+ *        definite.
+ *  flag: device int (nullable): 0, or nonzero if some factorization failed.
+ * Nothing is allocated or synchronized: the results are valid once the
+ * stream reaches the call's end.  SSRPA_ERR_ARG for a batch whose work
+ * memory exceeds 64 MiB (nothing is launched).  All calls on one GPU share
+ * the array, so calls that overlap on one GPU (different streams or
+ * threads) race; serialize them on one stream. */
+SSRPA_API ssrpa_status ssrpa_trace_log_noalloc(ssrpa_context *ctx,
+                                               const double *x, int n,
+                                               int n_mat, double coupling,
+                                               double *f, int *flag,
+                                               void *hip_stream);
+
 /* Gauss-Legendre rule with n points mapped to [0, inf) by
  * w = omega0 (1 + x)/(1 - x), weight 2 omega0 w_x / (1 - x)^2 (host). */
 SSRPA_API ssrpa_status ssrpa_frequency_grid(int n, double omega0,

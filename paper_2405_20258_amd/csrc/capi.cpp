@@ -643,6 +643,8 @@ ssrpa_status ssrpa_context_create(int hip_device, size_t hbm_budget_bytes,
     size_t fr = 0, tot = 0;
     SSRPA_HIP(hipMemGetInfo(&fr, &tot));
     ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
+    // address of this device's fixed work array (allocation-free entry point)
+    noalloc_setup(hip_device);
   });
   if (st != SSRPA_OK) {
     delete ctx;
@@ -954,6 +956,20 @@ ssrpa_status ssrpa_trace_log(ssrpa_context *ctx, const double *x, int n,
     SSRPA_REQUIRE(hflag == 0, SSRPA_ERR_NUMERIC,
                   "I - c X is not positive definite for some matrix");
   });
+}
+
+ssrpa_status ssrpa_trace_log_noalloc(ssrpa_context *ctx, const double *x,
+                                     int n, int n_mat, double coupling,
+                                     double *f, int *flag, void *hip_stream) {
+  if (!ctx || !x || !f) return SSRPA_ERR_ARG;
+  try {
+    SSRPA_HIP(hipSetDevice(ctx->device));
+    trace_log_noalloc(ctx->device, x, n, n_mat, coupling, f, flag,
+                      Stream(hip_stream).s);
+    return SSRPA_OK;
+  } catch (...) {
+    return finish(ctx, std::current_exception());
+  }
 }
 
 ssrpa_status ssrpa_frequency_grid(int n, double omega0, double *omega,

@@ -23,6 +23,7 @@
 // from the upper triangle of the trailing block.  A matrix whose pivot is
 // not positive is marked failed and skipped from then on; its F is NaN.
 #include <cmath>
+#include <mutex>
 
 #include "internal.hpp"
 
@@ -263,6 +264,71 @@ void quadrature(const double *w, const double *f, int n, double *ec,
                 hipStream_t s) {
   hipLaunchKernelGGL(quadrature_kernel, dim3(1), dim3(64), 0, s, w, f, n, ec);
   SSRPA_HIP(hipGetLastError());
+}
+
+// ---- allocation-free form ---------------------------------------------------
+//
+// Work memory of the batch (D, pivots, failure marks) in a fixed device array
+// instead of the context's allocator.  Each device holds its own copy of the
+// array; its address is looked up once per device while that device is
+// current (noalloc_setup, called when a context is created) and passed to the
+// kernels.  Every call on a device shares the array: calls that overlap on one
+// device race.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+}  // namespace
+
+void noalloc_setup(int device) {
+  SSRPA_REQUIRE(device >= 0 && device < kMaxDevices, SSRPA_ERR_ARG,
+                "device %d beyond the %d devices with a fixed work array",
+                device, kMaxDevices);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void *p = nullptr;
+  SSRPA_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  SSRPA_REQUIRE(p != nullptr, SSRPA_ERR_HIP, "no address for the work array");
+  g_scratch_ptr[device] = p;
+}
+
+size_t trace_log_noalloc_bytes(int n, int n_mat) {
+  return align256(sizeof(double) * 2 * (size_t)n * n * n_mat) +
+         align256(sizeof(double) * (size_t)n * n_mat) +
+         align256(sizeof(int) * (size_t)n_mat);
+}
+
+void trace_log_noalloc(int device, const double *x, int n, int n_mat,
+                       double coupling, double *f, int *flag, hipStream_t s) {
+  SSRPA_REQUIRE(n >= 1 && n_mat >= 1, SSRPA_ERR_ARG, "trace_log: empty batch");
+  SSRPA_REQUIRE(n_mat <= 65535, SSRPA_ERR_ARG, "trace_log: more than 65535 matrices");
+  const size_t need = trace_log_noalloc_bytes(n, n_mat);
+  SSRPA_REQUIRE(need <= kNoAllocScratchBytes, SSRPA_ERR_ARG,
+                "%d matrices of order %d need %zu bytes of work memory, beyond "
+                "the fixed %zu-byte array of the allocation-free form",
+                n_mat, n, need, kNoAllocScratchBytes);
+  void *base = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (device >= 0 && device < kMaxDevices) base = g_scratch_ptr[device];
+  }
+  SSRPA_REQUIRE(base, SSRPA_ERR_STATE,
+                "work array of device %d not set up (create a context first)",
+                device);
+  char *b = static_cast<char *>(base);
+  double *d = reinterpret_cast<double *>(b);
+  b += align256(sizeof(double) * 2 * (size_t)n * n * n_mat);
+  double *piv = reinterpret_cast<double *>(b);
+  b += align256(sizeof(double) * (size_t)n * n_mat);
+  int *fail = reinterpret_cast<int *>(b);
+  if (flag) fill_zero(flag, sizeof(int), s);
+  // build_b_kernel clears the failure marks; every other word of the array
+  // is written before it is read
+  trace_log_on(x, n, n_mat, coupling, f, flag, d, piv, fail, s);
 }
 
 }  // namespace ssrpa

@@ -284,6 +284,15 @@ void eig_lowest(Context *ctx, const double *a, int n, int n_eig, double *eigval,
 // *flag (device int) nonzero on a non-positive pivot.
 void trace_log(Context *ctx, const double *x, int n, int n_mat, double coupling,
                double *f, int *flag, hipStream_t s);
+// Allocation-free trace_log: work memory in a fixed per-device array of
+// kNoAllocScratchBytes (no allocator call); f and flag (nullable) are device
+// memory; nothing is synchronized.  noalloc_setup(device) looks the array's
+// address up once per device, with that device current.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+void noalloc_setup(int device);
+size_t trace_log_noalloc_bytes(int n, int n_mat);
+void trace_log_noalloc(int device, const double *x, int n, int n_mat,
+                       double coupling, double *f, int *flag, hipStream_t s);
 // ec[0] = (1/2pi) sum_j w[j] f[j]   (device scalars)
 void quadrature(const double *w, const double *f, int n, double *ec,
                 hipStream_t s);

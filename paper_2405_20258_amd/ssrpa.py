@@ -86,6 +86,8 @@ ssrpa_correlation_energy = _sig("ssrpa_correlation_energy", _i,
                                 [_p, _i, _i, _dp, _dp, _i, _i, _d, _dp, _dp,
                                  _p, _p])
 ssrpa_trace_log = _sig("ssrpa_trace_log", _i, [_p, _p, _i, _i, _d, _dp, _p])
+ssrpa_trace_log_noalloc = _sig("ssrpa_trace_log_noalloc", _i,
+                               [_p, _p, _i, _i, _d, _p, _p, _p])
 ssrpa_frequency_grid = _sig("ssrpa_frequency_grid", _i, [_i, _d, _dp, _dp])
 ssrpa_stage_times = _sig("ssrpa_stage_times", _i, [_p, _i, _dp, _ip])
 STAGES = ["pair_fft", "chi0_herk", "eigen", "projection", "freq_herk",
