@@ -190,14 +190,27 @@ def serve_stream(ssrpa, ctx, n_req, rate, max_running):
             if i not in done and srv.poll(i)["state"] >= ssrpa.REQ_DONE:
                 done.add(i)
                 p = srv.poll(i)
-                print(f"# request {r['index']} done: {p['t_done'] - p['t_submit']:.2f} s"
+                what = ("done" if p["state"] == ssrpa.REQ_DONE else
+                        f"FAILED (status {p['status']}: {srv.error(i)})")
+                print(f"# request {r['index']} {what}: "
+                      f"{p['t_done'] - p['t_submit']:.2f} s"
                       f" (N_v {r['n_v']}, {r['precision']})", file=sys.stderr,
                       flush=True)
         time.sleep(0.05)
     srv.drain()
     res = [(r, srv.poll(i)) for r, i in ids]
+    srv_err = [srv.error(i) for _, i in ids]
+    dev = [srv.device_times(i) for _, i in ids]
     reserved_peak, high = srv.memory()
     srv.close()
+    # requests whose device intervals intersect another's (device clock)
+    overl = sum(any(dev[i][0] < dev[j][1] and dev[j][0] < dev[i][1]
+                    for j in range(len(dev)) if j != i)
+                for i in range(len(dev)))
+    failed = [{"request": r["index"], "status": p["status"], "n_v": r["n_v"],
+               "precision": r["precision"], "error": srv_err[i]}
+              for (r, p), i in zip(res, range(len(res)))
+              if p["state"] != ssrpa.REQ_DONE]
     lat = np.array([p["t_done"] - p["t_submit"] for _, p in res])
     ok = sum(p["state"] == ssrpa.REQ_DONE for _, p in res)
     span = max(p["t_done"] for _, p in res) - min(p["t_submit"] for _, p in res)
@@ -209,6 +222,8 @@ def serve_stream(ssrpa, ctx, n_req, rate, max_running):
             "makespan_s": round(span, 3),
             "reserved_peak_gb": round(reserved_peak / 1e9, 2),
             "hbm_high_water_gb": round(high / 1e9, 2),
+            "requests_overlapping_on_device": int(overl),
+            "failed": failed,
             "mix": {"fp64": sum(r["precision"] == "fp64" for r, _ in res),
                     "bf16x3": sum(r["precision"] == "bf16x3" for r, _ in res)}}
 

@@ -300,16 +300,17 @@ typedef struct ssrpa_server ssrpa_server;
 enum { SSRPA_REQ_QUEUED = 0, SSRPA_REQ_RUNNING = 1, SSRPA_REQ_DONE = 2,
        SSRPA_REQ_FAILED = 3 };
 
-/* A server owns a dispatcher thread over `ctx`.  Submitted requests wait in
- * arrival order; the dispatcher admits the first waiting request whose
- * ssrpa_footprint fits the memory not yet reserved (budget minus the
- * footprints of running requests), up to `max_running` at once, and runs
- * each admitted request (system creation, static chi0, subspace, E_c) on a
- * worker thread with its own HIP stream, so the device work of different
- * requests overlaps.  A request that has waited longer than
- * `max_bypass_s` seconds is not overtaken by later ones.  Each result is
- * independent of the mix: kernels and reduction orders depend only on the
- * request's own sizes. */
+/* A server owns `max_running` (1..64) worker threads over `ctx`, each with
+ * one HIP stream (non-blocking, default priority) created here and destroyed
+ * by ssrpa_server_destroy after the workers have been joined.  Submitted
+ * requests wait in arrival order; a free worker admits the first waiting
+ * request whose ssrpa_footprint fits the memory not yet reserved (budget
+ * minus the footprints of running requests) and runs it (system creation,
+ * static chi0, subspace, E_c) on its stream, so the device work of different
+ * requests overlaps.  A request that has waited longer than `max_bypass_s`
+ * seconds is not overtaken by later ones.  Each result is independent of the
+ * mix: kernels and reduction orders depend only on the request's own sizes.
+ * SSRPA_ERR_HIP if a stream or event cannot be created. */
 SSRPA_API ssrpa_status ssrpa_server_create(ssrpa_context *ctx, int max_running,
                                            double max_bypass_s,
                                            ssrpa_server **out);
@@ -334,6 +335,22 @@ SSRPA_API ssrpa_status ssrpa_server_poll(ssrpa_server *srv, uint64_t request_id,
                                          int *state, ssrpa_status *status,
                                          double *ec, double *t_submit,
                                          double *t_start, double *t_done);
+
+/* Device times of a finished request, in milliseconds since the server was
+ * created, from HIP events recorded on the request's stream before its first
+ * and after its last device work (the device clock, so two requests whose
+ * intervals intersect had work queued on the device at the same time).
+ * SSRPA_ERR_STATE while the request has not finished; -1 if the events
+ * could not be read. */
+SSRPA_API ssrpa_status ssrpa_server_device_times(ssrpa_server *srv,
+                                                 uint64_t request_id,
+                                                 double *start_ms,
+                                                 double *end_ms);
+
+/* Error text of a failed request (the message of the call that failed);
+ * "" for any other state or an unknown id.  Valid until the server is
+ * destroyed. */
+SSRPA_API const char *ssrpa_server_error(ssrpa_server *srv, uint64_t request_id);
 
 /* Block until every submitted request has finished. */
 SSRPA_API ssrpa_status ssrpa_server_drain(ssrpa_server *srv);

@@ -37,11 +37,11 @@ static size_t round_alloc(size_t bytes) {
   return (bytes + g - 1) / g * g;
 }
 
-void Context::trim_locked(size_t need) {
-  // largest cached blocks first
+void Context::trim_locked(size_t need, std::vector<void *> &victims) {
+  // largest cached blocks first; the caller frees them outside the lock
   while (!free_blocks.empty() && in_use + cached + need > budget) {
     auto it = std::prev(free_blocks.end());
-    (void)hipFree(it->second);
+    victims.push_back(it->second);
     cached -= it->first;
     free_blocks.erase(it);
   }
@@ -49,39 +49,55 @@ void Context::trim_locked(size_t need) {
 
 void *Context::alloc(size_t bytes) {
   bytes = round_alloc(bytes == 0 ? 8 : bytes);
-  std::lock_guard<std::mutex> g(mu);
-  // reuse a cached block of at least `bytes` and at most 1.25x larger
-  auto it = free_blocks.lower_bound(bytes);
-  if (it != free_blocks.end() && it->first <= bytes + bytes / 4) {
-    void *p = it->second;
-    const size_t sz = it->first;
-    free_blocks.erase(it);
-    cached -= sz;
-    in_use += sz;
-    high_water = std::max(high_water, in_use);
-    // record the actual block size for release
-    sizes_[p] = sz;
-    return p;
+  std::vector<void *> victims;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    // reuse a cached block of at least `bytes` and at most 1.25x larger
+    auto it = free_blocks.lower_bound(bytes);
+    if (it != free_blocks.end() && it->first <= bytes + bytes / 4) {
+      void *p = it->second;
+      const size_t sz = it->first;
+      free_blocks.erase(it);
+      cached -= sz;
+      in_use += sz;
+      high_water = std::max(high_water, in_use);
+      // record the actual block size for release
+      sizes_[p] = sz;
+      return p;
+    }
+    trim_locked(bytes, victims);
+    if (in_use + cached + bytes > budget)
+      fail(SSRPA_ERR_NOMEM, "HBM budget exceeded: %zu in use + %zu requested > %zu",
+           in_use, bytes, budget);
+    in_use += bytes;  // reserved while the lock is released
   }
-  trim_locked(bytes);
-  if (in_use + cached + bytes > budget)
-    fail(SSRPA_ERR_NOMEM, "HBM budget exceeded: %zu in use + %zu requested > %zu",
-         in_use, bytes, budget);
+  // cached blocks are idle (released only after their stream finished); the
+  // runtime calls run without the lock so other threads keep allocating
+  for (void *v : victims) (void)hipFree(v);
+  victims.clear();
   void *p = nullptr;
   hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     // give every cached block back and retry once
-    for (auto &fb : free_blocks) (void)hipFree(fb.second);
-    free_blocks.clear();
-    cached = 0;
+    {
+      std::lock_guard<std::mutex> g(mu);
+      for (auto &fb : free_blocks) victims.push_back(fb.second);
+      free_blocks.clear();
+      cached = 0;
+    }
+    for (void *v : victims) (void)hipFree(v);
     e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
+      {
+        std::lock_guard<std::mutex> g(mu);
+        in_use -= bytes;
+      }
       fail(SSRPA_ERR_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     }
   }
-  in_use += bytes;
+  std::lock_guard<std::mutex> g(mu);
   high_water = std::max(high_water, in_use);
   sizes_[p] = bytes;
   return p;
@@ -145,7 +161,22 @@ DevBuf::DevBuf(Context *ctx, size_t bytes) : ctx_(ctx), bytes_(bytes) {
 }
 
 DevBuf::~DevBuf() {
-  if (ptr_ && ctx_) ctx_->release(ptr_, bytes_);
+  if (ptr_ && ctx_) {
+    // a block released while a failed call unwinds may still be read or
+    // written by work queued on the call's stream
+    sync_api_stream_on_unwind();
+    ctx_->release(ptr_, bytes_);
+  }
+}
+
+ApiStream &api_stream() {
+  static thread_local ApiStream a;
+  return a;
+}
+
+void sync_api_stream_on_unwind() {
+  const ApiStream &a = api_stream();
+  if (a.set && std::uncaught_exceptions() > 0) (void)hipStreamSynchronize(a.s);
 }
 
 namespace {
@@ -718,43 +749,64 @@ ssrpa_status ssrpa_system_create(ssrpa_context *ctx, const ssrpa_system_desc *de
   if (!ctx || !out) return SSRPA_ERR_ARG;
   *out = nullptr;
   ssrpa_system *sys = nullptr;
+  hipStream_t s = Stream(hip_stream).s;
   ssrpa_status st = guarded(ctx, [&] {
     set_device(ctx);
     Geometry g = make_geometry(desc);
-    hipStream_t s = Stream(hip_stream).s;
+    // every host-side check and table comes first: no device work is queued
+    // before the description has been accepted
+    const int n_b = desc->n_v + desc->n_c;
+    std::vector<double> energy(desc->energy, desc->energy + n_b);
+    for (int i = 0; i < n_b; ++i)
+      SSRPA_REQUIRE(std::isfinite(energy[i]), SSRPA_ERR_ARG, "non-finite energy");
+    double vmax = -INFINITY, cmin = INFINITY;
+    for (int i = 0; i < desc->n_v; ++i) vmax = std::max(vmax, energy[i]);
+    for (int i = desc->n_v; i < n_b; ++i) cmin = std::min(cmin, energy[i]);
+    SSRPA_REQUIRE(cmin > vmax, SSRPA_ERR_ARG,
+                  "every conduction energy must lie above every valence energy");
+    const size_t box = (size_t)g.n1 * g.n2 * g.n3;
+    std::vector<int> bidx(desc->n_pw);
+    for (int p = 0; p < desc->n_pw; ++p) {
+      const int a = ((desc->miller[3 * p] % g.n1) + g.n1) % g.n1;
+      const int b = ((desc->miller[3 * p + 1] % g.n2) + g.n2) % g.n2;
+      const int c = ((desc->miller[3 * p + 2] % g.n3) + g.n3) % g.n3;
+      bidx[p] = (c * g.n2 + b) * g.n1 + a;
+    }
+    {
+      std::vector<char> seen(box, 0);
+      for (int p = 0; p < desc->n_pw; ++p) {
+        SSRPA_REQUIRE(!seen[bidx[p]], SSRPA_ERR_ARG, "duplicate plane wave %d", p);
+        seen[bidx[p]] = 1;
+      }
+    }
+    // per-G tables
+    std::vector<int> code(g.n_g);
+    std::vector<double> scale(2 * (size_t)g.ld_g, 0.0);
+    const double on = g.volume / (double)box;
+    for (int i = 0; i < g.n_g; ++i) {
+      const int a = g.miller_chi[3 * i], b = g.miller_chi[3 * i + 1],
+                c = g.miller_chi[3 * i + 2];
+      const int col = (a + g.m1) * g.n2 + ((b % g.n2) + g.n2) % g.n2;
+      const int k3 = ((c % g.n3) + g.n3) % g.n3;
+      code[i] = col | (k3 << 20);
+      scale[i] = on * g.sqrt_v[i];
+      scale[g.ld_g + i] = on;
+    }
+    // from here on device work is queued on s: a failure waits for it
+    // before the host sources above and the buffers below are released
+    ApiCall call(s);
     sys = new ssrpa_system();
     sys->ctx = ctx;
     sys->geo = std::move(g);
     sys->n_v = desc->n_v;
     sys->n_c = desc->n_c;
-    sys->n_b = desc->n_v + desc->n_c;
+    sys->n_b = n_b;
     sys->n_pw = desc->n_pw;
-    sys->energy.assign(desc->energy, desc->energy + sys->n_b);
-    for (int i = 0; i < sys->n_b; ++i)
-      SSRPA_REQUIRE(std::isfinite(sys->energy[i]), SSRPA_ERR_ARG, "non-finite energy");
-    double vmax = -INFINITY, cmin = INFINITY;
-    for (int i = 0; i < sys->n_v; ++i) vmax = std::max(vmax, sys->energy[i]);
-    for (int i = sys->n_v; i < sys->n_b; ++i) cmin = std::min(cmin, sys->energy[i]);
-    SSRPA_REQUIRE(cmin > vmax, SSRPA_ERR_ARG,
-                  "every conduction energy must lie above every valence energy");
+    sys->energy = std::move(energy);
     const Geometry &gg = sys->geo;
-    const size_t box = (size_t)gg.n1 * gg.n2 * gg.n3;
     sys->energy_d = DevBuf(ctx, sizeof(double) * sys->n_b);
     SSRPA_HIP(hipMemcpyAsync(sys->energy_d.as(), sys->energy.data(),
                              sizeof(double) * sys->n_b, hipMemcpyHostToDevice, s));
-    // per-G tables
-    std::vector<int> code(gg.n_g);
-    std::vector<double> scale(2 * (size_t)gg.ld_g, 0.0);
-    const double on = gg.volume / (double)box;
-    for (int i = 0; i < gg.n_g; ++i) {
-      const int a = gg.miller_chi[3 * i], b = gg.miller_chi[3 * i + 1],
-                c = gg.miller_chi[3 * i + 2];
-      const int col = (a + gg.m1) * gg.n2 + ((b % gg.n2) + gg.n2) % gg.n2;
-      const int k3 = ((c % gg.n3) + gg.n3) % gg.n3;
-      code[i] = col | (k3 << 20);
-      scale[i] = on * gg.sqrt_v[i];
-      scale[gg.ld_g + i] = on;
-    }
     sys->gcol = DevBuf(ctx, sizeof(int) * gg.n_g);
     sys->sqrtv_d = DevBuf(ctx, sizeof(double) * 2 * (size_t)gg.ld_g + sizeof(double) * gg.n_g);
     SSRPA_HIP(hipMemcpyAsync(sys->gcol.as(), code.data(), sizeof(int) * gg.n_g,
@@ -777,20 +829,8 @@ ssrpa_status ssrpa_system_create(ssrpa_context *ctx, const ssrpa_system_desc *de
                              sizeof(int) * gg.zcol.size(), hipMemcpyHostToDevice, s));
     sys->dev_flag = DevBuf(ctx, 64);
     fill_zero(sys->dev_flag.as(), 64, s);
-    upload_twiddles(*sys);
+    upload_twiddles(*sys, s);
     // orbital staging: coefficients -> psi(r)
-    std::vector<int> bidx(sys->n_pw);
-    for (int p = 0; p < sys->n_pw; ++p) {
-      const int a = ((desc->miller[3 * p] % gg.n1) + gg.n1) % gg.n1;
-      const int b = ((desc->miller[3 * p + 1] % gg.n2) + gg.n2) % gg.n2;
-      const int c = ((desc->miller[3 * p + 2] % gg.n3) + gg.n3) % gg.n3;
-      bidx[p] = (c * gg.n2 + b) * gg.n1 + a;
-    }
-    std::vector<int> seen(box, 0);
-    for (int p = 0; p < sys->n_pw; ++p) {
-      SSRPA_REQUIRE(!seen[bidx[p]], SSRPA_ERR_ARG, "duplicate plane wave %d", p);
-      seen[bidx[p]] = 1;
-    }
     DevBuf bidx_d(ctx, sizeof(int) * sys->n_pw);
     SSRPA_HIP(hipMemcpyAsync(bidx_d.as(), bidx.data(), sizeof(int) * sys->n_pw,
                              hipMemcpyHostToDevice, s));
@@ -808,7 +848,11 @@ ssrpa_status ssrpa_system_create(ssrpa_context *ctx, const ssrpa_system_desc *de
     SSRPA_HIP(hipStreamSynchronize(s));
   });
   if (st != SSRPA_OK) {
-    delete sys;
+    if (sys) {
+      // the system's own buffers may still be targets of queued copies
+      (void)hipStreamSynchronize(s);
+      delete sys;
+    }
     return st;
   }
   {
@@ -822,8 +866,10 @@ ssrpa_status ssrpa_system_create(ssrpa_context *ctx, const ssrpa_system_desc *de
 ssrpa_status ssrpa_system_destroy(ssrpa_system *sys) {
   if (!sys) return SSRPA_ERR_ARG;
   Context *ctx = sys->ctx;
+  // every call on the system waited for its own device work before it
+  // returned (a failed call included), so its buffers are idle here and go
+  // back to the context's cache without a device-wide wait
   (void)hipSetDevice(ctx->device);
-  (void)hipDeviceSynchronize();
   delete sys;
   std::lock_guard<std::mutex> g(ctx->mu);
   ctx->live_systems -= 1;
@@ -845,6 +891,7 @@ ssrpa_status ssrpa_orbitals_realspace(ssrpa_system *sys, double *psi,
   return guarded(sys->ctx, [&] {
     set_device(sys->ctx);
     hipStream_t s = Stream(hip_stream).s;
+    ApiCall call(s);
     const size_t n = (size_t)sys->geo.n1 * sys->geo.n2 * sys->geo.n3 * sys->n_b;
     copy_interleaved(sys->psi_r.as<double>(), psi, n, s);
     SSRPA_HIP(hipStreamSynchronize(s));
@@ -859,6 +906,7 @@ ssrpa_status ssrpa_pair_matrix(ssrpa_system *sys, int v0, int n_vb, int scaled,
     SSRPA_REQUIRE(v0 >= 0 && n_vb >= 1 && v0 + n_vb <= sys->n_v, SSRPA_ERR_ARG,
                   "valence range [%d, %d) outside [0, %d)", v0, v0 + n_vb, sys->n_v);
     hipStream_t s = Stream(hip_stream).s;
+    ApiCall call(s);
     const Geometry &g = sys->geo;
     const long rows = (long)n_vb * sys->n_c;
     DevBuf w(sys->ctx, sizeof(double) * 2 * (size_t)rows * g.ld_g);
@@ -878,6 +926,7 @@ ssrpa_status ssrpa_chi0_static(ssrpa_system *sys, ssrpa_precision precision,
                   SSRPA_ERR_ARG, "unknown precision %d", (int)precision);
     SSRPA_REQUIRE(valence_block >= 0, SSRPA_ERR_ARG, "negative valence block");
     hipStream_t s = Stream(hip_stream).s;
+    ApiCall call(s);
     const int vb = resolve_block(*sys, valence_block, 0, 1);
     if (vb < sys->n_v) {
       sys->w_cache.reset();
@@ -900,6 +949,7 @@ ssrpa_status ssrpa_subspace(ssrpa_system *sys, int n_eig, double *eigval,
   return guarded(sys->ctx, [&] {
     set_device(sys->ctx);
     hipStream_t s = Stream(hip_stream).s;
+    ApiCall call(s);
     compute_subspace(*sys, n_eig, s);
     if (eigval) std::memcpy(eigval, sys->sub.eigval.data(), sizeof(double) * n_eig);
     if (basis) {
@@ -924,6 +974,7 @@ ssrpa_status ssrpa_correlation_energy(ssrpa_system *sys, int n_eig, int n_freq,
     SSRPA_REQUIRE(n_eig >= 1, SSRPA_ERR_ARG, "n_eig must be >= 1");
     SSRPA_REQUIRE(std::isfinite(coupling), SSRPA_ERR_ARG, "bad coupling");
     hipStream_t s = Stream(hip_stream).s;
+    ApiCall call(s);
     const int vb = resolve_block(*sys, valence_block, n_eig, n_freq);
     if (vb < sys->n_v) {
       sys->w_cache.reset();
@@ -944,6 +995,7 @@ ssrpa_status ssrpa_trace_log(ssrpa_context *ctx, const double *x, int n,
     set_device(ctx);
     SSRPA_REQUIRE(n >= 1 && n_mat >= 1, SSRPA_ERR_ARG, "empty batch");
     hipStream_t s = Stream(hip_stream).s;
+    ApiCall call(s);
     DevBuf fd(ctx, sizeof(double) * n_mat + 64);
     int *flag = reinterpret_cast<int *>(fd.as<double>() + n_mat);
     fill_zero(flag, sizeof(int), s);

@@ -677,10 +677,11 @@ __global__ __launch_bounds__(256) void pair_z_kernel(
 }
 }  // namespace
 
-void upload_twiddles(System &sys) {
+void upload_twiddles(System &sys, hipStream_t s) {
   const Geometry &g = sys.geo;
   const int lens[3] = {g.n1, g.n2, g.n3};
-  std::vector<double> tw;
+  std::vector<double> &tw = sys.fft_tw_host;
+  tw.clear();
   for (int d = 0; d < 3; ++d) {
     const int N = lens[d];
     for (int t = 0; t < N; ++t) {
@@ -692,8 +693,8 @@ void upload_twiddles(System &sys) {
     }
   }
   sys.fft_tw = DevBuf(sys.ctx, tw.size() * sizeof(double));
-  SSRPA_HIP(hipMemcpy(sys.fft_tw.as(), tw.data(), tw.size() * sizeof(double),
-                      hipMemcpyHostToDevice));
+  SSRPA_HIP(hipMemcpyAsync(sys.fft_tw.as(), tw.data(), tw.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s));
 }
 
 void launch_orbital_fft(System &sys, const double *coeff_dev,

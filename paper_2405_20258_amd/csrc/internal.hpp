@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <exception>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -40,6 +41,28 @@ struct Error : std::runtime_error {
   } while (0)
 
 struct Context;
+
+// The HIP stream of the library call running on this thread.  Device work
+// of a call is queued on that stream; a call that fails part-way unwinds its
+// device buffers while such work may still be queued, so a buffer released
+// during exception unwinding first waits for this stream (ApiCall sets it).
+struct ApiStream {
+  hipStream_t s = nullptr;
+  bool set = false;
+};
+ApiStream &api_stream();
+void sync_api_stream_on_unwind();
+struct ApiCall {
+  ApiStream prev;
+  explicit ApiCall(hipStream_t s) : prev(api_stream()) {
+    api_stream().s = s;
+    api_stream().set = true;
+  }
+  ~ApiCall() {
+    sync_api_stream_on_unwind();
+    api_stream() = prev;
+  }
+};
 
 // Device allocation charged against a context's HBM budget; freed on
 // destruction.  Move-only.
@@ -101,7 +124,8 @@ struct Context {
   void release(void *p, size_t bytes);
   void set_error(const std::string &m);
   std::string error();
-  void trim_locked(size_t need);   // free cached blocks until `need` fits
+  // move cached blocks to `victims` (to be freed) until `need` fits
+  void trim_locked(size_t need, std::vector<void *> &victims);
   ~Context();
   std::map<void *, size_t> sizes_;  // live allocations and their block sizes
 };
@@ -186,6 +210,7 @@ struct System {
   DevBuf ystage;                 // x-y stage of the staged pair transform
   DevBuf sqrtv_d;                // per G: v(G)^1/2 * Omega / N
   DevBuf fft_tw;                 // twiddle tables for N1, N2, N3
+  std::vector<double> fft_tw_host;  // their source (kept for the async copy)
   DevBuf chibar0;                // n_g x n_g complex (interleaved), symmetrized
   bool have_chi0 = false;
   Subspace sub;
@@ -204,7 +229,7 @@ struct System {
 // ---------------------------------------------------------------------------
 
 // FFT stage (fft.hip)
-void upload_twiddles(System &sys);
+void upload_twiddles(System &sys, hipStream_t s);
 // psi_r <- orbitals on the grid; box_index_dev[pw] = linear grid index of
 // the plane wave's Miller triple (mod N).
 void launch_orbital_fft(System &sys, const double *coeff_dev,

@@ -105,6 +105,10 @@ ssrpa_server_submit = _sig("ssrpa_server_submit", _i,
                             _dp, _i, ctypes.POINTER(ctypes.c_uint64)])
 ssrpa_server_poll = _sig("ssrpa_server_poll", _i,
                          [_p, ctypes.c_uint64, _ip, _ip, _dp, _dp, _dp, _dp])
+ssrpa_server_device_times = _sig("ssrpa_server_device_times", _i,
+                                 [_p, ctypes.c_uint64, _dp, _dp])
+ssrpa_server_error = _sig("ssrpa_server_error", ctypes.c_char_p,
+                          [_p, ctypes.c_uint64])
 ssrpa_server_drain = _sig("ssrpa_server_drain", _i, [_p])
 ssrpa_server_memory = _sig("ssrpa_server_memory", _i,
                            [_p, ctypes.POINTER(_sz), ctypes.POINTER(_sz)])
@@ -383,6 +387,17 @@ class Server:
                                  ctypes.byref(t2)))
         return dict(state=st.value, status=status.value, ec=ec.value,
                     t_submit=t0.value, t_start=t1.value, t_done=t2.value)
+
+    def device_times(self, rid: int):
+        """(start_ms, end_ms) of a finished request on the device clock."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(ssrpa_server_device_times(self.handle, rid, ctypes.byref(a),
+                                         ctypes.byref(b)))
+        return a.value, b.value
+
+    def error(self, rid: int) -> str:
+        """Message of a failed request ("" otherwise)."""
+        return ssrpa_server_error(self.handle, rid).decode()
 
     def drain(self):
         _check(ssrpa_server_drain(self.handle))
