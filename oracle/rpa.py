@@ -7,8 +7,9 @@ the benchmark use it.  It shares no code with the HIP path.
 Everything here follows the paper's Method section (Weinberg et al.,
 "Static Subspace Approximation for Random Phase Approximation Correlation
 Energies: Implementation and Performance", arXiv:2405.20258), restricted to
-one q-point (q = 0), the Gamma point (one k-point, weight 1), an insulator
-(f_v = 1, f_c = 0) and spin degeneracy (the factor 2 of Eq. 2):
+one q-point (q = 0), the Gamma point (one k-point, weight 1) and spin
+degeneracy (the factor 2 of Eq. 2); occupations are those of an insulator
+(f_v = 1, f_c = 0) or, with partial occupations, given per band (Eqs. 4-6):
 
 * Eq. (1)  E_c = int_0^inf d omega / (2 pi) Tr[ln(1 - chi0 v) + chi0 v]
 * Eq. (3)  plane-wave matrix elements M_vc(G) = <psi_v | e^{iG.r} | psi_c>
@@ -91,6 +92,36 @@ def gnorm2(a: float, miller: np.ndarray) -> np.ndarray:
 def coulomb(a: float, miller: np.ndarray) -> np.ndarray:
     """Bare Coulomb kernel v(G) = 4 pi / |G|^2 (G != 0), Hartree atomic units."""
     return 4.0 * math.pi / gnorm2(a, miller)
+
+
+def coulomb_slab(a: float, miller: np.ndarray) -> np.ndarray:
+    """Coulomb kernel truncated along z for a slab (Computational Details:
+    truncation along the axis normal to the surface).
+
+    The interaction is cut at |z| = z_c = a/2 (half the cell height), so a
+    charge in the slab does not see its periodic images along z:
+    v(G) = int d^2 rho int_{-z_c}^{z_c} dz e^{-iG.r} / |r|
+         = 4 pi / |G|^2 [1 - e^{-G_par z_c} cos(G_z z_c)],
+    G_par = (G_x^2 + G_y^2)^1/2 (the term in sin(G_z z_c) vanishes since
+    G_z z_c = pi n).  At G_par = 0 the limit 4 pi / G_z^2 [1 - cos(G_z z_c)]
+    holds, which is zero for even n.
+    """
+    b = recip_unit(a)
+    m = np.asarray(miller, dtype=np.float64)
+    gpar = b * np.sqrt(m[:, 0] ** 2 + m[:, 1] ** 2)
+    gz = b * m[:, 2]
+    zc = 0.5 * float(a)
+    g2 = gpar * gpar + gz * gz
+    return 4.0 * math.pi / g2 * (1.0 - np.exp(-gpar * zc) * np.cos(gz * zc))
+
+
+def coulomb_kernel(a: float, miller: np.ndarray, truncation=None) -> np.ndarray:
+    """v(G): bare (truncation None) or "slab" (truncated along z)."""
+    if truncation is None:
+        return coulomb(a, miller)
+    if truncation == "slab":
+        return coulomb_slab(a, miller)
+    raise ValueError(f"unknown truncation {truncation!r}")
 
 
 # ---------------------------------------------------------------------------
@@ -202,11 +233,50 @@ def energy_factor(eps_v, eps_c, omega: float) -> np.ndarray:
     return -4.0 * de / (de * de + omega * omega)
 
 
-def scaled_pair_matrix(a, m_vcg, miller_chi) -> np.ndarray:
+def band_sets(occ):
+    """Valence set V (f > 0) and conduction set C (f < 1), band indices.
+
+    Eq. (4) sorts the non-zero terms of Eq. (2) into (occupied, empty),
+    (occupied, partial), (partial, empty) and (partial, partial) pairs; the
+    index change before Eq. (5) lets v run over occupied and partially
+    occupied bands and c over partially occupied and empty ones.
+    """
+    f = np.asarray(occ, dtype=np.float64)
+    return np.nonzero(f > 0.0)[0], np.nonzero(f < 1.0)[0]
+
+
+def energy_factor_occ(eps, occ, omega: float) -> np.ndarray:
+    """Delta_vc(i omega) over V x C, [v, c], with occupation factors.
+
+    For two bands n < m (ascending energies) Eq. (2) holds the ordered terms
+    (n, m) and (m, n): 2 (f_m - f_n) / (e_m - e_n - i w) and
+    2 (f_n - f_m) / (e_n - e_m - i w), whose sum is
+    -4 (f_n - f_m) de / (de^2 + w^2), de = e_m - e_n (the occupied-empty
+    case f_n = 1, f_m = 0 gives energy_factor).  Each unordered pair is
+    counted once: a pair of two partially occupied bands appears in V x C in
+    both orders, and the order with v >= c (band index) gets 0.  A pair with
+    equal occupations contributes 0; unequal occupations at equal energies
+    have no static limit and are rejected.
+    """
+    f = np.asarray(occ, dtype=np.float64)
+    e = np.asarray(eps, dtype=np.float64)
+    v, c = band_sets(f)
+    de = e[c][None, :] - e[v][:, None]
+    df = f[v][:, None] - f[c][None, :]
+    keep = (v[:, None] < c[None, :]) & (df != 0.0)
+    if np.any(keep & (de <= 0.0)):
+        raise ValueError("bands with different occupations need ascending, "
+                         "distinct energies")
+    out = np.zeros(de.shape)
+    out[keep] = -4.0 * df[keep] * de[keep] / (de[keep] ** 2 + omega * omega)
+    return out
+
+
+def scaled_pair_matrix(a, m_vcg, miller_chi, truncation=None) -> np.ndarray:
     """W_p(G) = M_p(G) v(G)^1/2 as a (pairs, G) matrix, pair p = v N_c + c."""
     nv, nc, ng = m_vcg.shape
     return (m_vcg.reshape(nv * nc, ng)
-            * np.sqrt(coulomb(a, miller_chi))[None, :])
+            * np.sqrt(coulomb_kernel(a, miller_chi, truncation))[None, :])
 
 
 def chi0(a, m_vcg, delta_vc) -> np.ndarray:
@@ -222,9 +292,9 @@ def chibar(a, w, delta_p) -> np.ndarray:
     return (np.conj(w).T * np.asarray(delta_p)[None, :]) @ w / cell_volume(a)
 
 
-def symmetrize_chi0(a, chi, miller_chi) -> np.ndarray:
+def symmetrize_chi0(a, chi, miller_chi, truncation=None) -> np.ndarray:
     """v^1/2 chi0 v^1/2 from chi0."""
-    s = np.sqrt(coulomb(a, miller_chi))
+    s = np.sqrt(coulomb_kernel(a, miller_chi, truncation))
     return s[:, None] * chi * s[None, :]
 
 
@@ -255,6 +325,33 @@ def project(w: np.ndarray, c_s: np.ndarray) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # Trace-log per frequency and quadrature (Eq. 1)
 # ---------------------------------------------------------------------------
+
+
+def _log1p_plus(y: np.ndarray) -> np.ndarray:
+    """g(y) = ln(1 + y) - y, accurate to rounding also for small |y|.
+
+    For |y| < 0.1 the Taylor series -sum_{k>=2} (-y)^k / k (60 terms, far
+    past convergence); otherwise log1p(y) - y, which loses nothing there.
+    """
+    y = np.asarray(y, dtype=np.float64)
+    out = np.log1p(y) - y
+    small = np.abs(y) < 0.1
+    ys = y[small]
+    acc = np.zeros_like(ys)
+    term = ys * ys
+    for k in range(2, 62):
+        acc += (term if k % 2 else -term) / k
+        term = term * ys
+    out[small] = acc
+    return out
+
+
+def trace_log(chis: np.ndarray, coupling: float = 1.0) -> float:
+    """F = Tr ln(I - l chis) + l Tr chis = sum_k [ln(1 - l mu_k) + l mu_k]
+    over the eigenvalues mu_k of the Hermitian chis (the definition of the
+    trace of the logarithm), each term evaluated without cancellation."""
+    mu = scipy.linalg.eigvalsh(chis)
+    return float(np.sum(_log1p_plus(-coupling * mu)))
 
 
 def trace_log_cholesky(chis: np.ndarray, coupling: float = 1.0) -> float:
@@ -305,22 +402,117 @@ def semi_infinite_rule(n: int, omega0: float = 1.0):
 # ---------------------------------------------------------------------------
 
 
-def pair_weights(eps, n_v, omega) -> np.ndarray:
-    """Delta_p(i omega) flattened over pairs p = v N_c + c."""
+def pair_weights(eps, n_v, omega, occ=None) -> np.ndarray:
+    """Delta_p(i omega) flattened over pairs p = v N_c + c.
+
+    occ None: insulator (bands < n_v occupied); else pairs over V x C of
+    band_sets(occ) with energy_factor_occ."""
+    if occ is not None:
+        return energy_factor_occ(eps, occ, omega).ravel()
     return energy_factor(eps[:n_v], eps[n_v:], omega).ravel()
 
 
-def w_matrix(a, fft, miller_psi, coeff, n_v, ecut_chi, v_range=None):
-    """(W, Miller_chi) for all pairs (or valence bands v_range) via FFTs."""
+def w_matrix(a, fft, miller_psi, coeff, n_v, ecut_chi, v_range=None,
+             occ=None, truncation=None):
+    """(W, Miller_chi) for all pairs (or valence bands v_range) via FFTs.
+
+    occ None: V = bands < n_v, C = the rest; else the sets of band_sets."""
     mchi = chi_gvectors(a, ecut_chi)
     psi = orbitals_realspace(a, fft, miller_psi, coeff)
-    v0, v1 = (0, n_v) if v_range is None else v_range
-    m = pair_matrix_fft(a, fft, psi[v0:v1], psi[n_v:], mchi)
-    return scaled_pair_matrix(a, m, mchi), mchi
+    if occ is None:
+        vset, cset = np.arange(n_v), np.arange(n_v, coeff.shape[0])
+    else:
+        vset, cset = band_sets(occ)
+    if v_range is not None:
+        vset = vset[v_range[0]:v_range[1]]
+    m = pair_matrix_fft(a, fft, psi[vset], psi[cset], mchi)
+    return scaled_pair_matrix(a, m, mchi, truncation), mchi
+
+
+def chi0_eq2_literal(a, miller_psi, coeff, eps, occ, miller_chi,
+                     omega: float) -> np.ndarray:
+    """Eq. (2) as printed, at q = 0 and one k-point (g = 1): the double sum
+    over all ordered band pairs (n, n') with 2 (f_n' - f_n) and the complex
+    denominator e_n' - e_n - i w, the matrix elements from the plane-wave
+    convolution (no grid).  For time-reversal symmetric (real) orbitals this
+    equals the pair form used everywhere else, transposed (reading of the
+    exponent sign: e^{+iG.r} in Eq. 3 relabels G -> -G).  Small inputs only.
+    """
+    f = np.asarray(occ, dtype=np.float64)
+    e = np.asarray(eps, dtype=np.float64)
+    nb = coeff.shape[0]
+    # x[n', n, G] = <psi_n'| e^{iG.r} |psi_n>
+    x = pair_matrix_convolution(miller_psi, coeff, coeff, miller_chi)
+    ng = x.shape[2]
+    out = np.zeros((ng, ng), dtype=np.complex128)
+    for n in range(nb):
+        for n2 in range(nb):
+            df = f[n2] - f[n]
+            if df == 0.0:
+                continue
+            t = 2.0 * df / (e[n2] - e[n] - 1j * omega)
+            out += t * np.outer(x[n2, n], np.conj(x[n2, n]))
+    return out / cell_volume(a)
+
+
+def trace_log_general(a_mat: np.ndarray, coupling: float = 1.0) -> float:
+    """Tr ln(I - l A) + l Tr A for a matrix A that is similar to a Hermitian
+    one (real spectrum), from its eigenvalues, term by term."""
+    mu = np.real(np.linalg.eigvals(a_mat))
+    return float(np.sum(_log1p_plus(-coupling * mu)))
+
+
+def correlation_energy_chi0_basis(a, fft, miller_psi, coeff, energy, n_v,
+                                  ecut_chi, n_eig, omega, weight, occ=None,
+                                  truncation=None):
+    """Static subspace from the eigenvectors of chi0 itself (Method, static
+    subspace paragraph, read literally), step by step:
+
+    1. M (Eq. 3) and chi0(0) = M^H Delta(0) M / Omega (Eq. 6).
+    2. C_s = the n_eig eigenvectors of chi0(0) with the most negative
+       eigenvalues.
+    3. For every frequency chi0_s = (M C_s)^H Delta (M C_s) / Omega
+       (Eqs. 7, 8) and the projected Coulomb kernel v_s = C_s^H v C_s, then
+       F = Tr ln(1 - chi0_s v_s) + Tr chi0_s v_s from the eigenvalues of
+       chi0_s v_s (C_s chi0_s C_s^H v restricted to the subspace).
+    4. E_c = (1/2 pi) sum_j w_j F_j.
+    """
+    mchi = chi_gvectors(a, ecut_chi)
+    psi = orbitals_realspace(a, fft, miller_psi, coeff)
+    if occ is None:
+        vset, cset = np.arange(n_v), np.arange(n_v, coeff.shape[0])
+    else:
+        vset, cset = band_sets(occ)
+    m = pair_matrix_fft(a, fft, psi[vset], psi[cset], mchi)
+    nv_, nc_, ng = m.shape
+    mm = m.reshape(nv_ * nc_, ng)
+    eps = np.asarray(energy)
+    c0 = chibar(a, mm, pair_weights(eps, n_v, 0.0, occ))   # paper's chi0
+    lam, vec = scipy.linalg.eigh(c0)
+    c_s = vec[:, :n_eig]
+    v = coulomb_kernel(a, mchi, truncation)
+    v_s = (np.conj(c_s).T * v[None, :]) @ c_s
+    ms = mm @ c_s
+    f = np.empty(len(omega))
+    for j, om in enumerate(omega):
+        chis = chibar(a, ms, pair_weights(eps, n_v, float(om), occ))
+        f[j] = trace_log_general(chis @ v_s)
+    return dict(ec=quadrature(weight, f), integrand=f, eigval=lam[:n_eig],
+                gap=(math.inf if n_eig >= ng else
+                     (lam[n_eig] - lam[n_eig - 1]) / abs(lam[0])))
+
+
+def epsilon_inverse(chis: np.ndarray) -> np.ndarray:
+    """eps^-1 = (I - X)^-1 for the (projected) symmetrized matrix X
+    (Implementation section, last paragraph: the factorization of the
+    dielectric matrix 1 - chi0 v also yields eps^-1)."""
+    n = chis.shape[0]
+    return np.linalg.inv(np.eye(n) - chis)
 
 
 def correlation_energy(a, fft, miller_psi, coeff, energy, n_v, ecut_chi,
-                       n_eig, omega, weight, coupling=1.0, w=None):
+                       n_eig, omega, weight, coupling=1.0, w=None, occ=None,
+                       truncation=None):
     """Static-subspace RPA correlation energy, step by step.
 
     1. M by FFT (Eq. 3) and W = M v^1/2.
@@ -328,15 +520,21 @@ def correlation_energy(a, fft, miller_psi, coeff, energy, n_v, ecut_chi,
     3. C_s from its n_eig most negative eigenvectors.
     4. For every frequency: chibar_s = C_s^H chibar(i w) C_s computed as
        W_s^H diag(Delta) W_s / Omega (Eqs. 7, 8), then
-       F = ln det(I - chibar_s) + Tr chibar_s.
+       F = Tr ln(I - chibar_s) + Tr chibar_s from its eigenvalues (the
+       Cholesky and LU forms of the paper's ln det agree with it, see
+       trace_log_cholesky / trace_log_lu; the eigenvalue form has no
+       rounding floor from cancelling ln det against the trace).
     5. E_c = (1/2 pi) sum_j w_j F_j.
-    n_eig >= N_G means the full G basis (C_s = I).
+    n_eig >= N_G means the full G basis (C_s = I).  occ: occupation factors
+    (Eqs. 4-6), None for an insulator with n_v occupied bands.  truncation:
+    None (bare Coulomb kernel) or "slab" (coulomb_slab).
     """
     if w is None:
-        w, _ = w_matrix(a, fft, miller_psi, coeff, n_v, ecut_chi)
+        w, _ = w_matrix(a, fft, miller_psi, coeff, n_v, ecut_chi, occ=occ,
+                        truncation=truncation)
     ng = w.shape[1]
     eps = np.asarray(energy)
-    cb0 = chibar(a, w, pair_weights(eps, n_v, 0.0))
+    cb0 = chibar(a, w, pair_weights(eps, n_v, 0.0, occ))
     full = n_eig >= ng
     if full:
         lam = scipy.linalg.eigvalsh(cb0)
@@ -347,9 +545,9 @@ def correlation_energy(a, fft, miller_psi, coeff, energy, n_v, ecut_chi,
     f = np.empty(len(omega))
     chis_all = []
     for j, om in enumerate(omega):
-        chis = chibar(a, ws, pair_weights(eps, n_v, float(om)))
+        chis = chibar(a, ws, pair_weights(eps, n_v, float(om), occ))
         chis_all.append(chis)
-        f[j] = trace_log_cholesky(chis, coupling)
+        f[j] = trace_log(chis, coupling)
     ec = quadrature(weight, f)
     return dict(ec=ec, integrand=f, eigval=lam, gap=gap, chibar0=cb0,
                 chis=chis_all)

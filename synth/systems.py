@@ -20,7 +20,11 @@ synthetic systems stand in for them):
   0.1 + 4.9 u^(2/3), u ~ U[0, 1) (a free-electron sqrt(E) density of states
   from a 0.1 Ha band edge up to 5 Ha).
 * Random numbers: numpy PCG64 ``default_rng(seed)`` drawn in the order
-  Re xi, Im xi, eps_v, eps_c.
+  Re xi, Im xi, eps_v, eps_c (real orbitals: xi, eps_v, eps_c).
+* Real (time-reversal symmetric) orbitals: real coefficients in the cos/sin
+  basis of each {G, -G} pair, a real QR, then c(-G) = conj c(G).
+* Partial occupations: Fermi-Dirac factors at temperature kT around a
+  chemical potential mu, values within 1e-12 of 0 or 1 set to 0 or 1.
 * Chi0 cutoff: the midpoint between the closed shell |n|^2 <= nsq_chi and the
   next integer shell, so the G count is unambiguous.
 * Frequencies: Gauss-Legendre nodes x_k, weights w_k on [-1, 1] (numpy's
@@ -103,6 +107,11 @@ class System:
     n_v: int
     n_c: int
     ecut_chi: float
+    # occupation factors f_n in [0, 1] (None: insulator, f = 1 for the first
+    # n_v bands and 0 for the rest); with occupations, n_v counts the bands
+    # with f > 0
+    occ: Optional[np.ndarray] = None
+    real_orbitals: bool = False
 
     @property
     def n_pw(self) -> int:
@@ -113,13 +122,43 @@ class System:
         return self.n_v + self.n_c
 
 
+def _real_to_pw(miller: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """Map real coefficients in the cos/sin basis to plane-wave coefficients.
+
+    For each pair {G, -G} (G the lexicographically larger member) the real
+    pair (x_G, x_-G) becomes c(G) = (x_G + i x_-G)/sqrt 2, c(-G) = conj c(G);
+    G = 0 keeps its real coefficient.  The map is unitary, so orthonormal
+    real columns give orthonormal orbitals with c(-G) = conj c(G), i.e.
+    real orbitals psi(r) (time-reversal symmetric, as at the Gamma point).
+    """
+    index = {tuple(int(v) for v in m): i for i, m in enumerate(miller)}
+    out = np.zeros(x.shape, dtype=np.complex128)
+    r2 = 1.0 / math.sqrt(2.0)
+    for i, m in enumerate(miller):
+        t = tuple(int(v) for v in m)
+        if t == (0, 0, 0):
+            out[i] = x[i]
+            continue
+        j = index[(-t[0], -t[1], -t[2])]
+        if t > (-t[0], -t[1], -t[2]):
+            out[i] = (x[i] + 1j * x[j]) * r2
+            out[j] = (x[i] - 1j * x[j]) * r2
+    return out
+
+
 def make_system(spec: SystemSpec, seed: int, n_v: Optional[int] = None,
-                n_c: Optional[int] = None, qr: str = "numpy") -> System:
+                n_c: Optional[int] = None, qr: str = "numpy",
+                real_orbitals: bool = False) -> System:
     """Draw one seeded synthetic system of the given shape.
 
     qr="torch" orthonormalizes on the GPU (torch.linalg.qr) for large inputs;
     the random numbers are the same, the orbitals agree with the numpy QR up
     to rounding and per-band phases.
+
+    real_orbitals=True draws real coefficients xi ~ N(0, 1) (one draw per
+    plane wave and band, no imaginary part) in the cos/sin basis, takes a
+    real reduced QR and maps them to plane waves with c(-G) = conj c(G)
+    (see _real_to_pw); the energies follow as before.
     """
     n_v = spec.n_v if n_v is None else n_v
     n_c = spec.n_c if n_c is None else n_c
@@ -133,10 +172,18 @@ def make_system(spec: SystemSpec, seed: int, n_v: Optional[int] = None,
     envelope = np.exp(-g2 / (2.0 * spec.sigma ** 2))
     rng = np.random.default_rng(seed)
     xr = rng.standard_normal((n_pw, nb))
-    xi = rng.standard_normal((n_pw, nb))
+    xi = None if real_orbitals else rng.standard_normal((n_pw, nb))
     eps_v = np.sort(rng.uniform(-1.0, 0.0, n_v))
     u = rng.uniform(0.0, 1.0, n_c)
     eps_c = np.sort(0.1 + 4.9 * u ** (2.0 / 3.0))
+    if real_orbitals:
+        q, _ = np.linalg.qr(xr * envelope[:, None], mode="reduced")
+        coeff = np.ascontiguousarray(_real_to_pw(miller, q).T)
+        energy = np.concatenate([eps_v, eps_c]).astype(np.float64)
+        return System(spec=spec, seed=seed, a=spec.a, fft=(spec.fft,) * 3,
+                      miller=miller, coeff=coeff, energy=energy, n_v=n_v,
+                      n_c=n_c, ecut_chi=ecut_from_shell(spec.a, spec.nsq_chi),
+                      real_orbitals=True)
     z = (xr + 1j * xi) * envelope[:, None]
     if qr == "torch":
         import torch
@@ -150,6 +197,33 @@ def make_system(spec: SystemSpec, seed: int, n_v: Optional[int] = None,
     return System(spec=spec, seed=seed, a=spec.a, fft=(spec.fft,) * 3,
                   miller=miller, coeff=coeff, energy=energy, n_v=n_v,
                   n_c=n_c, ecut_chi=ecut_from_shell(spec.a, spec.nsq_chi))
+
+
+def fermi_dirac_occupations(energy: np.ndarray, mu: float, kt: float,
+                            cut: float = 1e-12) -> np.ndarray:
+    """Finite-temperature occupations f = 1 / (1 + exp((e - mu) / kT)).
+
+    Values within `cut` of 1 or 0 are set to exactly 1 or 0, so that the
+    fully occupied and the empty bands are well defined.  Energies must be
+    ascending; f is then non-increasing.
+    """
+    x = (np.asarray(energy, dtype=np.float64) - mu) / kt
+    f = 0.5 * (1.0 - np.tanh(0.5 * x))   # 1/(1 + e^x) without overflow
+    f[f > 1.0 - cut] = 1.0
+    f[f < cut] = 0.0
+    return f
+
+
+def with_occupations(s: System, occ: np.ndarray) -> System:
+    """The same orbitals and energies with occupation factors `occ`.
+
+    n_v becomes the number of bands with f > 0 and n_c the rest, so the
+    bands keep their order; the library derives the partially occupied set
+    from `occ` itself.
+    """
+    occ = np.asarray(occ, dtype=np.float64)
+    n_val = int(np.count_nonzero(occ > 0.0))
+    return dataclasses.replace(s, occ=occ, n_v=n_val, n_c=s.n_bands - n_val)
 
 
 def small_spec(a: float = 8.0, fft: int = 16, n_v: int = 4, n_c: int = 28,

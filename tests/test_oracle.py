@@ -323,7 +323,7 @@ def test_subspace_keeps_the_largest_magnitude_end(small):
     n = 10
 
     def ec_of(cs):
-        f = [rpa.trace_log_cholesky(rpa.chibar(
+        f = [rpa.trace_log(rpa.chibar(
             s.a, rpa.project(w, cs), rpa.pair_weights(s.energy, s.n_v, o)))
             for o in om]
         return rpa.quadrature(wt, f)
@@ -343,6 +343,13 @@ def test_trace_log_three_ways(small):
     ref = float(np.sum(np.log1p(-mu) + mu))
     assert abs(rpa.trace_log_cholesky(cb) - ref) < 1e-12 * abs(ref)
     assert abs(rpa.trace_log_lu(cb) - ref) < 1e-12 * abs(ref)
+    assert abs(rpa.trace_log(cb) - ref) < 1e-12 * abs(ref)
+    # far from the origin the eigenvalue form keeps its relative accuracy
+    # where ln det and the trace cancel: X = -t I gives n (ln(1 + t) - t)
+    for t in (1e-4, 1e-6, 1e-9):
+        x = -t * np.eye(7)
+        exact = 7 * (-t * t / 2 + t ** 3 / 3 - t ** 4 / 4 + t ** 5 / 5)
+        assert abs(rpa.trace_log(x) - exact) < 1e-14 * abs(exact)
 
 
 def test_exponent_sign_relabels_g(small):
@@ -376,3 +383,226 @@ def test_tiny_workload_against_plasmon_formula():
     assert abs(full["ec"] - exact) < 1e-7 * abs(exact)
     assert full["ec"] < sub["ec"] < 0.0
     assert sub["gap"] > 1e-8
+
+
+# ------------------------------------------- partial occupations (Eqs. 4-6)
+
+@pytest.fixture(scope="module")
+def partial():
+    """Small real-orbital system with Fermi-Dirac occupations: 3 + 4 of its
+    bands are partially occupied, so all four pair classes of Eq. (4) are
+    present, the partial-partial class among them."""
+    spec = sy.small_spec(n_v=4, n_c=12, nsq_chi=3, e_psi=3.0)
+    s0 = sy.make_system(spec, 17, real_orbitals=True)
+    e = s0.energy.copy()
+    e[:4] = [-0.9, -0.12, -0.05, -0.01]
+    e[4:] = np.sort(np.concatenate([[0.06, 0.09, 0.13, 0.16],
+                                    np.linspace(0.8, 3.0, 8)]))
+    s0 = dataclasses_replace(s0, energy=e)
+    occ = sy.fermi_dirac_occupations(e, 0.03, 0.02)
+    s = sy.with_occupations(s0, occ)
+    part = np.count_nonzero((occ > 0) & (occ < 1))
+    assert part >= 6 and np.count_nonzero(occ == 1) >= 1
+    return s
+
+
+def dataclasses_replace(obj, **kw):
+    import dataclasses
+    return dataclasses.replace(obj, **kw)
+
+
+def test_partial_occupations_equal_eq2_summed_over_ordered_pairs(partial):
+    """The pair form (each unordered pair once, Delta with f_v - f_c) equals
+    Eq. (2) evaluated literally over all ordered band pairs with complex
+    resonant denominators, for time-reversal symmetric orbitals.  A second
+    count of the partial-partial pairs, a missing factor (f_v - f_c), the
+    factor 4 or a sign would each break the equality."""
+    s = partial
+    mchi = rpa.chi_gvectors(s.a, s.ecut_chi)
+    w, _ = rpa.w_matrix(s.a, s.fft, s.miller, s.coeff, s.n_v, s.ecut_chi,
+                        occ=s.occ)
+    vset, cset = rpa.band_sets(s.occ)
+    psi = rpa.orbitals_realspace(s.a, s.fft, s.miller, s.coeff)
+    m = rpa.pair_matrix_fft(s.a, s.fft, psi[vset], psi[cset], mchi)
+    for om in (0.0, 0.3, 2.0):
+        d = rpa.energy_factor_occ(s.energy, s.occ, om)
+        pair_form = rpa.chi0(s.a, m, d)
+        literal = rpa.chi0_eq2_literal(s.a, s.miller, s.coeff, s.energy,
+                                       s.occ, mchi, om)
+        scale = np.max(np.abs(pair_form))
+        assert np.max(np.abs(literal - pair_form.T)) < 1e-13 * scale, om
+        # the partial-partial pairs matter at this size
+        assert scale > 0
+
+
+def test_partial_occupations_reduce_to_the_insulator(small):
+    """Occupations 1, ..., 1, 0, ..., 0 give the insulator's chi0 and E_c."""
+    s, w, mchi, d = small
+    occ = np.concatenate([np.ones(s.n_v), np.zeros(s.n_c)])
+    om, wt = sy.frequency_grid(16)
+    a = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                               s.n_v, s.ecut_chi, 10, om, wt)
+    b = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                               s.n_v, s.ecut_chi, 10, om, wt, occ=occ)
+    assert a["ec"] == b["ec"]
+    assert np.array_equal(rpa.pair_weights(s.energy, s.n_v, 0.7),
+                          rpa.pair_weights(s.energy, s.n_v, 0.7, occ))
+
+
+def test_partial_occupations_plasmon_formula(partial):
+    """Full-basis E_c with occupations from the 64-point rule against the
+    exact frequency integral: Delta_p = (f_v - f_c) x the insulator factor,
+    so the pair-space plasmon formula holds with rows scaled by
+    (f_v - f_c)^1/2 over the pairs that count."""
+    s = partial
+    w, _ = rpa.w_matrix(s.a, s.fft, s.miller, s.coeff, s.n_v, s.ecut_chi,
+                        occ=s.occ)
+    vset, cset = rpa.band_sets(s.occ)
+    df = s.occ[vset][:, None] - s.occ[cset][None, :]
+    de = s.energy[cset][None, :] - s.energy[vset][:, None]
+    keep = ((vset[:, None] < cset[None, :]) & (df != 0.0)).ravel()
+    wk = w[keep] * np.sqrt(df.ravel()[keep])[:, None]
+    exact = rpa.plasmon_ec(s.a, wk, de.ravel()[keep])
+    om, wt = sy.frequency_grid(64)
+    ng = w.shape[1]
+    r = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                               s.n_v, s.ecut_chi, ng, om, wt, occ=s.occ)
+    assert exact < 0.0
+    assert abs(r["ec"] - exact) < 5e-11 * abs(exact)
+
+
+def test_partial_occupations_invariants(partial):
+    """chi0 with partial occupations is Hermitian and negative semidefinite
+    (f non-increasing), F_j <= 0 and E_c <= 0; equal occupations of two
+    partially occupied bands contribute nothing."""
+    s = partial
+    w, _ = rpa.w_matrix(s.a, s.fft, s.miller, s.coeff, s.n_v, s.ecut_chi,
+                        occ=s.occ)
+    cb = rpa.chibar(s.a, w, rpa.pair_weights(s.energy, s.n_v, 0.0, s.occ))
+    assert np.max(np.abs(cb - cb.conj().T)) < 1e-15 * np.max(np.abs(cb))
+    assert np.max(np.linalg.eigvalsh(cb)) < 1e-14 * np.max(np.abs(cb))
+    om, wt = sy.frequency_grid(16)
+    r = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                               s.n_v, s.ecut_chi, 8, om, wt, occ=s.occ)
+    assert r["ec"] < 0 and np.all(r["integrand"] <= 0)
+    occ2 = s.occ.copy()
+    pp = np.nonzero((occ2 > 0) & (occ2 < 1))[0]
+    occ2[pp[1]] = occ2[pp[0]]
+    e2 = s.energy.copy()
+    e2[pp[1]] = e2[pp[0]]           # a degenerate pair with equal f
+    d = rpa.energy_factor_occ(e2, occ2, 0.0)
+    vset, cset = rpa.band_sets(occ2)
+    iv = int(np.nonzero(vset == pp[0])[0][0])
+    ic = int(np.nonzero(cset == pp[1])[0][0])
+    assert d[iv, ic] == 0.0
+
+
+# ------------------------------------------- slab Coulomb truncation
+
+def test_slab_kernel_against_its_defining_integral():
+    """v_slab(G) is the Fourier transform of 1/|r| cut at |z| = a/2: the
+    in-plane transform of 1/|r| is 2 pi e^{-G_par |z|} / G_par (a textbook
+    identity), and the z integral over [-a/2, a/2] is done by quadrature
+    here, independently of the closed form."""
+    from scipy.integrate import quad
+    a = 11.0
+    b = 2.0 * math.pi / a
+    zc = a / 2
+    ms = np.array([(1, 0, 0), (1, 1, 0), (0, 2, 1), (1, 2, 3), (3, 1, 2),
+                   (2, 2, 5), (1, 0, 4)])
+    v = rpa.coulomb_slab(a, ms)
+    for m, vm in zip(ms, v):
+        gpar = b * math.hypot(m[0], m[1])
+        gz = b * m[2]
+        re, _ = quad(lambda z: 2.0 * math.pi * math.exp(-gpar * abs(z))
+                     / gpar * math.cos(gz * z), -zc, zc, limit=400,
+                     epsabs=1e-14, epsrel=1e-13)
+        assert abs(vm - re) < 1e-11 * abs(re), (m, vm, re)
+    # G_par = 0: the limit 4 pi / G_z^2 (1 - cos(G_z a/2)), zero for even n
+    v0 = rpa.coulomb_slab(a, np.array([(0, 0, 1), (0, 0, 2), (0, 0, 3)]))
+    g1 = b
+    assert abs(v0[0] - 4 * math.pi / g1 ** 2 * 2.0) < 1e-12 * v0[0]
+    assert v0[1] == 0.0
+    assert abs(v0[2] - 4 * math.pi / (3 * g1) ** 2 * 2.0) < 1e-12 * v0[2]
+    # far from the plane (large G_par) the truncation does not matter
+    vb = rpa.coulomb_slab(a, np.array([(9, 0, 1)]))
+    assert abs(vb[0] / rpa.coulomb(a, np.array([(9, 0, 1)]))[0] - 1) < 1e-6
+
+
+def test_slab_truncation_energy_properties(small):
+    """With the slab kernel the correlation energy stays negative, chi0
+    stays negative semidefinite, and the G with v = 0 (G_par = 0, even n)
+    drop out of the symmetrized matrix."""
+    s, _, mchi, _ = small
+    om, wt = sy.frequency_grid(16)
+    r = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                               s.n_v, s.ecut_chi, 10 ** 9, om, wt,
+                               truncation="slab")
+    rb = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                                s.n_v, s.ecut_chi, 10 ** 9, om, wt)
+    assert r["ec"] < 0 and rb["ec"] < r["ec"] * 0.5
+    v = rpa.coulomb_slab(s.a, mchi)
+    zero = np.nonzero(v == 0.0)[0]
+    assert len(zero) >= 2
+    cb = r["chibar0"]
+    assert np.all(cb[zero] == 0.0) and np.all(cb[:, zero] == 0.0)
+
+
+# ------------------------------ basis from chi0's eigenvectors; eps^-1
+
+def test_chi0_basis_full_size_equals_full_basis(small):
+    """With all N_G eigenvectors of chi0 the subspace is the whole basis:
+    C_s is unitary, chi0_s v_s = C_s^H chi0 v C_s is similar to chi0 v, and
+    E_c equals the full-basis E_c (also with the slab kernel)."""
+    s, w, mchi, _ = small
+    om, wt = sy.frequency_grid(16)
+    ng = len(mchi)
+    for tr in (None, "slab"):
+        full = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                                      s.n_v, s.ecut_chi, 10 ** 9, om, wt,
+                                      truncation=tr)
+        sub = rpa.correlation_energy_chi0_basis(
+            s.a, s.fft, s.miller, s.coeff, s.energy, s.n_v, s.ecut_chi, ng,
+            om, wt, truncation=tr)
+        assert abs(sub["ec"] - full["ec"]) < 1e-12 * abs(full["ec"]), tr
+
+
+def test_chi0_basis_subspace_properties(small):
+    """In a proper subspace the chi0 basis gives E_c < 0 with every F_j < 0,
+    its eigenvalues are chi0's most negative ones, and it converges to the
+    full-basis value as N_eig grows (as the symmetrized basis does)."""
+    s, w, mchi, _ = small
+    om, wt = sy.frequency_grid(16)
+    ng = len(mchi)
+    full = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                                  s.n_v, s.ecut_chi, 10 ** 9, om, wt)["ec"]
+    errs = []
+    for n in (5, 10, 20, 40):
+        r = rpa.correlation_energy_chi0_basis(
+            s.a, s.fft, s.miller, s.coeff, s.energy, s.n_v, s.ecut_chi, n,
+            om, wt)
+        assert r["ec"] < 0 and np.all(r["integrand"] < 0)
+        errs.append(abs(r["ec"] - full))
+    assert errs[-1] < errs[0] and errs[-1] < 0.05 * abs(full)
+    psi = rpa.orbitals_realspace(s.a, s.fft, s.miller, s.coeff)
+    m = rpa.pair_matrix_fft(s.a, s.fft, psi[: s.n_v], psi[s.n_v:], mchi)
+    c0 = rpa.chi0(s.a, m, rpa.energy_factor(s.energy[: s.n_v],
+                                            s.energy[s.n_v:], 0.0))
+    lam = np.linalg.eigvalsh(c0)
+    r = rpa.correlation_energy_chi0_basis(s.a, s.fft, s.miller, s.coeff,
+                                          s.energy, s.n_v, s.ecut_chi, 7, om,
+                                          wt)
+    assert np.max(np.abs(r["eigval"] - lam[:7])) < 1e-13 * abs(lam[0])
+    assert ng > 40
+
+
+def test_epsilon_inverse_rank_one_closed_form():
+    """For X = -a u u^H (|u| = 1) the inverse of I - X is
+    I - a/(1 + a) u u^H (Sherman-Morrison)."""
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal(9) + 1j * rng.standard_normal(9)
+    u /= np.linalg.norm(u)
+    a = 0.37
+    x = -a * np.outer(u, np.conj(u))
+    ref = np.eye(9) - a / (1 + a) * np.outer(u, np.conj(u))
+    assert np.max(np.abs(rpa.epsilon_inverse(x) - ref)) < 1e-15
