@@ -159,9 +159,15 @@ def precision_sweep(ssrpa, ctx, s, om, wt, coeff_d, stream):
             "full_rpa_freq_time_ms": round(t_full * 1e3, 2), "rows": out}
 
 
-def serve_stream(ssrpa, ctx, n_req, rate, max_running):
-    """Replay the Poisson request stream through the native server."""
+def serve_stream(ssrpa, n_req, rate, max_running):
+    """Replay the Poisson request stream through the native server.
+
+    The systems are generated first (their orthonormalization uses torch on
+    the GPU); torch's cached blocks are then returned and the serving context
+    is created, so its HBM budget (90% of the free memory) is measured on
+    the device as the server will find it."""
     import numpy as np
+    import torch
     from synth import systems as sy
     reqs = sy.serving_stream(n_req, rate)
     print(f"# generating {n_req} serving systems", file=sys.stderr, flush=True)
@@ -173,6 +179,9 @@ def serve_stream(ssrpa, ctx, n_req, rate, max_running):
             print(f"# generated {k + 1}/{len(reqs)}", file=sys.stderr,
                   flush=True)
     om, wt = ssrpa.frequency_grid(16)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    ctx = ssrpa.Context(0)
     srv = ssrpa.Server(ctx, max_running=max_running, max_bypass_s=2.0)
     ids = []
     t0 = time.perf_counter()
@@ -203,6 +212,7 @@ def serve_stream(ssrpa, ctx, n_req, rate, max_running):
     dev = [srv.device_times(i) for _, i in ids]
     reserved_peak, high = srv.memory()
     srv.close()
+    ctx.close()
     # requests whose device intervals intersect another's (device clock)
     overl = sum(any(dev[i][0] < dev[j][1] and dev[j][0] < dev[i][1]
                     for j in range(len(dev)) if j != i)
@@ -226,6 +236,46 @@ def serve_stream(ssrpa, ctx, n_req, rate, max_running):
             "failed": failed,
             "mix": {"fp64": sum(r["precision"] == "fp64" for r, _ in res),
                     "bf16x3": sum(r["precision"] == "bf16x3" for r, _ in res)}}
+
+
+def tiny_time_to_ec(ssrpa, stream):
+    """The tiny workload's whole solve (N_eig = 75) on the GPU from host
+    orbitals, and the oracle's on the host's cores (FFTs, BLAS, eigh)."""
+    import numpy as np
+    import torch
+    from oracle import rpa
+    from synth import systems as sy
+    s = sy.make_system(sy.TINY, sy.CONFIG_SEED_BASE[sy.TINY.name])
+    om, wt = sy.frequency_grid(16)
+    ctx = ssrpa.Context(0)
+
+    def solve():
+        g = ssrpa.System(ctx, s.a, s.fft, s.miller, s.coeff, s.energy, s.n_v,
+                         s.ecut_chi, stream)
+        g.chi0_static("fp64")
+        g.subspace(75)
+        ec, _ = g.correlation_energy(75, om, wt, "fp64")
+        g.close()
+        return ec
+
+    solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        ec = solve()
+    torch.cuda.synchronize()
+    gpu_ms = (time.perf_counter() - t0) * 1e3 / reps
+    ctx.close()
+    print("# timing the oracle's tiny-workload solve", file=sys.stderr,
+          flush=True)
+    t0 = time.perf_counter()
+    ref = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                                 s.n_v, s.ecut_chi, 75, om, wt)
+    cpu_s = time.perf_counter() - t0
+    return {"workload": sy.TINY.name, "n_eig": 75, "gpu_ms": round(gpu_ms, 3),
+            "oracle_s": round(cpu_s, 3), "cores": os.cpu_count(),
+            "rel_diff": abs(ec - ref["ec"]) / abs(ref["ec"])}
 
 
 def main():
@@ -339,13 +389,31 @@ def main():
     if args.sweep:
         out["precision_sweep"] = precision_sweep(ssrpa, ctx, s, om, wt,
                                                  coeff_d, stream)
+    # the same solve from host orbitals (PCIe copy inside system creation),
+    # after the timed region; the timed steps start from orbitals in HBM
+    torch.cuda.synchronize()
+    th0 = time.perf_counter()
+    g = ssrpa.System(ctx, s.a, s.fft, s.miller, s.coeff, s.energy, s.n_v,
+                     s.ecut_chi, stream)
+    g.chi0_static(prec, valence_block=vb)
+    g.subspace(n_eig)
+    ec_h, _ = g.correlation_energy(n_eig, om, wt, prec, valence_block=vb)
+    g.close()
+    torch.cuda.synchronize()
+    out["time_to_ec_host_orbitals_ms"] = round((time.perf_counter() - th0) * 1e3, 3)
+    assert ec_h == ec, (ec_h, ec)
     if args.serve:
-        out["serving"] = serve_stream(ssrpa, ctx, args.serve_requests,
+        ctx.close()
+        del coeff_d
+        torch.cuda.empty_cache()
+        out["serving"] = serve_stream(ssrpa, args.serve_requests,
                                       args.serve_rate, args.serve_max_running)
     if not args.no_cpu_baseline:
         print("# timing the oracle on a bounded sample", file=sys.stderr,
               flush=True)
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_sample_bands)
+        out["cpu_baseline"]["tiny_workload_time_to_ec"] = tiny_time_to_ec(
+            ssrpa, stream)
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -19,13 +19,16 @@
  *
  * Conventions (Hartree atomic units throughout):
  *  - Valence bands 0..n_v-1 have occupation 1, conduction bands n_v..n_b-1
- *    occupation 0; spin degeneracy 2; one k-point of weight 1.
+ *    occupation 0, unless occupation factors are given (partial occupations,
+ *    Eqs. 4-6; see ssrpa_system_desc); spin degeneracy 2; one k-point of
+ *    weight 1.
  *  - Delta_vc(i w) = -4 (e_c - e_v) / ((e_c - e_v)^2 + w^2): the resonant and
  *    anti-resonant terms of Eq. (2) together, so chi0 is Hermitian and
  *    negative semidefinite at every imaginary frequency.
  *  - M_vc(G) = <psi_v| e^{+iG.r} |psi_c>; chi0_GG' = (1/Omega) sum_vc
  *    conj(M_vc(G)) Delta_vc M_vc(G') (Eq. 6), with 1/Omega exactly once.
- *  - v(G) = 4 pi / |G|^2; the symmetrized matrix is v^1/2 chi0 v^1/2.
+ *  - v(G) = 4 pi / |G|^2 (or its slab-truncated form, see
+ *    ssrpa_system_desc); the symmetrized matrix is v^1/2 chi0 v^1/2.
  *  - The chi0 basis is {G != 0 : |G|^2 / 2 <= ecut_chi}, in the order reported
  *    by ssrpa_chi_gvectors (lexicographic in the Miller indices).
  *
@@ -93,14 +96,47 @@ typedef struct ssrpa_system_desc {
                              SSRPA_ERR_ALIAS                                  */
   int32_t n_pw;           /* wavefunction plane waves                         */
   const int32_t *miller;  /* host, n_pw x 3 Miller indices of the plane waves */
-  int32_t n_v;            /* valence bands (occupied)                         */
-  int32_t n_c;            /* conduction bands (empty)                         */
+  int32_t n_v;            /* valence bands: occupied (and, with occupation,
+                             partially occupied) bands 0..n_v-1              */
+  int32_t n_c;            /* the remaining bands n_v..n_v+n_c-1               */
   const double *coeff;    /* (n_v + n_c) x n_pw complex, one band per row;
                              orthonormal rows; host or device (see below)     */
   int32_t coeff_on_device;/* 0: coeff is host memory, 1: device memory        */
-  const double *energy;   /* host, n_v + n_c band energies (Ha), each
-                             conduction energy above every valence energy    */
+  const double *energy;   /* host, n_v + n_c band energies (Ha); without
+                             occupation each energy of bands >= n_v lies above
+                             every energy of bands < n_v                      */
   double ecut_chi;        /* Ha; chi0 basis {G != 0 : |G|^2/2 <= ecut_chi}     */
+  const double *occupation; /* host, n_v + n_c occupation factors f_n, or
+                             NULL for an insulator (f = 1 below n_v, 0 from
+                             n_v on).  Partial occupations (Method, Eqs. 4-6):
+                             f_n in [0, 1], non-increasing along the bands,
+                             energies non-decreasing and bands of equal energy
+                             with equal f; n_v = the number of bands with
+                             f > 0.  The valence set is {f > 0}, the
+                             conduction set {f < 1}; a pair of two partially
+                             occupied bands counts once (lower band as v),
+                             and Delta_vc(i w) = -4 (f_v - f_c) de /
+                             (de^2 + w^2).  SSRPA_ERR_ARG otherwise.          */
+  int32_t coulomb_truncation; /* 0: bare v(G) = 4 pi / |G|^2.  1: slab
+                             truncation along a3 (Computational Details: for
+                             surfaces the interaction is cut along the axis
+                             normal to the slab): v(G) = 4 pi / |G|^2
+                             [1 - exp(-G_par z_c) cos(G_z z_c)], z_c = |a3|/2,
+                             G_z = G . a3/|a3|, G_par the rest; a3 must be
+                             normal to a1 and a2 (else SSRPA_ERR_ARG).  G
+                             with v(G) = 0 drop out of v^1/2 chi0 v^1/2.      */
+  int32_t real_orbitals;  /* 1: the orbitals are real (c(-G) = conj c(G) for
+                             every plane wave, within 1e-10; time-reversal
+                             symmetric orbitals at the Gamma point).  The
+                             pair densities are then real: two conduction
+                             orbitals share one complex pair transform, and
+                             chi0, the subspace and the frequency
+                             contractions work in the real cos/sin basis of
+                             the chi0 set (a quarter of the complex flops).
+                             FP64 contractions only.  The plane-wave set must
+                             hold -G with every G.  Outputs are reported in
+                             the plane-wave basis except chi_sub (cos/sin
+                             basis for n_eig >= N_G).  0: general complex.   */
 } ssrpa_system_desc;
 
 /* Human-readable name of a status code (static string). */
@@ -156,6 +192,13 @@ SSRPA_API ssrpa_status ssrpa_system_create(ssrpa_context *ctx,
                                            ssrpa_system **out);
 SSRPA_API ssrpa_status ssrpa_system_destroy(ssrpa_system *sys);
 
+/* The band sets of a system (Method, Eqs. 4-6): *n_val valence bands
+ * 0..n_val-1 (f > 0) and *n_cond conduction bands c_first..c_first+n_cond-1
+ * (f < 1).  Pair rows of a valence block are p = (v - v0) n_cond + c with
+ * band c_first + c.  Insulator: c_first = n_val.  Nullable outputs. */
+SSRPA_API ssrpa_status ssrpa_system_bands(const ssrpa_system *sys, int *n_val,
+                                          int *c_first, int *n_cond);
+
 /* Number of chi0 basis vectors N_G and (if `miller` is not NULL) their host
  * n_g x 3 Miller indices in the library's order. */
 SSRPA_API ssrpa_status ssrpa_chi_gvectors(const ssrpa_system *sys, int *n_g,
@@ -194,6 +237,26 @@ SSRPA_API ssrpa_status ssrpa_subspace(ssrpa_system *sys, int n_eig,
                                       double *eigval, double *basis,
                                       void *hip_stream);
 
+/* Which static matrix defines the subspace basis (Method, static subspace
+ * paragraph).  SYMMETRIZED: eigenvectors of v^1/2 chi0 v^1/2 (then
+ * Tr ln(1 - chi0 v) = ln det(I - X) with X the projected symmetrized
+ * matrix).  CHI0: eigenvectors of chi0 itself, as the paper states; the
+ * Coulomb kernel is then projected too, v_s = C_s^H v C_s = Z Z^H, and
+ * det(1 - chi0_s v_s) = det(I - Z^H chi0_s Z), so X = Z^H chi0_s Z. */
+typedef enum ssrpa_basis {
+  SSRPA_BASIS_SYMMETRIZED = 0,
+  SSRPA_BASIS_CHI0 = 1
+} ssrpa_basis;
+
+/* ssrpa_subspace with a choice of basis.  For SSRPA_BASIS_CHI0 `eigval`
+ * receives the n_eig most negative eigenvalues of the paper's chi0 (with
+ * 1/Omega) and `basis` its eigenvectors; the later ssrpa_correlation_energy
+ * and ssrpa_epsilon_inverse use the projected kernel v_s.
+ * SSRPA_ERR_ARG for an unknown kind. */
+SSRPA_API ssrpa_status ssrpa_subspace_basis(ssrpa_system *sys, ssrpa_basis kind,
+                                            int n_eig, double *eigval,
+                                            double *basis, void *hip_stream);
+
 /* Correlation energy by quadrature of Eq. (1) over `n_freq` imaginary
  * frequencies `omega` (host, Ha) with weights `weight` (host).
  *  n_eig < N_G: static-subspace form; requires ssrpa_subspace(sys, n_eig, ..)
@@ -214,6 +277,22 @@ SSRPA_API ssrpa_status ssrpa_correlation_energy(ssrpa_system *sys, int n_eig,
                                                 double *integrand,
                                                 double *chi_sub,
                                                 void *hip_stream);
+
+/* Inverse dielectric matrices eps^-1(i w_j) = (I - X_j)^-1 (Implementation
+ * section, last paragraph: the factorization of 1 - chi0 v also gives
+ * eps^-1 for later GW steps).  X_j is the matrix that
+ * ssrpa_correlation_energy returns in chi_sub: v^1/2 chi0 v^1/2 in the full
+ * basis (n_eig >= N_G) or projected onto the current subspace (n_eig < N_G,
+ * after ssrpa_subspace / ssrpa_subspace_basis).  eps_inv: device,
+ * n_freq x n x n complex, n = min(n_eig, N_G); by Gauss-Jordan elimination
+ * in FP64 on the GPU.  In the G basis the subspace form reads
+ * eps^-1 = I + C_s (eps_s^-1 - I) C_s^H.  SSRPA_ERR_NUMERIC if some
+ * I - X_j is not positive definite. */
+SSRPA_API ssrpa_status ssrpa_epsilon_inverse(ssrpa_system *sys, int n_eig,
+                                             int n_freq, const double *omega,
+                                             ssrpa_precision precision,
+                                             int valence_block, double *eps_inv,
+                                             void *hip_stream);
 
 /* F_j = ln det(I - l X_j) + l Tr X_j for a batch of Hermitian matrices X_j
  * (device, n_mat x n x n complex), by Cholesky factors in FP64 on the GPU.

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libssrpa.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["capi.cpp", "serve.cpp", "fft.hip", "gemm.hip", "gemm_mixed.hip", "eig.hip",
-           "chol.hip", "util.hip"]
+           "chol.hip", "util.hip", "real.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-fvisibility=hidden", "-Wall", "-Wno-unused-function",

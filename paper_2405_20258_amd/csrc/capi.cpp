@@ -10,12 +10,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdlib>
 #include <cstring>
 #include <thread>
+#include <tuple>
 
 #include "internal.hpp"
 
@@ -77,25 +79,46 @@ void *Context::alloc(size_t bytes) {
   victims.clear();
   void *p = nullptr;
   hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) {
+  // The budget is a model: memory held outside this context (other
+  // libraries, other processes) can make the device refuse an allocation
+  // that fits it.  Then the cached blocks go back to the device, and while
+  // other threads of this context keep releasing memory (concurrent
+  // solves finishing) the allocation is retried; it fails once no release
+  // has come for kOomWaitSeconds, or after kOomGiveUpSeconds in all.
+  constexpr double kOomWaitSeconds = 5.0, kOomGiveUpSeconds = 600.0;
+  const auto t_start = std::chrono::steady_clock::now();
+  while (e != hipSuccess) {
     (void)hipGetLastError();
-    // give every cached block back and retry once
+    uint64_t gen;
     {
       std::lock_guard<std::mutex> g(mu);
       for (auto &fb : free_blocks) victims.push_back(fb.second);
       free_blocks.clear();
       cached = 0;
+      gen = release_gen;
     }
     for (void *v : victims) (void)hipFree(v);
+    victims.clear();
     e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
+    if (e == hipSuccess) break;
+    (void)hipGetLastError();
+    const double waited = std::chrono::duration<double>(
+                              std::chrono::steady_clock::now() - t_start).count();
+    bool released = false;
+    if (waited < kOomGiveUpSeconds) {
+      std::unique_lock<std::mutex> lk(mu);
+      released = cv_release.wait_for(
+          lk, std::chrono::duration<double>(kOomWaitSeconds),
+          [&] { return release_gen != gen; });
+    }
+    if (!released) {
       {
         std::lock_guard<std::mutex> g(mu);
         in_use -= bytes;
       }
       fail(SSRPA_ERR_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     }
+    e = hipMalloc(&p, bytes);
   }
   std::lock_guard<std::mutex> g(mu);
   high_water = std::max(high_water, in_use);
@@ -113,6 +136,8 @@ void Context::release(void *p, size_t) {
   in_use -= sz;
   free_blocks.emplace(sz, p);
   cached += sz;
+  release_gen += 1;
+  cv_release.notify_all();
 }
 
 // Error text is kept per calling thread and context, so concurrent callers
@@ -251,6 +276,24 @@ Geometry make_geometry(const ssrpa_system_desc *d) {
     nb[i] = (int)std::floor(gmax * al / (2.0 * kPi)) + 1;
     SSRPA_REQUIRE(nb[i] < 512, SSRPA_ERR_ARG, "ecut_chi too large");
   }
+  // slab truncation along a3: z_c = |a3|/2, a3 normal to a1 and a2
+  g.truncation = d->coulomb_truncation;
+  SSRPA_REQUIRE(g.truncation == 0 || g.truncation == 1, SSRPA_ERR_ARG,
+                "unknown Coulomb truncation %d", g.truncation);
+  double nz[3] = {0, 0, 0}, zc = 0.0;
+  if (g.truncation == 1) {
+    const double *a3 = g.lattice + 6;
+    const double l3 = std::sqrt(a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2]);
+    for (int i = 0; i < 2; ++i) {
+      const double *ai = g.lattice + 3 * i;
+      const double li = std::sqrt(ai[0] * ai[0] + ai[1] * ai[1] + ai[2] * ai[2]);
+      const double dot = ai[0] * a3[0] + ai[1] * a3[1] + ai[2] * a3[2];
+      SSRPA_REQUIRE(std::fabs(dot) <= 1e-10 * li * l3, SSRPA_ERR_ARG,
+                    "slab truncation needs a3 normal to a1 and a2");
+    }
+    for (int c = 0; c < 3; ++c) nz[c] = a3[c] / l3;
+    zc = 0.5 * l3;
+  }
   g.m1 = g.m2 = g.m3 = 0;
   for (int a = -nb[0]; a <= nb[0]; ++a)
     for (int b = -nb[1]; b <= nb[1]; ++b)
@@ -261,7 +304,16 @@ Geometry make_geometry(const ssrpa_system_desc *d) {
           g.miller_chi.push_back(a);
           g.miller_chi.push_back(b);
           g.miller_chi.push_back(c);
-          g.sqrt_v.push_back(std::sqrt(4.0 * kPi / g2));
+          double v = 4.0 * kPi / g2;
+          if (g.truncation == 1) {
+            double gv[3];
+            for (int q = 0; q < 3; ++q)
+              gv[q] = a * g.recip[q] + b * g.recip[3 + q] + c * g.recip[6 + q];
+            const double gz = gv[0] * nz[0] + gv[1] * nz[1] + gv[2] * nz[2];
+            const double gpar = std::sqrt(std::max(0.0, g2 - gz * gz));
+            v *= 1.0 - std::exp(-gpar * zc) * std::cos(gz * zc);
+          }
+          g.sqrt_v.push_back(std::sqrt(std::max(0.0, v)));
           g.m1 = std::max(g.m1, std::abs(a));
           g.m2 = std::max(g.m2, std::abs(b));
           g.m3 = std::max(g.m3, std::abs(c));
@@ -269,7 +321,53 @@ Geometry make_geometry(const ssrpa_system_desc *d) {
       }
   g.n_g = (int)g.sqrt_v.size();
   SSRPA_REQUIRE(g.n_g >= 1, SSRPA_ERR_ARG, "empty chi0 basis (ecut_chi too small)");
-  g.ld_g = round_up(g.n_g, 64);
+  {
+    double smax = 0.0;
+    for (double x : g.sqrt_v) smax = std::max(smax, x);
+    g.store_scale.resize(g.n_g);
+    g.rescale.resize(g.n_g);
+    for (int i = 0; i < g.n_g; ++i) {
+      const double sv = g.sqrt_v[i];
+      const bool tiny = sv <= 1e-6 * smax;
+      g.store_scale[i] = tiny ? 1.0 : sv;
+      g.rescale[i] = tiny ? sv : 1.0;
+      g.rescaled |= tiny;
+    }
+  }
+  g.real = d->real_orbitals != 0;
+  SSRPA_REQUIRE(d->real_orbitals == 0 || d->real_orbitals == 1, SSRPA_ERR_ARG,
+                "real_orbitals must be 0 or 1");
+  // real path: 128-wide contraction tiles
+  g.ld_g = round_up(g.n_g, g.real ? 128 : 64);
+  if (g.real) {
+    std::map<std::tuple<int, int, int>, int> at;
+    for (int i = 0; i < g.n_g; ++i)
+      at[std::make_tuple(g.miller_chi[3 * i], g.miller_chi[3 * i + 1],
+                         g.miller_chi[3 * i + 2])] = i;
+    g.neg.resize(g.n_g);
+    for (int i = 0; i < g.n_g; ++i) {
+      auto it = at.find(std::make_tuple(-g.miller_chi[3 * i], -g.miller_chi[3 * i + 1],
+                                        -g.miller_chi[3 * i + 2]));
+      SSRPA_REQUIRE(it != at.end(), SSRPA_ERR_ARG, "chi0 set not symmetric");
+      g.neg[i] = it->second;
+    }
+    // the set is lexicographic, so the larger member of {G, -G} has the
+    // larger index
+    g.nh = g.n_g / 2;
+    g.hj.assign(g.n_g, 0);
+    g.hs.assign(g.n_g, 0);
+    for (int i = 0; i < g.n_g; ++i)
+      if (g.neg[i] < i) {
+        const int j = (int)g.hpos.size();
+        g.hpos.push_back(i);
+        g.hneg.push_back(g.neg[i]);
+        g.hj[i] = g.hj[g.neg[i]] = j;
+        g.hs[i] = 1;
+        g.hs[g.neg[i]] = -1;
+      }
+    SSRPA_REQUIRE((int)g.hpos.size() == g.nh && 2 * g.nh == g.n_g, SSRPA_ERR_ARG,
+                  "chi0 set without its G -> -G pairing");
+  }
   // alias-free bound N_i >= 2 max|n_psi,i| + max|n_chi,i| + 1
   int mp[3] = {0, 0, 0};
   for (int p = 0; p < d->n_pw; ++p)
@@ -303,6 +401,56 @@ Geometry make_geometry(const ssrpa_system_desc *d) {
 
 size_t bytes_c(size_t n) { return 16 * n; }
 
+}  // namespace
+
+BandSets band_sets(const ssrpa_system_desc *d) {
+  BandSets b;
+  const int n_b = d->n_v + d->n_c;
+  const double *e = d->energy;
+  for (int i = 0; i < n_b; ++i)
+    SSRPA_REQUIRE(std::isfinite(e[i]), SSRPA_ERR_ARG, "non-finite energy");
+  if (!d->occupation) {
+    double vmax = -INFINITY, cmin = INFINITY;
+    for (int i = 0; i < d->n_v; ++i) vmax = std::max(vmax, e[i]);
+    for (int i = d->n_v; i < n_b; ++i) cmin = std::min(cmin, e[i]);
+    SSRPA_REQUIRE(cmin > vmax, SSRPA_ERR_ARG,
+                  "every conduction energy must lie above every valence energy");
+    b.n_val = d->n_v;
+    b.c_first = d->n_v;
+    b.n_cond = d->n_c;
+    return b;
+  }
+  // partial occupations (Eqs. 4-6): f in [0, 1], non-increasing along the
+  // bands, energies non-decreasing, equal energies only with equal f
+  const double *f = d->occupation;
+  int n_pos = 0, n_full = 0;
+  for (int i = 0; i < n_b; ++i) {
+    SSRPA_REQUIRE(std::isfinite(f[i]) && f[i] >= 0.0 && f[i] <= 1.0,
+                  SSRPA_ERR_ARG, "occupation %d = %g outside [0, 1]", i, f[i]);
+    if (i > 0) {
+      SSRPA_REQUIRE(f[i] <= f[i - 1], SSRPA_ERR_ARG,
+                    "occupations must not increase along the bands (band %d)", i);
+      SSRPA_REQUIRE(e[i] >= e[i - 1], SSRPA_ERR_ARG,
+                    "energies must be ascending with occupations (band %d)", i);
+      SSRPA_REQUIRE(e[i] > e[i - 1] || f[i] == f[i - 1], SSRPA_ERR_ARG,
+                    "bands %d and %d have equal energies but different "
+                    "occupations", i - 1, i);
+    }
+    n_pos += f[i] > 0.0;
+    n_full += f[i] == 1.0;
+  }
+  SSRPA_REQUIRE(n_pos == d->n_v, SSRPA_ERR_ARG,
+                "n_v = %d but %d bands have a positive occupation", d->n_v, n_pos);
+  SSRPA_REQUIRE(n_full < n_b, SSRPA_ERR_ARG, "no band with occupation below 1");
+  b.n_val = n_pos;
+  b.c_first = n_full;
+  b.n_cond = n_b - n_full;
+  b.partial = n_pos > n_full;
+  return b;
+}
+
+namespace {
+
 struct Footprint {
   size_t resident, block, subspace, freq, eig, total;
 };
@@ -310,21 +458,22 @@ struct Footprint {
 Footprint footprint_of(const ssrpa_system_desc *d, const Geometry &g, int n_eig,
                        int n_freq, int vb, ssrpa_precision prec) {
   Footprint f{};
+  const BandSets bs = band_sets(d);
   const size_t nb = (size_t)d->n_v + d->n_c;
   const size_t box = (size_t)g.n1 * g.n2 * g.n3;
   const size_t ng = g.n_g, ldg = g.ld_g;
   const bool full = n_eig >= g.n_g;
   const size_t ne = full ? ng : (size_t)n_eig;
   const size_t lde = full ? ldg : (size_t)round_up(n_eig, 64);
-  const size_t pairs = (size_t)vb * d->n_c;
+  const size_t pairs = (size_t)vb * bs.n_cond;
   // orbitals on the grid, chi0, per-G tables, and the coefficient copy that
   // lives while the orbitals are staged
   f.resident = bytes_c(nb * box) + bytes_c(ng * ng) + 64 * ldg +
                bytes_c(nb * (size_t)d->n_pw);
-  f.block = pairs * (2 * ldg * 8 + 8);
+  f.block = pairs * (2 * ldg * 8 + 8 + (bs.partial ? 8 : 0));
   if (staged_grid(g)) {
     const size_t ypp = stage_bytes_per_pair(g);
-    f.block += (size_t)vb * stage_chunk_c(vb, d->n_c, ypp) * ypp;
+    f.block += (size_t)vb * stage_chunk_c(vb, bs.n_cond, ypp) * ypp;
   }
   f.subspace = full ? 0 : pairs * 2 * lde * 8 + bytes_c(ldg * lde);
   // FP64 split-K partial tiles: the frequency contraction, the
@@ -452,16 +601,48 @@ int resolve_block(System &sys, int requested, int n_eig, int n_freq) {
 }
 
 // Pair matrix of one block (cached when one block covers all valence bands).
+// Packed pair rows of the real path: F = M_v,c1 + i M_v,c2 for the
+// conduction pairs (c1, c2) packed into one orbital (planar complex rows).
+void packed_pairs(System &sys, int v0, int nvb, bool scaled, DevBuf &f,
+                  hipStream_t s) {
+  f.ensure(sys.ctx, (size_t)nvb * sys.orb_nc * 2 * sys.geo.ld_g * sizeof(double), s);
+  launch_pair_matrix(sys, v0, nvb, scaled, f.as<double>(), s);
+}
+
+// Pair rows of one block: complex planar rows (2 ld_g doubles), or in the
+// real path real rows of ld_g doubles in the cos/sin basis.
 const double *block_pairs(System &sys, int v0, int nvb, DevBuf &scratch,
                           hipStream_t s) {
   const bool single = (v0 == 0 && nvb == sys.n_v);
-  const size_t bytes = (size_t)nvb * sys.n_c * 2 * sys.geo.ld_g * sizeof(double);
+  const size_t bytes = (size_t)nvb * sys.n_c * (sys.real ? 1 : 2) *
+                       sys.geo.ld_g * sizeof(double);
   if (single && sys.w_cache_valid) return sys.w_cache.as<double>();
   DevBuf &dst = single ? sys.w_cache : scratch;
   dst.ensure(sys.ctx, bytes, s);
   {
     StageScope sc(sys.timer, SSRPA_STAGE_PAIR_FFT, s);
-    launch_pair_matrix(sys, v0, nvb, true, dst.as<double>(), s);
+    const Geometry &g = sys.geo;
+    if (sys.real) {
+      DevBuf f;
+      packed_pairs(sys, v0, nvb, true, f, s);
+      const int *t = sys.rtab.as<int>();
+      unpack_real_rows(f.as<double>(), nvb, sys.n_c, g.ld_g, g.nh, t, t + g.nh,
+                       dst.as<double>(), s);
+    } else {
+      launch_pair_matrix(sys, v0, nvb, true, dst.as<double>(), s);
+    }
+    if (sys.partial) {
+      // rows carry (f_v - f_c)^1/2: every contraction of the block then
+      // weighs pair p with (f_v - f_c) Delta_p (Eq. 5 with occupations)
+      const long rows = (long)nvb * sys.n_c;
+      sys.rowscale.ensure(sys.ctx, sizeof(double) * rows, s);
+      pair_energy_diffs(sys.energy_d.as<double>(), sys.occ_d.as<double>(),
+                        sys.c_first, v0, nvb, sys.n_c, nullptr,
+                        sys.rowscale.as<double>(), s);
+      // a real row of ld_g doubles is a "planar" row of half that width
+      scale_rows(dst.as<double>(), rows, sys.real ? g.ld_g / 2 : g.ld_g,
+                 sys.rowscale.as<double>(), s);
+    }
   }
   if (single) sys.w_cache_valid = true;
   return dst.as<double>();
@@ -479,8 +660,9 @@ void static_chi0(System &sys, ssrpa_precision prec, int vb, hipStream_t s) {
     const int nvb = std::min(vb, sys.n_v - v0);
     const double *w = block_pairs(sys, v0, nvb, scratch, s);
     de.ensure(ctx, sizeof(double) * (size_t)nvb * sys.n_c, s);
-    pair_energy_diffs(sys.energy_d.as<double>(), sys.n_v, v0, nvb, sys.n_c,
-                      de.as<double>(), s);
+    pair_energy_diffs(sys.energy_d.as<double>(),
+                      sys.partial ? sys.occ_d.as<double>() : nullptr,
+                      sys.c_first, v0, nvb, sys.n_c, de.as<double>(), nullptr, s);
     HerkArgs h{};
     h.a = w;
     h.lda = 2L * g.ld_g;
@@ -494,7 +676,13 @@ void static_chi0(System &sys, ssrpa_precision prec, int vb, hipStream_t s) {
     h.wscale = 1.0 / g.volume;
     h.timer = &sys.timer;
     h.stage = SSRPA_STAGE_CHI0_HERK;
-    herk(ctx, h, prec, sys.chibar0.as<double>(), 0, v0 > 0 ? 1 : 0, ws, s);
+    if (sys.real) {
+      h.lda = g.ld_g;
+      h.im_off = 0;
+      syrk(ctx, h, sys.chibar0.as<double>(), 0, v0 > 0 ? 1 : 0, ws, s);
+    } else {
+      herk(ctx, h, prec, sys.chibar0.as<double>(), 0, v0 > 0 ? 1 : 0, ws, s);
+    }
     block_done("static chi0", v0, nvb, sys.n_v, s);
   }
   SSRPA_HIP(hipStreamSynchronize(s));
@@ -502,21 +690,85 @@ void static_chi0(System &sys, ssrpa_precision prec, int vb, hipStream_t s) {
   sys.sub = Subspace();
 }
 
-void compute_subspace(System &sys, int n_eig, hipStream_t s) {
+void compute_subspace(System &sys, int n_eig, int kind, hipStream_t s) {
   Context *ctx = sys.ctx;
   const Geometry &g = sys.geo;
   SSRPA_REQUIRE(sys.have_chi0, SSRPA_ERR_STATE,
                 "ssrpa_chi0_static must run before ssrpa_subspace");
   SSRPA_REQUIRE(n_eig >= 1 && n_eig <= g.n_g, SSRPA_ERR_ARG,
                 "n_eig=%d outside [1, %d]", n_eig, g.n_g);
+  SSRPA_REQUIRE(kind == SSRPA_BASIS_SYMMETRIZED || kind == SSRPA_BASIS_CHI0,
+                SSRPA_ERR_ARG, "unknown basis kind %d", kind);
   Subspace sub;
   sub.n_eig = n_eig;
-  sub.ld_e = round_up(n_eig, 64);
+  sub.kind = kind;
+  // the real path contracts with 128-wide tiles
+  sub.ld_e = round_up(n_eig, sys.real ? 128 : 64);
   sub.basis = DevBuf(ctx, sizeof(double) * 2 * (size_t)g.ld_g * sub.ld_e);
   DevBuf ev(ctx, sizeof(double) * n_eig);
   StageScope sc(sys.timer, SSRPA_STAGE_EIGEN, s);
-  eig_lowest(ctx, sys.chibar0.as<double>(), g.n_g, n_eig, ev.as<double>(),
-             sub.basis.as<double>(), sub.ld_e, sys.dev_flag.as<int>(), s);
+  // s(G) and r(G) in the order of the basis the static matrix is held in
+  const double *tab = sys.real ? sys.rscale.as<double>()
+                               : sys.sqrtv_d.as<double>() + 2 * (size_t)g.ld_g;
+  const double *rs = tab + g.n_g;
+  DevBuf tmp;
+  const double *a = sys.chibar0.as<double>();
+  if (kind == SSRPA_BASIS_CHI0 || g.rescaled) {
+    tmp = DevBuf(ctx, bytes_c((size_t)g.n_g * g.n_g));
+    copy_interleaved(a, tmp.as<double>(), (size_t)g.n_g * g.n_g, s);
+    if (kind == SSRPA_BASIS_CHI0)
+      scale_sym(tmp.as<double>(), g.n_g, tab, 1, s);   // chi0 = S^-1 (.) S^-1
+    else
+      scale_sym(tmp.as<double>(), g.n_g, rs, 0, s);    // R (.) R
+    a = tmp.as<double>();
+  }
+  eig_lowest(ctx, a, g.n_g, n_eig, ev.as<double>(), sub.basis.as<double>(),
+             sub.ld_e, sys.dev_flag.as<int>(), s);
+  tmp.reset();
+  if (kind == SSRPA_BASIS_SYMMETRIZED && g.rescaled) {
+    // the projection multiplies the stored rows: W C_s = W_stored (R C_s)
+    sub.basis_r = DevBuf(ctx, sub.basis.bytes());
+    copy_interleaved(sub.basis.as<double>(), sub.basis_r.as<double>(),
+                     sub.basis.bytes() / 16, s);
+    scale_rows(sub.basis_r.as<double>(), g.n_g, sub.ld_e, rs, s);
+  }
+  if (kind == SSRPA_BASIS_CHI0) {
+    // v_s = C_s^H v C_s = (V^1/2 C_s)^H (V^1/2 C_s), V^1/2 = S R
+    const int le = sub.ld_e;
+    DevBuf av(ctx, sub.basis.bytes());
+    copy_interleaved(sub.basis.as<double>(), av.as<double>(), sub.basis.bytes() / 16, s);
+    scale_rows(av.as<double>(), g.n_g, le, tab, s);
+    scale_rows(av.as<double>(), g.n_g, le, rs, s);
+    DevBuf vs(ctx, bytes_c((size_t)n_eig * n_eig)), ws;
+    HerkArgs h{};
+    h.a = av.as<double>();
+    h.lda = 2L * le;
+    h.im_off = le;
+    h.ncol = n_eig;
+    h.ld = le;
+    h.k = g.n_g;
+    h.n_omega = 1;
+    h.unit_weight = 1;
+    herk(ctx, h, SSRPA_FP64, vs.as<double>(), 0, 0, ws, s);
+    // v_s = U diag(l) U^H, Z = U diag(l^1/2): every eigenpair of v_s
+    DevBuf lam(ctx, sizeof(double) * n_eig);
+    DevBuf z(ctx, sizeof(double) * 2 * (size_t)le * le);
+    eig_lowest(ctx, vs.as<double>(), n_eig, n_eig, lam.as<double>(),
+               z.as<double>(), le, sys.dev_flag.as<int>(), s);
+    scale_cols(z.as<double>(), le, le, n_eig, lam.as<double>(), 1, s);
+    // B = S^-1 C_s Z, the operand that turns the stored rows into M C_s Z
+    sub.proj = DevBuf(ctx, sub.basis.bytes());
+    GemmArgs gm{};
+    gm.a = sub.basis.as<double>(); gm.lda = 2L * le; gm.a_im = le;
+    gm.b = z.as<double>(); gm.ldb = 2L * le; gm.b_im = le;
+    gm.c = sub.proj.as<double>(); gm.ldc = 2L * le; gm.c_im = le;
+    gm.m = g.ld_g; gm.n = le; gm.k = le;
+    gm.alpha = 1.0; gm.beta = 0.0;
+    DevBuf gws;
+    gemm(ctx, gm, SSRPA_FP64, gws, s);
+    scale_rows(sub.proj.as<double>(), g.n_g, le, tab, s, true);
+    SSRPA_HIP(hipStreamSynchronize(s));  // work buffers are freed on return
+  }
   sub.eigval.resize(n_eig);
   SSRPA_HIP(hipMemcpyAsync(sub.eigval.data(), ev.as(), sizeof(double) * n_eig,
                            hipMemcpyDeviceToHost, s));
@@ -568,27 +820,36 @@ EcResult energy(System &sys, int n_eig, int n_freq, const double *omega,
     const long rows = (long)nvb * sys.n_c;
     const double *w = block_pairs(sys, v0, nvb, scratch, s);
     de.ensure(ctx, sizeof(double) * rows, s);
-    pair_energy_diffs(sys.energy_d.as<double>(), sys.n_v, v0, nvb, sys.n_c,
-                      de.as<double>(), s);
+    pair_energy_diffs(sys.energy_d.as<double>(),
+                      sys.partial ? sys.occ_d.as<double>() : nullptr,
+                      sys.c_first, v0, nvb, sys.n_c, de.as<double>(), nullptr, s);
     HerkArgs h{};
+    const long wcols = sys.real ? 1 : 2;   // real rows hold no imaginary plane
     if (full) {
       h.a = w;
-      h.lda = 2L * g.ld_g;
-      h.im_off = g.ld_g;
+      h.lda = wcols * g.ld_g;
+      h.im_off = sys.real ? 0 : g.ld_g;
     } else {
       // W_s = W C_s  (Eq. 7)
-      wsub.ensure(ctx, sizeof(double) * 2 * (size_t)rows * ld, s);
-      GemmArgs gm{};
-      gm.a = w; gm.lda = 2L * g.ld_g; gm.a_im = g.ld_g;
-      gm.b = sys.sub.basis.as<double>(); gm.ldb = 2L * ld; gm.b_im = ld;
-      gm.c = wsub.as<double>(); gm.ldc = 2L * ld; gm.c_im = ld;
-      gm.m = rows; gm.n = ld; gm.k = g.ld_g;
-      gm.alpha = 1.0; gm.beta = 0.0;
+      wsub.ensure(ctx, sizeof(double) * wcols * (size_t)rows * ld, s);
       StageScope sc(sys.timer, SSRPA_STAGE_PROJECTION, s);
-      gemm(ctx, gm, prec, gws, s);
+      if (sys.real) {
+        // real basis vectors: the real plane of the stored operand
+        gemm_real(w, g.ld_g, sys.sub.projection(), 2L * ld, wsub.as<double>(),
+                  ld, rows, g.ld_g, ld, s);
+      } else {
+        GemmArgs gm{};
+        gm.a = w; gm.lda = 2L * g.ld_g; gm.a_im = g.ld_g;
+        gm.b = sys.sub.projection();
+        gm.ldb = 2L * ld; gm.b_im = ld;
+        gm.c = wsub.as<double>(); gm.ldc = 2L * ld; gm.c_im = ld;
+        gm.m = rows; gm.n = ld; gm.k = g.ld_g;
+        gm.alpha = 1.0; gm.beta = 0.0;
+        gemm(ctx, gm, prec, gws, s);
+      }
       h.a = wsub.as<double>();
-      h.lda = 2L * ld;
-      h.im_off = ld;
+      h.lda = wcols * ld;
+      h.im_off = sys.real ? 0 : ld;
     }
     h.ncol = n;
     h.ld = ld;
@@ -599,8 +860,18 @@ EcResult energy(System &sys, int n_eig, int n_freq, const double *omega,
     h.wscale = 1.0 / g.volume;
     h.timer = &sys.timer;
     h.stage = SSRPA_STAGE_FREQ_HERK;
-    herk(ctx, h, prec, chis, 2L * n * n, v0 > 0 ? 1 : 0, ws, s);
+    if (sys.real)
+      syrk(ctx, h, chis, 2L * n * n, v0 > 0 ? 1 : 0, ws, s);
+    else
+      herk(ctx, h, prec, chis, 2L * n * n, v0 > 0 ? 1 : 0, ws, s);
     block_done("subspace chi0(iw)", v0, nvb, sys.n_v, s);
+  }
+  if (full && g.rescaled) {
+    // full basis: v^1/2 chi0(i w) v^1/2 = R (stored matrix) R
+    const double *rs = sys.real ? sys.rscale.as<double>() + g.n_g
+                                : sys.sqrtv_d.as<double>() + 2 * (size_t)g.ld_g + g.n_g;
+    for (int j = 0; j < n_freq; ++j)
+      scale_sym(chis + 2L * n * n * j, n, rs, 0, s);
   }
   fill_zero(sys.dev_flag.as(), sizeof(int), s);
   {
@@ -756,14 +1027,8 @@ ssrpa_status ssrpa_system_create(ssrpa_context *ctx, const ssrpa_system_desc *de
     // every host-side check and table comes first: no device work is queued
     // before the description has been accepted
     const int n_b = desc->n_v + desc->n_c;
+    const BandSets bs = band_sets(desc);
     std::vector<double> energy(desc->energy, desc->energy + n_b);
-    for (int i = 0; i < n_b; ++i)
-      SSRPA_REQUIRE(std::isfinite(energy[i]), SSRPA_ERR_ARG, "non-finite energy");
-    double vmax = -INFINITY, cmin = INFINITY;
-    for (int i = 0; i < desc->n_v; ++i) vmax = std::max(vmax, energy[i]);
-    for (int i = desc->n_v; i < n_b; ++i) cmin = std::min(cmin, energy[i]);
-    SSRPA_REQUIRE(cmin > vmax, SSRPA_ERR_ARG,
-                  "every conduction energy must lie above every valence energy");
     const size_t box = (size_t)g.n1 * g.n2 * g.n3;
     std::vector<int> bidx(desc->n_pw);
     for (int p = 0; p < desc->n_pw; ++p) {
@@ -779,6 +1044,22 @@ ssrpa_status ssrpa_system_create(ssrpa_context *ctx, const ssrpa_system_desc *de
         seen[bidx[p]] = 1;
       }
     }
+    // real orbitals: the plane-wave set holds -G with every G
+    std::vector<int> negpw;
+    if (g.real) {
+      SSRPA_REQUIRE(bs.n_cond >= 1, SSRPA_ERR_ARG, "no conduction band");
+      std::vector<int> at(box, -1);
+      for (int p = 0; p < desc->n_pw; ++p) at[bidx[p]] = p;
+      negpw.resize(desc->n_pw);
+      for (int p = 0; p < desc->n_pw; ++p) {
+        const int a = ((-desc->miller[3 * p] % g.n1) + g.n1) % g.n1;
+        const int b = ((-desc->miller[3 * p + 1] % g.n2) + g.n2) % g.n2;
+        const int c = ((-desc->miller[3 * p + 2] % g.n3) + g.n3) % g.n3;
+        negpw[p] = at[(c * g.n2 + b) * g.n1 + a];
+        SSRPA_REQUIRE(negpw[p] >= 0, SSRPA_ERR_ARG,
+                      "real orbitals: plane wave %d has no partner -G", p);
+      }
+    }
     // per-G tables
     std::vector<int> code(g.n_g);
     std::vector<double> scale(2 * (size_t)g.ld_g, 0.0);
@@ -789,7 +1070,7 @@ ssrpa_status ssrpa_system_create(ssrpa_context *ctx, const ssrpa_system_desc *de
       const int col = (a + g.m1) * g.n2 + ((b % g.n2) + g.n2) % g.n2;
       const int k3 = ((c % g.n3) + g.n3) % g.n3;
       code[i] = col | (k3 << 20);
-      scale[i] = on * g.sqrt_v[i];
+      scale[i] = on * g.store_scale[i];
       scale[g.ld_g + i] = on;
     }
     // from here on device work is queued on s: a failure waits for it
@@ -798,8 +1079,14 @@ ssrpa_status ssrpa_system_create(ssrpa_context *ctx, const ssrpa_system_desc *de
     sys = new ssrpa_system();
     sys->ctx = ctx;
     sys->geo = std::move(g);
-    sys->n_v = desc->n_v;
-    sys->n_c = desc->n_c;
+    sys->n_v = bs.n_val;
+    sys->n_c = bs.n_cond;
+    sys->c_first = bs.c_first;
+    sys->partial = bs.partial;
+    sys->real = sys->geo.real;
+    sys->n_orb = sys->real ? bs.n_val + (bs.n_cond + 1) / 2 : n_b;
+    sys->orb_c0 = sys->real ? bs.n_val : bs.c_first;
+    sys->orb_nc = sys->real ? (bs.n_cond + 1) / 2 : bs.n_cond;
     sys->n_b = n_b;
     sys->n_pw = desc->n_pw;
     sys->energy = std::move(energy);
@@ -807,16 +1094,25 @@ ssrpa_status ssrpa_system_create(ssrpa_context *ctx, const ssrpa_system_desc *de
     sys->energy_d = DevBuf(ctx, sizeof(double) * sys->n_b);
     SSRPA_HIP(hipMemcpyAsync(sys->energy_d.as(), sys->energy.data(),
                              sizeof(double) * sys->n_b, hipMemcpyHostToDevice, s));
+    if (bs.partial) {
+      sys->occ.assign(desc->occupation, desc->occupation + n_b);
+      sys->occ_d = DevBuf(ctx, sizeof(double) * sys->n_b);
+      SSRPA_HIP(hipMemcpyAsync(sys->occ_d.as(), sys->occ.data(),
+                               sizeof(double) * sys->n_b, hipMemcpyHostToDevice, s));
+    }
     sys->gcol = DevBuf(ctx, sizeof(int) * gg.n_g);
-    sys->sqrtv_d = DevBuf(ctx, sizeof(double) * 2 * (size_t)gg.ld_g + sizeof(double) * gg.n_g);
+    sys->sqrtv_d = DevBuf(ctx, sizeof(double) * 2 * ((size_t)gg.ld_g + gg.n_g));
     SSRPA_HIP(hipMemcpyAsync(sys->gcol.as(), code.data(), sizeof(int) * gg.n_g,
                              hipMemcpyHostToDevice, s));
     SSRPA_HIP(hipMemcpyAsync(sys->sqrtv_d.as(), scale.data(),
                              sizeof(double) * 2 * (size_t)gg.ld_g,
                              hipMemcpyHostToDevice, s));
-    // plain v^1/2 after the two scale tables (for chi0 <-> symmetrized)
+    // s(G) and r(G) after the two scale tables (chi0 <-> symmetrized)
     SSRPA_HIP(hipMemcpyAsync(sys->sqrtv_d.as<double>() + 2 * (size_t)gg.ld_g,
-                             gg.sqrt_v.data(), sizeof(double) * gg.n_g,
+                             gg.store_scale.data(), sizeof(double) * gg.n_g,
+                             hipMemcpyHostToDevice, s));
+    SSRPA_HIP(hipMemcpyAsync(sys->sqrtv_d.as<double>() + 2 * (size_t)gg.ld_g + gg.n_g,
+                             gg.rescale.data(), sizeof(double) * gg.n_g,
                              hipMemcpyHostToDevice, s));
     sys->zcode = DevBuf(ctx, sizeof(int) * gg.n_g);
     sys->cmap = DevBuf(ctx, sizeof(int) * gg.cmap.size());
@@ -843,7 +1139,50 @@ ssrpa_status ssrpa_system_create(ssrpa_context *ctx, const ssrpa_system_desc *de
                                hipMemcpyHostToDevice, s));
       cptr = coeff_d.as<double>();
     }
-    sys->psi_r = DevBuf(ctx, bytes_c(box * sys->n_b));
+    DevBuf packed;
+    if (gg.real) {
+      // check c(-G) = conj c(G) on the device, then pack two conduction
+      // orbitals per complex orbital before the orbital FFT
+      DevBuf chk(ctx, sizeof(int) * sys->n_pw + sizeof(double) * real_check_blocks());
+      int *negd = chk.as<int>();
+      double *bmax = reinterpret_cast<double *>(chk.as<char>() + sizeof(int) * sys->n_pw);
+      SSRPA_HIP(hipMemcpyAsync(negd, negpw.data(), sizeof(int) * sys->n_pw,
+                               hipMemcpyHostToDevice, s));
+      real_check(cptr, sys->n_pw, sys->n_b, negd, bmax, s);
+      std::vector<double> hb(real_check_blocks());
+      SSRPA_HIP(hipMemcpyAsync(hb.data(), bmax, sizeof(double) * hb.size(),
+                               hipMemcpyDeviceToHost, s));
+      SSRPA_HIP(hipStreamSynchronize(s));
+      double worst = 0.0;
+      for (double x : hb) worst = std::max(worst, x);
+      SSRPA_REQUIRE(worst <= 1e-10, SSRPA_ERR_ARG,
+                    "real_orbitals = 1 but |c(-G) - conj c(G)| reaches %g", worst);
+      packed = DevBuf(ctx, sizeof(double) * 2 * (size_t)sys->n_pw * sys->n_orb);
+      pack_coefficients(cptr, sys->n_pw, sys->n_v, sys->c_first, sys->n_b,
+                        sys->orb_nc, packed.as<double>(), s);
+      cptr = packed.as<double>();
+      // cos/sin basis tables
+      std::vector<int> t;
+      t.insert(t.end(), gg.hpos.begin(), gg.hpos.end());
+      t.insert(t.end(), gg.hneg.begin(), gg.hneg.end());
+      t.insert(t.end(), gg.neg.begin(), gg.neg.end());
+      t.insert(t.end(), gg.hj.begin(), gg.hj.end());
+      t.insert(t.end(), gg.hs.begin(), gg.hs.end());
+      sys->rtab = DevBuf(ctx, sizeof(int) * t.size());
+      SSRPA_HIP(hipMemcpyAsync(sys->rtab.as(), t.data(), sizeof(int) * t.size(),
+                               hipMemcpyHostToDevice, s));
+      std::vector<double> rsc(2 * (size_t)gg.n_g);
+      for (int j = 0; j < gg.n_g; ++j) {
+        const int gpos = gg.hpos[j < gg.nh ? j : j - gg.nh];
+        rsc[j] = gg.store_scale[gpos];
+        rsc[gg.n_g + j] = gg.rescale[gpos];
+      }
+      sys->rscale = DevBuf(ctx, sizeof(double) * rsc.size());
+      SSRPA_HIP(hipMemcpyAsync(sys->rscale.as(), rsc.data(), sizeof(double) * rsc.size(),
+                               hipMemcpyHostToDevice, s));
+      SSRPA_HIP(hipStreamSynchronize(s));  // rsc and t are freed on return
+    }
+    sys->psi_r = DevBuf(ctx, bytes_c(box * sys->n_orb));
     launch_orbital_fft(*sys, cptr, bidx_d.as<int>(), s);
     SSRPA_HIP(hipStreamSynchronize(s));
   });
@@ -876,6 +1215,15 @@ ssrpa_status ssrpa_system_destroy(ssrpa_system *sys) {
   return SSRPA_OK;
 }
 
+ssrpa_status ssrpa_system_bands(const ssrpa_system *sys, int *n_val,
+                                int *c_first, int *n_cond) {
+  if (!sys) return SSRPA_ERR_ARG;
+  if (n_val) *n_val = sys->n_v;
+  if (c_first) *c_first = sys->c_first;
+  if (n_cond) *n_cond = sys->n_c;
+  return SSRPA_OK;
+}
+
 ssrpa_status ssrpa_chi_gvectors(const ssrpa_system *sys, int *n_g,
                                 int32_t *miller) {
   if (!sys || !n_g) return SSRPA_ERR_ARG;
@@ -892,8 +1240,12 @@ ssrpa_status ssrpa_orbitals_realspace(ssrpa_system *sys, double *psi,
     set_device(sys->ctx);
     hipStream_t s = Stream(hip_stream).s;
     ApiCall call(s);
-    const size_t n = (size_t)sys->geo.n1 * sys->geo.n2 * sys->geo.n3 * sys->n_b;
-    copy_interleaved(sys->psi_r.as<double>(), psi, n, s);
+    const size_t box = (size_t)sys->geo.n1 * sys->geo.n2 * sys->geo.n3;
+    if (sys->real)
+      unpack_orbitals(sys->psi_r.as<double>(), (long)box, sys->n_v, sys->c_first,
+                      sys->n_b, psi, s);
+    else
+      copy_interleaved(sys->psi_r.as<double>(), psi, box * sys->n_b, s);
     SSRPA_HIP(hipStreamSynchronize(s));
   });
 }
@@ -910,7 +1262,14 @@ ssrpa_status ssrpa_pair_matrix(ssrpa_system *sys, int v0, int n_vb, int scaled,
     const Geometry &g = sys->geo;
     const long rows = (long)n_vb * sys->n_c;
     DevBuf w(sys->ctx, sizeof(double) * 2 * (size_t)rows * g.ld_g);
-    launch_pair_matrix(*sys, v0, n_vb, scaled != 0, w.as<double>(), s);
+    if (sys->real) {
+      DevBuf f;
+      packed_pairs(*sys, v0, n_vb, scaled != 0, f, s);
+      unpack_pw_rows(f.as<double>(), n_vb, sys->n_c, g.ld_g, g.n_g,
+                     sys->rtab.as<int>() + 2 * g.nh, w.as<double>(), s);
+    } else {
+      launch_pair_matrix(*sys, v0, n_vb, scaled != 0, w.as<double>(), s);
+    }
     planar_to_interleaved(w.as<double>(), (int)rows, g.n_g, g.ld_g, m, s);
     SSRPA_HIP(hipStreamSynchronize(s));
   });
@@ -925,6 +1284,8 @@ ssrpa_status ssrpa_chi0_static(ssrpa_system *sys, ssrpa_precision precision,
     SSRPA_REQUIRE(precision >= SSRPA_FP64 && precision <= SSRPA_BF16X3,
                   SSRPA_ERR_ARG, "unknown precision %d", (int)precision);
     SSRPA_REQUIRE(valence_block >= 0, SSRPA_ERR_ARG, "negative valence block");
+    SSRPA_REQUIRE(!sys->real || precision == SSRPA_FP64, SSRPA_ERR_ARG,
+                  "real-orbital systems contract in FP64 only");
     hipStream_t s = Stream(hip_stream).s;
     ApiCall call(s);
     const int vb = resolve_block(*sys, valence_block, 0, 1);
@@ -935,9 +1296,20 @@ ssrpa_status ssrpa_chi0_static(ssrpa_system *sys, ssrpa_precision precision,
     static_chi0(*sys, precision, vb, s);
     if (chi0) {
       const Geometry &g = sys->geo;
-      copy_interleaved(sys->chibar0.as<double>(), chi0, (size_t)g.n_g * g.n_g, s);
+      // the resident matrix is S chi0 S (S = diag s(G)), in the cos/sin
+      // basis on the real path
+      if (sys->real) {
+        const int *t = sys->rtab.as<int>();
+        real_to_pw_sym(sys->chibar0.as<double>(), g.n_g, g.nh, t + 2 * g.nh + g.n_g,
+                       t + 2 * g.nh + 2 * g.n_g, chi0, s);
+      } else {
+        copy_interleaved(sys->chibar0.as<double>(), chi0, (size_t)g.n_g * g.n_g, s);
+      }
+      const double *tab = sys->sqrtv_d.as<double>() + 2 * (size_t)g.ld_g;
       if (!symmetrized)
-        scale_sym(chi0, g.n_g, sys->sqrtv_d.as<double>() + 2 * (size_t)g.ld_g, 1, s);
+        scale_sym(chi0, g.n_g, tab, 1, s);
+      else if (g.rescaled)
+        scale_sym(chi0, g.n_g, tab + g.n_g, 0, s);
       SSRPA_HIP(hipStreamSynchronize(s));
     }
   });
@@ -945,16 +1317,31 @@ ssrpa_status ssrpa_chi0_static(ssrpa_system *sys, ssrpa_precision precision,
 
 ssrpa_status ssrpa_subspace(ssrpa_system *sys, int n_eig, double *eigval,
                             double *basis, void *hip_stream) {
+  return ssrpa_subspace_basis(sys, SSRPA_BASIS_SYMMETRIZED, n_eig, eigval,
+                              basis, hip_stream);
+}
+
+ssrpa_status ssrpa_subspace_basis(ssrpa_system *sys, ssrpa_basis kind,
+                                  int n_eig, double *eigval, double *basis,
+                                  void *hip_stream) {
   if (!sys) return SSRPA_ERR_ARG;
   return guarded(sys->ctx, [&] {
     set_device(sys->ctx);
     hipStream_t s = Stream(hip_stream).s;
     ApiCall call(s);
-    compute_subspace(*sys, n_eig, s);
+    compute_subspace(*sys, n_eig, (int)kind, s);
     if (eigval) std::memcpy(eigval, sys->sub.eigval.data(), sizeof(double) * n_eig);
     if (basis) {
-      planar_to_interleaved(sys->sub.basis.as<double>(), sys->geo.n_g, n_eig,
-                            sys->sub.ld_e, basis, s);
+      const Geometry &g = sys->geo;
+      if (sys->real) {
+        const int *t = sys->rtab.as<int>();
+        real_basis_to_pw(sys->sub.basis.as<double>(), sys->sub.ld_e, g.n_g, n_eig,
+                         g.nh, t + 2 * g.nh + g.n_g, t + 2 * g.nh + 2 * g.n_g,
+                         basis, s);
+      } else {
+        planar_to_interleaved(sys->sub.basis.as<double>(), g.n_g, n_eig,
+                              sys->sub.ld_e, basis, s);
+      }
       SSRPA_HIP(hipStreamSynchronize(s));
     }
   });
@@ -973,6 +1360,8 @@ ssrpa_status ssrpa_correlation_energy(ssrpa_system *sys, int n_eig, int n_freq,
                   SSRPA_ERR_ARG, "unknown precision %d", (int)precision);
     SSRPA_REQUIRE(n_eig >= 1, SSRPA_ERR_ARG, "n_eig must be >= 1");
     SSRPA_REQUIRE(std::isfinite(coupling), SSRPA_ERR_ARG, "bad coupling");
+    SSRPA_REQUIRE(!sys->real || precision == SSRPA_FP64, SSRPA_ERR_ARG,
+                  "real-orbital systems contract in FP64 only");
     hipStream_t s = Stream(hip_stream).s;
     ApiCall call(s);
     const int vb = resolve_block(*sys, valence_block, n_eig, n_freq);
@@ -984,6 +1373,44 @@ ssrpa_status ssrpa_correlation_energy(ssrpa_system *sys, int n_eig, int n_freq,
                         coupling, chi_sub, s);
     *ec = r.ec;
     if (integrand) std::memcpy(integrand, r.f.data(), sizeof(double) * n_freq);
+  });
+}
+
+ssrpa_status ssrpa_epsilon_inverse(ssrpa_system *sys, int n_eig, int n_freq,
+                                   const double *omega,
+                                   ssrpa_precision precision, int valence_block,
+                                   double *eps_inv, void *hip_stream) {
+  if (!sys || !eps_inv || !omega) return SSRPA_ERR_ARG;
+  return guarded(sys->ctx, [&] {
+    set_device(sys->ctx);
+    SSRPA_REQUIRE(precision >= SSRPA_FP64 && precision <= SSRPA_BF16X3,
+                  SSRPA_ERR_ARG, "unknown precision %d", (int)precision);
+    SSRPA_REQUIRE(n_eig >= 1 && n_freq >= 1, SSRPA_ERR_ARG, "bad sizes");
+    SSRPA_REQUIRE(!sys->real || precision == SSRPA_FP64, SSRPA_ERR_ARG,
+                  "real-orbital systems contract in FP64 only");
+    hipStream_t s = Stream(hip_stream).s;
+    ApiCall call(s);
+    const int vb = resolve_block(*sys, valence_block, n_eig, n_freq);
+    if (vb < sys->n_v) {
+      sys->w_cache.reset();
+      sys->w_cache_valid = false;
+    }
+    // X_j in the subspace (or the full basis), then (I - X_j)^-1 in place;
+    // the quadrature weights do not matter here
+    const int n = std::min(n_eig, sys->geo.n_g);
+    std::vector<double> zero(n_freq, 0.0);
+    DevBuf x(sys->ctx, bytes_c((size_t)n * n * n_freq));
+    (void)energy(*sys, n_eig, n_freq, omega, zero.data(), precision, vb, 1.0,
+                 x.as<double>(), s);
+    fill_zero(sys->dev_flag.as(), sizeof(int), s);
+    inverse_one_minus(sys->ctx, x.as<double>(), n, n_freq, 1.0, eps_inv,
+                      sys->dev_flag.as<int>(), s);
+    int flag = 0;
+    SSRPA_HIP(hipMemcpyAsync(&flag, sys->dev_flag.as(), sizeof(int),
+                             hipMemcpyDeviceToHost, s));
+    SSRPA_HIP(hipStreamSynchronize(s));
+    SSRPA_REQUIRE(flag == 0, SSRPA_ERR_NUMERIC,
+                  "1 - chi0_s v is not positive definite at some frequency");
   });
 }
 

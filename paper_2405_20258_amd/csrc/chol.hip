@@ -266,6 +266,116 @@ void quadrature(const double *w, const double *f, int n, double *ec,
   SSRPA_HIP(hipGetLastError());
 }
 
+// ---- inverse of I - X -------------------------------------------------------
+//
+// eps^-1 = (I - l X)^-1 for Hermitian X with I - l X positive definite
+// (the dielectric matrix of the Implementation section's last paragraph),
+// by Gauss-Jordan elimination without pivoting (stable for a positive
+// definite matrix).  Step k maps, with old values o and pivot p = o_kk,
+//   a_kj = o_kj / p,  a_kk = 1 / p,  a_ik = -o_ik / p,
+//   a_ij = o_ij - o_ik o_kj / p          (i, j != k),
+// so the n steps leave the inverse in place.  Row and column k are copied
+// out before each step so that no work-group reads a value another one has
+// already overwritten.
+
+namespace {
+
+__global__ void build_eps_kernel(const double *__restrict__ x, double c, long n,
+                                 long n_mat, double *__restrict__ a,
+                                 int *__restrict__ fail) {
+  const long total = n * n * n_mat;
+  const long t0 = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  for (long idx = t0; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    const long e = idx % (n * n);
+    const bool diag = e / n == e % n;
+    a[2 * idx] = (diag ? 1.0 : 0.0) - c * x[2 * idx];
+    a[2 * idx + 1] = diag ? 0.0 : -c * x[2 * idx + 1];
+  }
+  for (long j = t0; j < n_mat; j += (long)gridDim.x * blockDim.x) fail[j] = 0;
+}
+
+// rc[mat][0..n) = row k, rc[mat][n..2n) = column k
+__global__ void gj_save_kernel(const double2 *__restrict__ a, int n, int k,
+                               double2 *__restrict__ rc) {
+  const int mat = blockIdx.y;
+  const double2 *A = a + (long)mat * n * n;
+  double2 *R = rc + (long)mat * 2 * n;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += gridDim.x * blockDim.x) {
+    R[i] = A[(long)k * n + i];
+    R[n + i] = A[(long)i * n + k];
+  }
+}
+
+__global__ void gj_step_kernel(double2 *__restrict__ a, int n, int k,
+                               const double2 *__restrict__ rc,
+                               int *__restrict__ fail) {
+  const int mat = blockIdx.y;
+  if (fail[mat]) return;
+  const double2 *R = rc + (long)mat * 2 * n;
+  const double p = R[k].x;  // real: the matrix stays Hermitian
+  if (!(p > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) fail[mat] = 1;
+    return;
+  }
+  const double inv = 1.0 / p;
+  double2 *A = a + (long)mat * n * n;
+  const long nn = (long)n * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn;
+       e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    const double2 o = A[e];
+    double2 r;
+    if (i == k && j == k) {
+      r = make_double2(inv, 0.0);
+    } else if (i == k) {
+      r = make_double2(o.x * inv, o.y * inv);
+    } else if (j == k) {
+      r = make_double2(-o.x * inv, -o.y * inv);
+    } else {
+      const double2 cik = R[n + i], ckj = R[j];
+      r.x = o.x - (cik.x * ckj.x - cik.y * ckj.y) * inv;
+      r.y = o.y - (cik.x * ckj.y + cik.y * ckj.x) * inv;
+    }
+    A[e] = r;
+  }
+}
+
+__global__ void gj_flag_kernel(const int *__restrict__ fail, int n_mat,
+                               int *__restrict__ flag) {
+  for (int j = threadIdx.x; j < n_mat; j += blockDim.x)
+    if (fail[j]) *flag = 1;  // every writer stores the same value
+}
+
+}  // namespace
+
+void inverse_one_minus(Context *ctx, const double *x, int n, int n_mat,
+                       double coupling, double *out, int *flag, hipStream_t s) {
+  SSRPA_REQUIRE(n >= 1 && n_mat >= 1 && n_mat <= 65535, SSRPA_ERR_ARG,
+                "inverse: bad batch");
+  DevBuf rc(ctx, sizeof(double2) * 2 * (size_t)n * n_mat + sizeof(int) * n_mat);
+  int *fail = reinterpret_cast<int *>(rc.as<double2>() + 2 * (size_t)n * n_mat);
+  const long total = (long)n * n * n_mat;
+  hipLaunchKernelGGL(build_eps_kernel,
+                     dim3((unsigned)std::min<long>((total + 255) / 256, 65536)),
+                     dim3(256), 0, s, x, coupling, (long)n, (long)n_mat, out,
+                     fail);
+  double2 *A = reinterpret_cast<double2 *>(out);
+  const unsigned sb = (unsigned)std::max(1, std::min(64, (n + 255) / 256));
+  const unsigned ub =
+      (unsigned)std::max(1L, std::min<long>(((long)n * n + 255) / 256, 1024));
+  for (int k = 0; k < n; ++k) {
+    hipLaunchKernelGGL(gj_save_kernel, dim3(sb, n_mat), dim3(256), 0, s,
+                       (const double2 *)A, n, k, rc.as<double2>());
+    hipLaunchKernelGGL(gj_step_kernel, dim3(ub, n_mat), dim3(256), 0, s, A, n, k,
+                       (const double2 *)rc.as<double2>(), fail);
+  }
+  hipLaunchKernelGGL(gj_flag_kernel, dim3(1), dim3(256), 0, s,
+                     (const int *)fail, n_mat, flag);
+  SSRPA_HIP(hipGetLastError());
+  SSRPA_HIP(hipStreamSynchronize(s));  // the work buffer is freed on return
+}
+
 // ---- allocation-free form ---------------------------------------------------
 //
 // Work memory of the batch (D, pivots, failure marks) in a fixed device array

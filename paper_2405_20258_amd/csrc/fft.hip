@@ -702,20 +702,20 @@ void launch_orbital_fft(System &sys, const double *coeff_dev,
   const Geometry &g = sys.geo;
   const long box = (long)g.n1 * g.n2 * g.n3;
   double2 *psi = sys.psi_r.as<double2>();
-  fill_zero(psi, sizeof(double2) * box * sys.n_b, s);
-  const long total = (long)sys.n_pw * sys.n_b;
+  fill_zero(psi, sizeof(double2) * box * sys.n_orb, s);
+  const long total = (long)sys.n_pw * sys.n_orb;
   const int blocks = (int)std::min<long>((total + 255) / 256, 65536);
   hipLaunchKernelGGL(scatter_coeff_kernel, dim3(blocks), dim3(256), 0, s,
                      reinterpret_cast<const double2 *>(coeff_dev),
-                     box_index_dev, sys.n_pw, sys.n_b, box, psi);
+                     box_index_dev, sys.n_pw, sys.n_orb, box, psi);
   SSRPA_HIP(hipGetLastError());
   const double2 *tw = sys.fft_tw.as<double2>();
   const long plane = (long)g.n1 * g.n2;
   // x lines: contiguous; y lines: stride n1; z lines: stride n1*n2
-  fft_lines(psi, g.n1, 1, g.n1, g.n2, plane, (long)sys.n_b * g.n3, tw, 1.0, s);
-  fft_lines(psi, g.n2, g.n1, 1, g.n1, plane, (long)sys.n_b * g.n3,
+  fft_lines(psi, g.n1, 1, g.n1, g.n2, plane, (long)sys.n_orb * g.n3, tw, 1.0, s);
+  fft_lines(psi, g.n2, g.n1, 1, g.n1, plane, (long)sys.n_orb * g.n3,
             tw + g.n1, 1.0, s);
-  fft_lines(psi, g.n3, plane, 1, (int)plane, box, sys.n_b, tw + g.n1 + g.n2,
+  fft_lines(psi, g.n3, plane, 1, (int)plane, box, sys.n_orb, tw + g.n1 + g.n2,
             1.0 / std::sqrt(g.volume), s);
 }
 
@@ -729,7 +729,7 @@ void staged_pairs(System &sys, int v0, int nvb, const double *gscale,
   const Geometry &g = sys.geo;
   const int ny1 = 2 * g.m1 + 1, ny2 = 2 * g.m2 + 1;
   const size_t ypp = stage_bytes_per_pair(g);
-  const int ncc_max = stage_chunk_c(nvb, sys.n_c, ypp);
+  const int ncc_max = stage_chunk_c(nvb, sys.orb_nc, ypp);
   sys.ystage.ensure(sys.ctx, (size_t)nvb * ncc_max * ypp, s);
   // double-buffer the x outputs when that costs no work-groups per CU
   const size_t l1 = plane_lds_bytes<S>(ny1, ny2, 1);
@@ -753,25 +753,25 @@ void staged_pairs(System &sys, int v0, int nvb, const double *gscale,
   const bool zfft = g.n3 == S::N && 2 * g.m3 + 1 <= g.n3;
   const int nblk = (g.ncol + kZWaves * S::L - 1) / (kZWaves * S::L);
   const size_t zlds = sizeof(double2) * (S::N + (size_t)kZWaves * S::L * S::SL);
-  for (int c0 = 0; c0 < sys.n_c; c0 += ncc_max) {
-    const int ncc = std::min(ncc_max, sys.n_c - c0);
+  for (int c0 = 0; c0 < sys.orb_nc; c0 += ncc_max) {
+    const int ncc = std::min(ncc_max, sys.orb_nc - c0);
     const long tiles = (long)((nvb + 7) / 8) * ((ncc + 7) / 8);
     const long blocks = (tiles + 7) / 8 * 8 * 64;
     SSRPA_REQUIRE(blocks < (1L << 31), SSRPA_ERR_ARG, "pair grid too large");
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * S::W), lds, s,
-                       psi, v0, nvb, sys.n_v, c0, ncc, g.n3, g.m1, g.m2, nxo,
+                       psi, v0, nvb, sys.orb_c0, c0, ncc, g.n3, g.m1, g.m2, nxo,
                        sys.cmap.as<int>(), g.ldy, tw, yst);
     SSRPA_HIP(hipGetLastError());
     if (zfft) {
       const long zb = (long)nvb * ncc * nblk;
       SSRPA_REQUIRE(zb < (1L << 31), SSRPA_ERR_ARG, "pair grid too large");
       hipLaunchKernelGGL((pair_zfft_kernel<R1, R2>), dim3((unsigned)zb),
-                         dim3(64 * kZWaves), zlds, s, yst, ncc, c0, sys.n_c,
+                         dim3(64 * kZWaves), zlds, s, yst, ncc, c0, sys.orb_nc,
                          g.ncol, g.ldy, nblk, sys.zcol.as<int4>(), gscale,
                          g.n_g, g.ld_g, tw + g.n1 + g.n2, w);
     } else {
       hipLaunchKernelGGL(pair_z_kernel, dim3((unsigned)(nvb * ncc)), dim3(256),
-                         sizeof(double2) * g.n3, s, yst, ncc, c0, sys.n_c, g.n3,
+                         sizeof(double2) * g.n3, s, yst, ncc, c0, sys.orb_nc, g.n3,
                          g.ldy, sys.zcode.as<int>(), gscale, g.n_g, g.ld_g,
                          tw + g.n1 + g.n2, w);
     }
@@ -835,7 +835,7 @@ void launch_pair_matrix(System &sys, int v0, int nvb, bool scaled, double *w,
                                           2 * pg.lx * g.n1 + ny * g.n2);
   SSRPA_REQUIRE(shmem <= 160 * 1024, SSRPA_ERR_ARG,
                 "pair FFT needs %zu bytes of LDS", shmem);
-  const int tiles_c = (sys.n_c + kTileC - 1) / kTileC;
+  const int tiles_c = (sys.orb_nc + kTileC - 1) / kTileC;
   const int tiles_v = (nvb + kTileV - 1) / kTileV;
   const long blocks = (long)tiles_v * tiles_c * kTileV * kTileC;
   SSRPA_REQUIRE(blocks < (1L << 31), SSRPA_ERR_ARG, "pair grid too large");
@@ -851,7 +851,7 @@ void launch_pair_matrix(System &sys, int v0, int nvb, bool scaled, double *w,
           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));           \
     hipLaunchKernelGGL((pair_fft_kernel<G>), dim3((unsigned)blocks),          \
                        dim3(kPairThreads), shmem, s, psi, pg, v0, nvb,        \
-                       sys.n_v, sys.n_c, gcol, gscale, g.n_g, g.ld_g, tw, w); \
+                       sys.orb_c0, sys.orb_nc, gcol, gscale, g.n_g, g.ld_g, tw, w); \
   } while (0)
   if (gpt <= 2) SSRPA_PAIR(2);
   else if (gpt <= 4) SSRPA_PAIR(4);

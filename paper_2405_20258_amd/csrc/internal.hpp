@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <condition_variable>
 #include <cstdint>
 #include <cstdio>
 #include <exception>
@@ -119,7 +120,9 @@ struct Context {
   size_t high_water = 0;   // peak of in_use
   int live_systems = 0;    // systems created on this context and not destroyed
   std::multimap<size_t, void *> free_blocks;
+  uint64_t release_gen = 0; // counts releases (wakes allocations that wait)
   std::mutex mu;           // guards everything above
+  std::condition_variable cv_release;
   void *alloc(size_t bytes);
   void release(void *p, size_t bytes);
   void set_error(const std::string &m);
@@ -141,6 +144,19 @@ struct Geometry {
   int ld_g;          // n_g rounded up to a multiple of 64 (zero padded)
   std::vector<int32_t> miller_chi;  // n_g x 3
   std::vector<double> sqrt_v;       // v(G)^1/2 per chi0 vector
+  // The pair rows are stored scaled by s(G) = v(G)^1/2, except where v(G)
+  // is (nearly) zero under a truncated kernel: there s = 1 and the stored
+  // matrices are brought to v^1/2 (...) v^1/2 by r(G) = v^1/2 / s.
+  // Bare kernel: s = v^1/2, r = 1, rescaled = false.
+  std::vector<double> store_scale, rescale;
+  bool rescaled = false;
+  int truncation = 0;
+  // Real-orbital path: the cos/sin basis.  nh = n_g / 2 pairs {G, -G};
+  // hpos[j] / hneg[j] = indices of the larger member G of pair j and of -G;
+  // per G: neg = index of -G, hj = its pair, hs = +1 (G = H) or -1.
+  bool real = false;
+  int nh = 0;
+  std::vector<int> hpos, hneg, neg, hj, hs;
   // Columns (n1, n2) that hold chi0 vectors, in order of first appearance:
   // cmap[(n1 + m1) * (2 m2 + 1) + n2 + m2] = column or -1; per G,
   // zcode = column | (n3 mod N3) << 20.  ldy = ncol rounded up to 8.
@@ -196,19 +212,60 @@ struct Subspace {
   int ld_e = 0;                  // n_eig rounded up to 64
   std::vector<double> eigval;    // host copy, ascending
   DevBuf basis;                  // planar rows: ld_g rows x [re(ld_e) | im(ld_e)]
+  DevBuf basis_r;                // rows scaled by r(G) (truncated kernel only)
+  // basis kind: 0 eigenvectors of v^1/2 chi0 v^1/2, 1 eigenvectors of chi0
+  int kind = 0;
+  // kind 1: B = S^-1 C_s Z with v_s = C_s^H v C_s = Z Z^H, the operand of
+  // the projection (planar, like basis)
+  DevBuf proj;
+  // operand of the projection W_s = W_stored (operand)
+  const double *projection() const {
+    if (kind == 1) return proj.as<double>();
+    return (basis_r.empty() ? basis : basis_r).as<double>();
+  }
 };
+
+// Valence and conduction sets of a description (Method, Eqs. 4-6): bands
+// [0, n_val) have f > 0, bands [c_first, n_b) have f < 1; they overlap in
+// the partially occupied bands [c_first, n_val).  Insulator: c_first = n_val.
+struct BandSets {
+  int n_val = 0, c_first = 0, n_cond = 0;
+  bool partial = false;
+};
+// Validate the occupations (or their absence) and energies of a description.
+BandSets band_sets(const ssrpa_system_desc *d);
 
 struct System {
   Context *ctx = nullptr;
   Geometry geo;
-  int n_v = 0, n_c = 0, n_b = 0, n_pw = 0;
+  // n_v: valence set size; n_c: conduction set size (pair columns);
+  // c_first: band index of conduction column 0 (n_v for an insulator)
+  int n_v = 0, n_c = 0, n_b = 0, n_pw = 0, c_first = 0;
+  bool partial = false;          // partially occupied bands present
+  // Orbitals held in psi_r (n_orb of them) and where the pair transform
+  // finds its conduction columns: orb_nc orbitals from index orb_c0.
+  // Complex orbitals: n_orb = n_b, orb_c0 = c_first, orb_nc = n_c.  Real
+  // orbitals: the valence set unpacked, then the conduction set packed two
+  // per complex orbital: n_orb = n_v + orb_nc, orb_c0 = n_v,
+  // orb_nc = (n_c + 1) / 2.
+  int n_orb = 0, orb_c0 = 0, orb_nc = 0;
+  bool real = false;             // real-orbital (cos/sin basis) path
+  // real path tables (ints): hpos, hneg (nh each), neg, hj, hs (n_g each)
+  DevBuf rtab;
+  // real path: s(G) and r(G) in the order of the cos/sin basis (n_g each)
+  DevBuf rscale;
   std::vector<double> energy;
+  std::vector<double> occ;       // host occupation factors (partial only)
   DevBuf energy_d;               // n_b doubles
+  DevBuf occ_d;                  // n_b doubles (partial only)
+  DevBuf rowscale;               // per pair row (f_v - f_c)^1/2 (partial only)
   DevBuf psi_r;                  // n_b x N3 x N2 x N1 complex (interleaved)
   DevBuf gcol;                   // per G: int (column index | n3 mod N3 << 20)
   DevBuf zcode, cmap, zcol;      // Geometry::zcode / cmap / zcol on the device
   DevBuf ystage;                 // x-y stage of the staged pair transform
-  DevBuf sqrtv_d;                // per G: v(G)^1/2 * Omega / N
+  // per-G scale tables: [0, ld_g) s(G) Omega/N, [ld_g, 2 ld_g) Omega/N,
+  // then s(G) (n_g) and r(G) (n_g)
+  DevBuf sqrtv_d;
   DevBuf fft_tw;                 // twiddle tables for N1, N2, N3
   std::vector<double> fft_tw_host;  // their source (kept for the async copy)
   DevBuf chibar0;                // n_g x n_g complex (interleaved), symmetrized
@@ -294,6 +351,33 @@ size_t gemm_bf16x3_wide_workspace(const GemmArgs &g);
 void gemm_f32_wide(Context *ctx, const GemmArgs &g, DevBuf &ws, hipStream_t s);
 size_t gemm_f32_wide_workspace(const GemmArgs &g);
 
+// Real-orbital path (real.hip)
+// X_w = A^T diag(d_w) A for real A (h.a rows of h.lda doubles; h.ld a
+// multiple of 128), written as interleaved complex with imaginary part 0.
+void syrk(Context *ctx, const HerkArgs &h, double *out, long out_stride,
+          int beta, DevBuf &ws, hipStream_t s);
+size_t syrk_f64_workspace(const HerkArgs &h);
+// C = A B for real row-major operands; k, n multiples of 128.
+void gemm_real(const double *a, long lda, const double *b, long ldb, double *c,
+               long ldc, long m, int k, int n, hipStream_t s);
+void pack_coefficients(const double *coeff, int n_pw, int nv, int c0, int n_b,
+                       int n_pack, double *out, hipStream_t s);
+void unpack_real_rows(const double *f, int nvb, int n_c, int ld, int nh,
+                      const int *hpos, const int *hneg, double *w,
+                      hipStream_t s);
+void unpack_pw_rows(const double *f, int nvb, int n_c, int ld, int n_g,
+                    const int *neg, double *m, hipStream_t s);
+void real_to_pw_sym(const double *cr, int n, int nh, const int *hj,
+                    const int *hs, double *out, hipStream_t s);
+void real_basis_to_pw(const double *x, int ld_e, int n_g, int n_eig, int nh,
+                      const int *hj, const int *hs, double *y, hipStream_t s);
+void unpack_orbitals(const double *psi, long box, int nv, int c0, int n_b,
+                     double *out, hipStream_t s);
+int real_check_blocks();
+void real_check(const double *coeff, int n_pw, int n_b, const int *negpw,
+                double *blockmax, hipStream_t s);
+
+
 // Eigensolver (eig.hip): n_eig most negative eigenpairs of a Hermitian n x n
 // interleaved matrix (not modified).  eigval: device (n_eig); basis: planar
 // rows (ld_rows >= n rows, row stride 2*ld_e, im at +ld_e), padded rows/cols
@@ -309,6 +393,10 @@ void eig_lowest(Context *ctx, const double *a, int n, int n_eig, double *eigval,
 // *flag (device int) nonzero on a non-positive pivot.
 void trace_log(Context *ctx, const double *x, int n, int n_mat, double coupling,
                double *f, int *flag, hipStream_t s);
+// out_j = (I - c X_j)^-1 for Hermitian X_j (device, n x n interleaved each);
+// *flag (device int) set nonzero where I - c X_j is not positive definite.
+void inverse_one_minus(Context *ctx, const double *x, int n, int n_mat,
+                       double coupling, double *out, int *flag, hipStream_t s);
 // Allocation-free trace_log: work memory in a fixed per-device array of
 // kNoAllocScratchBytes (no allocator call); f and flag (nullable) are device
 // memory; nothing is synchronized.  noalloc_setup(device) looks the array's
@@ -329,8 +417,21 @@ void scale_sym(double *x, int n, const double *sv, int inverse, hipStream_t s);
 // planar rows (row stride 2*ld, im at +ld) -> interleaved rows x cols
 void planar_to_interleaved(const double *src, int rows, int cols, int ld,
                            double *dst, hipStream_t s);
-void pair_energy_diffs(const double *energy, int n_v_total, int v0, int nvb,
-                       int n_c, double *de, hipStream_t s);
+// de[p] = e_c - e_v for the rows p = (v - v0) n_c + c of a block, band
+// c_first + c as conduction band.  With occupations (occ != nullptr), rows
+// that do not count (v >= c band, or f_v = f_c) get de = 1 and, when
+// rowscale != nullptr, rowscale[p] = (f_v - f_c)^1/2, 0 for those rows.
+void pair_energy_diffs(const double *energy, const double *occ, int c_first,
+                       int v0, int nvb, int n_c, double *de, double *rowscale,
+                       hipStream_t s);
+// Scale column j < ncol of planar rows (stride 2 ld) by f[j], or by
+// sqrt(max(f[j], 0)) when from_eigs.
+void scale_cols(double *w, long rows, int ld, int ncol, const double *f,
+                int from_eigs, hipStream_t s);
+// Scale each planar row (2 ld doubles) of w by rowscale[p] (by its
+// reciprocal when inverse).
+void scale_rows(double *w, long rows, int ld, const double *rowscale,
+                hipStream_t s, bool inverse = false);
 void copy_interleaved(const double *src, double *dst, size_t n_complex,
                       hipStream_t s);
 

@@ -36,6 +36,7 @@ struct Request {
   std::vector<int32_t> miller;
   std::vector<double> coeff;
   std::vector<double> energy;
+  std::vector<double> occupation;
   ssrpa_system_desc desc{};
   int n_eig = 0, n_freq = 0, vb = 0;
   std::vector<double> omega, weight;
@@ -241,6 +242,10 @@ ssrpa_status ssrpa_server_submit(ssrpa_server *srv, const ssrpa_system_desc *des
   r->desc.miller = r->miller.data();
   r->desc.coeff = r->coeff.data();
   r->desc.energy = r->energy.data();
+  if (desc->occupation) {
+    r->occupation.assign(desc->occupation, desc->occupation + nb);
+    r->desc.occupation = r->occupation.data();
+  }
   r->n_eig = n_eig;
   r->n_freq = n_freq;
   r->omega.assign(omega, omega + n_freq);

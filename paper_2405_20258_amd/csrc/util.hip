@@ -42,13 +42,53 @@ __global__ void planar_to_interleaved_kernel(const double *src, int rows,
   }
 }
 
-__global__ void pair_de_kernel(const double *energy, int n_v, int v0, int nvb,
-                               int n_c, double *de) {
+__global__ void pair_de_kernel(const double *energy, const double *occ,
+                               int c_first, int v0, int nvb, int n_c,
+                               double *de, double *rowscale) {
   const long total = (long)nvb * n_c;
   for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
        idx += (long)gridDim.x * blockDim.x) {
-    const int v = v0 + (int)(idx / n_c), c = (int)(idx % n_c);
-    de[idx] = energy[n_v + c] - energy[v];
+    const int v = v0 + (int)(idx / n_c), c = c_first + (int)(idx % n_c);
+    if (!occ) {
+      de[idx] = energy[c] - energy[v];
+      continue;
+    }
+    // a pair counts once (v below c) and only with unequal occupations
+    const double df = occ[v] - occ[c];
+    const bool keep = v < c && df != 0.0;
+    if (de) de[idx] = keep ? energy[c] - energy[v] : 1.0;
+    if (rowscale) rowscale[idx] = keep ? sqrt(df) : 0.0;
+  }
+}
+
+// w[p][:] *= rowscale[p] over planar rows of 2 ld doubles; grid (x: row
+// segments, y: rows).
+__global__ void scale_rows_kernel(double *w, long rows, int ld,
+                                  const double *rowscale, int inverse) {
+  const long r = blockIdx.y + (long)gridDim.y * blockIdx.z;
+  if (r >= rows) return;
+  const double f = inverse ? 1.0 / rowscale[r] : rowscale[r];
+  if (f == 1.0) return;
+  double *row = w + r * 2L * ld;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 2 * ld;
+       i += gridDim.x * blockDim.x)
+    row[i] *= f;
+}
+
+// planar rows (row stride 2 ld, im at +ld): column j times f[j], j < ncol;
+// f[j] = sqrt(max(lam[j], 0)) when from_eigs (scaled by the square roots of
+// non-negative eigenvalues)
+__global__ void scale_cols_kernel(double *w, long rows, int ld, int ncol,
+                                  const double *f, int from_eigs) {
+  const long total = rows * ncol;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    const long r = idx / ncol;
+    const int j = (int)(idx % ncol);
+    const double x = f[j];
+    const double m = from_eigs ? sqrt(x > 0.0 ? x : 0.0) : x;
+    w[r * 2 * ld + j] *= m;
+    w[r * 2 * ld + ld + j] *= m;
   }
 }
 
@@ -91,10 +131,30 @@ void planar_to_interleaved(const double *src, int rows, int cols, int ld,
   SSRPA_HIP(hipGetLastError());
 }
 
-void pair_energy_diffs(const double *energy, int n_v, int v0, int nvb, int n_c,
-                       double *de, hipStream_t s) {
-  hipLaunchKernelGGL(pair_de_kernel, dim3(grid_for((long)nvb * n_c)), dim3(256),
-                     0, s, energy, n_v, v0, nvb, n_c, de);
+void pair_energy_diffs(const double *energy, const double *occ, int c_first,
+                       int v0, int nvb, int n_c, double *de, double *rowscale,
+                       hipStream_t s) {
+  const long total = (long)nvb * n_c;
+  hipLaunchKernelGGL(pair_de_kernel, dim3(grid_for(total)), dim3(256), 0, s,
+                     energy, occ, c_first, v0, nvb, n_c, de, rowscale);
+  SSRPA_HIP(hipGetLastError());
+}
+
+void scale_rows(double *w, long rows, int ld, const double *rowscale,
+                hipStream_t s, bool inverse) {
+  if (rows <= 0) return;
+  const long ry = std::min<long>(rows, 65535);
+  const long rz = (rows + ry - 1) / ry;
+  const int bx = std::max(1, std::min(8, (2 * ld + 255) / 256));
+  hipLaunchKernelGGL(scale_rows_kernel, dim3(bx, (unsigned)ry, (unsigned)rz),
+                     dim3(256), 0, s, w, rows, ld, rowscale, (int)inverse);
+  SSRPA_HIP(hipGetLastError());
+}
+
+void scale_cols(double *w, long rows, int ld, int ncol, const double *f,
+                int from_eigs, hipStream_t s) {
+  hipLaunchKernelGGL(scale_cols_kernel, dim3(grid_for(rows * ncol)), dim3(256),
+                     0, s, w, rows, ld, ncol, f, from_eigs);
   SSRPA_HIP(hipGetLastError());
 }
 

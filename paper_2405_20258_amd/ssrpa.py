@@ -49,7 +49,11 @@ class ssrpa_system_desc(ctypes.Structure):
                 ("coeff", _dp),
                 ("coeff_on_device", ctypes.c_int32),
                 ("energy", _dp),
-                ("ecut_chi", ctypes.c_double)]
+                ("ecut_chi", ctypes.c_double),
+                ("occupation", _dp),
+                ("coulomb_truncation", ctypes.c_int32),
+                ("real_orbitals", ctypes.c_int32)]
+TRUNCATIONS = {None: 0, "slab": 1}
 
 
 def _sig(name, res, args):
@@ -77,11 +81,17 @@ ssrpa_system_create = _sig("ssrpa_system_create", _i,
                            [_p, ctypes.POINTER(ssrpa_system_desc), _p,
                             ctypes.POINTER(_p)])
 ssrpa_system_destroy = _sig("ssrpa_system_destroy", _i, [_p])
+ssrpa_system_bands = _sig("ssrpa_system_bands", _i, [_p, _ip, _ip, _ip])
 ssrpa_chi_gvectors = _sig("ssrpa_chi_gvectors", _i, [_p, _ip, _i32p])
 ssrpa_orbitals_realspace = _sig("ssrpa_orbitals_realspace", _i, [_p, _p, _p])
 ssrpa_pair_matrix = _sig("ssrpa_pair_matrix", _i, [_p, _i, _i, _i, _p, _p])
 ssrpa_chi0_static = _sig("ssrpa_chi0_static", _i, [_p, _i, _i, _p, _i, _p])
 ssrpa_subspace = _sig("ssrpa_subspace", _i, [_p, _i, _dp, _p, _p])
+ssrpa_subspace_basis = _sig("ssrpa_subspace_basis", _i,
+                            [_p, _i, _i, _dp, _p, _p])
+BASES = {"symmetrized": 0, "chi0": 1}
+ssrpa_epsilon_inverse = _sig("ssrpa_epsilon_inverse", _i,
+                             [_p, _i, _i, _dp, _i, _i, _p, _p])
 ssrpa_correlation_energy = _sig("ssrpa_correlation_energy", _i,
                                 [_p, _i, _i, _dp, _dp, _i, _i, _d, _dp, _dp,
                                  _p, _p])
@@ -162,8 +172,11 @@ def frequency_grid(n: int, omega0: float = 1.0):
     return om, wt
 
 
-def make_desc(a, fft, miller, coeff, energy, n_v, ecut_chi, keep):
-    """ssrpa_system_desc from host arrays; `keep` holds the buffers alive."""
+def make_desc(a, fft, miller, coeff, energy, n_v, ecut_chi, keep, occ=None,
+              truncation=None, real=False):
+    """ssrpa_system_desc from host arrays; `keep` holds the buffers alive.
+    occ: occupation factors per band (None: insulator); truncation: None or
+    "slab"."""
     lattice = np.asarray(a, dtype=np.float64)
     if lattice.ndim == 0:
         lattice = np.eye(3) * float(lattice)
@@ -187,7 +200,14 @@ def make_desc(a, fft, miller, coeff, energy, n_v, ecut_chi, keep):
         d.coeff_on_device = 1
     d.energy = energy.ctypes.data_as(_dp)
     d.ecut_chi = float(ecut_chi)
-    keep.extend([miller, energy, coeff])
+    if occ is not None:
+        occ = np.ascontiguousarray(occ, dtype=np.float64)
+        d.occupation = occ.ctypes.data_as(_dp)
+    else:
+        d.occupation = None
+    d.coulomb_truncation = TRUNCATIONS[truncation]
+    d.real_orbitals = 1 if real else 0
+    keep.extend([miller, energy, coeff, occ])
     return d
 
 
@@ -230,25 +250,32 @@ class System:
     """A resident system: orbitals on the device plus chi0 / subspace state."""
 
     def __init__(self, ctx: Context, a, fft, miller, coeff, energy, n_v,
-                 ecut_chi, stream=None):
+                 ecut_chi, stream=None, occ=None, truncation=None, real=False):
         self.ctx = ctx
         keep = []
         self.desc = make_desc(a, fft, miller, coeff, energy, n_v, ecut_chi,
-                              keep)
+                              keep, occ, truncation, real)
         h = _p()
         _check(ssrpa_system_create(ctx.handle, ctypes.byref(self.desc),
                                    _stream(stream), ctypes.byref(h)),
                ctx.handle)
         self.handle = h
         ctx._systems.add(self)
-        self.n_v = int(n_v)
-        self.n_c = int(len(energy) - n_v)
+        nv, c0, nc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(ssrpa_system_bands(h, ctypes.byref(nv), ctypes.byref(c0),
+                                  ctypes.byref(nc)), ctx.handle)
+        self.n_v, self.c_first, self.n_c = nv.value, c0.value, nc.value
         self.fft = tuple(int(x) for x in fft)
 
     @classmethod
-    def from_synthetic(cls, ctx: Context, s, stream=None):
+    def from_synthetic(cls, ctx: Context, s, stream=None, truncation=None,
+                       real=None):
+        """real None: the system's own flag (synthetic real orbitals)."""
+        if real is None:
+            real = bool(getattr(s, "real_orbitals", False))
         return cls(ctx, s.a, s.fft, s.miller, s.coeff, s.energy, s.n_v,
-                   s.ecut_chi, stream)
+                   s.ecut_chi, stream, getattr(s, "occ", None), truncation,
+                   real)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -294,11 +321,22 @@ class System:
                                     valence_block, _addr(out_dev),
                                     int(symmetrized), _stream(stream)))
 
-    def subspace(self, n_eig: int, basis_dev=None, stream=None) -> np.ndarray:
+    def subspace(self, n_eig: int, basis_dev=None, stream=None,
+                 kind: str = "symmetrized") -> np.ndarray:
         ev = np.empty(n_eig)
-        self._chk(ssrpa_subspace(self.handle, n_eig, _dptr(ev),
-                                 _addr(basis_dev), _stream(stream)))
+        self._chk(ssrpa_subspace_basis(self.handle, BASES[kind], n_eig,
+                                       _dptr(ev), _addr(basis_dev),
+                                       _stream(stream)))
         return ev
+
+    def epsilon_inverse(self, n_eig: int, omega, out_dev, precision="fp64",
+                        valence_block: int = 0, stream=None):
+        """(I - X_j)^-1 for every frequency into out_dev (device,
+        n_freq x n x n complex)."""
+        om = np.ascontiguousarray(omega, dtype=np.float64)
+        self._chk(ssrpa_epsilon_inverse(self.handle, n_eig, len(om), _dptr(om),
+                                        PRECISIONS[precision], valence_block,
+                                        _addr(out_dev), _stream(stream)))
 
     def correlation_energy(self, n_eig: int, omega: Sequence[float],
                            weight: Sequence[float], precision="fp64",
@@ -368,7 +406,8 @@ class Server:
         """Queue a synthetic system `s` (host arrays); returns the request id."""
         keep = []
         d = make_desc(s.a, s.fft, s.miller, s.coeff, s.energy, s.n_v,
-                      s.ecut_chi, keep)
+                      s.ecut_chi, keep, getattr(s, "occ", None), None,
+                      bool(getattr(s, "real_orbitals", False)))
         om = np.ascontiguousarray(omega, dtype=np.float64)
         wt = np.ascontiguousarray(weight, dtype=np.float64)
         rid = ctypes.c_uint64()

@@ -144,6 +144,83 @@ void trace_log(Context *ctx, const double *x, int n, int n_mat, double,
   SSRPA_HIP(hipStreamSynchronize(s));
 }
 
+void syrk(Context *ctx, const HerkArgs &h, double *out, long, int beta,
+          DevBuf &ws, hipStream_t s) {
+  ws.ensure(ctx, 4096, s);
+  double *w = ws.as<double>();
+  const double *a = h.a;
+  mock_enqueue(s, [=] {
+    rd(a);
+    if (beta) rd(out);
+    wr(w, 1.0);
+    wr(out, -0.5);
+  });
+}
+size_t syrk_f64_workspace(const HerkArgs &) { return 4096; }
+void gemm_real(const double *a, long, const double *b, long, double *c, long,
+               long, int, int, hipStream_t s) {
+  mock_enqueue(s, [=] {
+    rd(a);
+    rd(b);
+    wr(c, 0.125);
+  });
+}
+void pack_coefficients(const double *coeff, int, int, int, int, int,
+                       double *out, hipStream_t s) {
+  mock_enqueue(s, [=] {
+    rd(coeff);
+    wr(out, 1.0);
+  });
+}
+void unpack_real_rows(const double *f, int, int, int, int, const int *hpos,
+                      const int *, double *w, hipStream_t s) {
+  mock_enqueue(s, [=] {
+    rd(f);
+    rd(hpos);
+    wr(w, 0.25);
+  });
+}
+void unpack_pw_rows(const double *f, int, int, int, int, const int *neg,
+                    double *m, hipStream_t s) {
+  mock_enqueue(s, [=] {
+    rd(f);
+    rd(neg);
+    wr(m, 0.25);
+  });
+}
+void real_to_pw_sym(const double *cr, int, int, const int *hj, const int *,
+                    double *out, hipStream_t s) {
+  mock_enqueue(s, [=] {
+    rd(cr);
+    rd(hj);
+    wr(out, 1.0);
+  });
+}
+void real_basis_to_pw(const double *x, int, int, int, int, const int *hj,
+                      const int *, double *y, hipStream_t s) {
+  mock_enqueue(s, [=] {
+    rd(x);
+    rd(hj);
+    wr(y, 1.0);
+  });
+}
+void unpack_orbitals(const double *psi, long, int, int, int, double *out,
+                     hipStream_t s) {
+  mock_enqueue(s, [=] {
+    rd(psi);
+    wr(out, 1.0);
+  });
+}
+int real_check_blocks() { return 4; }
+void real_check(const double *coeff, int, int, const int *negpw,
+                double *blockmax, hipStream_t s) {
+  mock_enqueue(s, [=] {
+    rd(coeff);
+    rd(negpw);
+    for (int i = 0; i < 4; ++i) blockmax[i] = 0.0;
+  });
+}
+
 void noalloc_setup(int) {}
 size_t trace_log_noalloc_bytes(int n, int n_mat) {
   return 16 * (size_t)n * n * n_mat;
@@ -185,12 +262,43 @@ void planar_to_interleaved(const double *src, int, int, int, double *dst,
   });
 }
 
-void pair_energy_diffs(const double *energy, int, int, int, int, double *de,
-                       hipStream_t s) {
+void pair_energy_diffs(const double *energy, const double *occ, int, int, int,
+                       int, double *de, double *rowscale, hipStream_t s) {
   mock_enqueue(s, [=] {
     rd(energy);
+    rd(occ);
     wr(de, 1.0);
+    wr(rowscale, 1.0);
   });
+}
+
+void scale_rows(double *w, long, int, const double *rowscale, hipStream_t s,
+                bool) {
+  mock_enqueue(s, [=] {
+    rd(rowscale);
+    wr(w, 0.5);
+  });
+}
+
+void scale_cols(double *w, long, int, int, const double *f, int,
+                hipStream_t s) {
+  mock_enqueue(s, [=] {
+    rd(f);
+    wr(w, 1.0);
+  });
+}
+
+void inverse_one_minus(Context *ctx, const double *x, int n, int n_mat, double,
+                       double *out, int *flag, hipStream_t s) {
+  DevBuf rc(ctx, sizeof(double) * 4 * (size_t)n * n_mat + 64);
+  double *p = rc.as<double>();
+  mock_enqueue(s, [=] {
+    rd(x);
+    wr(p, 1.0);
+    wr(out, 1.0);
+    if (flag) rd(flag);
+  });
+  SSRPA_HIP(hipStreamSynchronize(s));
 }
 
 void copy_interleaved(const double *src, double *dst, size_t, hipStream_t s) {

@@ -128,3 +128,54 @@ def test_null_handles_are_rejected(lib):
     assert lib.ssrpa_system_destroy(None) == lib.ERR_ARG
     assert lib.ssrpa_chi0_static(None, 0, 0, None, 1, None) == lib.ERR_ARG
     assert lib.ssrpa_ticket_query(None, None) == lib.ERR_ARG
+
+
+def test_occupation_validation_on_the_host(lib):
+    """Partial occupations (Eqs. 4-6) are validated before any device work:
+    f in [0, 1], non-increasing along the bands, ascending energies with
+    equal f at equal energies, and n_v = the count of f > 0."""
+    s = sy.make_system(sy.TINY, 1000)
+    occ = sy.fermi_dirac_occupations(s.energy, 0.05, 0.01)
+    sp = sy.with_occupations(s, occ)
+    b = ctypes.c_size_t()
+
+    def fp(occ_, n_v=sp.n_v, energy=sp.energy):
+        keep = []
+        d = lib.make_desc(sp.a, sp.fft, sp.miller, sp.coeff, energy, n_v,
+                          sp.ecut_chi, keep, occ_)
+        return lib.ssrpa_footprint(ctypes.byref(d), 75, 16, lib.FP64, 0,
+                                   ctypes.byref(b))
+    assert fp(occ) == lib.OK
+    with_occ = b.value
+    assert fp(None, n_v=s.n_v) == lib.OK
+    assert with_occ > b.value          # more pairs: V x C grows
+    bad = occ.copy()
+    bad[3] = 1.5
+    assert fp(bad) == lib.ERR_ARG      # outside [0, 1]
+    bad = occ.copy()
+    k = int(np.nonzero((occ > 0) & (occ < 1))[0][0])
+    bad[k], bad[k + 1] = bad[k + 1], bad[k]
+    assert fp(bad) == lib.ERR_ARG      # increasing along the bands
+    assert fp(occ, n_v=sp.n_v - 1) == lib.ERR_ARG
+    e2 = sp.energy.copy()
+    e2[k + 1] = e2[k]                   # equal energies, different f
+    assert fp(occ, energy=e2) == lib.ERR_ARG
+
+
+def test_slab_truncation_needs_a_normal_third_axis(lib):
+    s = sy.make_system(sy.TINY, 1000)
+    b = ctypes.c_size_t()
+    keep = []
+    d = lib.make_desc(s.a, s.fft, s.miller, s.coeff, s.energy, s.n_v,
+                      s.ecut_chi, keep, None, "slab")
+    assert lib.ssrpa_footprint(ctypes.byref(d), 75, 16, lib.FP64, 0,
+                               ctypes.byref(b)) == lib.OK
+    lat = np.eye(3) * s.a
+    lat[2, 0] = 0.5                      # a3 tilted: not normal to a1
+    d = lib.make_desc(lat, s.fft, s.miller, s.coeff, s.energy, s.n_v,
+                      s.ecut_chi, keep, None, "slab")
+    assert lib.ssrpa_footprint(ctypes.byref(d), 75, 16, lib.FP64, 0,
+                               ctypes.byref(b)) == lib.ERR_ARG
+    d.coulomb_truncation = 7
+    assert lib.ssrpa_footprint(ctypes.byref(d), 75, 16, lib.FP64, 0,
+                               ctypes.byref(b)) == lib.ERR_ARG

@@ -7,13 +7,11 @@ CPU (or its stored outputs in tests/golden/ are read).
 Tolerances (FP64 path): pair matrix elements 1e-12 relative to the largest
 element; chi0 1e-10 in max-norm relative; eigenvalues 1e-10 relative to the
 largest |eigenvalue|; subspace projector 1e-8 absolute; per-frequency F_j
-and E_c 1e-10 relative.  On the small ragged system (E_c ~ 3e-3) E_c also
-gets an absolute floor of 1e-12: F_j = ln det(I - X_j) + Tr X_j cancels to
-second order in X_j, so at the high-frequency nodes of the mapped rule
-(weights up to ~500) the FP64 rounding of the log-determinant of a
-near-identity matrix (~n eps per node) leaves ~5e-13 in E_c on both sides;
-the oracle's rank-one pin shows the same floor.  The workload tests keep
-the plain 1e-10 relative bound.  Eigenvectors are compared through the projector
+and E_c 1e-10 relative, with no absolute floor: the oracle takes F_j from
+the eigenvalues of X_j term by term (ln(1 - mu) + mu without cancellation)
+and the library from Cholesky pivots of I - X_j kept as p - 1, so neither
+side has the rounding floor of ln det(I - X_j) + Tr X_j at the
+high-frequency nodes.  Eigenvectors are compared through the projector
 C_s C_s^H because each vector is defined only up to a phase.
 """
 import json
@@ -271,7 +269,7 @@ def test_subspace_and_energy_ragged(env):
         ec, f = g.correlation_energy(n_eig, om, wt, "fp64")
         rel = abs(ec - ref["ec"]) / abs(ref["ec"])
         _log(f"  E_c gpu {ec!r} oracle {ref['ec']!r} rel {rel:.2e}")
-        assert abs(ec - ref["ec"]) < 1e-10 * abs(ref["ec"]) + 1e-12
+        assert abs(ec - ref["ec"]) < 1e-10 * abs(ref["ec"])
         assert np.max(np.abs(f - ref["integrand"])) < \
             1e-10 * np.max(np.abs(ref["integrand"]))
     g.close()
@@ -340,9 +338,9 @@ def test_energy_odd_frequency_counts(env, n_freq):
     ref = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
                                  s.n_v, s.ecut_chi, n_eig, om, wt)
     _log(f"  E_c gpu {ec!r} oracle {ref['ec']!r}")
-    assert abs(ec - ref["ec"]) < 1e-10 * abs(ref["ec"]) + 1e-12
+    assert abs(ec - ref["ec"]) < 1e-10 * abs(ref["ec"])
     assert np.max(np.abs(f - ref["integrand"])) < \
-        1e-10 * np.max(np.abs(ref["integrand"])) + 1e-13
+        1e-10 * np.max(np.abs(ref["integrand"]))
     g.close()
 
 
@@ -443,7 +441,7 @@ def test_medium_workload_against_golden(env):
             werr = max(werr, abs(val - ref))
             wmax = max(wmax, abs(ref))
     _log(f"medium W sample err {werr:.2e} (max {wmax:.2e})")
-    assert werr < 1e-12 * max(wmax, 1e-3) * 10
+    assert werr < 1e-12 * wmax
     _log("medium workload: chi0")
     out = torch.empty((ng, ng), dtype=torch.complex128, device="cuda")
     g.chi0_static("fp64", out_dev=out, symmetrized=True)
