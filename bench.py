@@ -50,6 +50,14 @@ def parse():
     ap.add_argument("--precision", default="fp64",
                     choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--n-eig", type=int, default=0)
+    ap.add_argument("--orbitals", default="complex",
+                    choices=["complex", "real"],
+                    help="real: time-reversal symmetric (Gamma-point) "
+                         "orbitals, contracted in the real cos/sin basis")
+    ap.add_argument("--occupations", default="insulator",
+                    choices=["insulator", "fermi"],
+                    help="fermi: Fermi-Dirac occupations (mu = 0.05 Ha, "
+                         "kT = 0.01 Ha), partially occupied bands")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-bands", type=int, default=4,
                     help="valence bands in the oracle's timed sample")
@@ -299,8 +307,16 @@ def main():
     print(f"# generating {spec.name} (seed {seed})", file=sys.stderr,
           flush=True)
     # the large share's 40651 x 8704 orthonormalization runs on the GPU
+    real = args.orbitals == "real"
     s = sy.make_system(spec, seed, qr="torch" if args.workload == "large"
-                       else "numpy")
+                       else "numpy", real_orbitals=real)
+    workload = spec.name
+    if real:
+        workload = workload.replace("_fp64", "_real_fp64", 1)
+    if args.occupations == "fermi":
+        s = sy.with_occupations(s, sy.fermi_dirac_occupations(s.energy, 0.05,
+                                                              0.01))
+        workload += "_fermi_mu0.05_kt0.01"
     om, wt = ssrpa.frequency_grid(spec.n_freq)
     coeff_d = torch.from_numpy(s.coeff).to("cuda")   # inputs resident in HBM
     torch.cuda.synchronize()
@@ -310,24 +326,25 @@ def main():
 
     def step():
         g = ssrpa.System(ctx, s.a, s.fft, s.miller, coeff_d, s.energy, s.n_v,
-                         s.ecut_chi, stream)
+                         s.ecut_chi, stream, s.occ, None, real)
         g.stage_times(True)
         g.chi0_static(prec, valence_block=vb)
         g.subspace(n_eig)
         ec, f = g.correlation_energy(n_eig, om, wt, prec, valence_block=vb)
         st = g.stage_times(False)
         n_g = g.n_g
+        n_pairs = g.n_v * g.n_c
         g.close()
-        return ec, st, n_g
+        return ec, st, n_g, n_pairs
 
     for i in range(args.warmup):
-        ec, st, n_g = step()
+        ec, st, n_g, pairs = step()
         print(f"# warmup {i}: E_c = {ec!r}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stage = {k: [0.0, 0] for k in ssrpa.STAGES}
     for i in range(args.steps):
-        ec, st, n_g = step()
+        ec, st, n_g, pairs = step()
         for k, (ms, n) in st.items():
             stage[k][0] += ms
             stage[k][1] += n
@@ -335,8 +352,9 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    pairs = s.n_v * s.n_c
-    herk_flops_step = 4.0 * n_g * n_g * pairs
+    # algorithmic flops of the static contraction: one triangle, complex
+    # MAC = 8 flops (4 N_G^2 K); the real path's real MACs: N_G^2 K
+    herk_flops_step = (1.0 if real else 4.0) * n_g * n_g * pairs
     herk_ms, herk_launches = stage["chi0_herk"]
     value = herk_flops_step * args.steps / (herk_ms * 1e-3) / 1e12
     per_launch_flops = herk_flops_step * args.steps / herk_launches
@@ -355,7 +373,7 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[prec],
         "data": "synthetic",
-        "config": {"workload": spec.name, "n_g": n_g, "pairs": pairs,
+        "config": {"workload": workload, "n_g": n_g, "pairs": pairs,
                    "n_eig": n_eig, "n_freq": spec.n_freq,
                    "valence_block": vb, "precision": prec,
                    "fft": list(s.fft)},
@@ -367,7 +385,8 @@ def main():
                      "peak": PEAK[prec], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK[prec], 4),
                      "traffic": None,
-                     "kernel": HERK_KERNEL[prec],
+                     "kernel": ("syrk_f64_kernel (static chi0, real)"
+                                if real else HERK_KERNEL[prec]),
                      "flops_per_launch": per_launch_flops,
                      "avg_launch_ms": round(avg_launch_s * 1e3, 4)},
     }
@@ -394,7 +413,7 @@ def main():
     torch.cuda.synchronize()
     th0 = time.perf_counter()
     g = ssrpa.System(ctx, s.a, s.fft, s.miller, s.coeff, s.energy, s.n_v,
-                     s.ecut_chi, stream)
+                     s.ecut_chi, stream, s.occ, None, real)
     g.chi0_static(prec, valence_block=vb)
     g.subspace(n_eig)
     ec_h, _ = g.correlation_energy(n_eig, om, wt, prec, valence_block=vb)
