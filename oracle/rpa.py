@@ -554,6 +554,157 @@ def correlation_energy(a, fft, miller_psi, coeff, energy, n_v, ecut_chi,
 
 
 # ---------------------------------------------------------------------------
+# k-point sampling and q != 0 (Eqs. 1-3 with the sums over k and q)
+# ---------------------------------------------------------------------------
+#
+# Orbitals at a k-point are psi_nk(r) = Omega^-1/2 sum_G c_nk(G) e^{i(k+G).r};
+# their periodic parts u_nk(r) = Omega^-1/2 sum_G c_nk(G) e^{iG.r} are what
+# orbitals_realspace returns for the coefficients of k.  With q on the mesh
+# and k + q = k' + G0 (k' a mesh point, G0 a reciprocal lattice vector),
+# u_{k+q}(r) = e^{-iG0.r} u_k'(r).
+#
+# Pair matrix, with the bra on the valence side as at q = 0 (reading of the
+# exponent sign): P_vc,k(q; G) = int u*_vk u_c,k+q e^{iG.r} dr.  Eq. (3)'s
+# element (bra at k + q) is M(G) = conj P(-G), so the paper's
+# v(q+G)^1/2 chi0(q) v(q+G')^1/2 equals, at G -> -G and complex conjugated,
+# the matrix built from P with v(G - q) = 4 pi / |G - q|^2 on the set
+# {G : |G - q|^2 / 2 <= E_chi, G != q}: the same spectrum, F_j and E_c(q).
+#
+# Delta (reading 2 with k): the anti-resonant term of the pair (v at k,
+# c at k + q) in Eq. (2) is the pair (c at k, v at k + q); for a k set closed
+# under k -> -k with psi_{-k} = conj psi_k (time reversal) it equals the
+# resonant term of (v at -k - q, c at -k), so
+# chi0(q) = (1/Omega) sum_k g_k sum_vc conj(P) Delta P with
+# Delta = -4 (e_c,k+q - e_vk) / ((e_c,k+q - e_vk)^2 + w^2) (insulators).
+
+
+def chi_gvectors_q(a: float, ecut_chi: float, q) -> np.ndarray:
+    """Miller indices G of the chi0 basis at q (fractional coordinates):
+    |G - q|^2 / 2 <= ecut_chi, G != q.  Lexicographic in (n1, n2, n3)."""
+    b = recip_unit(a)
+    qf = np.asarray(q, dtype=np.float64)
+    nmax = int(math.floor(math.sqrt(2.0 * ecut_chi) / b + np.max(np.abs(qf)))) + 1
+    out = []
+    for n1 in range(-nmax, nmax + 1):
+        for n2 in range(-nmax, nmax + 1):
+            for n3 in range(-nmax, nmax + 1):
+                d = np.array([n1, n2, n3], dtype=np.float64) - qf
+                d2 = float(d @ d)
+                if d2 == 0.0:
+                    continue
+                if 0.5 * b * b * d2 <= ecut_chi:
+                    out.append((n1, n2, n3))
+    return np.array(out, dtype=np.int64).reshape(-1, 3)
+
+
+def coulomb_q(a: float, miller: np.ndarray, q) -> np.ndarray:
+    """v(G - q) = 4 pi / |G - q|^2 for the chi0 basis at q."""
+    b = recip_unit(a)
+    d = np.asarray(miller, dtype=np.float64) - np.asarray(q, dtype=np.float64)
+    return 4.0 * math.pi / (b * b * np.sum(d * d, axis=1))
+
+
+def pair_matrix_kq(a, fft, u_v, u_c, g0, miller_chi) -> np.ndarray:
+    """P_vc(G) = (Omega / N) sum_j conj(u_v(r_j)) u_c(r_j) e^{-iG0.r_j}
+    e^{iG.r_j}: u_v the periodic parts at k, u_c those at k' with
+    k + q = k' + G0.  Returns [v, c, G]."""
+    n1, n2, n3 = fft
+    m = np.asarray(miller_chi) - np.asarray(g0)[None, :]
+    out = np.empty((u_v.shape[0], u_c.shape[0], m.shape[0]), dtype=np.complex128)
+    omega = cell_volume(a)
+    for iv in range(u_v.shape[0]):
+        rho = np.conj(u_v[iv])[None] * u_c
+        f = scipy.fft.ifftn(rho, axes=(1, 2, 3), workers=-1)
+        out[iv] = omega * f[:, m[:, 0] % n1, m[:, 1] % n2, m[:, 2] % n3]
+    return out
+
+
+def correlation_energy_q(a, fft, kpoints, q, kq, g0, ecut_chi, n_eig, omega,
+                         weight):
+    """E_c(q) of Eq. (1) for one q of a k mesh, step by step (insulators).
+
+    kpoints: list of dicts with keys miller, coeff, energy, n_v, weight (g_k).
+    kq[i], g0[i]: k_i + q = k_kq[i] + g0[i].  Steps as in correlation_energy,
+    with the pair rows of every k stacked (weights g_k folded into Delta).
+    Returns dict(ec, integrand, eigval, gap, chibar0, chis).
+    """
+    mchi = chi_gvectors_q(a, ecut_chi, q)
+    sv = np.sqrt(coulomb_q(a, mchi, q))
+    us = [orbitals_realspace(a, fft, k["miller"], k["coeff"]) for k in kpoints]
+    ws, des, gks = [], [], []
+    for i, k in enumerate(kpoints):
+        kp = kpoints[kq[i]]
+        nv = k["n_v"]
+        p = pair_matrix_kq(a, fft, us[i][:nv], us[kq[i]][kp["n_v"]:], g0[i], mchi)
+        ws.append(p.reshape(-1, len(mchi)) * sv[None, :])
+        de = kp["energy"][kp["n_v"]:][None, :] - k["energy"][:nv][:, None]
+        des.append(de.ravel())
+        gks.append(np.full(de.size, float(k["weight"])))
+    w = np.concatenate(ws)
+    de = np.concatenate(des)
+    gk = np.concatenate(gks)
+
+    def delta(om):
+        return gk * (-4.0 * de / (de * de + om * om))
+    ng = len(mchi)
+    cb0 = chibar(a, w, delta(0.0))
+    if n_eig >= ng:
+        lam = scipy.linalg.eigvalsh(cb0)
+        wsub, gap = w, math.inf
+    else:
+        lam, c_s, gap = subspace(cb0, n_eig)
+        wsub = project(w, c_s)
+    f = np.empty(len(omega))
+    chis_all = []
+    for j, om in enumerate(omega):
+        chis = chibar(a, wsub, delta(float(om)))
+        chis_all.append(chis)
+        f[j] = trace_log(chis)
+    return dict(ec=quadrature(weight, f), integrand=f, eigval=lam, gap=gap,
+                chibar0=cb0, chis=chis_all, miller_chi=mchi)
+
+
+def chi0_q_eq2_literal(a, kpoints, q, kq, g0, miller_chi_paper, omega):
+    """Eq. (2) as printed at q: sum over k and all ordered band pairs
+    (n at k, n' at k + q) of 2 g_k (f_n',k+q - f_nk) M(G) conj M(G') /
+    (e_n',k+q - e_nk - i w) with Eq. (3)'s M = <psi_n',k+q| e^{i(q+G).r}
+    |psi_nk>, from plane-wave coefficients (no grid): the coefficient of
+    the Bloch function at k + q is c_k'(G + G0).  Occupations 1 below n_v,
+    0 above.  Small inputs only; returns chi0_GG'(q) over miller_chi_paper
+    (the G of q + G).  Since M(G) = conj P(-G), this equals the pair form
+    built from P at (-G, -G') when the k set is time-reversal symmetric."""
+    mc = np.asarray(miller_chi_paper, dtype=np.int64)
+    out = np.zeros((len(mc), len(mc)), dtype=np.complex128)
+    for i, k in enumerate(kpoints):
+        kp = kpoints[kq[i]]
+        # <psi_n',k+q| e^{i(q+G).r} |psi_nk> = sum_G1 conj(c_n',k+q(G1)) c_nk(G1 - G)
+        # with the k+q coefficients c_k'(. + G0)
+        idx_k = {tuple(int(x) for x in m): j for j, m in enumerate(k["miller"])}
+        mkp = np.asarray(kp["miller"], dtype=np.int64) - np.asarray(g0[i])[None, :]
+        nb, nbp = k["coeff"].shape[0], kp["coeff"].shape[0]
+        x = np.zeros((nbp, nb, len(mc)), dtype=np.complex128)
+        for ig, g in enumerate(mc):
+            src, dst = [], []
+            for j1, g1 in enumerate(mkp):
+                j = idx_k.get((int(g1[0] - g[0]), int(g1[1] - g[1]), int(g1[2] - g[2])))
+                if j is not None:
+                    src.append(j1)
+                    dst.append(j)
+            if src:
+                x[:, :, ig] = np.conj(kp["coeff"][:, src]) @ k["coeff"][:, dst].T
+        f_k = (np.arange(nb) < k["n_v"]).astype(float)
+        f_kp = (np.arange(nbp) < kp["n_v"]).astype(float)
+        for n in range(nb):
+            for n2 in range(nbp):
+                df = f_kp[n2] - f_k[n]
+                if df == 0.0:
+                    continue
+                t = 2.0 * k["weight"] * df / (kp["energy"][n2] - k["energy"][n] - 1j * omega)
+                out += t * np.outer(x[n2, n], np.conj(x[n2, n]))
+    return out / cell_volume(a)
+
+
+# ---------------------------------------------------------------------------
 # Closed forms used to pin the above
 # ---------------------------------------------------------------------------
 

@@ -199,6 +199,69 @@ def make_system(spec: SystemSpec, seed: int, n_v: Optional[int] = None,
                   n_c=n_c, ecut_chi=ecut_from_shell(spec.a, spec.nsq_chi))
 
 
+def kmesh_system(a: float, fft: int, n_v: int, n_c: int, nsq_chi: int,
+                 seed: int, e_psi: float = 4.0, sigma: float = 2.0):
+    """A shifted 2 x 2 x 2 k mesh {+-1/4}^3 (fractions of the reciprocal
+    vectors), weights 1/8, time-reversal symmetric: for each k of the half
+    set (k_x = +1/4) random orbitals on the sphere |k + G|^2/2 <= e_psi
+    (Gaussian |k + G| decay, reduced QR) and energies as in make_system; at
+    -k the coefficients c_-k(G) = conj c_k(-G) and the same energies.
+    Returns (kpoints: list of dicts miller, coeff, energy, n_v, weight,
+    kfrac; ecut_chi), drawn per half-set k-point in order with
+    default_rng(seed)."""
+    b = 2.0 * math.pi / a
+    rng = np.random.default_rng(seed)
+    half = [(0.25, sy, sz) for sy in (0.25, -0.25) for sz in (0.25, -0.25)]
+    kpts = {}
+    for kf in half:
+        kv = np.array(kf)
+        nmax = int(math.floor(math.sqrt(2.0 * e_psi) / b)) + 2
+        r = np.arange(-nmax, nmax + 1)
+        n1, n2, n3 = np.meshgrid(r, r, r, indexing="ij")
+        m = np.stack([n1.ravel(), n2.ravel(), n3.ravel()], axis=1)
+        kg2 = b * b * np.sum((m + kv[None, :]) ** 2, axis=1)
+        m = m[0.5 * kg2 <= e_psi].astype(np.int32)
+        kg2 = b * b * np.sum((m + kv[None, :]) ** 2, axis=1)
+        nb = n_v + n_c
+        if nb > len(m):
+            raise ValueError("too many bands for the sphere")
+        z = (rng.standard_normal((len(m), nb)) + 1j *
+             rng.standard_normal((len(m), nb))) * np.exp(
+                 -kg2 / (2.0 * sigma ** 2))[:, None]
+        q, _ = np.linalg.qr(z, mode="reduced")
+        eps_v = np.sort(rng.uniform(-1.0, 0.0, n_v))
+        eps_c = np.sort(0.1 + 4.9 * rng.uniform(0.0, 1.0, n_c) ** (2.0 / 3.0))
+        e = np.concatenate([eps_v, eps_c])
+        kpts[kf] = dict(miller=m, coeff=np.ascontiguousarray(q.T), energy=e,
+                        n_v=n_v, weight=1.0 / 8.0, kfrac=np.array(kf))
+        mk = kf
+        km = tuple(-x for x in mk)
+        # time reversal: c_-k(G) = conj c_k(-G), on the sphere -S(k)
+        mneg = (-m).astype(np.int32)
+        kpts[km] = dict(miller=mneg, coeff=np.ascontiguousarray(np.conj(q.T)),
+                        energy=e.copy(), n_v=n_v, weight=1.0 / 8.0,
+                        kfrac=np.array(km))
+    order = sorted(kpts.keys())
+    return [kpts[k] for k in order], ecut_from_shell(a, nsq_chi)
+
+
+def kmesh_q_map(kpoints, q):
+    """For q (fractions) on the mesh: kq[i], g0[i] with k_i + q = k_kq[i] + g0[i]."""
+    kq, g0 = [], []
+    ks = [np.asarray(k["kfrac"]) for k in kpoints]
+    for k in ks:
+        t = k + np.asarray(q)
+        for j, kk in enumerate(ks):
+            d = t - kk
+            if np.all(np.abs(d - np.round(d)) < 1e-12):
+                kq.append(j)
+                g0.append(np.round(d).astype(np.int32))
+                break
+        else:
+            raise ValueError("q is not on the mesh")
+    return np.array(kq, dtype=np.int32), np.array(g0, dtype=np.int32)
+
+
 def fermi_dirac_occupations(energy: np.ndarray, mu: float, kt: float,
                             cut: float = 1e-12) -> np.ndarray:
     """Finite-temperature occupations f = 1 / (1 + exp((e - mu) / kT)).

@@ -606,3 +606,75 @@ def test_epsilon_inverse_rank_one_closed_form():
     x = -a * np.outer(u, np.conj(u))
     ref = np.eye(9) - a / (1 + a) * np.outer(u, np.conj(u))
     assert np.max(np.abs(rpa.epsilon_inverse(x) - ref)) < 1e-15
+
+
+# ------------------------------------------------ k-point sampling, q != 0
+
+@pytest.fixture(scope="module")
+def kmesh():
+    kp, ecut = sy.kmesh_system(7.0, 16, 3, 9, 3, 11, e_psi=3.0)
+    return kp, ecut
+
+
+@pytest.mark.parametrize("q", [(0.0, 0.0, 0.0), (0.5, 0.0, 0.0),
+                               (0.5, 0.5, 0.0)])
+def test_kq_pair_form_equals_eq2_over_ordered_pairs(kmesh, q):
+    """chi0(q) of the pair form (P from FFTs of products of periodic parts,
+    the e^{-iG0.r} of an umklapp included, each k weighted, Delta the sum
+    of resonant and anti-resonant terms) equals Eq. (2) evaluated literally
+    over every k and every ordered band pair with complex denominators and
+    Eq. (3)'s matrix elements from plane-wave coefficients, at G -> -G, for
+    this time-reversal symmetric k set."""
+    kp, ecut = kmesh
+    a, fft = 7.0, (16, 16, 16)
+    kq, g0 = sy.kmesh_q_map(kp, q)
+    mchi = rpa.chi_gvectors_q(a, ecut, q)
+    us = [rpa.orbitals_realspace(a, fft, k["miller"], k["coeff"]) for k in kp]
+    for om in (0.0, 0.7):
+        ps, ds = [], []
+        for i, k in enumerate(kp):
+            kk = kp[kq[i]]
+            p = rpa.pair_matrix_kq(a, fft, us[i][:3], us[kq[i]][3:], g0[i], mchi)
+            ps.append(p.reshape(-1, len(mchi)))
+            de = (kk["energy"][3:][None, :] - k["energy"][:3][:, None]).ravel()
+            ds.append(k["weight"] * (-4.0 * de / (de * de + om * om)))
+        pair = rpa.chibar(a, np.concatenate(ps), np.concatenate(ds))
+        lit = rpa.chi0_q_eq2_literal(a, kp, q, kq, g0, -mchi, om)
+        scale = np.max(np.abs(pair))
+        assert np.max(np.abs(lit - pair)) < 1e-13 * scale, (q, om)
+        assert np.max(np.abs(pair - pair.conj().T)) < 1e-15 * scale
+
+
+def test_kq_single_gamma_point_is_the_gamma_path(small):
+    """One k-point at Gamma with weight 1 and q = 0 reproduces the Gamma-point
+    correlation energy."""
+    s, w, mchi, _ = small
+    om, wt = sy.frequency_grid(16)
+    kp = [dict(miller=s.miller, coeff=s.coeff, energy=s.energy, n_v=s.n_v,
+               weight=1.0, kfrac=np.zeros(3))]
+    r = rpa.correlation_energy_q(s.a, s.fft, kp, (0, 0, 0), [0],
+                                 np.zeros((1, 3), dtype=int), s.ecut_chi, 10,
+                                 om, wt)
+    ref = rpa.correlation_energy(s.a, s.fft, s.miller, s.coeff, s.energy,
+                                 s.n_v, s.ecut_chi, 10, om, wt)
+    assert abs(r["ec"] - ref["ec"]) < 1e-13 * abs(ref["ec"])
+    assert np.array_equal(r["miller_chi"], mchi)
+
+
+def test_kq_energy_independent_of_the_q_representative(kmesh):
+    """q and q - G describe the same response: the chi0 set shifts by G, the
+    umklapp vectors change, and E_c(q) is unchanged; E_c(q) < 0 and the
+    static matrix is negative semidefinite."""
+    kp, ecut = kmesh
+    a, fft = 7.0, (16, 16, 16)
+    om, wt = sy.frequency_grid(16)
+    out = []
+    for q in ((0.5, 0.0, 0.0), (-0.5, 0.0, 0.0), (0.5, 0.0, 1.0)):
+        kq, g0 = sy.kmesh_q_map(kp, q)
+        r = rpa.correlation_energy_q(a, fft, kp, q, kq, g0, ecut, 20, om, wt)
+        out.append(r)
+        assert r["ec"] < 0 and np.all(r["integrand"] < 0)
+        assert np.max(np.linalg.eigvalsh(r["chibar0"])) < \
+            1e-14 * np.max(np.abs(r["chibar0"]))
+    for r in out[1:]:
+        assert abs(r["ec"] - out[0]["ec"]) < 1e-12 * abs(out[0]["ec"])
