@@ -245,6 +245,38 @@ def kmesh_system(a: float, fft: int, n_v: int, n_c: int, nsq_chi: int,
     return [kpts[k] for k in order], ecut_from_shell(a, nsq_chi)
 
 
+def kmesh_partners(kpoints, q0, seed: int, e_psi: float, a: float,
+                   sigma: float = 2.0):
+    """Weight-0 k-points at k + q0 for every k of `kpoints` (a small-q0
+    evaluation of the q -> 0 term): random orbitals on the sphere
+    |k + q0 + G|^2/2 <= e_psi and energies drawn as in kmesh_system, with
+    default_rng(seed), in the order of `kpoints`."""
+    b = 2.0 * math.pi / a
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in kpoints:
+        kv = np.asarray(k["kfrac"], dtype=np.float64) + np.asarray(q0)
+        nmax = int(math.floor(math.sqrt(2.0 * e_psi) / b)) + 2
+        r = np.arange(-nmax, nmax + 1)
+        n1, n2, n3 = np.meshgrid(r, r, r, indexing="ij")
+        m = np.stack([n1.ravel(), n2.ravel(), n3.ravel()], axis=1)
+        kg2 = b * b * np.sum((m + kv[None, :]) ** 2, axis=1)
+        m = m[0.5 * kg2 <= e_psi].astype(np.int32)
+        kg2 = b * b * np.sum((m + kv[None, :]) ** 2, axis=1)
+        n_v = int(k["n_v"])
+        nb = len(k["energy"])
+        z = (rng.standard_normal((len(m), nb)) + 1j *
+             rng.standard_normal((len(m), nb))) * np.exp(
+                 -kg2 / (2.0 * sigma ** 2))[:, None]
+        qr, _ = np.linalg.qr(z, mode="reduced")
+        eps_v = np.sort(rng.uniform(-1.0, 0.0, n_v))
+        eps_c = np.sort(0.1 + 4.9 * rng.uniform(0.0, 1.0, nb - n_v) ** (2.0 / 3.0))
+        out.append(dict(miller=m, coeff=np.ascontiguousarray(qr.T),
+                        energy=np.concatenate([eps_v, eps_c]), n_v=n_v,
+                        weight=0.0, kfrac=kv))
+    return out
+
+
 def kmesh_q_map(kpoints, q):
     """For q (fractions) on the mesh: kq[i], g0[i] with k_i + q = k_kq[i] + g0[i]."""
     kq, g0 = [], []

@@ -678,3 +678,43 @@ def test_kq_energy_independent_of_the_q_representative(kmesh):
             1e-14 * np.max(np.abs(r["chibar0"]))
     for r in out[1:]:
         assert abs(r["ec"] - out[0]["ec"]) < 1e-12 * abs(out[0]["ec"])
+
+
+def test_kq_zero_weight_partners_and_small_q0(kmesh):
+    """Weight-0 k-points add no pairs: the 8-point mesh with 8 more points of
+    weight 0 gives the same E_c(q).  With partners at k + q0 that carry the
+    orbitals of k, the G = 0 row of chi0(q0) vanishes (the orbitals of one k
+    are orthonormal) and E_c(q0) tends to the q = 0 value (G = 0 left out)
+    as q0^2: the odd orders cancel on a time-reversal symmetric mesh."""
+    kp, ecut = kmesh
+    a, fft = 7.0, (16, 16, 16)
+    om, wt = sy.frequency_grid(12)
+    q = (0.5, 0.0, 0.0)
+    kq, g0 = sy.kmesh_q_map(kp, q)
+    r1 = rpa.correlation_energy_q(a, fft, kp, q, kq, g0, ecut, 20, om, wt)
+    extra = sy.kmesh_partners(kp, (0.05, 0.0, 0.0), 5, 3.0, a)
+    kq2 = np.concatenate([kq, np.arange(8, 16)])
+    g02 = np.concatenate([g0, np.zeros((8, 3), dtype=int)])
+    r2 = rpa.correlation_energy_q(a, fft, kp + extra, q, kq2, g02, ecut, 20,
+                                  om, wt)
+    assert abs(r2["ec"] - r1["ec"]) < 1e-13 * abs(r1["ec"])
+    kq0, g00 = sy.kmesh_q_map(kp, (0.0, 0.0, 0.0))
+    r0 = rpa.correlation_energy_q(a, fft, kp, (0, 0, 0), kq0, g00, ecut, 500,
+                                  om, wt)
+    diffs = []
+    for e in (1e-2, 1e-3):
+        q0 = (e, 0.0, 0.0)
+        copies = [dict(k, weight=0.0, kfrac=np.asarray(k["kfrac"]) + q0)
+                  for k in kp]
+        kqc = np.concatenate([np.arange(8, 16)] * 2)
+        r = rpa.correlation_energy_q(a, fft, kp + copies, q0, kqc,
+                                     np.zeros((16, 3), dtype=int), ecut, 500,
+                                     om, wt)
+        m = r["miller_chi"]
+        i0 = int(np.flatnonzero(np.all(m == 0, axis=1))[0])
+        sv = np.sqrt(rpa.coulomb_q(a, m, q0))
+        chi0 = r["chibar0"] / (sv[:, None] * sv[None, :])
+        assert np.max(np.abs(chi0[i0])) < 1e-15 * np.max(np.abs(chi0))
+        diffs.append(r["ec"] - r0["ec"])
+    assert abs(diffs[1]) < abs(diffs[0]) and \
+        abs(diffs[0] / diffs[1] - 100.0) < 1.0, diffs
