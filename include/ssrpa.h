@@ -352,6 +352,56 @@ typedef enum ssrpa_stage {
 SSRPA_API ssrpa_status ssrpa_stage_times(ssrpa_system *sys, int enable,
                                          double *ms, int *launches);
 
+/* ---- k-point sampling and q != 0 (Eqs. 1-3 with the sums over k, q) ---- */
+
+typedef struct ssrpa_kmesh ssrpa_kmesh;
+
+/* A k mesh of n_k k-points for an insulator.  descs[i] holds the orbitals of
+ * k-point i as plane-wave coefficients: psi_nk(r) = Omega^-1/2 sum_G
+ * c_nk(G) e^{i(k+G).r}, `miller` the G (the sphere |k + G|^2/2 <= E_psi of
+ * that k), bands 0..n_v-1 occupied.  All descriptions share lattice, FFT
+ * grid, ecut_chi, n_v and n_c; occupation NULL, real_orbitals 0 and no
+ * Coulomb truncation.  kfrac (host, n_k x 3): k in fractions of b1, b2, b3;
+ * kweight (host, n_k): g_k of Eq. (2), >= 0 with at least one > 0; a
+ * k-point of weight 0 adds no pairs of its own and serves only as a k + q
+ * partner (for example the shifted points k + q0 of a small-q0 evaluation
+ * of the q -> 0 term, whose basis then holds G = 0).  The orbitals are
+ * staged once (their periodic parts u_nk on the grid) and stay resident. */
+SSRPA_API ssrpa_status ssrpa_kmesh_create(ssrpa_context *ctx, int n_k,
+                                          const ssrpa_system_desc *descs,
+                                          const double *kfrac,
+                                          const double *kweight,
+                                          void *hip_stream, ssrpa_kmesh **out);
+SSRPA_API ssrpa_status ssrpa_kmesh_destroy(ssrpa_kmesh *km);
+
+/* The chi0 basis at q (fractions of b1, b2, b3): the G with
+ * |G - q|^2 / 2 <= ecut_chi, G != q, lexicographic (see below for the sign
+ * convention).  miller (host, nullable) n_g x 3.  A q on the reciprocal
+ * lattice must be passed as q = 0 (SSRPA_ERR_ARG otherwise). */
+SSRPA_API ssrpa_status ssrpa_kmesh_chi_gvectors(const ssrpa_kmesh *km,
+                                                const double *q, int *n_g,
+                                                int32_t *miller);
+
+/* E_c(q), the q term of Eq. (1): kq[i] (n_k) and g0[i] (n_k x 3 ints) with
+ * k_i + q = k_kq[i] + g0[i] for every k-point of nonzero weight (entries of
+ * weight-0 points are not read).  Pair matrix with the bra
+ * on the valence side, P_vc,k(q; G) = int u*_vk u_c,k+q e^{iG.r} (u_{k+q}
+ * = e^{-iG0.r} u_kq[i]); Eq. (3)'s element is conj P(-G), so with
+ * v(G - q) = 4 pi / |G - q|^2 the matrices are those of the paper at -G,
+ * complex conjugated: the same eigenvalues, F_j and E_c(q).  chi0(q) =
+ * (1/Omega) sum_k g_k sum_vc conj(P) Delta P with Delta the resonant plus
+ * anti-resonant factor of reading Delta (exact for a time-reversal
+ * symmetric k mesh).  n_eig < N_G(q): static subspace, else the full basis.
+ * Outputs: *ec, integrand (host, nullable, n_freq), chi0 (device, nullable:
+ * the static chi0(q), N_G x N_G interleaved complex, rows and columns in
+ * ssrpa_kmesh_chi_gvectors order).  FP64.  Device work runs on hip_stream;
+ * the call returns after it finished.  E_c = sum_q w_q E_c(q) is left to the caller.
+ * SSRPA_ERR_ALIAS when N_i < 2 max|n_psi,i| + max|n_chi,i| + max|g0_i| + 1. */
+SSRPA_API ssrpa_status ssrpa_kmesh_correlation_energy(
+    ssrpa_kmesh *km, const double *q, const int32_t *kq, const int32_t *g0,
+    int n_eig, int n_freq, const double *omega, const double *weight,
+    double *ec, double *integrand, double *chi0, void *hip_stream);
+
 /* ---- serving: the same solve, enqueued without blocking the caller ------ */
 
 /* Start a whole E_c solve (system creation from `desc` is done by the

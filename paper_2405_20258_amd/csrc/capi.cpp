@@ -231,7 +231,7 @@ void invert3(const double *a, double *inv, double *det) {
   inv[8] = (a[0] * a[4] - a[1] * a[3]) / d;
 }
 
-double gnorm2(const Geometry &g, int n1, int n2, int n3) {
+double gnorm2(const Geometry &g, double n1, double n2, double n3) {
   double v[3];
   for (int c = 0; c < 3; ++c)
     v[c] = n1 * g.recip[c] + n2 * g.recip[3 + c] + n3 * g.recip[6 + c];
@@ -239,7 +239,11 @@ double gnorm2(const Geometry &g, int n1, int n2, int n3) {
 }
 
 // Validate a description and derive the geometry (no device work).
-Geometry make_geometry(const ssrpa_system_desc *d) {
+// qf: the q-point in fractions of the reciprocal vectors (nullptr: q = 0).
+// The chi0 set is {G : |G - q|^2 / 2 <= ecut_chi, G != q} with
+// v(G - q) = 4 pi / |G - q|^2 (the pair matrix has its bra on the valence
+// side, so Eq. (3)'s q + G appears as G - q, see the k-mesh entry points).
+Geometry make_geometry(const ssrpa_system_desc *d, const double *qf = nullptr) {
   SSRPA_REQUIRE(d, SSRPA_ERR_ARG, "null system description");
   SSRPA_REQUIRE(d->n_v >= 1 && d->n_c >= 1, SSRPA_ERR_ARG,
                 "need at least one valence and one conduction band");
@@ -273,9 +277,19 @@ Geometry make_geometry(const ssrpa_system_desc *d) {
     const double al = std::sqrt(g.lattice[3 * i] * g.lattice[3 * i] +
                                 g.lattice[3 * i + 1] * g.lattice[3 * i + 1] +
                                 g.lattice[3 * i + 2] * g.lattice[3 * i + 2]);
-    nb[i] = (int)std::floor(gmax * al / (2.0 * kPi)) + 1;
+    nb[i] = (int)std::floor(gmax * al / (2.0 * kPi)) + 1 +
+            (qf ? (int)std::ceil(std::fabs(qf[i])) : 0);
     SSRPA_REQUIRE(nb[i] < 512, SSRPA_ERR_ARG, "ecut_chi too large");
   }
+  const double q0 = qf ? qf[0] : 0.0, q1 = qf ? qf[1] : 0.0, q2 = qf ? qf[2] : 0.0;
+  const bool q_lattice = q0 == std::round(q0) && q1 == std::round(q1) &&
+                         q2 == std::round(q2);
+  SSRPA_REQUIRE(!qf || (std::isfinite(q0) && std::isfinite(q1) && std::isfinite(q2)),
+                SSRPA_ERR_ARG, "non-finite q");
+  // a q on the reciprocal lattice is q = 0 (pass it reduced)
+  SSRPA_REQUIRE(!q_lattice || (q0 == 0.0 && q1 == 0.0 && q2 == 0.0), SSRPA_ERR_ARG,
+                "q is a reciprocal lattice vector: pass q = 0");
+  g.q_zero = q_lattice;
   // slab truncation along a3: z_c = |a3|/2, a3 normal to a1 and a2
   g.truncation = d->coulomb_truncation;
   SSRPA_REQUIRE(g.truncation == 0 || g.truncation == 1, SSRPA_ERR_ARG,
@@ -298,8 +312,8 @@ Geometry make_geometry(const ssrpa_system_desc *d) {
   for (int a = -nb[0]; a <= nb[0]; ++a)
     for (int b = -nb[1]; b <= nb[1]; ++b)
       for (int c = -nb[2]; c <= nb[2]; ++c) {
-        if (a == 0 && b == 0 && c == 0) continue;
-        const double g2 = gnorm2(g, a, b, c);
+        if (g.q_zero && a == 0 && b == 0 && c == 0) continue;
+        const double g2 = gnorm2(g, a - q0, b - q1, c - q2);
         if (0.5 * g2 <= d->ecut_chi) {
           g.miller_chi.push_back(a);
           g.miller_chi.push_back(b);
@@ -308,7 +322,8 @@ Geometry make_geometry(const ssrpa_system_desc *d) {
           if (g.truncation == 1) {
             double gv[3];
             for (int q = 0; q < 3; ++q)
-              gv[q] = a * g.recip[q] + b * g.recip[3 + q] + c * g.recip[6 + q];
+              gv[q] = (a - q0) * g.recip[q] + (b - q1) * g.recip[3 + q] +
+                      (c - q2) * g.recip[6 + q];
             const double gz = gv[0] * nz[0] + gv[1] * nz[1] + gv[2] * nz[2];
             const double gpar = std::sqrt(std::max(0.0, g2 - gz * gz));
             v *= 1.0 - std::exp(-gpar * zc) * std::cos(gz * zc);
@@ -390,7 +405,7 @@ Geometry make_geometry(const ssrpa_system_desc *d) {
     if (col < 0) {
       col = g.ncol++;
       // the (0, 0) column skips n3 = 0 (G = 0 is not in the set)
-      g.zcol.insert(g.zcol.end(), {i, c, c, (a == 0 && b == 0) ? 1 : 0});
+      g.zcol.insert(g.zcol.end(), {i, c, c, (g.q_zero && a == 0 && b == 0) ? 1 : 0});
     }
     g.zcol[4 * col + 2] = c;  // n3 ascends within a column
     g.zcode[i] = col | ((((c % g.n3) + g.n3) % g.n3) << 20);
@@ -601,6 +616,50 @@ int resolve_block(System &sys, int requested, int n_eig, int n_freq) {
 }
 
 // Pair matrix of one block (cached when one block covers all valence bands).
+// Per-G tables of the system's geometry on the device (pair-transform
+// columns and scales, s(G) and r(G)), the error flag and the twiddles.  The
+// host tables stay in the system for the asynchronous copies.
+void upload_geometry(System &sys, hipStream_t s) {
+  Context *ctx = sys.ctx;
+  const Geometry &g = sys.geo;
+  const size_t box = (size_t)g.n1 * g.n2 * g.n3;
+  std::vector<int> &code = sys.code_host;
+  std::vector<double> &scale = sys.scale_host;
+  code.assign(g.n_g, 0);
+  // [0, ld_g) s(G) Omega/N, [ld_g, 2 ld_g) Omega/N, then s(G), r(G)
+  scale.assign(2 * ((size_t)g.ld_g + g.n_g), 0.0);
+  const double on = g.volume / (double)box;
+  for (int i = 0; i < g.n_g; ++i) {
+    const int a = g.miller_chi[3 * i], b = g.miller_chi[3 * i + 1],
+              c = g.miller_chi[3 * i + 2];
+    const int col = (a + g.m1) * g.n2 + ((b % g.n2) + g.n2) % g.n2;
+    const int k3 = ((c % g.n3) + g.n3) % g.n3;
+    code[i] = col | (k3 << 20);
+    scale[i] = on * g.store_scale[i];
+    scale[g.ld_g + i] = on;
+    scale[2 * (size_t)g.ld_g + i] = g.store_scale[i];
+    scale[2 * (size_t)g.ld_g + g.n_g + i] = g.rescale[i];
+  }
+  sys.gcol = DevBuf(ctx, sizeof(int) * g.n_g);
+  sys.sqrtv_d = DevBuf(ctx, sizeof(double) * scale.size());
+  SSRPA_HIP(hipMemcpyAsync(sys.gcol.as(), code.data(), sizeof(int) * g.n_g,
+                           hipMemcpyHostToDevice, s));
+  SSRPA_HIP(hipMemcpyAsync(sys.sqrtv_d.as(), scale.data(),
+                           sizeof(double) * scale.size(), hipMemcpyHostToDevice, s));
+  sys.zcode = DevBuf(ctx, sizeof(int) * g.n_g);
+  sys.cmap = DevBuf(ctx, sizeof(int) * g.cmap.size());
+  SSRPA_HIP(hipMemcpyAsync(sys.zcode.as(), g.zcode.data(), sizeof(int) * g.n_g,
+                           hipMemcpyHostToDevice, s));
+  SSRPA_HIP(hipMemcpyAsync(sys.cmap.as(), g.cmap.data(),
+                           sizeof(int) * g.cmap.size(), hipMemcpyHostToDevice, s));
+  sys.zcol = DevBuf(ctx, sizeof(int) * g.zcol.size());
+  SSRPA_HIP(hipMemcpyAsync(sys.zcol.as(), g.zcol.data(),
+                           sizeof(int) * g.zcol.size(), hipMemcpyHostToDevice, s));
+  sys.dev_flag = DevBuf(ctx, 64);
+  fill_zero(sys.dev_flag.as(), 64, s);
+  upload_twiddles(sys, s);
+}
+
 // Packed pair rows of the real path: F = M_v,c1 + i M_v,c2 for the
 // conduction pairs (c1, c2) packed into one orbital (planar complex rows).
 void packed_pairs(System &sys, int v0, int nvb, bool scaled, DevBuf &f,
@@ -613,7 +672,7 @@ void packed_pairs(System &sys, int v0, int nvb, bool scaled, DevBuf &f,
 // real path real rows of ld_g doubles in the cos/sin basis.
 const double *block_pairs(System &sys, int v0, int nvb, DevBuf &scratch,
                           hipStream_t s) {
-  const bool single = (v0 == 0 && nvb == sys.n_v);
+  const bool single = sys.sources.empty() && v0 == 0 && nvb == sys.n_v;
   const size_t bytes = (size_t)nvb * sys.n_c * (sys.real ? 1 : 2) *
                        sys.geo.ld_g * sizeof(double);
   if (single && sys.w_cache_valid) return sys.w_cache.as<double>();
@@ -648,6 +707,37 @@ const double *block_pairs(System &sys, int v0, int nvb, DevBuf &scratch,
   return dst.as<double>();
 }
 
+// Pair sources: the system's own pairs (one source), or the k-mesh sources.
+int n_sources(const System &sys) {
+  return sys.sources.empty() ? 1 : (int)sys.sources.size();
+}
+
+// Point the pair transform at source i; returns its weight g_k.
+double select_source(System &sys, int i) {
+  if (sys.sources.empty()) {
+    sys.src_psi_v = sys.src_psi_c = nullptr;
+    return 1.0;
+  }
+  const System::PairSource &p = sys.sources[i];
+  sys.src_psi_v = p.psi_v;
+  sys.src_psi_c = p.psi_c;
+  return p.weight;
+}
+
+// e_c - e_v for the rows of one block of source i (the occupations of
+// partially occupied systems included, see pair_energy_diffs).
+void source_energy_diffs(System &sys, int i, int v0, int nvb, double *de,
+                         hipStream_t s) {
+  if (sys.sources.empty()) {
+    pair_energy_diffs(sys.energy_d.as<double>(),
+                      sys.partial ? sys.occ_d.as<double>() : nullptr,
+                      sys.c_first, v0, nvb, sys.n_c, de, nullptr, s);
+  } else {
+    const System::PairSource &p = sys.sources[i];
+    pair_energy_diffs2(p.e_v, p.e_c, sys.c_first, v0, nvb, sys.n_c, de, s);
+  }
+}
+
 void static_chi0(System &sys, ssrpa_precision prec, int vb, hipStream_t s) {
   Context *ctx = sys.ctx;
   const Geometry &g = sys.geo;
@@ -656,13 +746,14 @@ void static_chi0(System &sys, ssrpa_precision prec, int vb, hipStream_t s) {
   DevBuf scratch, de, ws;
   DevBuf om(ctx, sizeof(double));
   fill_zero(om.as(), sizeof(double), s);
-  for (int v0 = 0; v0 < sys.n_v; v0 += vb) {
+  int blk = 0;
+  for (int si = 0; si < n_sources(sys); ++si)
+  for (int v0 = 0; v0 < sys.n_v; v0 += vb, ++blk) {
+    const double gk = select_source(sys, si);
     const int nvb = std::min(vb, sys.n_v - v0);
     const double *w = block_pairs(sys, v0, nvb, scratch, s);
     de.ensure(ctx, sizeof(double) * (size_t)nvb * sys.n_c, s);
-    pair_energy_diffs(sys.energy_d.as<double>(),
-                      sys.partial ? sys.occ_d.as<double>() : nullptr,
-                      sys.c_first, v0, nvb, sys.n_c, de.as<double>(), nullptr, s);
+    source_energy_diffs(sys, si, v0, nvb, de.as<double>(), s);
     HerkArgs h{};
     h.a = w;
     h.lda = 2L * g.ld_g;
@@ -673,18 +764,19 @@ void static_chi0(System &sys, ssrpa_precision prec, int vb, hipStream_t s) {
     h.de = de.as<double>();
     h.omega = om.as<double>();
     h.n_omega = 1;
-    h.wscale = 1.0 / g.volume;
+    h.wscale = gk / g.volume;
     h.timer = &sys.timer;
     h.stage = SSRPA_STAGE_CHI0_HERK;
     if (sys.real) {
       h.lda = g.ld_g;
       h.im_off = 0;
-      syrk(ctx, h, sys.chibar0.as<double>(), 0, v0 > 0 ? 1 : 0, ws, s);
+      syrk(ctx, h, sys.chibar0.as<double>(), 0, blk > 0 ? 1 : 0, ws, s);
     } else {
-      herk(ctx, h, prec, sys.chibar0.as<double>(), 0, v0 > 0 ? 1 : 0, ws, s);
+      herk(ctx, h, prec, sys.chibar0.as<double>(), 0, blk > 0 ? 1 : 0, ws, s);
     }
     block_done("static chi0", v0, nvb, sys.n_v, s);
   }
+  sys.src_psi_v = sys.src_psi_c = nullptr;
   SSRPA_HIP(hipStreamSynchronize(s));
   sys.have_chi0 = true;
   sys.sub = Subspace();
@@ -815,14 +907,15 @@ EcResult energy(System &sys, int n_eig, int n_freq, const double *omega,
   SSRPA_HIP(hipMemcpyAsync(w_d, weight, sizeof(double) * n_freq,
                            hipMemcpyHostToDevice, s));
   DevBuf scratch, de, ws, wsub, gws;
-  for (int v0 = 0; v0 < sys.n_v; v0 += vb) {
+  int blk = 0;
+  for (int si = 0; si < n_sources(sys); ++si)
+  for (int v0 = 0; v0 < sys.n_v; v0 += vb, ++blk) {
+    const double gk = select_source(sys, si);
     const int nvb = std::min(vb, sys.n_v - v0);
     const long rows = (long)nvb * sys.n_c;
     const double *w = block_pairs(sys, v0, nvb, scratch, s);
     de.ensure(ctx, sizeof(double) * rows, s);
-    pair_energy_diffs(sys.energy_d.as<double>(),
-                      sys.partial ? sys.occ_d.as<double>() : nullptr,
-                      sys.c_first, v0, nvb, sys.n_c, de.as<double>(), nullptr, s);
+    source_energy_diffs(sys, si, v0, nvb, de.as<double>(), s);
     HerkArgs h{};
     const long wcols = sys.real ? 1 : 2;   // real rows hold no imaginary plane
     if (full) {
@@ -857,15 +950,16 @@ EcResult energy(System &sys, int n_eig, int n_freq, const double *omega,
     h.de = de.as<double>();
     h.omega = om_d;
     h.n_omega = n_freq;
-    h.wscale = 1.0 / g.volume;
+    h.wscale = gk / g.volume;
     h.timer = &sys.timer;
     h.stage = SSRPA_STAGE_FREQ_HERK;
     if (sys.real)
-      syrk(ctx, h, chis, 2L * n * n, v0 > 0 ? 1 : 0, ws, s);
+      syrk(ctx, h, chis, 2L * n * n, blk > 0 ? 1 : 0, ws, s);
     else
-      herk(ctx, h, prec, chis, 2L * n * n, v0 > 0 ? 1 : 0, ws, s);
+      herk(ctx, h, prec, chis, 2L * n * n, blk > 0 ? 1 : 0, ws, s);
     block_done("subspace chi0(iw)", v0, nvb, sys.n_v, s);
   }
+  sys.src_psi_v = sys.src_psi_c = nullptr;
   if (full && g.rescaled) {
     // full basis: v^1/2 chi0(i w) v^1/2 = R (stored matrix) R
     const double *rs = sys.real ? sys.rscale.as<double>() + g.n_g
@@ -897,6 +991,17 @@ EcResult energy(System &sys, int n_eig, int n_freq, const double *omega,
 }  // namespace ssrpa
 
 using namespace ssrpa;
+
+// A k mesh: one system per k-point (orbitals staged on the grid as the
+// periodic parts u_nk(r)), their reduced coordinates and weights g_k.
+struct ssrpa_kmesh {
+  ssrpa_context *ctx = nullptr;
+  std::vector<ssrpa_system *> k;
+  std::vector<double> kfrac, kweight;
+  ssrpa_system_desc d0{};
+  std::vector<int32_t> miller0;
+  int mp[3] = {0, 0, 0};   // max |n_psi,i| over every k-point
+};
 
 struct ssrpa_ticket {
   std::thread th;
@@ -1060,19 +1165,6 @@ ssrpa_status ssrpa_system_create(ssrpa_context *ctx, const ssrpa_system_desc *de
                       "real orbitals: plane wave %d has no partner -G", p);
       }
     }
-    // per-G tables
-    std::vector<int> code(g.n_g);
-    std::vector<double> scale(2 * (size_t)g.ld_g, 0.0);
-    const double on = g.volume / (double)box;
-    for (int i = 0; i < g.n_g; ++i) {
-      const int a = g.miller_chi[3 * i], b = g.miller_chi[3 * i + 1],
-                c = g.miller_chi[3 * i + 2];
-      const int col = (a + g.m1) * g.n2 + ((b % g.n2) + g.n2) % g.n2;
-      const int k3 = ((c % g.n3) + g.n3) % g.n3;
-      code[i] = col | (k3 << 20);
-      scale[i] = on * g.store_scale[i];
-      scale[g.ld_g + i] = on;
-    }
     // from here on device work is queued on s: a failure waits for it
     // before the host sources above and the buffers below are released
     ApiCall call(s);
@@ -1100,32 +1192,7 @@ ssrpa_status ssrpa_system_create(ssrpa_context *ctx, const ssrpa_system_desc *de
       SSRPA_HIP(hipMemcpyAsync(sys->occ_d.as(), sys->occ.data(),
                                sizeof(double) * sys->n_b, hipMemcpyHostToDevice, s));
     }
-    sys->gcol = DevBuf(ctx, sizeof(int) * gg.n_g);
-    sys->sqrtv_d = DevBuf(ctx, sizeof(double) * 2 * ((size_t)gg.ld_g + gg.n_g));
-    SSRPA_HIP(hipMemcpyAsync(sys->gcol.as(), code.data(), sizeof(int) * gg.n_g,
-                             hipMemcpyHostToDevice, s));
-    SSRPA_HIP(hipMemcpyAsync(sys->sqrtv_d.as(), scale.data(),
-                             sizeof(double) * 2 * (size_t)gg.ld_g,
-                             hipMemcpyHostToDevice, s));
-    // s(G) and r(G) after the two scale tables (chi0 <-> symmetrized)
-    SSRPA_HIP(hipMemcpyAsync(sys->sqrtv_d.as<double>() + 2 * (size_t)gg.ld_g,
-                             gg.store_scale.data(), sizeof(double) * gg.n_g,
-                             hipMemcpyHostToDevice, s));
-    SSRPA_HIP(hipMemcpyAsync(sys->sqrtv_d.as<double>() + 2 * (size_t)gg.ld_g + gg.n_g,
-                             gg.rescale.data(), sizeof(double) * gg.n_g,
-                             hipMemcpyHostToDevice, s));
-    sys->zcode = DevBuf(ctx, sizeof(int) * gg.n_g);
-    sys->cmap = DevBuf(ctx, sizeof(int) * gg.cmap.size());
-    SSRPA_HIP(hipMemcpyAsync(sys->zcode.as(), gg.zcode.data(), sizeof(int) * gg.n_g,
-                             hipMemcpyHostToDevice, s));
-    SSRPA_HIP(hipMemcpyAsync(sys->cmap.as(), gg.cmap.data(),
-                             sizeof(int) * gg.cmap.size(), hipMemcpyHostToDevice, s));
-    sys->zcol = DevBuf(ctx, sizeof(int) * gg.zcol.size());
-    SSRPA_HIP(hipMemcpyAsync(sys->zcol.as(), gg.zcol.data(),
-                             sizeof(int) * gg.zcol.size(), hipMemcpyHostToDevice, s));
-    sys->dev_flag = DevBuf(ctx, 64);
-    fill_zero(sys->dev_flag.as(), 64, s);
-    upload_twiddles(*sys, s);
+    upload_geometry(*sys, s);
     // orbital staging: coefficients -> psi(r)
     DevBuf bidx_d(ctx, sizeof(int) * sys->n_pw);
     SSRPA_HIP(hipMemcpyAsync(bidx_d.as(), bidx.data(), sizeof(int) * sys->n_pw,
@@ -1412,6 +1479,168 @@ ssrpa_status ssrpa_epsilon_inverse(ssrpa_system *sys, int n_eig, int n_freq,
     SSRPA_REQUIRE(flag == 0, SSRPA_ERR_NUMERIC,
                   "1 - chi0_s v is not positive definite at some frequency");
   });
+}
+
+ssrpa_status ssrpa_kmesh_create(ssrpa_context *ctx, int n_k,
+                                const ssrpa_system_desc *descs,
+                                const double *kfrac, const double *kweight,
+                                void *hip_stream, ssrpa_kmesh **out) {
+  if (!ctx || !out || !descs || !kfrac || !kweight || n_k < 1) return SSRPA_ERR_ARG;
+  *out = nullptr;
+  auto *km = new (std::nothrow) ssrpa_kmesh();
+  if (!km) return SSRPA_ERR_NOMEM;
+  km->ctx = ctx;
+  ssrpa_status st = guarded(ctx, [&] {
+    const ssrpa_system_desc &a = descs[0];
+    for (int i = 0; i < n_k; ++i) {
+      const ssrpa_system_desc &d = descs[i];
+      SSRPA_REQUIRE(!d.occupation && !d.real_orbitals && !d.coulomb_truncation,
+                    SSRPA_ERR_ARG,
+                    "k meshes take insulators, complex orbitals and the bare Coulomb kernel");
+      SSRPA_REQUIRE(d.n_v == a.n_v && d.n_c == a.n_c && d.ecut_chi == a.ecut_chi &&
+                        d.coulomb_truncation == a.coulomb_truncation &&
+                        std::memcmp(d.fft, a.fft, sizeof(a.fft)) == 0 &&
+                        std::memcmp(d.lattice, a.lattice, sizeof(a.lattice)) == 0,
+                    SSRPA_ERR_ARG, "k-point %d differs in cell, grid, cutoff or bands", i);
+      SSRPA_REQUIRE(std::isfinite(kweight[i]) && kweight[i] >= 0.0, SSRPA_ERR_ARG,
+                    "k weight %d must be non-negative", i);
+      for (int c = 0; c < 3; ++c)
+        SSRPA_REQUIRE(std::isfinite(kfrac[3 * i + c]), SSRPA_ERR_ARG, "bad k-point");
+      for (int p = 0; p < d.n_pw; ++p)
+        for (int c = 0; c < 3; ++c)
+          km->mp[c] = std::max(km->mp[c], std::abs(d.miller[3 * p + c]));
+    }
+    SSRPA_REQUIRE(std::any_of(kweight, kweight + n_k, [](double w) { return w > 0.0; }),
+                  SSRPA_ERR_ARG, "every k weight is zero");
+    km->kfrac.assign(kfrac, kfrac + 3 * (size_t)n_k);
+    km->kweight.assign(kweight, kweight + n_k);
+    km->d0 = a;
+    km->miller0.assign(a.miller, a.miller + 3 * (size_t)a.n_pw);
+    km->d0.miller = km->miller0.data();
+    km->d0.coeff = nullptr;
+    km->d0.energy = nullptr;
+    for (int i = 0; i < n_k; ++i) {
+      ssrpa_system *sy = nullptr;
+      const ssrpa_status s2 = ssrpa_system_create(ctx, &descs[i], hip_stream, &sy);
+      if (s2 != SSRPA_OK) fail(s2, "k-point %d: %s", i, ctx->error().c_str());
+      km->k.push_back(sy);
+    }
+  });
+  if (st != SSRPA_OK) {
+    for (auto *sy : km->k) ssrpa_system_destroy(sy);
+    delete km;
+    return st;
+  }
+  *out = km;
+  return SSRPA_OK;
+}
+
+ssrpa_status ssrpa_kmesh_destroy(ssrpa_kmesh *km) {
+  if (!km) return SSRPA_ERR_ARG;
+  for (auto *sy : km->k) ssrpa_system_destroy(sy);
+  delete km;
+  return SSRPA_OK;
+}
+
+ssrpa_status ssrpa_kmesh_chi_gvectors(const ssrpa_kmesh *km, const double *q,
+                                      int *n_g, int32_t *miller) {
+  if (!km || !q || !n_g) return SSRPA_ERR_ARG;
+  return guarded(km->ctx, [&] {
+    ssrpa_system_desc d = km->d0;
+    // the geometry reads the cell, grid, cutoff and G set only
+    d.coeff = reinterpret_cast<const double *>(km->miller0.data());
+    d.energy = d.coeff;
+    const Geometry g = make_geometry(&d, q);
+    *n_g = g.n_g;
+    if (miller) std::memcpy(miller, g.miller_chi.data(), sizeof(int32_t) * 3 * g.n_g);
+  });
+}
+
+ssrpa_status ssrpa_kmesh_correlation_energy(
+    ssrpa_kmesh *km, const double *q, const int32_t *kq, const int32_t *g0,
+    int n_eig, int n_freq, const double *omega, const double *weight,
+    double *ec, double *integrand, double *chi0, void *hip_stream) {
+  if (!km || !q || !kq || !g0 || !ec || !omega || !weight) return SSRPA_ERR_ARG;
+  Context *ctx = km->ctx;
+  const int n_k = (int)km->k.size();
+  ssrpa_system *qs = nullptr;
+  std::vector<DevBuf> shifted;
+  hipStream_t s = Stream(hip_stream).s;
+  ssrpa_status st = guarded(ctx, [&] {
+    set_device(ctx);
+    SSRPA_REQUIRE(n_eig >= 1 && n_freq >= 1, SSRPA_ERR_ARG, "bad sizes");
+    int g0max[3] = {0, 0, 0};
+    for (int i = 0; i < n_k; ++i) {
+      if (km->kweight[i] == 0.0) continue;   // a k + q partner only
+      SSRPA_REQUIRE(kq[i] >= 0 && kq[i] < n_k, SSRPA_ERR_ARG, "kq[%d] out of range", i);
+      for (int c = 0; c < 3; ++c) {
+        // k_i + q = k_kq[i] + g0[i]
+        const double d = km->kfrac[3 * i + c] + q[c] - km->kfrac[3 * kq[i] + c] - g0[3 * i + c];
+        SSRPA_REQUIRE(std::fabs(d) < 1e-9, SSRPA_ERR_ARG,
+                      "k_%d + q is not k_%d + g0 (axis %d)", i, kq[i], c);
+        g0max[c] = std::max(g0max[c], std::abs(g0[3 * i + c]));
+      }
+    }
+    ssrpa_system_desc d = km->d0;
+    // the geometry reads the cell, grid, cutoff and G set only
+    d.coeff = reinterpret_cast<const double *>(km->miller0.data());
+    d.energy = d.coeff;
+    Geometry g = make_geometry(&d, q);
+    // no aliasing: products of orbitals of two k-points read at G - g0
+    const int nn[3] = {g.n1, g.n2, g.n3}, mc[3] = {g.m1, g.m2, g.m3};
+    for (int c = 0; c < 3; ++c)
+      SSRPA_REQUIRE(nn[c] >= 2 * km->mp[c] + mc[c] + g0max[c] + 1, SSRPA_ERR_ALIAS,
+                    "FFT size %d along axis %d is below the bound %d at this q",
+                    nn[c], c, 2 * km->mp[c] + mc[c] + g0max[c] + 1);
+    ApiCall call(s);
+    qs = new ssrpa_system();
+    const ssrpa_system *k0 = km->k[0];
+    qs->ctx = ctx;
+    qs->geo = std::move(g);
+    qs->n_v = k0->n_v;
+    qs->n_c = k0->n_c;
+    qs->c_first = k0->c_first;
+    qs->n_b = k0->n_b;
+    qs->n_orb = k0->n_b;
+    qs->orb_c0 = k0->c_first;
+    qs->orb_nc = k0->n_c;
+    upload_geometry(*qs, s);
+    const Geometry &gg = qs->geo;
+    const long box = (long)gg.n1 * gg.n2 * gg.n3;
+    shifted.resize(n_k);
+    for (int i = 0; i < n_k; ++i) {
+      if (km->kweight[i] == 0.0) continue;
+      const ssrpa_system *si = km->k[i], *sc = km->k[kq[i]];
+      const double *pv = si->psi_r.as<double>();
+      const int *gi = g0 + 3 * i;
+      if (gi[0] || gi[1] || gi[2]) {
+        // u_{k+q} = e^{-iG0.r} u_k': the phase goes on the valence side
+        shifted[i] = DevBuf(ctx, 2 * sizeof(double) * box * si->n_v);
+        phase_shift(si->psi_r.as<double>(), si->n_v, gg.n1, gg.n2, gg.n3, gi,
+                    shifted[i].as<double>(), s);
+        pv = shifted[i].as<double>();
+      }
+      qs->sources.push_back({pv, sc->psi_r.as<double>(), si->energy_d.as<double>(),
+                             sc->energy_d.as<double>(), km->kweight[i]});
+    }
+    const int vb = resolve_block(*qs, 0, n_eig, n_freq);
+    static_chi0(*qs, SSRPA_FP64, vb, s);
+    if (chi0) {
+      // the resident matrix is S chi0 S with S = diag v(G - q)^1/2
+      copy_interleaved(qs->chibar0.as<double>(), chi0, (size_t)gg.n_g * gg.n_g, s);
+      scale_sym(chi0, gg.n_g, qs->sqrtv_d.as<double>() + 2 * (size_t)gg.ld_g, 1, s);
+    }
+    if (n_eig < gg.n_g) compute_subspace(*qs, n_eig, SSRPA_BASIS_SYMMETRIZED, s);
+    EcResult r = energy(*qs, n_eig, n_freq, omega, weight, SSRPA_FP64, vb, 1.0,
+                        nullptr, s);
+    *ec = r.ec;
+    if (integrand) std::memcpy(integrand, r.f.data(), sizeof(double) * n_freq);
+  });
+  if (qs) {
+    (void)hipStreamSynchronize(s);
+    delete qs;
+  }
+  return st;
 }
 
 ssrpa_status ssrpa_trace_log(ssrpa_context *ctx, const double *x, int n,

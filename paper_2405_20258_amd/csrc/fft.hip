@@ -219,7 +219,8 @@ struct PairGeo {
 // acc(G) += Y(n1, n2; j3) e^{2 pi i n3 j3 / N3}.
 template <int GPT>
 __global__ __launch_bounds__(kPairThreads) void pair_fft_kernel(
-    const double2 *__restrict__ psi, PairGeo geo, int v0, int nvb, int n_v,
+    const double2 *__restrict__ psi, const double2 *__restrict__ psi_c,
+    PairGeo geo, int v0, int nvb, int n_v,
     int n_c, const int *__restrict__ gcol, const double *__restrict__ gscale,
     int n_g, int ld_g, const double2 *__restrict__ tw_g,
     double *__restrict__ w) {
@@ -246,7 +247,7 @@ __global__ __launch_bounds__(kPairThreads) void pair_fft_kernel(
   const long plane = (long)n1 * n2;
   const long box = plane * n3;
   const double2 *pv = psi + (long)(v0 + vl) * box;
-  const double2 *pc = psi + (long)(n_v + c) * box;
+  const double2 *pc = psi_c + (long)(n_v + c) * box;
 
   int code[GPT];
   double2 acc[GPT];
@@ -516,7 +517,8 @@ __device__ __forceinline__ void line_batch(int nl, Load load, Store store,
 // per plane suffices; with nxo = 1 a second barrier guards the buffer.
 template <int R1, int R2>
 __global__ __launch_bounds__((64 * LineSplit<R1, R2>::W)) void pair_plane_kernel(
-    const double2 *__restrict__ psi, int v0, int nvb, int n_v, int c0,
+    const double2 *__restrict__ psi, const double2 *__restrict__ psi_c, int v0,
+    int nvb, int n_v, int c0,
     int ncc, int n3, int m1, int m2, int nxo, const int *__restrict__ cmap_g,
     int ldy, const double2 *__restrict__ tw_g, double2 *__restrict__ yst) {
   using S = LineSplit<R1, R2>;
@@ -543,7 +545,7 @@ __global__ __launch_bounds__((64 * LineSplit<R1, R2>::W)) void pair_plane_kernel
   const long plane = (long)N * N;
   const long box = plane * n3;
   const double2 *pv = psi + (long)(v0 + vl) * box;
-  const double2 *pc = psi + (long)(n_v + c0 + cl) * box;
+  const double2 *pc = psi_c + (long)(n_v + c0 + cl) * box;
   double2 *yp = yst + ((long)vl * ncc + cl) * n3 * (long)ldy;
   constexpr int nbx = (N + S::L - 1) / S::L;
   const int nby = (ny1 + S::L - 1) / S::L;
@@ -746,7 +748,14 @@ void staged_pairs(System &sys, int v0, int nvb, const double *gscale,
     SSRPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds));
-  const double2 *psi = sys.psi_r.as<double2>();
+  // valence and conduction orbitals: the system's own, or those of a pair
+  // source (k and k + q of a k mesh)
+  const double2 *psi = sys.src_psi_v
+                            ? reinterpret_cast<const double2 *>(sys.src_psi_v)
+                            : sys.psi_r.as<double2>();
+  const double2 *psi_c = sys.src_psi_c
+                              ? reinterpret_cast<const double2 *>(sys.src_psi_c)
+                              : sys.psi_r.as<double2>();
   const double2 *tw = sys.fft_tw.as<double2>();
   double2 *yst = sys.ystage.as<double2>();
   // z: transform the columns when N3 has the same split, else direct sums
@@ -759,7 +768,7 @@ void staged_pairs(System &sys, int v0, int nvb, const double *gscale,
     const long blocks = (tiles + 7) / 8 * 8 * 64;
     SSRPA_REQUIRE(blocks < (1L << 31), SSRPA_ERR_ARG, "pair grid too large");
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * S::W), lds, s,
-                       psi, v0, nvb, sys.orb_c0, c0, ncc, g.n3, g.m1, g.m2, nxo,
+                       psi, psi_c, v0, nvb, sys.orb_c0, c0, ncc, g.n3, g.m1, g.m2, nxo,
                        sys.cmap.as<int>(), g.ldy, tw, yst);
     SSRPA_HIP(hipGetLastError());
     if (zfft) {
@@ -840,7 +849,12 @@ void launch_pair_matrix(System &sys, int v0, int nvb, bool scaled, double *w,
   const long blocks = (long)tiles_v * tiles_c * kTileV * kTileC;
   SSRPA_REQUIRE(blocks < (1L << 31), SSRPA_ERR_ARG, "pair grid too large");
   const int gpt = (g.n_g + kPairThreads - 1) / kPairThreads;
-  const double2 *psi = sys.psi_r.as<double2>();
+  const double2 *psi = sys.src_psi_v
+                            ? reinterpret_cast<const double2 *>(sys.src_psi_v)
+                            : sys.psi_r.as<double2>();
+  const double2 *psi_c = sys.src_psi_c
+                              ? reinterpret_cast<const double2 *>(sys.src_psi_c)
+                              : sys.psi_r.as<double2>();
   const int *gcol = sys.gcol.as<int>();
   const double2 *tw = sys.fft_tw.as<double2>();
 #define SSRPA_PAIR(G)                                                         \
@@ -850,7 +864,7 @@ void launch_pair_matrix(System &sys, int v0, int nvb, bool scaled, double *w,
           reinterpret_cast<const void *>(&pair_fft_kernel<G>),                \
           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));           \
     hipLaunchKernelGGL((pair_fft_kernel<G>), dim3((unsigned)blocks),          \
-                       dim3(kPairThreads), shmem, s, psi, pg, v0, nvb,        \
+                       dim3(kPairThreads), shmem, s, psi, psi_c, pg, v0, nvb, \
                        sys.orb_c0, sys.orb_nc, gcol, gscale, g.n_g, g.ld_g, tw, w); \
   } while (0)
   if (gpt <= 2) SSRPA_PAIR(2);

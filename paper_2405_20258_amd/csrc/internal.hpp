@@ -151,6 +151,7 @@ struct Geometry {
   std::vector<double> store_scale, rescale;
   bool rescaled = false;
   int truncation = 0;
+  bool q_zero = true;   // q = 0: G = 0 left out of the set
   // Real-orbital path: the cos/sin basis.  nh = n_g / 2 pairs {G, -G};
   // hpos[j] / hneg[j] = indices of the larger member G of pair j and of -G;
   // per G: neg = index of -G, hj = its pair, hs = +1 (G = H) or -1.
@@ -249,6 +250,11 @@ struct System {
   // per complex orbital: n_orb = n_v + orb_nc, orb_c0 = n_v,
   // orb_nc = (n_c + 1) / 2.
   int n_orb = 0, orb_c0 = 0, orb_nc = 0;
+  // When set, the pair transform takes valence orbital v from src_psi_v + v
+  // and conduction orbital orb_c0 + c from src_psi_c (the pair sources of a
+  // k mesh at q); otherwise both from psi_r.
+  // (complex interleaved grids)
+  const double *src_psi_v = nullptr, *src_psi_c = nullptr;
   bool real = false;             // real-orbital (cos/sin basis) path
   // real path tables (ints): hpos, hneg (nh each), neg, hj, hs (n_g each)
   DevBuf rtab;
@@ -278,6 +284,17 @@ struct System {
   bool w_cache_valid = false;
   // Device-side error flag (non-positive pivot, etc.): int.
   DevBuf dev_flag;
+  std::vector<int> code_host;      // sources of the per-G table copies
+  std::vector<double> scale_host;
+  // Pair sources of a k mesh at q (empty: the system's own pairs).  Each
+  // adds the rows of valence orbitals psi_v (energies e_v) against
+  // conduction orbitals c_first.. of psi_c (energies e_c), weight g_k.
+  struct PairSource {
+    const double *psi_v, *psi_c;   // complex interleaved grids
+    const double *e_v, *e_c;
+    double weight;
+  };
+  std::vector<PairSource> sources;
   StageTimer timer;
 };
 
@@ -424,6 +441,12 @@ void planar_to_interleaved(const double *src, int rows, int cols, int ld,
 void pair_energy_diffs(const double *energy, const double *occ, int c_first,
                        int v0, int nvb, int n_c, double *de, double *rowscale,
                        hipStream_t s);
+// de[p] = e_c[c_first + c] - e_v[v0 + v] for a block of a pair source.
+void pair_energy_diffs2(const double *e_v, const double *e_c, int c_first,
+                        int v0, int nvb, int n_c, double *de, hipStream_t s);
+// dst = src times e^{+iG0.r} on the grid, n_b orbitals (umklapp shift).
+void phase_shift(const double *src, long n_b, int n1, int n2, int n3,
+                 const int *g0, double *dst, hipStream_t s);
 // Scale column j < ncol of planar rows (stride 2 ld) by f[j], or by
 // sqrt(max(f[j], 0)) when from_eigs.
 void scale_cols(double *w, long rows, int ld, int ncol, const double *f,

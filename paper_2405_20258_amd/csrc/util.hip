@@ -61,6 +61,41 @@ __global__ void pair_de_kernel(const double *energy, const double *occ,
   }
 }
 
+// de[p] = e_c[c_first + c] - e_v[v0 + v] (two band lists: k and k + q)
+__global__ void pair_de2_kernel(const double *e_v, const double *e_c,
+                                int c_first, int v0, int nvb, int n_c,
+                                double *de) {
+  const long total = (long)nvb * n_c;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int v = v0 + (int)(idx / n_c), c = c_first + (int)(idx % n_c);
+    de[idx] = e_c[c] - e_v[v];
+  }
+}
+
+// dst[b][r] = src[b][r] e^{+i 2 pi (g0 . j / N)} for n_b orbitals on the
+// grid (x fastest): the valence orbitals shifted by an umklapp vector
+__global__ void phase_shift_kernel(const double2 *src, long n_b, int n1, int n2,
+                                   int n3, int g1, int g2, int g3,
+                                   double2 *dst) {
+  const long box = (long)n1 * n2 * n3;
+  const long total = box * n_b;
+  const double tp = 6.283185307179586476925286766559;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long)gridDim.x * blockDim.x) {
+    const long r = idx % box;
+    const int j1 = (int)(r % n1), j2 = (int)((r / n1) % n2), j3 = (int)(r / ((long)n1 * n2));
+    // phase fraction reduced exactly in integers before the sine and cosine
+    const long num = ((long)g1 * j1 * n2 * n3 + (long)g2 * j2 * n1 * n3 +
+                      (long)g3 * j3 * n1 * n2) % ((long)n1 * n2 * n3);
+    const double ang = tp * (double)num / (double)((long)n1 * n2 * n3);
+    double sn, cs;
+    sincos(ang, &sn, &cs);
+    const double2 a = src[idx];
+    dst[idx] = make_double2(a.x * cs - a.y * sn, a.x * sn + a.y * cs);
+  }
+}
+
 // w[p][:] *= rowscale[p] over planar rows of 2 ld doubles; grid (x: row
 // segments, y: rows).
 __global__ void scale_rows_kernel(double *w, long rows, int ld,
@@ -137,6 +172,22 @@ void pair_energy_diffs(const double *energy, const double *occ, int c_first,
   const long total = (long)nvb * n_c;
   hipLaunchKernelGGL(pair_de_kernel, dim3(grid_for(total)), dim3(256), 0, s,
                      energy, occ, c_first, v0, nvb, n_c, de, rowscale);
+  SSRPA_HIP(hipGetLastError());
+}
+
+void pair_energy_diffs2(const double *e_v, const double *e_c, int c_first,
+                        int v0, int nvb, int n_c, double *de, hipStream_t s) {
+  hipLaunchKernelGGL(pair_de2_kernel, dim3(grid_for((long)nvb * n_c)), dim3(256),
+                     0, s, e_v, e_c, c_first, v0, nvb, n_c, de);
+  SSRPA_HIP(hipGetLastError());
+}
+
+void phase_shift(const double *src, long n_b, int n1, int n2, int n3,
+                 const int *g0, double *dst, hipStream_t s) {
+  const long total = (long)n1 * n2 * n3 * n_b;
+  hipLaunchKernelGGL(phase_shift_kernel, dim3(grid_for(total)), dim3(256), 0, s,
+                     reinterpret_cast<const double2 *>(src), n_b, n1, n2, n3,
+                     g0[0], g0[1], g0[2], reinterpret_cast<double2 *>(dst));
   SSRPA_HIP(hipGetLastError());
 }
 

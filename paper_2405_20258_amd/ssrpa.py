@@ -125,6 +125,16 @@ ssrpa_server_memory = _sig("ssrpa_server_memory", _i,
 ssrpa_server_destroy = _sig("ssrpa_server_destroy", _i, [_p])
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = range(4)
 
+ssrpa_kmesh_create = _sig("ssrpa_kmesh_create", _i,
+                          [_p, _i, ctypes.POINTER(ssrpa_system_desc), _dp, _dp,
+                           _p, ctypes.POINTER(_p)])
+ssrpa_kmesh_destroy = _sig("ssrpa_kmesh_destroy", _i, [_p])
+ssrpa_kmesh_chi_gvectors = _sig("ssrpa_kmesh_chi_gvectors", _i,
+                                [_p, _dp, _ip, _i32p])
+ssrpa_kmesh_correlation_energy = _sig(
+    "ssrpa_kmesh_correlation_energy", _i,
+    [_p, _dp, _i32p, _i32p, _i, _i, _dp, _dp, _dp, _dp, _p, _p])
+
 EXPORTED = [n for n in dir() if n.startswith("ssrpa_") and
             n != "ssrpa_system_desc"]
 
@@ -369,6 +379,69 @@ class System:
             PRECISIONS[precision], valence_block, _stream(stream),
             ctypes.byref(t)))
         return Ticket(t, len(om))
+
+
+class KMesh:
+    """A resident k mesh (insulator): kpoints is a list of dicts with keys
+    miller, coeff, energy, n_v, weight (g_k) and kfrac (k in fractions of the
+    reciprocal vectors)."""
+
+    def __init__(self, ctx: Context, a, fft, kpoints, ecut_chi, stream=None):
+        self.ctx = ctx
+        keep = []
+        n = len(kpoints)
+        descs = (ssrpa_system_desc * n)()
+        for i, k in enumerate(kpoints):
+            descs[i] = make_desc(a, fft, k["miller"], k["coeff"], k["energy"],
+                                 k["n_v"], ecut_chi, keep)
+        kfrac = np.ascontiguousarray([k["kfrac"] for k in kpoints],
+                                     dtype=np.float64)
+        kw = np.ascontiguousarray([k["weight"] for k in kpoints],
+                                  dtype=np.float64)
+        h = _p()
+        _check(ssrpa_kmesh_create(ctx.handle, n, descs, _dptr(kfrac), _dptr(kw),
+                                  _stream(stream), ctypes.byref(h)), ctx.handle)
+        self.handle = h
+        ctx._systems.add(self)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            if self.ctx.handle:
+                ssrpa_kmesh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def gvectors(self, q) -> np.ndarray:
+        qa = np.ascontiguousarray(q, dtype=np.float64)
+        n = ctypes.c_int()
+        _check(ssrpa_kmesh_chi_gvectors(self.handle, _dptr(qa), ctypes.byref(n),
+                                        None), self.ctx.handle)
+        m = np.empty((n.value, 3), dtype=np.int32)
+        _check(ssrpa_kmesh_chi_gvectors(self.handle, _dptr(qa), ctypes.byref(n),
+                                        m.ctypes.data_as(_i32p)), self.ctx.handle)
+        return m
+
+    def correlation_energy(self, q, kq, g0, n_eig: int, omega, weight,
+                           chi0_dev=None, stream=None):
+        """E_c(q) and its integrand; kq, g0 with k_i + q = k_kq[i] + g0[i]."""
+        qa = np.ascontiguousarray(q, dtype=np.float64)
+        kq = np.ascontiguousarray(kq, dtype=np.int32)
+        g0 = np.ascontiguousarray(g0, dtype=np.int32).reshape(-1, 3)
+        om = np.ascontiguousarray(omega, dtype=np.float64)
+        wt = np.ascontiguousarray(weight, dtype=np.float64)
+        f = np.empty(len(om))
+        ec = ctypes.c_double()
+        _check(ssrpa_kmesh_correlation_energy(
+            self.handle, _dptr(qa), kq.ctypes.data_as(_i32p),
+            g0.ctypes.data_as(_i32p), n_eig, len(om), _dptr(om), _dptr(wt),
+            ctypes.byref(ec), _dptr(f), _addr(chi0_dev), _stream(stream)),
+            self.ctx.handle)
+        return ec.value, f
 
 
 class Ticket:

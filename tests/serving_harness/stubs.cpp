@@ -272,6 +272,23 @@ void pair_energy_diffs(const double *energy, const double *occ, int, int, int,
   });
 }
 
+void pair_energy_diffs2(const double *e_v, const double *e_c, int, int, int,
+                        int, double *de, hipStream_t s) {
+  mock_enqueue(s, [=] {
+    rd(e_v);
+    rd(e_c);
+    wr(de, 1.0);
+  });
+}
+
+void phase_shift(const double *src, long, int, int, int, const int *,
+                 double *dst, hipStream_t s) {
+  mock_enqueue(s, [=] {
+    rd(src);
+    wr(dst, 1.0);
+  });
+}
+
 void scale_rows(double *w, long, int, const double *rowscale, hipStream_t s,
                 bool) {
   mock_enqueue(s, [=] {
