@@ -58,6 +58,10 @@ def parse():
                     choices=["insulator", "fermi"],
                     help="fermi: Fermi-Dirac occupations (mu = 0.05 Ha, "
                          "kT = 0.01 Ha), partially occupied bands")
+    ap.add_argument("--kmesh", action="store_true",
+                    help="k-mesh workload instead: the medium cell on a "
+                         "2x2x2 mesh (32 x 512 bands per k-point), E_c(q) at "
+                         "q = (1/2, 0, 0), FP64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-bands", type=int, default=4,
                     help="valence bands in the oracle's timed sample")
@@ -286,6 +290,151 @@ def tiny_time_to_ec(ssrpa, stream):
             "rel_diff": abs(ec - ref["ec"]) / abs(ref["ec"])}
 
 
+def cpu_baseline_kmesh(kp, spec, ecut, q, kq, g0, n_vb):
+    """Time the oracle's chi0(q) contraction on the pairs of k-point 0."""
+    import numpy as np
+    from oracle import rpa
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()]
+                      or [os.cpu_count()])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count()
+    fft = (spec.fft,) * 3
+    t0 = time.perf_counter()
+    mchi = rpa.chi_gvectors_q(spec.a, ecut, q)
+    u0 = rpa.orbitals_realspace(spec.a, fft, kp[0]["miller"],
+                                kp[0]["coeff"][:n_vb])
+    k1 = kp[kq[0]]
+    u1 = rpa.orbitals_realspace(spec.a, fft, k1["miller"],
+                                k1["coeff"][k1["n_v"]:])
+    p = rpa.pair_matrix_kq(spec.a, fft, u0, u1, g0[0], mchi)
+    w = p.reshape(-1, len(mchi)) * np.sqrt(rpa.coulomb_q(spec.a, mchi, q))
+    de = (k1["energy"][k1["n_v"]:][None, :] -
+          kp[0]["energy"][:n_vb][:, None]).ravel()
+    d = kp[0]["weight"] * (-4.0 / de)
+    t1 = time.perf_counter()
+    cb = rpa.chibar(spec.a, w, d)
+    t2 = time.perf_counter()
+    del cb
+    ng = len(mchi)
+    flops = 4.0 * ng * ng * w.shape[0]
+    return {"value": flops / (t2 - t1) / 1e12, "unit": "TFLOP/s",
+            "cores": int(threads), "kind": "oracle",
+            "sample": (f"chi0(q) contraction of the oracle on {w.shape[0]} "
+                       f"pairs (k-point 0, valence bands 0-{n_vb - 1} x "
+                       f"{spec.n_c} conduction at k + q) of "
+                       f"{len(kp) * spec.n_v * spec.n_c}; W from the "
+                       f"oracle's FFT path ({t1 - t0:.1f} s, not in the "
+                       f"rate); contraction {t2 - t1:.2f} s"),
+            "host_cpus": os.cpu_count()}
+
+
+def kmesh_main(args):
+    """The k-mesh workload: E_c(q) of the medium cell on the 2x2x2 mesh."""
+    import numpy as np
+    import torch
+
+    from paper_2405_20258_amd import ssrpa
+    from synth import systems as sy
+    spec = sy.KMESH_MEDIUM
+    seed = sy.CONFIG_SEED_BASE[spec.name]
+    n_eig = args.n_eig or spec.n_eig
+    print(f"# generating {spec.name} (seed {seed})", file=sys.stderr,
+          flush=True)
+    kp, _ = sy.kmesh_system(spec.a, spec.fft, spec.n_v, spec.n_c,
+                            spec.nsq_chi, seed, e_psi=spec.e_psi,
+                            sigma=spec.sigma)
+    b = 2.0 * math.pi / spec.a
+    ecut = 0.5 * b * b * (spec.nsq_chi + 0.4)
+    q = sy.KMESH_Q
+    kq, g0 = sy.kmesh_q_map(kp, q)
+    fft = (spec.fft,) * 3
+    om, wt = ssrpa.frequency_grid(spec.n_freq)
+    # inputs resident in HBM
+    kp_dev = [dict(k, coeff=torch.from_numpy(k["coeff"]).to("cuda"))
+              for k in kp]
+    torch.cuda.synchronize()
+    ctx = ssrpa.Context(0)
+    stream = torch.cuda.current_stream()
+
+    def step(points):
+        km = ssrpa.KMesh(ctx, spec.a, fft, points, ecut, stream)
+        km.stage_times(True)
+        ec, _ = km.correlation_energy(q, kq, g0, n_eig, om, wt, stream=stream)
+        st = km.stage_times(False)
+        n_g = len(km.gvectors(q))
+        km.close()
+        return ec, st, n_g
+
+    for i in range(args.warmup):
+        ec, st, n_g = step(kp_dev)
+        print(f"# warmup {i}: E_c(q) = {ec!r}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stage = {k: [0.0, 0] for k in ssrpa.STAGES}
+    for i in range(args.steps):
+        ec, st, n_g = step(kp_dev)
+        for k, (ms, n) in st.items():
+            stage[k][0] += ms
+            stage[k][1] += n
+        print(f"# step {i}: E_c(q) = {ec!r}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    pairs = len(kp) * spec.n_v * spec.n_c
+    herk_flops_step = 4.0 * n_g * n_g * pairs
+    herk_ms, herk_launches = stage["chi0_herk"]
+    value = herk_flops_step * args.steps / (herk_ms * 1e-3) / 1e12
+    per_launch_flops = herk_flops_step * args.steps / herk_launches
+    avg_launch_s = herk_ms * 1e-3 / herk_launches
+    achieved = per_launch_flops / avg_launch_s / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": spec.name, "n_g": n_g, "pairs": pairs,
+                   "n_k": len(kp), "q": list(q), "n_eig": n_eig,
+                   "n_freq": spec.n_freq, "precision": "fp64",
+                   "fft": list(fft)},
+        "time_to_ec_ms": round(ms_per_step, 3),
+        "ec_q": ec,
+        "stage_ms_per_step": {k: round(v[0] / args.steps, 3)
+                              for k, v in stage.items()},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3),
+                     "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK["fp64"], 4),
+                     "traffic": None,
+                     "kernel": "herk_f64_kernel (static chi0(q), one launch "
+                               "per k-point)",
+                     "flops_per_launch": per_launch_flops,
+                     "avg_launch_ms": round(avg_launch_s * 1e3, 4)},
+    }
+    # the same solve from host orbitals, after the timed region
+    torch.cuda.synchronize()
+    th0 = time.perf_counter()
+    ec_h, _, _ = step(kp)
+    torch.cuda.synchronize()
+    out["time_to_ec_host_orbitals_ms"] = round((time.perf_counter() - th0) * 1e3, 3)
+    assert ec_h == ec, (ec_h, ec)
+    if not args.no_cpu_baseline:
+        print("# timing the oracle on a bounded sample", file=sys.stderr,
+              flush=True)
+        out["cpu_baseline"] = cpu_baseline_kmesh(kp, spec, ecut, q, kq, g0,
+                                                 args.cpu_sample_bands)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -293,6 +442,9 @@ def main():
                           "--gpus N > 1 is not supported (the multi-GPU "
                           "sharding is described in the design notes)"}))
         sys.exit(2)
+    if args.kmesh:
+        kmesh_main(args)
+        return
     import numpy as np
     import torch
 

@@ -402,6 +402,11 @@ SSRPA_API ssrpa_status ssrpa_kmesh_correlation_energy(
     int n_eig, int n_freq, const double *omega, const double *weight,
     double *ec, double *integrand, double *chi0, void *hip_stream);
 
+/* Stage times of the mesh's ssrpa_kmesh_correlation_energy calls, as
+ * ssrpa_stage_times for a system. */
+SSRPA_API ssrpa_status ssrpa_kmesh_stage_times(ssrpa_kmesh *km, int enable,
+                                               double *ms, int *launches);
+
 /* ---- serving: the same solve, enqueued without blocking the caller ------ */
 
 /* Start a whole E_c solve (system creation from `desc` is done by the

@@ -870,6 +870,26 @@ void compute_subspace(System &sys, int n_eig, int kind, hipStream_t s) {
   sys.sub = std::move(sub);
 }
 
+// Milliseconds and launch counts per stage from a timer's event pairs.
+void read_stage_times(StageTimer &tm, double *ms, int *launches) {
+  if (!ms && !launches) return;
+  double acc[SSRPA_N_STAGES] = {0};
+  int cnt[SSRPA_N_STAGES] = {0};
+  for (auto &r : tm.recs) {
+    SSRPA_HIP(hipEventSynchronize(r.b));
+    float t = 0.f;
+    SSRPA_HIP(hipEventElapsedTime(&t, r.a, r.b));
+    if (r.stage >= 0 && r.stage < SSRPA_N_STAGES) {
+      acc[r.stage] += t;
+      cnt[r.stage] += 1;
+    }
+  }
+  for (int i = 0; i < SSRPA_N_STAGES; ++i) {
+    if (ms) ms[i] = acc[i];
+    if (launches) launches[i] = cnt[i];
+  }
+}
+
 struct EcResult {
   double ec = 0.0;
   std::vector<double> f;
@@ -1001,6 +1021,7 @@ struct ssrpa_kmesh {
   ssrpa_system_desc d0{};
   std::vector<int32_t> miller0;
   int mp[3] = {0, 0, 0};   // max |n_psi,i| over every k-point
+  StageTimer timer;        // stage events of the per-q solves
 };
 
 struct ssrpa_ticket {
@@ -1604,6 +1625,7 @@ ssrpa_status ssrpa_kmesh_correlation_energy(
     qs->n_orb = k0->n_b;
     qs->orb_c0 = k0->c_first;
     qs->orb_nc = k0->n_c;
+    qs->timer.on = km->timer.on;
     upload_geometry(*qs, s);
     const Geometry &gg = qs->geo;
     const long box = (long)gg.n1 * gg.n2 * gg.n3;
@@ -1638,9 +1660,24 @@ ssrpa_status ssrpa_kmesh_correlation_energy(
   });
   if (qs) {
     (void)hipStreamSynchronize(s);
+    // the stage events outlive the per-q system
+    auto &r = qs->timer.recs;
+    km->timer.recs.insert(km->timer.recs.end(), r.begin(), r.end());
+    r.clear();
     delete qs;
   }
   return st;
+}
+
+ssrpa_status ssrpa_kmesh_stage_times(ssrpa_kmesh *km, int enable, double *ms,
+                                     int *launches) {
+  if (!km) return SSRPA_ERR_ARG;
+  return guarded(km->ctx, [&] {
+    set_device(km->ctx);
+    read_stage_times(km->timer, ms, launches);
+    km->timer.clear();
+    km->timer.on = enable != 0;
+  });
 }
 
 ssrpa_status ssrpa_trace_log(ssrpa_context *ctx, const double *x, int n,
@@ -1725,23 +1762,7 @@ ssrpa_status ssrpa_stage_times(ssrpa_system *sys, int enable, double *ms,
   if (!sys) return SSRPA_ERR_ARG;
   return guarded(sys->ctx, [&] {
     set_device(sys->ctx);
-    if (ms || launches) {
-      double acc[SSRPA_N_STAGES] = {0};
-      int cnt[SSRPA_N_STAGES] = {0};
-      for (auto &r : sys->timer.recs) {
-        SSRPA_HIP(hipEventSynchronize(r.b));
-        float t = 0.f;
-        SSRPA_HIP(hipEventElapsedTime(&t, r.a, r.b));
-        if (r.stage >= 0 && r.stage < SSRPA_N_STAGES) {
-          acc[r.stage] += t;
-          cnt[r.stage] += 1;
-        }
-      }
-      for (int i = 0; i < SSRPA_N_STAGES; ++i) {
-        if (ms) ms[i] = acc[i];
-        if (launches) launches[i] = cnt[i];
-      }
-    }
+    read_stage_times(sys->timer, ms, launches);
     sys->timer.clear();
     sys->timer.on = enable != 0;
   });

@@ -131,6 +131,8 @@ ssrpa_kmesh_create = _sig("ssrpa_kmesh_create", _i,
 ssrpa_kmesh_destroy = _sig("ssrpa_kmesh_destroy", _i, [_p])
 ssrpa_kmesh_chi_gvectors = _sig("ssrpa_kmesh_chi_gvectors", _i,
                                 [_p, _dp, _ip, _i32p])
+ssrpa_kmesh_stage_times = _sig("ssrpa_kmesh_stage_times", _i,
+                               [_p, _i, _dp, _ip])
 ssrpa_kmesh_correlation_energy = _sig(
     "ssrpa_kmesh_correlation_energy", _i,
     [_p, _dp, _i32p, _i32p, _i, _i, _dp, _dp, _dp, _dp, _p, _p])
@@ -425,6 +427,14 @@ class KMesh:
         _check(ssrpa_kmesh_chi_gvectors(self.handle, _dptr(qa), ctypes.byref(n),
                                         m.ctypes.data_as(_i32p)), self.ctx.handle)
         return m
+
+    def stage_times(self, enable: bool = True):
+        """{stage: (ms, launches)} since the last call; (re)starts timing."""
+        ms = np.zeros(len(STAGES))
+        n = (ctypes.c_int * len(STAGES))()
+        _check(ssrpa_kmesh_stage_times(self.handle, int(enable), _dptr(ms), n),
+               self.ctx.handle)
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(STAGES)}
 
     def correlation_energy(self, q, kq, g0, n_eig: int, omega, weight,
                            chi0_dev=None, stream=None):

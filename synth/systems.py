@@ -71,8 +71,16 @@ LARGE_SHARE = SystemSpec("large_share_a30_fft72_nv512_nc8192_ng15966",
                          a=30.0, fft=72, n_v=512, n_c=8192, nsq_chi=244,
                          n_freq=20, n_eig=1600, valence_block=32)
 
+# k-mesh workload: the medium cell on the 2 x 2 x 2 mesh of kmesh_system,
+# 32 x 512 bands per k-point (131072 pairs over the mesh), chi0 cutoff at
+# 0.5 b^2 (97 + 0.4), evaluated at q = (1/2, 0, 0)
+KMESH_MEDIUM = SystemSpec("kmesh_medium_a20_fft48_k8_nv32_nc512_q0.5",
+                          a=20.0, fft=48, n_v=32, n_c=512, nsq_chi=97,
+                          n_freq=16, n_eig=400)
+KMESH_Q = (0.5, 0.0, 0.0)
+
 CONFIG_SEED_BASE = {TINY.name: 1000, MEDIUM.name: 2000,
-                    LARGE_SHARE.name: 3000}
+                    LARGE_SHARE.name: 3000, KMESH_MEDIUM.name: 4000}
 
 
 def ecut_from_shell(a: float, nsq: int) -> float:
