@@ -72,9 +72,10 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-max-running", type=int, default=4)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
-                    help="also run one plain device copy of this many MiB "
-                         "(reference dispatch for the FETCH_SIZE/WRITE_SIZE "
-                         "counter scale)")
+                    help="also run two plain device copies of this many MiB "
+                         "(torch's elementwise kernel and the library's "
+                         "16-byte copy16_kernel: reference dispatches for "
+                         "the FETCH_SIZE/WRITE_SIZE counter scale)")
     ap.add_argument("--sweep", action="store_true",
                     help="also run the mixed-precision sweep: E_c at N_eig = "
                          "5/10/20%% of N_G in FP64, FP32 and BF16x3, with "
@@ -549,6 +550,8 @@ def main():
         torch.cuda.synchronize()
         torch.mul(src, 1.0, out=dst)     # one streaming read + write kernel
         torch.cuda.synchronize()
+        # the library's own 16-byte-wide copy (copy16_kernel)
+        ctx.device_copy(src, dst, n * 8, stream)
         out["copy_calibration_bytes"] = 2 * n * 8
         del src, dst
     if args.traffic_json and os.path.exists(args.traffic_json):

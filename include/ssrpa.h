@@ -325,6 +325,16 @@ SSRPA_API ssrpa_status ssrpa_trace_log_noalloc(ssrpa_context *ctx,
                                                double *f, int *flag,
                                                void *hip_stream);
 
+/* Measurement aid, no step of the method: a plain device-to-device copy of
+ * `bytes` (a multiple of 16; both pointers 16-byte aligned, device memory)
+ * with 16-byte loads and stores, the access width of the contraction
+ * kernels.  Its dispatch is the reference for scaling the beyond-L2 byte
+ * counters (FETCH_SIZE, WRITE_SIZE) of the other kernels.  Returns after
+ * the copy finished. */
+SSRPA_API ssrpa_status ssrpa_device_copy(ssrpa_context *ctx, const void *src,
+                                         void *dst, size_t bytes,
+                                         void *hip_stream);
+
 /* Gauss-Legendre rule with n points mapped to [0, inf) by
  * w = omega0 (1 + x)/(1 - x), weight 2 omega0 w_x / (1 - x)^2 (host). */
 SSRPA_API ssrpa_status ssrpa_frequency_grid(int n, double omega0,

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <chrono>
 #include <atomic>
 #include <cmath>
@@ -1667,6 +1668,22 @@ ssrpa_status ssrpa_kmesh_correlation_energy(
     delete qs;
   }
   return st;
+}
+
+ssrpa_status ssrpa_device_copy(ssrpa_context *ctx, const void *src, void *dst,
+                               size_t bytes, void *hip_stream) {
+  if (!ctx) return SSRPA_ERR_ARG;
+  return guarded(ctx, [&] {
+    set_device(ctx);
+    SSRPA_REQUIRE(src && dst && bytes % 16 == 0 &&
+                      (reinterpret_cast<uintptr_t>(src) & 15) == 0 &&
+                      (reinterpret_cast<uintptr_t>(dst) & 15) == 0,
+                  SSRPA_ERR_ARG, "copy needs 16-byte aligned pointers and sizes");
+    hipStream_t s = Stream(hip_stream).s;
+    ApiCall call(s);
+    if (bytes) device_copy16(src, dst, bytes, s);
+    SSRPA_HIP(hipStreamSynchronize(s));
+  });
 }
 
 ssrpa_status ssrpa_kmesh_stage_times(ssrpa_kmesh *km, int enable, double *ms,

@@ -13,6 +13,7 @@
 #include <cmath>
 
 #include "internal.hpp"
+#include "tiles.hpp"
 
 namespace ssrpa {
 
@@ -29,43 +30,6 @@ constexpr int kFlush = 1024;   // K rows accumulated in FP32 before flushing
 // lane l holds row 4 (l/16) + e, column l % 16.
 __device__ __forceinline__ int accf_row(int l, int e) { return 4 * (l >> 4) + e; }
 __device__ __forceinline__ int accf_col(int l) { return l & 15; }
-
-__device__ __forceinline__ int xcd_remap_m(int b, int total) {
-  const int per = total / 8;
-  if (b >= per * 8) return b;
-  return (b & 7) * per + (b >> 3);
-}
-
-// Same blocked lower-triangle tile order as the FP64 HERK (the reduction
-// kernel decodes tile ids with it).
-constexpr int kSBm = 8;
-__device__ __forceinline__ int2 tri_tile_m(int t, int T) {
-  const int nb = (T + kSBm - 1) / kSBm;
-  int acc = 0;
-  for (int bI = 0; bI < nb; ++bI) {
-    const int rI = min(kSBm, T - bI * kSBm);
-    for (int bJ = 0; bJ <= bI; ++bJ) {
-      const int cJ = min(kSBm, T - bJ * kSBm);
-      const int cnt = bJ < bI ? rI * cJ : rI * (rI + 1) / 2;
-      if (t < acc + cnt) {
-        const int l = t - acc;
-        int i, j;
-        if (bJ < bI) {
-          i = l / cJ;
-          j = l - i * cJ;
-        } else {
-          i = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
-          while (i * (i + 1) / 2 > l) --i;
-          while ((i + 1) * (i + 2) / 2 <= l) ++i;
-          j = l - i * (i + 1) / 2;
-        }
-        return make_int2(bI * kSBm + i, bJ * kSBm + j);
-      }
-      acc += cnt;
-    }
-  }
-  return make_int2(0, 0);
-}
 
 __device__ __forceinline__ double weight_m(const HerkArgs &h, long p, double om) {
   if (h.unit_weight) return 1.0;
@@ -122,7 +86,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g, int m_tiles,
   __shared__ float As[2][16][kT + 4];   // [part][k][m]
   __shared__ float Bs[2][16][kT + 4];   // [part][k][n]
   const int total = m_tiles * n_tiles;
-  const int b = xcd_remap_m(blockIdx.x, total);
+  const int b = xcd_remap(blockIdx.x, total);
   const int mt = b / n_tiles, nt = b % n_tiles;
   const long M0 = (long)mt * kT;
   const int N0 = nt * kT;
@@ -238,7 +202,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(GemmArgs g,
                                                          int n_tiles) {
   __shared__ BfTile At, Bt;   // At: [part][hl][m][k], Bt: [part][hl][n][k]
   const int total = m_tiles * n_tiles;
-  const int b = xcd_remap_m(blockIdx.x, total);
+  const int b = xcd_remap(blockIdx.x, total);
   const int mt = b / n_tiles, nt = b % n_tiles;
   const long M0 = (long)mt * kT;
   const int N0 = nt * kT;
@@ -479,9 +443,9 @@ __global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(
   extern __shared__ uint4 gsm[];
   uint4 *As = gsm;                          // [part][col][kGColStride]
   uint4 *Bs = gsm + 4 * kGT * kGColStride;
-  const int tile_id = xcd_remap_m(blockIdx.x, n_tiles);
+  const int tile_id = xcd_remap(blockIdx.x, n_tiles);
   const int split = blockIdx.y;
-  const int2 tile = tri_tile_m(tile_id, T);
+  const int2 tile = tri_tile_blocked(tile_id, T);
   const int I0 = tile.x * kGT, J0 = tile.y * kGT;
   const int kb0 = split * kb_per_split;
   const int kb1 = min(nkb, kb0 + kb_per_split);
@@ -636,9 +600,9 @@ __global__ __launch_bounds__(256, 2) void gram_f32_kernel(
   extern __shared__ uint4 fsm[];
   uint4 *As = fsm;                          // [part][col][kGColStride]
   uint4 *Bs = fsm + 2 * kGT * kGColStride;
-  const int tile_id = xcd_remap_m(blockIdx.x, n_tiles);
+  const int tile_id = xcd_remap(blockIdx.x, n_tiles);
   const int split = blockIdx.y;
-  const int2 tile = tri_tile_m(tile_id, T);
+  const int2 tile = tri_tile_blocked(tile_id, T);
   const int I0 = tile.x * kGT, J0 = tile.y * kGT;
   const int kb0 = split * kb_per_split;
   const int kb1 = min(nkb, kb0 + kb_per_split);
@@ -754,7 +718,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_wide_kernel(
   uint4 *As = wsm;                          // [part][row][kGColStride]
   uint4 *Bs = wsm + 4 * kGT * kGColStride;  // [part][col][kGColStride]
   const int total = m_tiles * n_tiles;
-  const int t = xcd_remap_m(blockIdx.x, total);
+  const int t = xcd_remap(blockIdx.x, total);
   const int mt = t / n_tiles, nt = t - mt * n_tiles;
   const long M0 = (long)mt * kGT;
   const int N0 = nt * kGT;
@@ -897,7 +861,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_wide_kernel(
   uint4 *Bs = fwsm + 2 * kGT * kGColStride;  // [part][col][kGColStride]
   float *Af = reinterpret_cast<float *>(As);
   const int total = m_tiles * n_tiles;
-  const int t = xcd_remap_m(blockIdx.x, total);
+  const int t = xcd_remap(blockIdx.x, total);
   const int mt = t / n_tiles, nt = t - mt * n_tiles;
   const long M0 = (long)mt * kGT;
   const int N0 = nt * kGT;
@@ -1023,7 +987,7 @@ __global__ void gram_reduce_kernel(const double *__restrict__ partial,
                                    double sign, double *__restrict__ out,
                                    int beta) {
   const int tile_id = blockIdx.x;
-  const int2 tile = tri_tile_m(tile_id, T);
+  const int2 tile = tri_tile_blocked(tile_id, T);
   const int I0 = tile.x * kGT, J0 = tile.y * kGT;
   constexpr int per = kGT * kGT / kGRedParts;
   const int e0 = blockIdx.y * per;

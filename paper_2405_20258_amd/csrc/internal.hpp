@@ -455,6 +455,9 @@ void scale_cols(double *w, long rows, int ld, int ncol, const double *f,
 // reciprocal when inverse).
 void scale_rows(double *w, long rows, int ld, const double *rowscale,
                 hipStream_t s, bool inverse = false);
+// Plain streaming copy of `bytes` (a multiple of 16, 16-byte aligned
+// pointers) with 16-byte loads and stores.
+void device_copy16(const void *src, void *dst, size_t bytes, hipStream_t s);
 void copy_interleaved(const double *src, double *dst, size_t n_complex,
                       hipStream_t s);
 

@@ -1,0 +1,51 @@
+// Tile orders shared by the contraction kernels (FP64 HERK, the FP32 and
+// BF16x3 Gram kernels and their split-K reductions): every kernel that
+// decodes a tile id must use the same order, so it is defined once here.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ssrpa {
+
+// Spread consecutive block ids over the 8 XCDs so that neighbouring tiles
+// (which share operand panels) run on the same XCD and share its L2.
+__device__ __forceinline__ int xcd_remap(int b, int total) {
+  const int per = total / 8;
+  if (b >= per * 8) return b;
+  return (b & 7) * per + (b >> 3);
+}
+
+// Lower-triangle tile t -> (I, J) in blocks of kSB x kSB tiles: blocks in
+// lower-triangle order, tiles row by row inside a block.  Consecutive tile
+// ids (which the XCD remap keeps on one XCD) then share few operand panels,
+// so they hit in that XCD's L2.  T = tiles per side.
+constexpr int kSB = 8;
+__device__ __forceinline__ int2 tri_tile_blocked(int t, int T) {
+  const int nb = (T + kSB - 1) / kSB;
+  int acc = 0;
+  for (int bI = 0; bI < nb; ++bI) {
+    const int rI = min(kSB, T - bI * kSB);
+    for (int bJ = 0; bJ <= bI; ++bJ) {
+      const int cJ = min(kSB, T - bJ * kSB);
+      const int cnt = bJ < bI ? rI * cJ : rI * (rI + 1) / 2;
+      if (t < acc + cnt) {
+        const int l = t - acc;
+        int i, j;
+        if (bJ < bI) {
+          i = l / cJ;
+          j = l - i * cJ;
+        } else {
+          i = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
+          while (i * (i + 1) / 2 > l) --i;
+          while ((i + 1) * (i + 2) / 2 <= l) ++i;
+          j = l - i * (i + 1) / 2;
+        }
+        return make_int2(bI * kSB + i, bJ * kSB + j);
+      }
+      acc += cnt;
+    }
+  }
+  return make_int2(0, 0);  // not reached for t < T (T + 1) / 2
+}
+
+}  // namespace ssrpa

@@ -1,5 +1,7 @@
 // Small layout kernels: zero fill, symmetric scaling, planar <-> interleaved
 // conversion and the per-pair energy gaps e_c - e_v.
+#include <cstdint>
+
 #include "internal.hpp"
 
 namespace ssrpa {
@@ -133,6 +135,18 @@ __global__ void copy_kernel(const double *src, double *dst, long n) {
     dst[i] = src[i];
 }
 
+// 16-byte loads and stores, the access width of the contraction kernels
+__global__ void copy16_kernel(const double2 *__restrict__ src,
+                              double2 *__restrict__ dst, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+bool aligned16(const void *p) {
+  return (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+}
+
 unsigned grid_for(long n) {
   return (unsigned)std::max(1L, std::min((n + 255) / 256, 65536L));
 }
@@ -212,7 +226,21 @@ void scale_cols(double *w, long rows, int ld, int ncol, const double *f,
 void copy_interleaved(const double *src, double *dst, size_t n_complex,
                       hipStream_t s) {
   const long n = (long)(2 * n_complex);
-  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(256), 0, s, src, dst,
+  if (aligned16(src) && aligned16(dst)) {
+    hipLaunchKernelGGL(copy16_kernel, dim3(grid_for(n / 2)), dim3(256), 0, s,
+                       reinterpret_cast<const double2 *>(src),
+                       reinterpret_cast<double2 *>(dst), n / 2);
+  } else {
+    hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(256), 0, s, src,
+                       dst, n);
+  }
+  SSRPA_HIP(hipGetLastError());
+}
+
+void device_copy16(const void *src, void *dst, size_t bytes, hipStream_t s) {
+  const long n = (long)(bytes / 16);
+  hipLaunchKernelGGL(copy16_kernel, dim3(grid_for(n)), dim3(256), 0, s,
+                     static_cast<const double2 *>(src), static_cast<double2 *>(dst),
                      n);
   SSRPA_HIP(hipGetLastError());
 }

@@ -98,6 +98,7 @@ ssrpa_correlation_energy = _sig("ssrpa_correlation_energy", _i,
 ssrpa_trace_log = _sig("ssrpa_trace_log", _i, [_p, _p, _i, _i, _d, _dp, _p])
 ssrpa_trace_log_noalloc = _sig("ssrpa_trace_log_noalloc", _i,
                                [_p, _p, _i, _i, _d, _p, _p, _p])
+ssrpa_device_copy = _sig("ssrpa_device_copy", _i, [_p, _p, _p, _sz, _p])
 ssrpa_frequency_grid = _sig("ssrpa_frequency_grid", _i, [_i, _d, _dp, _dp])
 ssrpa_stage_times = _sig("ssrpa_stage_times", _i, [_p, _i, _dp, _ip])
 STAGES = ["pair_fft", "chi0_herk", "eigen", "projection", "freq_herk",
@@ -250,6 +251,11 @@ class Context:
         _check(ssrpa_trace_log(self.handle, _addr(x_dev), n, n_mat, coupling,
                                _dptr(f), _stream(stream)), self.handle)
         return f
+
+    def device_copy(self, src_dev, dst_dev, nbytes: int, stream=None):
+        """Plain 16-byte-wide device copy (reference dispatch for counters)."""
+        _check(ssrpa_device_copy(self.handle, _addr(src_dev), _addr(dst_dev),
+                                 nbytes, _stream(stream)), self.handle)
 
     def __del__(self):
         try:

@@ -272,6 +272,15 @@ void pair_energy_diffs(const double *energy, const double *occ, int, int, int,
   });
 }
 
+void device_copy16(const void *src, void *dst, size_t, hipStream_t s) {
+  const double *a = static_cast<const double *>(src);
+  double *b = static_cast<double *>(dst);
+  mock_enqueue(s, [=] {
+    rd(a);
+    wr(b, 1.0);
+  });
+}
+
 void pair_energy_diffs2(const double *e_v, const double *e_c, int, int, int,
                         int, double *de, hipStream_t s) {
   mock_enqueue(s, [=] {
