@@ -81,9 +81,10 @@ __device__ double block_sum(double v, double *red) {
 // column and rewritten once per panel.
 constexpr int kNb = 32;     // panel width; 2 kNb panel products fit 64 slots
 constexpr int kHT = 64;     // hemv and her2k tile
-constexpr int kStripMax = 4;   // one wave per tile writes the column partials
-constexpr int kStripWide = 32; // tile rows from which strips hold 4 tiles
-constexpr int kStripNarrow = 24; // tile rows from which strips hold 2 tiles (1 below)
+constexpr int kStripMax = 8;   // tiles per hemv strip at most
+// hemv work-groups resident at once: 2 per CU (256 threads, 2 waves per
+// SIMD) on the 256 CUs of the chip
+constexpr int kHemvResident = 512;
 constexpr int kColTpe = 16;   // threads per element in the col kernel
 constexpr int kColRows = 256 / kColTpe;  // elements per col work-group
 
@@ -102,17 +103,21 @@ struct TriWork {
   long ldp;       // row length of pcol
 };
 
-// Tiles per hemv strip for a trailing block of nt tile rows: short strips
-// (more work-groups, shorter chains) while latency dominates, long ones
-// once the block is large enough to be bandwidth-bound.
-__host__ __device__ inline int strip_width(int nt) {
-  return nt >= kStripWide ? kStripMax : (nt >= kStripNarrow ? 2 : 1);
-}
-
 // Strips before tile row I: row I has I + 1 tiles in I / sw + 1 strips.
 __host__ __device__ inline long strip_prefix(int I, int sw) {
   const long q = I / sw, r = I - q * sw;
   return I + sw * q * (q - 1) / 2 + q * r;
+}
+
+// Tiles per hemv strip for a trailing block of nt tile rows: the shortest
+// strips (most work-groups, shortest serial chains) for which the strips
+// and the nt panel-product groups still fit one round of resident
+// work-groups; a second round that holds only a few groups would double
+// the step's time.
+__host__ __device__ inline int strip_width(int nt) {
+  for (int sw = 1; sw < kStripMax; ++sw)
+    if (strip_prefix(nt, sw) + nt <= kHemvResident) return sw;
+  return kStripMax;
 }
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
@@ -491,10 +496,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void h
     uau += uv.x * acc[0].x + uv.y * acc[0].y;
   }
   __syncthreads();
-  if (J0 + wave < J1) {
-    const int J = J0 + wave, cj = J * kHT + lane;
-    const double2 tot = cadd(cadd(cs[wave][0][lane], cs[wave][1][lane]),
-                             cadd(cs[wave][2][lane], cs[wave][3][lane]));
+  for (int jt = wave; J0 + jt < J1; jt += 4) {
+    const int J = J0 + jt, cj = J * kHT + lane;
+    const double2 tot = cadd(cadd(cs[jt][0][lane], cs[jt][1][lane]),
+                             cadd(cs[jt][2][lane], cs[jt][3][lane]));
     t.pcol[(long)I * t.ldp + cj] = tot;
     const double2 uv = uat(cj);
     uau += uv.x * tot.x + uv.y * tot.y;
@@ -594,43 +599,93 @@ struct TriReal {
   double *bounds;    // [lo, hi, tnorm, pivmin]
 };
 
-__global__ void tri_phase_kernel(const double2 *__restrict__ ec, TriReal r,
-                                 int n) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  // one thread walks the chain; e_{k-1} stays in a register and the
-  // pointers do not alias, so the loads of later rows run ahead
-  const double *__restrict__ dp = r.d;
-  double *__restrict__ ep = r.e;
-  double2 *__restrict__ php = r.phase;
-  double2 ph = make_double2(1.0, 0.0);
-  php[0] = ph;
-  double lo = INFINITY, hi = -INFINITY, emax2 = 0.0, tn = 0.0, ek_prev = 0.0;
-  for (int k = 0; k < n; ++k) {
-    double ek = 0.0;
+__device__ __forceinline__ double2 unit_mul(double2 a, double2 b) {
+  double2 p = make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  const double nr = hypot(p.x, p.y);
+  return make_double2(p.x / nr, p.y / nr);
+}
+
+// |e_k| and the phases phase_{k+1} = phase_k e_k / |e_k| (phase_0 = 1) by
+// a prefix product over one work-group of kPhaseThreads threads: each
+// thread takes a chunk of consecutive k, the chunk products are scanned in
+// LDS, and each thread then walks its chunk from its prefix.  The same pass
+// finds the Gershgorin bounds of T, its norm and the pivot minimum.
+constexpr int kPhaseThreads = 1024;
+__global__ __launch_bounds__(kPhaseThreads) void tri_phase_kernel(
+    const double2 *__restrict__ ec, TriReal r, int n) {
+  __shared__ double2 sc[kPhaseThreads];
+  __shared__ double red[4][kPhaseThreads / 64];
+  const int tid = threadIdx.x;
+  const int per = (n + kPhaseThreads - 1) / kPhaseThreads;
+  const int k0 = min(n, tid * per), k1 = min(n, k0 + per);
+  auto unit = [&](int k) {
+    const double2 c = ec[k];
+    const double ek = hypot(c.x, c.y);
+    return ek > 0.0 ? make_double2(c.x / ek, c.y / ek) : make_double2(1.0, 0.0);
+  };
+  // chunk product of q_k, k in [k0, k1) below n - 1
+  double2 loc = make_double2(1.0, 0.0);
+  for (int k = k0; k < k1 && k < n - 1; ++k) loc = unit_mul(loc, unit(k));
+  sc[tid] = loc;
+  __syncthreads();
+  for (int off = 1; off < kPhaseThreads; off <<= 1) {
+    const double2 v = tid >= off ? unit_mul(sc[tid - off], sc[tid]) : sc[tid];
+    __syncthreads();
+    sc[tid] = v;
+    __syncthreads();
+  }
+  // phase_k0 = product of the chunks before this one
+  double2 ph = tid > 0 ? sc[tid - 1] : make_double2(1.0, 0.0);
+  if (tid == 0) r.phase[0] = make_double2(1.0, 0.0);
+  double lo = INFINITY, hi = -INFINITY, emax2 = 0.0, tn = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    double ek = 0.0, ekp = 0.0;
     if (k < n - 1) {
       const double2 c = ec[k];
       ek = hypot(c.x, c.y);
-      ep[k] = ek;
-      // phase_{k+1} = phase_k e_k / |e_k|
-      double2 q = ek > 0.0 ? make_double2(c.x / ek, c.y / ek) : make_double2(1.0, 0.0);
-      ph = make_double2(ph.x * q.x - ph.y * q.y, ph.x * q.y + ph.y * q.x);
-      const double nr = hypot(ph.x, ph.y);
-      ph.x /= nr;
-      ph.y /= nr;
-      php[k + 1] = ph;
+      r.e[k] = ek;
+      ph = unit_mul(ph, unit(k));
+      r.phase[k + 1] = ph;
       emax2 = fmax(emax2, ek * ek);
     }
-    const double rad = ek_prev + ek, dk = dp[k];
+    if (k > 0) {
+      const double2 c = ec[k - 1];
+      ekp = hypot(c.x, c.y);
+    }
+    const double rad = ekp + ek, dk = r.d[k];
     lo = fmin(lo, dk - rad);
     hi = fmax(hi, dk + rad);
     tn = fmax(tn, fabs(dk) + rad);
-    ek_prev = ek;
   }
-  const double span = fmax(hi - lo, tn) * 2.0 * DBL_EPSILON + DBL_MIN;
-  r.bounds[0] = lo - span;
-  r.bounds[1] = hi + span;
-  r.bounds[2] = tn;
-  r.bounds[3] = fmax(DBL_MIN, DBL_MIN * emax2);
+  // reductions: min lo, max hi, max tn, max emax2
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o));
+    hi = fmax(hi, __shfl_xor(hi, o));
+    tn = fmax(tn, __shfl_xor(tn, o));
+    emax2 = fmax(emax2, __shfl_xor(emax2, o));
+  }
+  const int w = tid >> 6;
+  if ((tid & 63) == 0) {
+    red[0][w] = lo;
+    red[1][w] = hi;
+    red[2][w] = tn;
+    red[3][w] = emax2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int i = 1; i < kPhaseThreads / 64; ++i) {
+      lo = fmin(lo, red[0][i]);
+      hi = fmax(hi, red[1][i]);
+      tn = fmax(tn, red[2][i]);
+      emax2 = fmax(emax2, red[3][i]);
+    }
+    const double span = fmax(hi - lo, tn) * 2.0 * DBL_EPSILON + DBL_MIN;
+    r.bounds[0] = lo - span;
+    r.bounds[1] = hi + span;
+    r.bounds[2] = tn;
+    r.bounds[3] = fmax(DBL_MIN, DBL_MIN * emax2);
+  }
 }
 
 // number of eigenvalues of T below sigma
@@ -1185,7 +1240,7 @@ void eig_lowest(Context *ctx, const double *a_in, int n, int n_eig,
   r.e = rw.as<double>();
   r.phase = phase;
   r.bounds = rw.as<double>() + n;
-  hipLaunchKernelGGL(tri_phase_kernel, dim3(1), dim3(64), 0, s,
+  hipLaunchKernelGGL(tri_phase_kernel, dim3(1), dim3(kPhaseThreads), 0, s,
                      (const double2 *)t.e, r, n);
   hipLaunchKernelGGL(multisect_kernel, dim3(n_eig), dim3(64), 0, s, r, n,
                      n_eig, eigval);

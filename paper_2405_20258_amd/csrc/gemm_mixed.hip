@@ -7,9 +7,11 @@
 //            while staged; a product is hi*hi' + hi*lo' + lo*hi' (the lo*lo'
 //            term, ~2^-16 relative, is dropped) on v_mfma_f32_16x16x32_bf16.
 //
-// Accumulation is FP32 inside a K chunk of kFlush rows and FP64 across
-// chunks (and across split-K partials and valence blocks), which keeps the
-// FP32 rounding walk short.
+// Accumulation is FP32 inside a K chunk and FP64 across chunks (and across
+// split-K partials and valence blocks), which keeps the FP32 rounding walk
+// short: 1024 rows for FP32; 4096 rows for the BF16x3 Gram and projection
+// passes, whose split products already carry ~2^-17 relative error per term
+// (the longer walk quarters their FP64 flush traffic).
 #include <cmath>
 
 #include "internal.hpp"
@@ -351,7 +353,8 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(GemmArgs g,
 //    one sign, restored by the reduction), rounded to FP32.
 
 constexpr int kGT = 128;          // Gram tile side
-constexpr int kGFlushSteps = 32;  // K steps of 32 rows between FP64 flushes
+constexpr int kGFlushSteps = 128;  // K steps of 32 rows between FP64 flushes
+                                   // (4096 rows)
 constexpr int kGColStride = 5;    // uint4 per column in LDS (4 + 1 pad)
 constexpr size_t kGChunkBytes = size_t(1) << 30;  // per copy
 constexpr size_t kGLds = 2 * 4 * kGT * kGColStride * sizeof(uint4);
