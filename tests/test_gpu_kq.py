@@ -201,3 +201,29 @@ def test_kq_small_q0_tends_to_q_zero(env, meshes):
         diffs.append(ec - e0)
     _log(f"E_c(q0) - E_c(0) at q0 = 1e-2, 1e-3: {diffs}")
     assert abs(diffs[0] / diffs[1] - 100.0) < 1.0
+
+
+def test_kq_gamma_mesh_equals_the_gamma_path(env):
+    """One k-point at Gamma (weight 1) and q = 0 through the k-mesh entry
+    points gives the Gamma-path E_c of the same orbitals (two library
+    paths, same arithmetic up to the order of the pair sources)."""
+    from synth import systems as sy
+    torch, ssrpa, ctx = env
+    s = sy.make_system(sy.TINY, 1000)
+    om, wt = sy.frequency_grid(16)
+    g = ssrpa.System.from_synthetic(ctx, s)
+    g.chi0_static()
+    g.subspace(75)
+    ec_g, f_g = g.correlation_energy(75, om, wt)
+    g.close()
+    kp = [dict(miller=s.miller, coeff=s.coeff, energy=s.energy, n_v=s.n_v,
+               weight=1.0, kfrac=np.zeros(3))]
+    km = ssrpa.KMesh(ctx, s.a, s.fft, kp, s.ecut_chi)
+    try:
+        ec_k, f_k = km.correlation_energy((0.0, 0.0, 0.0), [0],
+                                          np.zeros((1, 3), np.int32), 75, om, wt)
+    finally:
+        km.close()
+    _log(f"Gamma path {ec_g!r}, k mesh {ec_k!r}")
+    assert abs(ec_k - ec_g) < 1e-12 * abs(ec_g)
+    assert np.max(np.abs(f_k - f_g) / np.abs(f_g)) < 1e-12
