@@ -331,6 +331,46 @@ def cpu_baseline_kmesh(kp, spec, ecut, q, kq, g0, n_vb):
             "host_cpus": os.cpu_count()}
 
 
+def pair_stage_roofline(s, mchi, stage, steps, vb, real):
+    """Algorithmic work of the pair transform (a2) against its two bounds.
+
+    Per transformed pair (a product of two orbitals): length-N lines along x
+    on every plane, along y for the 2 m1 + 1 x frequencies that reach the
+    chi0 set, along z for the chi0 columns (n1, n2); 5 N log2 N flops per
+    line.  Bytes: every orbital read once and W written once per valence
+    block (the fully fused minimum), and that plus one write and one read of
+    the staged columns (N3 complex per chi0 column and pair) of this design.
+    The real-orbital path transforms two conduction orbitals per product.
+    """
+    import numpy as np
+    n1, n2, n3 = (int(x) for x in s.fft)
+    m1 = int(np.max(np.abs(mchi[:, 0])))
+    ncol = len({(int(a), int(b)) for a, b in mchi[:, :2]})
+    n_g = len(mchi)
+    fl = lambda n: 5.0 * n * math.log2(n)
+    per_pair = fl(n1) * n2 * n3 + fl(n2) * (2 * m1 + 1) * n3 + fl(n3) * ncol
+    ms, launches = stage["pair_fft"]
+    blocks = -(-s.n_v // vb)
+    passes = launches / steps / blocks          # pair transforms per block
+    n_cp = -(-s.n_c // 2) if real else s.n_c    # conduction orbitals per product
+    products = passes * s.n_v * n_cp
+    flops = products * per_pair
+    box = n1 * n2 * n3 * 16.0
+    w_bytes = passes * s.n_v * s.n_c * n_g * (8.0 if real else 16.0)
+    b_min = passes * blocks * (vb + n_cp) * box + w_bytes
+    b_staged = b_min + 2.0 * products * ncol * n3 * 16.0
+    t = ms / steps * 1e-3
+    return {"time_ms": round(ms / steps, 3), "transforms_per_block": passes,
+            "products": products, "flops": flops,
+            "valu_tflops": round(flops / t / 1e12, 3), "valu_peak_tflops": 78.6,
+            "valu_frac": round(flops / t / 1e12 / 78.6, 4),
+            "alg_bytes_min": b_min, "alg_bytes_staged": b_staged,
+            "alg_gbs_staged": round(b_staged / t / 1e9, 1),
+            "hbm_peak_gbs": 8000.0,
+            "hbm_frac_staged": round(b_staged / t / 8e12, 4),
+            "roof_ms": round(max(b_min / 8e12, flops / 78.6e12) * 1e3, 3)}
+
+
 def kmesh_main(args):
     """The k-mesh workload: E_c(q) of the medium cell on the 2x2x2 mesh."""
     import numpy as np
@@ -477,6 +517,8 @@ def main():
     stream = torch.cuda.current_stream()
     vb = spec.valence_block or s.n_v
 
+    mchi = []
+
     def step():
         g = ssrpa.System(ctx, s.a, s.fft, s.miller, coeff_d, s.energy, s.n_v,
                          s.ecut_chi, stream, s.occ, None, real)
@@ -487,6 +529,8 @@ def main():
         st = g.stage_times(False)
         n_g = g.n_g
         n_pairs = g.n_v * g.n_c
+        if not mchi:
+            mchi.append(g.gvectors())
         g.close()
         return ec, st, n_g, n_pairs
 
@@ -543,6 +587,8 @@ def main():
                      "flops_per_launch": per_launch_flops,
                      "avg_launch_ms": round(avg_launch_s * 1e3, 4)},
     }
+    out["pair_stage"] = pair_stage_roofline(s, mchi[0], stage, args.steps, vb,
+                                            real)
     if args.copy_calibration_mib:
         n = args.copy_calibration_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
