@@ -1013,14 +1013,16 @@ __global__ __launch_bounds__(256) void wy_t_kernel(const double2 *__restrict__ a
     out[idx] = T[idx / kWy][idx % kWy];
 }
 
-// Partial W1 = V^H C over a chunk of rows: part[chunk][j][e].  The
+// Partial W1 = V^H C over a chunk of rows: part[chunk][j][e].  Chunks hold
+// chunk_rows rows (a multiple of kWySub).  The
 // reflectors of the block are staged in LDS kWySub rows at a time (zero
 // outside their support), so the row loop reads them as broadcasts and only
 // the C loads go to memory.
-constexpr int kWyRows = 64;
 constexpr int kWySub = 64;
+constexpr int kWyRows = 64;   // rows per chunk (one partial per chunk)
 __global__ __launch_bounds__(256) void wy_vhc_kernel(const double2 *__restrict__ a,
                                                      int n, int k0, int nb,
+                                                     int chunk_rows,
                                                      const double *__restrict__ c,
                                                      int ld_e, int n_eig,
                                                      double2 *__restrict__ part) {
@@ -1028,8 +1030,8 @@ __global__ __launch_bounds__(256) void wy_vhc_kernel(const double2 *__restrict__
   const int e = blockIdx.x * 64 + (threadIdx.x & 63);
   const int jg = threadIdx.x >> 6;           // 0..3, 8 reflectors each
   const int chunk = blockIdx.y;
-  const int r0 = k0 + 1 + chunk * kWyRows;
-  const int r1 = min(n, r0 + kWyRows);
+  const int r0 = k0 + 1 + chunk * chunk_rows;
+  const int r1 = min(n, r0 + chunk_rows);
   double2 acc[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
@@ -1063,38 +1065,47 @@ __global__ __launch_bounds__(256) void wy_vhc_kernel(const double2 *__restrict__
     if (e < ld_e) p[(long)(jg * 8 + q) * ld_e + e] = acc[q];
 }
 
-// W2 = T (sum over chunks of the partials): w2[j][e].  A block takes 16
-// columns e; thread (e, jq) sums the partials of reflectors 2 jq, 2 jq + 1.
-constexpr int kTwCols = 16;
+// W2 = T (sum over chunks of the partials): w2[j][e].  A block takes
+// kTwCols columns e; thread (e, j, h) sums the partials of reflector j over
+// the chunks ch = h mod 2, the two halves meet in LDS, then thread (e, j)
+// forms row j of T W1.
+constexpr int kTwCols = 4;
 __global__ __launch_bounds__(256) void wy_tw_kernel(const double2 *__restrict__ part,
                                                     int n_chunks,
                                                     const double2 *__restrict__ t,
                                                     int nb, int ld_e, int n_eig,
                                                     double2 *__restrict__ w2) {
-  __shared__ double2 w1[kWy][kTwCols];
+  __shared__ double2 w1[2][kWy][kTwCols];
   const int el = threadIdx.x % kTwCols;
-  const int jq = threadIdx.x / kTwCols;   // 0..15
+  const int j = (threadIdx.x / kTwCols) % kWy;
+  const int h = threadIdx.x / (kTwCols * kWy);   // 0, 1
   const int e = blockIdx.x * kTwCols + el;
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int j = 2 * jq + q;
-    double2 s = make_double2(0.0, 0.0);
-    if (e < n_eig)
-      for (int ch = 0; ch < n_chunks; ++ch) {
-        const double2 v = part[((long)ch * kWy + j) * ld_e + e];
-        s.x += v.x;
-        s.y += v.y;
-      }
-    w1[j][el] = s;
+  double2 sa = make_double2(0.0, 0.0), sb = sa;
+  if (e < n_eig) {
+    int ch = h;
+    for (; ch + 2 < n_chunks; ch += 4) {
+      const double2 v = part[((long)ch * kWy + j) * ld_e + e];
+      const double2 u = part[((long)(ch + 2) * kWy + j) * ld_e + e];
+      sa.x += v.x;
+      sa.y += v.y;
+      sb.x += u.x;
+      sb.y += u.y;
+    }
+    if (ch < n_chunks) {
+      const double2 v = part[((long)ch * kWy + j) * ld_e + e];
+      sa.x += v.x;
+      sa.y += v.y;
+    }
   }
+  w1[h][j][el] = make_double2(sa.x + sb.x, sa.y + sb.y);
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int j = 2 * jq + q;
+  if (h == 0) {
     double2 s = make_double2(0.0, 0.0);
     if (j < nb)
       for (int l = j; l < nb; ++l) {
-        const double2 tv = t[j * kWy + l], x = w1[l][el];
+        const double2 tv = t[j * kWy + l];
+        const double2 x = make_double2(w1[0][l][el].x + w1[1][l][el].x,
+                                       w1[0][l][el].y + w1[1][l][el].y);
         s.x += tv.x * x.x - tv.y * x.y;
         s.y += tv.x * x.y + tv.y * x.x;
       }
@@ -1286,10 +1297,11 @@ void eig_lowest(Context *ctx, const double *a_in, int n, int n_eig,
       const int k0 = b * kWy;
       const int nb = std::min(kWy, (n - 1) - k0);
       const int rows = n - k0 - 1;
-      const int chunks = (rows + kWyRows - 1) / kWyRows;
+      const int chunk_rows = kWyRows;
+      const int chunks = (rows + chunk_rows - 1) / chunk_rows;
       hipLaunchKernelGGL(wy_vhc_kernel, dim3(ctiles, chunks), dim3(256), 0, s,
-                         (const double2 *)t.a, n, k0, nb, (const double *)basis,
-                         ld_e, n_eig, part.as<double2>());
+                         (const double2 *)t.a, n, k0, nb, chunk_rows,
+                         (const double *)basis, ld_e, n_eig, part.as<double2>());
       hipLaunchKernelGGL(wy_tw_kernel, dim3((ld_e + kTwCols - 1) / kTwCols),
                          dim3(256), 0, s,
                          (const double2 *)part.as<double2>(), chunks,
