@@ -23,6 +23,7 @@
 #include <cmath>
 
 #include "internal.hpp"
+#include "tiles.hpp"
 
 namespace ssrpa {
 
@@ -40,13 +41,6 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
 __device__ __forceinline__ int acc_row(int l, int e) { return (l >> 4) + 4 * e; }
 __device__ __forceinline__ int acc_col(int l) { return l & 15; }
 
-// lower-triangle tile t -> (I, J), I >= J, row by row
-__device__ __forceinline__ int2 tri_tile(int t) {
-  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while (i * (i + 1) / 2 > t) --i;
-  while ((i + 1) * (i + 2) / 2 <= t) ++i;
-  return make_int2(i, t - i * (i + 1) / 2);
-}
 
 // ---------------------------------------------------------------- SYRK f64
 //
@@ -56,13 +50,15 @@ __device__ __forceinline__ int2 tri_tile(int t) {
 // Grid (lower-triangle tiles, K splits, frequencies); partial tiles
 // [w][split][tile][128][128].
 __global__ __launch_bounds__(256, 2) void syrk_f64_kernel(
-    HerkArgs h, int n_tiles, long kchunk, double *__restrict__ partial) {
+    HerkArgs h, int T, int n_tiles, long kchunk, double *__restrict__ partial) {
   __shared__ double As[kRK][kRT + kRPad];
   __shared__ double Bs[kRK][kRT + kRPad];
-  const int tile_id = blockIdx.x;
+  // neighbouring tiles (which share operand panels) on one XCD, in blocks
+  // of 8 x 8 tiles
+  const int tile_id = xcd_remap(blockIdx.x, n_tiles);
   const int split = blockIdx.y;
   const int om_i = blockIdx.z;
-  const int2 tile = tri_tile(tile_id);
+  const int2 tile = tri_tile_blocked(tile_id, T);
   const int I0 = tile.x * kRT, J0 = tile.y * kRT;
   const double om = h.unit_weight ? 0.0 : h.omega[om_i];
   const long kbeg = split * kchunk;
@@ -152,13 +148,13 @@ __global__ __launch_bounds__(256, 2) void syrk_f64_kernel(
 
 // Sum the split partials in order and write the symmetric matrices as
 // interleaved complex (imaginary part 0), both halves.
-__global__ void syrk_reduce_kernel(const double *__restrict__ partial,
+__global__ void syrk_reduce_kernel(const double *__restrict__ partial, int T,
                                    int n_tiles, int nsplit, int ncol,
                                    double *__restrict__ out, long out_stride,
                                    int beta) {
   const int tile_id = blockIdx.x;
   const int om_i = blockIdx.y;
-  const int2 tile = tri_tile(tile_id);
+  const int2 tile = tri_tile_blocked(tile_id, T);
   const int I0 = tile.x * kRT, J0 = tile.y * kRT;
   double *o = out + om_i * out_stride;
   for (int e = threadIdx.x; e < kRT * kRT; e += blockDim.x) {
@@ -456,7 +452,8 @@ SyrkPlan syrk_plan(const HerkArgs &h) {
   p.T = h.ld / kRT;
   p.n_tiles = p.T * (p.T + 1) / 2;
   const long per_split = (long)p.n_tiles * h.n_omega;
-  const long resident = 512;
+  // resident blocks: 4 per CU (33 KB of LDS and 112 VGPRs each)
+  const long resident = 1024;
   const long kr = std::max(1L, (h.k + kRK - 1) / kRK);
   const long smax =
       std::max(1L, std::min(kr / 8, std::max(4L, 4 * resident / std::max(1L, per_split))));
@@ -497,14 +494,14 @@ void syrk(Context *ctx, const HerkArgs &h, double *out, long out_stride,
     const int ti = (h.timer && h.timer->on) ? h.timer->start(h.stage, s) : -1;
     hipLaunchKernelGGL(syrk_f64_kernel,
                        dim3(p.n_tiles, (unsigned)p.nsplit, h.n_omega), dim3(256),
-                       0, s, h, p.n_tiles, p.kchunk, ws.as<double>());
+                       0, s, h, p.T, p.n_tiles, p.kchunk, ws.as<double>());
     SSRPA_HIP(hipGetLastError());
     if (ti >= 0) h.timer->stop(ti, s);
   } else {
     fill_zero(ws.as(), p.bytes, s);
   }
   hipLaunchKernelGGL(syrk_reduce_kernel, dim3(p.n_tiles, h.n_omega), dim3(256), 0,
-                     s, ws.as<double>(), p.n_tiles, (int)p.nsplit, h.ncol, out,
+                     s, ws.as<double>(), p.T, p.n_tiles, (int)p.nsplit, h.ncol, out,
                      out_stride, beta);
   SSRPA_HIP(hipGetLastError());
 }
