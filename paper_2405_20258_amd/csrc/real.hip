@@ -452,8 +452,8 @@ SyrkPlan syrk_plan(const HerkArgs &h) {
   p.T = h.ld / kRT;
   p.n_tiles = p.T * (p.T + 1) / 2;
   const long per_split = (long)p.n_tiles * h.n_omega;
-  // resident blocks: 4 per CU (33 KB of LDS and 112 VGPRs each)
-  const long resident = 1024;
+  // resident blocks: 2 per CU (224 VGPRs each)
+  const long resident = 512;
   const long kr = std::max(1L, (h.k + kRK - 1) / kRK);
   const long smax =
       std::max(1L, std::min(kr / 8, std::max(4L, 4 * resident / std::max(1L, per_split))));
