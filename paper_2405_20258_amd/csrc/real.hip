@@ -49,7 +49,8 @@ __device__ __forceinline__ int acc_col(int l) { return l & 15; }
 // x wscale (or 1 with unit_weight), applied to the B operand while staging.
 // Grid (lower-triangle tiles, K splits, frequencies); partial tiles
 // [w][split][tile][128][128].
-__global__ __launch_bounds__(256, 2) void syrk_f64_kernel(
+constexpr int kSyrkThreads = 512;   // 8 waves, each a 64 x 32 part of the tile
+__global__ __launch_bounds__(kSyrkThreads) void syrk_f64_kernel(
     HerkArgs h, int T, int n_tiles, long kchunk, double *__restrict__ partial) {
   __shared__ double As[kRK][kRT + kRPad];
   __shared__ double Bs[kRK][kRT + kRPad];
@@ -65,29 +66,31 @@ __global__ __launch_bounds__(256, 2) void syrk_f64_kernel(
   const long kend = min(h.k, kbeg + kchunk);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
-  d4 acc[4][4];
+  // 2 x 4 waves of 64 x 32: a 64-row accumulator quadrant per wave would
+  // take 128 VGPRs and hold the kernel at 2 waves per SIMD
+  const int wr = (wave >> 2) * 64, wc = (wave & 3) * 32;
+  d4 acc[4][2];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0, 0, 0, 0};
-  // staging: 8 double2 per thread; it < 4: A rows, it >= 4: B rows; row
-  // r0 + 4 (it & 3), columns 2 c2, 2 c2 + 1 of the 128-wide panel
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0, 0, 0, 0};
+  // staging: 4 double2 per thread; it < 2: A rows, it >= 2: B rows; row
+  // r0 + 8 (it & 1), columns 2 c2, 2 c2 + 1 of the 128-wide panel
   const int r0 = threadIdx.x >> 6, c2 = (threadIdx.x & 63) * 2;
-  double2 pv[8];
-  double pw[4];
+  double2 pv[4];
+  double pw[2];
   auto fetch = [&](long k0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int it = 0; it < 8; ++it) {
-      const long p = k0 + r0 + 4 * (it & 3);
-      const int col0 = it < 4 ? I0 : J0;
+    for (int it = 0; it < 4; ++it) {
+      const long p = k0 + r0 + 8 * (it & 1);
+      const int col0 = it < 2 ? I0 : J0;
       pv[it] = make_double2(0.0, 0.0);
       if (p < kend)
         pv[it] = *reinterpret_cast<const double2 *>(h.a + p * h.lda + col0 + c2);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const long p = k0 + r0 + 4 * q;
+    for (int q = 0; q < 2; ++q) {
+      const long p = k0 + r0 + 8 * q;
       pw[q] = 0.0;
       if (p < kend) {
         if (h.unit_weight) {
@@ -102,13 +105,13 @@ __global__ __launch_bounds__(256, 2) void syrk_f64_kernel(
   fetch(kbeg);
   for (long k0 = kbeg; k0 < kend; k0 += kRK) {
 #pragma unroll
-    for (int it = 0; it < 8; ++it) {
-      const int r = r0 + 4 * (it & 3);
-      if (it < 4) {
+    for (int it = 0; it < 4; ++it) {
+      const int r = r0 + 8 * (it & 1);
+      if (it < 2) {
         As[r][c2] = pv[it].x;
         As[r][c2 + 1] = pv[it].y;
       } else {
-        const double w = pw[it & 3];
+        const double w = pw[it & 1];
         Bs[r][c2] = pv[it].x * w;
         Bs[r][c2 + 1] = pv[it].y * w;
       }
@@ -119,16 +122,15 @@ __global__ __launch_bounds__(256, 2) void syrk_f64_kernel(
     for (int ks = 0; ks < kRK; ks += 4) {
       const int kr = ks + (lane >> 4);
       const int cl = lane & 15;
-      double a[4], b[4];
+      double a[4], b[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = As[kr][wr + i * 16 + cl];
-        b[i] = Bs[kr][wc + i * 16 + cl];
-      }
+      for (int i = 0; i < 4; ++i) a[i] = As[kr][wr + i * 16 + cl];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[kr][wc + j * 16 + cl];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = mfma64(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma64(a[i], b[j], acc[i][j]);
     }
     __syncthreads();
   }
@@ -137,7 +139,7 @@ __global__ __launch_bounds__(256, 2) void syrk_f64_kernel(
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int r = wr + i * 16 + acc_row(lane, e);
@@ -187,7 +189,7 @@ __global__ void syrk_reduce_kernel(const double *__restrict__ partial, int T,
 // C = A B for real operands: A m x k (row stride lda), B k x n (row stride
 // ldb), C m x n (row stride ldc); k and n multiples of 128 (zero padded).
 // Grid: m tiles x n tiles of 128 x 128.
-__global__ __launch_bounds__(256, 2) void gemm_real_f64_kernel(
+__global__ __launch_bounds__(kSyrkThreads) void gemm_real_f64_kernel(
     const double *__restrict__ A, long lda, const double *__restrict__ B,
     long ldb, double *__restrict__ C, long ldc, long m, int k, int n_tiles) {
   __shared__ double As[kRK][kRT + kRPad];  // [k][m]
@@ -197,34 +199,35 @@ __global__ __launch_bounds__(256, 2) void gemm_real_f64_kernel(
   const int N0 = nt * kRT;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
-  d4 acc[4][4];
+  // 2 x 4 waves of 64 x 32 (as the SYRK)
+  const int wr = (wave >> 2) * 64, wc = (wave & 3) * 32;
+  d4 acc[4][2];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0, 0, 0, 0};
-  // A: 128 rows x 16 k: thread -> (row t/2, k (t%2)*8 .. +8);
-  // B: 16 k x 128 cols: thread -> (k t/16, cols (t%16)*8 .. +8)
-  const int arow = threadIdx.x >> 1, akq = (threadIdx.x & 1) * 8;
-  const int bkr = threadIdx.x >> 4, bcq = (threadIdx.x & 15) * 8;
-  double2 av[4], bv[4];
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0, 0, 0, 0};
+  // A: 128 rows x 16 k: thread -> (row t/4, k (t%4)*4 .. +4);
+  // B: 16 k x 128 cols: thread -> (k t/32, cols (t%32)*4 .. +4)
+  const int arow = threadIdx.x >> 2, akq = (threadIdx.x & 3) * 4;
+  const int bkr = threadIdx.x >> 5, bcq = (threadIdx.x & 31) * 4;
+  double2 av[2], bv[2];
   auto fetch = [&](int k0) __attribute__((always_inline)) {
     const long r = M0 + arow;
 #pragma unroll
-    for (int x = 0; x < 4; ++x) av[x] = make_double2(0.0, 0.0);
+    for (int x = 0; x < 2; ++x) av[x] = make_double2(0.0, 0.0);
     if (r < m) {
       const double *src = A + r * lda + k0 + akq;
 #pragma unroll
-      for (int x = 0; x < 4; ++x) av[x] = *reinterpret_cast<const double2 *>(src + 2 * x);
+      for (int x = 0; x < 2; ++x) av[x] = *reinterpret_cast<const double2 *>(src + 2 * x);
     }
     const double *sb = B + (long)(k0 + bkr) * ldb + N0 + bcq;
 #pragma unroll
-    for (int x = 0; x < 4; ++x) bv[x] = *reinterpret_cast<const double2 *>(sb + 2 * x);
+    for (int x = 0; x < 2; ++x) bv[x] = *reinterpret_cast<const double2 *>(sb + 2 * x);
   };
   fetch(0);
   for (int k0 = 0; k0 < k; k0 += kRK) {
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
+    for (int x = 0; x < 2; ++x) {
       As[akq + 2 * x][arow] = av[x].x;
       As[akq + 2 * x + 1][arow] = av[x].y;
       Bs[bkr][bcq + 2 * x] = bv[x].x;
@@ -236,23 +239,22 @@ __global__ __launch_bounds__(256, 2) void gemm_real_f64_kernel(
     for (int ks = 0; ks < kRK; ks += 4) {
       const int kr = ks + (lane >> 4);
       const int cl = lane & 15;
-      double a[4], b[4];
+      double a[4], b[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = As[kr][wr + i * 16 + cl];
-        b[i] = Bs[kr][wc + i * 16 + cl];
-      }
+      for (int i = 0; i < 4; ++i) a[i] = As[kr][wr + i * 16 + cl];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[kr][wc + j * 16 + cl];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = mfma64(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma64(a[i], b[j], acc[i][j]);
     }
     __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const long r = M0 + wr + i * 16 + acc_row(lane, e);
@@ -493,7 +495,7 @@ void syrk(Context *ctx, const HerkArgs &h, double *out, long out_stride,
   if (h.k > 0) {
     const int ti = (h.timer && h.timer->on) ? h.timer->start(h.stage, s) : -1;
     hipLaunchKernelGGL(syrk_f64_kernel,
-                       dim3(p.n_tiles, (unsigned)p.nsplit, h.n_omega), dim3(256),
+                       dim3(p.n_tiles, (unsigned)p.nsplit, h.n_omega), dim3(kSyrkThreads),
                        0, s, h, p.T, p.n_tiles, p.kchunk, ws.as<double>());
     SSRPA_HIP(hipGetLastError());
     if (ti >= 0) h.timer->stop(ti, s);
@@ -515,7 +517,7 @@ void gemm_real(const double *a, long lda, const double *b, long ldb, double *c,
   const int n_tiles = n / kRT;
   SSRPA_REQUIRE(m_tiles * n_tiles < (1L << 31), SSRPA_ERR_ARG, "gemm too large");
   hipLaunchKernelGGL(gemm_real_f64_kernel, dim3((unsigned)(m_tiles * n_tiles)),
-                     dim3(256), 0, s, a, lda, b, ldb, c, ldc, m, k, n_tiles);
+                     dim3(kSyrkThreads), 0, s, a, lda, b, ldb, c, ldc, m, k, n_tiles);
   SSRPA_HIP(hipGetLastError());
 }
 
