@@ -70,7 +70,10 @@ def parse():
                          "Poisson 4/s) and report p50/p99 latency")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-rate", type=float, default=4.0)
-    ap.add_argument("--serve-max-running", type=int, default=4)
+    ap.add_argument("--serve-max-running", type=int, default=2,
+                    help="requests on the device at once (2 measured best on "
+                         "one box: 1.17 systems/s against 1.08 at 3 and 1.03 "
+                         "at 4)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run two plain device copies of this many MiB "
                          "(torch's elementwise kernel and the library's "
