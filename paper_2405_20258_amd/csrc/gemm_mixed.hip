@@ -439,10 +439,45 @@ __global__ __launch_bounds__(256) void split_rows_bf16_kernel(
   }
 }
 
+// d_p x for the 8 rows of one 16-byte quarter of a column: x rebuilt as
+// hi + lo (exact in FP32) from the unweighted split copy, multiplied in FP64
+// by the row weights and split again, as split_rows_bf16_kernel does from
+// the FP64 rows.  in[4] / out[4]: parts re hi, re lo, im hi, im lo.
+__device__ __forceinline__ void reweight_quarter(const uint4 (&in)[4],
+                                                 const float *__restrict__ w8,
+                                                 uint4 (&out)[4]) {
+  unsigned ph[4][4];   // [part][word]
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {   // re, im
+    const unsigned *hi = reinterpret_cast<const unsigned *>(&in[2 * c]);
+    const unsigned *lo = reinterpret_cast<const unsigned *>(&in[2 * c + 1]);
+#pragma unroll
+    for (int wd = 0; wd < 4; ++wd) {
+      unsigned short h2[2], l2[2];
+#pragma unroll
+      for (int hf = 0; hf < 2; ++hf) {
+        const unsigned short xh = (unsigned short)(hi[wd] >> (16 * hf));
+        const unsigned short xl = (unsigned short)(lo[wd] >> (16 * hf));
+        const double y = (double)(bf2f(xh) + bf2f(xl)) * (double)w8[2 * wd + hf];
+        split_bf16(y, h2[hf], l2[hf]);
+      }
+      ph[2 * c][wd] = h2[0] | ((unsigned)h2[1] << 16);
+      ph[2 * c + 1][wd] = l2[0] | ((unsigned)l2[1] << 16);
+    }
+  }
+#pragma unroll
+  for (int pp = 0; pp < 4; ++pp)
+    out[pp] = make_uint4(ph[pp][0], ph[pp][1], ph[pp][2], ph[pp][3]);
+}
+
+// kWJ: the J operand is formed while staging from the I copy (unweighted
+// split rows) and this frequency's row weights wrow (wj unused), so several
+// frequencies share one converted copy of the rows.
+template <bool kWJ>
 __global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(
     const uint4 *__restrict__ wi, const uint4 *__restrict__ wj, int ldb,
     int nkb, int T, int n_tiles, int kb_per_split,
-    double *__restrict__ partial) {
+    const float *__restrict__ wrow, double *__restrict__ partial) {
   extern __shared__ uint4 gsm[];
   uint4 *As = gsm;                          // [part][col][kGColStride]
   uint4 *Bs = gsm + 4 * kGT * kGColStride;
@@ -495,13 +530,36 @@ __global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(
     const uint4 *sj = wj + (long)kb * 16 * ldb + soff;
     // item it: operand it / 8 (I, then J), part (it / 2) % 4, columns
     // + 64 (it % 2)
+    if constexpr (kWJ) {
+      (void)sj;
+      const float *w8 = wrow + (long)kb * 32 + 8 * (soff & 3);
 #pragma unroll
-    for (int it = 0; it < 16; ++it) {
-      const int op = it >> 3, part = (it >> 1) & 3, hc = it & 1;
-      const uint4 v =
-          (op ? sj : si)[(part * ldb + (op ? J0 : I0) + 64 * hc) * 4];
-      const int col = (soff >> 2) + 64 * hc;
-      (op ? Bs : As)[(part * kGT + col) * kGColStride + (soff & 3)] = v;
+      for (int it = 0; it < 8; ++it) {
+        const int part = (it >> 1) & 3, hc = it & 1;
+        const uint4 v = si[(part * ldb + I0 + 64 * hc) * 4];
+        const int col = (soff >> 2) + 64 * hc;
+        As[(part * kGT + col) * kGColStride + (soff & 3)] = v;
+      }
+#pragma unroll
+      for (int hc = 0; hc < 2; ++hc) {
+        uint4 in[4], out[4];
+#pragma unroll
+        for (int pp = 0; pp < 4; ++pp) in[pp] = si[(pp * ldb + J0 + 64 * hc) * 4];
+        reweight_quarter(in, w8, out);
+        const int col = (soff >> 2) + 64 * hc;
+#pragma unroll
+        for (int pp = 0; pp < 4; ++pp)
+          Bs[(pp * kGT + col) * kGColStride + (soff & 3)] = out[pp];
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < 16; ++it) {
+        const int op = it >> 3, part = (it >> 1) & 3, hc = it & 1;
+        const uint4 v =
+            (op ? sj : si)[(part * ldb + (op ? J0 : I0) + 64 * hc) * 4];
+        const int col = (soff >> 2) + 64 * hc;
+        (op ? Bs : As)[(part * kGT + col) * kGColStride + (soff & 3)] = v;
+      }
     }
     __syncthreads();
     bf8 a[4][4];
@@ -593,6 +651,15 @@ __global__ __launch_bounds__(256) void row_weights_f32_kernel(
   const int kb = pos >> 4, t = pos & 15;
   const int r = kb * 16 + 4 * (t & 3) + (t >> 2);
   wp[pos] = r < nrows ? (float)weight_m(h, k0 + r, h.omega[om_i]) : 0.0f;
+}
+
+// Natural-order row weights of one K chunk for the BF16x3 Gram pass
+// (Delta_p(i w) x wscale in FP32); zero past the chunk, up to n_pos.
+__global__ __launch_bounds__(256) void row_weights_bf_kernel(
+    HerkArgs h, long k0, int nrows, int n_pos, int om_i, float *__restrict__ wp) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= n_pos) return;
+  wp[r] = r < nrows ? (float)weight_m(h, k0 + r, h.omega[om_i]) : 0.0f;
 }
 
 template <bool kWeighted>
@@ -1034,7 +1101,8 @@ __global__ void gram_reduce_kernel(const double *__restrict__ partial,
 //  * FP32: one copy of a K chunk.
 //  * BF16x3, one matrix: an I and a J copy of a K chunk.
 //  * BF16x3, several frequencies: the I copy of the whole K range (split
-//    once) and a J copy of a K chunk per frequency.
+//    once) and the row weights of a K chunk per frequency; the Gram kernel
+//    forms the weighted J operand from the I copy while staging it.
 struct GramPlan {
   int ldb, T, n_tiles, nsplit, kb_per_split, rows_step;
   bool resident_i;
@@ -1091,8 +1159,8 @@ static GramPlan gram_plan(const HerkArgs &h, ssrpa_precision prec) {
   p.resident_i = h.n_omega > 1 && !h.unit_weight;
   p.i_bytes = p.resident_i ? (size_t)(p.nchunks * p.kc) * row_bytes
                            : (size_t)p.kc * row_bytes;
-  p.j_bytes = bf ? (size_t)p.kc * row_bytes : 0;
-  p.w_bytes = (!bf && p.resident_i) ? (size_t)p.kc * sizeof(float) : 0;
+  p.j_bytes = (bf && !p.resident_i) ? (size_t)p.kc * row_bytes : 0;
+  p.w_bytes = p.resident_i ? (size_t)p.kc * sizeof(float) : 0;
   return p;
 }
 
@@ -1115,9 +1183,12 @@ void herk_gram(Context *ctx, const HerkArgs &h, ssrpa_precision prec,
   float *wrow = reinterpret_cast<float *>(ws.as<char>() + p.partial_bytes + p.i_bytes +
                                           p.j_bytes);
   static bool attr = [] {
-    SSRPA_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&gram_bf16x3_kernel),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)kGLds));
+    SSRPA_HIP(hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&gram_bf16x3_kernel<false>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGLds));
+    SSRPA_HIP(hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&gram_bf16x3_kernel<true>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGLds));
     return true;
   }();
   (void)attr;
@@ -1156,20 +1227,28 @@ void herk_gram(Context *ctx, const HerkArgs &h, ssrpa_precision prec,
       const int nrows = chunk_rows(c);
       const int nkb = (nrows + p.rows_step - 1) / p.rows_step;
       if (bf) {
-        const uint4 *ci = wi;
         if (p.resident_i) {
-          ci = wi + c * (p.kc / 32) * blk_stride;
+          // the J operand is weighted while staged from the resident I copy
+          const uint4 *ci = wi + c * (p.kc / 32) * blk_stride;
+          const int n_pos = nkb * 32;
           if (nkb > 0)
-            hipLaunchKernelGGL(split_rows_bf16_kernel<false>, split_grid(nkb),
-                               dim3(256), 0, s, h, k0, nrows, p.ldb, om, 1, wj,
-                               nullptr);
-        } else if (nkb > 0) {
-          // both copies from one read of the rows
-          hipLaunchKernelGGL(split_rows_bf16_kernel<true>, split_grid(nkb), dim3(256),
-                             0, s, h, k0, nrows, p.ldb, om, 1, wi, wj);
+            hipLaunchKernelGGL(row_weights_bf_kernel, dim3((n_pos + 255) / 256),
+                               dim3(256), 0, s, h, k0, nrows, n_pos, om, wrow);
+          hipLaunchKernelGGL(gram_bf16x3_kernel<true>, gg, dim3(256), kGLds, s, ci,
+                             ci, p.ldb, nkb, p.T, p.n_tiles, p.kb_per_split, wrow,
+                             partial);
+        } else {
+          // one matrix: both copies from one read of the rows (weighting J
+          // while staged would be redone by every tile of a column; with
+          // unit weights the J copy is kGJScale x, rounded independently of
+          // the I copy)
+          if (nkb > 0)
+            hipLaunchKernelGGL(split_rows_bf16_kernel<true>, split_grid(nkb),
+                               dim3(256), 0, s, h, k0, nrows, p.ldb, om, 1, wi, wj);
+          hipLaunchKernelGGL(gram_bf16x3_kernel<false>, gg, dim3(256), kGLds, s, wi,
+                             wj, p.ldb, nkb, p.T, p.n_tiles, p.kb_per_split, nullptr,
+                             partial);
         }
-        hipLaunchKernelGGL(gram_bf16x3_kernel, gg, dim3(256), kGLds, s, ci, wj,
-                           p.ldb, nkb, p.T, p.n_tiles, p.kb_per_split, partial);
       } else if (p.resident_i) {
         // unweighted rows converted once; this frequency's Delta per row
         const int n_pos = nkb * 16;
