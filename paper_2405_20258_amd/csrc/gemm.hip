@@ -165,9 +165,13 @@ __global__ __launch_bounds__(256, 2) void herk_f64_pair_kernel(
   __shared__ double As[2][kKc][kT + kPad];
   __shared__ double Bs[2][kKc][kT + kPad];
   __shared__ double wk[2][kKc];
-  const int tile_id = xcd_remap(blockIdx.x, n_tiles);
-  const int split = blockIdx.y;
-  const int om0 = 2 * blockIdx.z;
+  // each XCD takes a contiguous run of (frequency pair, split, tile)
+  const int blk = xcd_linear(n_tiles);
+  const int per_pair = n_tiles * (int)gridDim.y;
+  const int pair = blk / per_pair;
+  const int split = (blk - pair * per_pair) / n_tiles;
+  const int tile_id = blk - pair * per_pair - split * n_tiles;
+  const int om0 = 2 * pair;
   const bool two = om0 + 1 < h.n_omega;
   const int2 tile = tri_tile_blocked(tile_id, h.ld / kT);
   const int I0 = tile.x * kT, J0 = tile.y * kT;

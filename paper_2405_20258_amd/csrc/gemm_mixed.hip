@@ -341,9 +341,10 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(GemmArgs g,
 // K-blocked layout [kb][part][col][rows of the block] with the rows of one
 // column contiguous (64 B), so that a lane's MFMA operand (consecutive rows
 // of one column) is a single 16-byte load; a Gram kernel then forms
-// sum_p conj(a_p[I]) b_p[J] over 128 x 128 tiles of the lower triangle.
+// sum_p conj(a_p[I]) b_p[J] over 128 x 128 tiles of the lower triangle
+// (64 x 64 for outputs of at most kGSmallCols columns).
 // FP32 accumulators are added into the block's own FP64 partial tile every
-// 1024 rows, and gram_reduce_kernel sums the split-K partials in order and
+// 1024 (FP32) or 4096 (BF16x3) rows, and gram_reduce_kernel sums the split-K partials in order and
 // mirrors the Hermitian half (deterministic).
 //  * BF16x3: the I operand is the rows as they are, the J operand the rows
 //    times d_p; each real part is split hi + lo (bf16) and a product is
@@ -352,12 +353,20 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(GemmArgs g,
 //  * FP32: one copy of the rows times sqrt|d_p| (the d_p of one HERK have
 //    one sign, restored by the reduction), rounded to FP32.
 
-constexpr int kGT = 128;          // Gram tile side
+constexpr int kGT = 128;          // Gram tile side (GEMMs; Gram kernels of
+                                   // large outputs), also the column
+                                   // multiple of the converted copies
+constexpr int kGSmallTile = 64;   // Gram tile side of small outputs
+constexpr int kGSmallCols = 1024; // largest output side on kGSmallTile tiles
 constexpr int kGFlushSteps = 128;  // K steps of 32 rows between FP64 flushes
                                    // (4096 rows)
 constexpr int kGColStride = 5;    // uint4 per column in LDS (4 + 1 pad)
 constexpr size_t kGChunkBytes = size_t(1) << 30;  // per copy
 constexpr size_t kGLds = 2 * 4 * kGT * kGColStride * sizeof(uint4);
+// LDS of a Gram block: two operands of `parts` planes of ts columns
+constexpr size_t gram_lds(int parts, int ts) {
+  return 2 * (size_t)parts * ts * kGColStride * sizeof(uint4);
+}
 
 // Splits one copy of a K chunk: the I operand from the rows as they are
 // (weighted = 0), the J operand from d_p x (weighted = 1; kGJScale x for a
@@ -440,7 +449,7 @@ __global__ __launch_bounds__(256) void split_rows_bf16_kernel(
 }
 
 // d_p x for the 8 rows of one 16-byte quarter of a column: x rebuilt as
-// hi + lo (exact in FP32) from the unweighted split copy, multiplied in FP64
+// hi + lo (exact in FP32) from the unweighted split copy, multiplied in FP32
 // by the row weights and split again, as split_rows_bf16_kernel does from
 // the FP64 rows.  in[4] / out[4]: parts re hi, re lo, im hi, im lo.
 __device__ __forceinline__ void reweight_quarter(const uint4 (&in)[4],
@@ -458,8 +467,11 @@ __device__ __forceinline__ void reweight_quarter(const uint4 (&in)[4],
       for (int hf = 0; hf < 2; ++hf) {
         const unsigned short xh = (unsigned short)(hi[wd] >> (16 * hf));
         const unsigned short xl = (unsigned short)(lo[wd] >> (16 * hf));
-        const double y = (double)(bf2f(xh) + bf2f(xl)) * (double)w8[2 * wd + hf];
-        split_bf16(y, h2[hf], l2[hf]);
+        // FP32 product: its rounding (2^-24) is far below the lo part's
+        // (2^-17), and the split of an FP32 value is exact
+        const float y = (bf2f(xh) + bf2f(xl)) * w8[2 * wd + hf];
+        h2[hf] = f2bf(y);
+        l2[hf] = f2bf(y - bf2f(h2[hf]));
       }
       ph[2 * c][wd] = h2[0] | ((unsigned)h2[1] << 16);
       ph[2 * c + 1][wd] = l2[0] | ((unsigned)l2[1] << 16);
@@ -472,52 +484,56 @@ __device__ __forceinline__ void reweight_quarter(const uint4 (&in)[4],
 
 // kWJ: the J operand is formed while staging from the I copy (unweighted
 // split rows) and this frequency's row weights wrow (wj unused), so several
-// frequencies share one converted copy of the rows.
-template <bool kWJ>
-__global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(
+// frequencies share one converted copy of the rows.  kTs: output tile side,
+// 128 (4 waves of 64 x 64) or 64 (4 waves of 32 x 32, for small outputs
+// whose 128-wide tiles would be mostly padding).
+template <int kTs, bool kWJ>
+__global__ __launch_bounds__(256, kTs == 128 ? 2 : 4) void gram_bf16x3_kernel(
     const uint4 *__restrict__ wi, const uint4 *__restrict__ wj, int ldb,
     int nkb, int T, int n_tiles, int kb_per_split,
     const float *__restrict__ wrow, double *__restrict__ partial) {
+  constexpr int kS = kTs / 32;    // 16 x 16 MFMA tiles per wave side
+  constexpr int kHc = kTs / 64;   // 64-column halves of a panel
   extern __shared__ uint4 gsm[];
   uint4 *As = gsm;                          // [part][col][kGColStride]
-  uint4 *Bs = gsm + 4 * kGT * kGColStride;
-  const int tile_id = xcd_remap(blockIdx.x, n_tiles);
-  const int split = blockIdx.y;
+  uint4 *Bs = gsm + 4 * kTs * kGColStride;
+  const int blk = xcd_linear(n_tiles);
+  const int split = blk / n_tiles, tile_id = blk - split * n_tiles;
   const int2 tile = tri_tile_blocked(tile_id, T);
-  const int I0 = tile.x * kGT, J0 = tile.y * kGT;
+  const int I0 = tile.x * kTs, J0 = tile.y * kTs;
   const int kb0 = split * kb_per_split;
   const int kb1 = min(nkb, kb0 + kb_per_split);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  const int wr = (wave >> 1) * (kTs / 2), wc = (wave & 1) * (kTs / 2);
   const int q = lane >> 4, cl = lane & 15;
-  double *pt = partial + ((long)split * n_tiles + tile_id) * 2L * kGT * kGT;
-  f4 re[4][4], im[4][4];
+  double *pt = partial + ((long)split * n_tiles + tile_id) * 2L * kTs * kTs;
+  f4 re[kS][kS], im[kS][kS];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < kS; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kS; ++j) {
       re[i][j] = f4{0, 0, 0, 0};
       im[i][j] = f4{0, 0, 0, 0};
     }
   // partial tiles start zeroed (a fill before the first chunk): every flush
   // adds, so the code has no per-element branches
   // Per-lane offsets; the empty asm statements mark them as redefined on
-  // every use, so the compiler rebuilds the 64 flush addresses and the 16
-  // staging addresses from them instead of hoisting (and spilling) them.
-  int foff = (wr + accf_row(lane, 0)) * kGT + wc + accf_col(lane);
+  // every use, so the compiler rebuilds the flush and staging addresses
+  // from them instead of hoisting (and spilling) them.
+  int foff = (wr + accf_row(lane, 0)) * kTs + wc + accf_col(lane);
   int soff = (threadIdx.x >> 2) * 4 + (threadIdx.x & 3);
   auto flush = [&]() __attribute__((always_inline)) {
     asm volatile("" : "+v"(foff));
     double *pl = pt + foff;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < kS; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < kS; ++j)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          double *p0 = pl + (i * 16 + e) * kGT + j * 16;
+          double *p0 = pl + (i * 16 + e) * kTs + j * 16;
           p0[0] += (double)re[i][j][e];
-          p0[kGT * kGT] += (double)im[i][j][e];
+          p0[kTs * kTs] += (double)im[i][j][e];
           re[i][j][e] = 0.f;
           im[i][j][e] = 0.f;
         }
@@ -528,20 +544,19 @@ __global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(
     asm volatile("" : "+v"(soff));
     const uint4 *si = wi + (long)kb * 16 * ldb + soff;
     const uint4 *sj = wj + (long)kb * 16 * ldb + soff;
-    // item it: operand it / 8 (I, then J), part (it / 2) % 4, columns
-    // + 64 (it % 2)
+    // item it: operand, part, 64-column half hc
     if constexpr (kWJ) {
       (void)sj;
       const float *w8 = wrow + (long)kb * 32 + 8 * (soff & 3);
 #pragma unroll
-      for (int it = 0; it < 8; ++it) {
-        const int part = (it >> 1) & 3, hc = it & 1;
+      for (int it = 0; it < 4 * kHc; ++it) {
+        const int part = it / kHc, hc = it % kHc;
         const uint4 v = si[(part * ldb + I0 + 64 * hc) * 4];
         const int col = (soff >> 2) + 64 * hc;
-        As[(part * kGT + col) * kGColStride + (soff & 3)] = v;
+        As[(part * kTs + col) * kGColStride + (soff & 3)] = v;
       }
 #pragma unroll
-      for (int hc = 0; hc < 2; ++hc) {
+      for (int hc = 0; hc < kHc; ++hc) {
         uint4 in[4], out[4];
 #pragma unroll
         for (int pp = 0; pp < 4; ++pp) in[pp] = si[(pp * ldb + J0 + 64 * hc) * 4];
@@ -549,36 +564,36 @@ __global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(
         const int col = (soff >> 2) + 64 * hc;
 #pragma unroll
         for (int pp = 0; pp < 4; ++pp)
-          Bs[(pp * kGT + col) * kGColStride + (soff & 3)] = out[pp];
+          Bs[(pp * kTs + col) * kGColStride + (soff & 3)] = out[pp];
       }
     } else {
 #pragma unroll
-      for (int it = 0; it < 16; ++it) {
-        const int op = it >> 3, part = (it >> 1) & 3, hc = it & 1;
+      for (int it = 0; it < 8 * kHc; ++it) {
+        const int op = it / (4 * kHc), part = (it / kHc) % 4, hc = it % kHc;
         const uint4 v =
             (op ? sj : si)[(part * ldb + (op ? J0 : I0) + 64 * hc) * 4];
         const int col = (soff >> 2) + 64 * hc;
-        (op ? Bs : As)[(part * kGT + col) * kGColStride + (soff & 3)] = v;
+        (op ? Bs : As)[(part * kTs + col) * kGColStride + (soff & 3)] = v;
       }
     }
     __syncthreads();
-    bf8 a[4][4];
+    bf8 a[kS][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < kS; ++i)
 #pragma unroll
       for (int pp = 0; pp < 4; ++pp)
         a[i][pp] = __builtin_bit_cast(
-            bf8, As[(pp * kGT + wr + i * 16 + cl) * kGColStride + q]);
+            bf8, As[(pp * kTs + wr + i * 16 + cl) * kGColStride + q]);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kS; ++j) {
       bf8 b[4];
 #pragma unroll
       for (int pp = 0; pp < 4; ++pp)
         b[pp] = __builtin_bit_cast(
-            bf8, Bs[(pp * kGT + wc + j * 16 + cl) * kGColStride + q]);
+            bf8, Bs[(pp * kTs + wc + j * 16 + cl) * kGColStride + q]);
       const bf8 nbh = neg_bf8(b[0]), nbl = neg_bf8(b[1]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < kS; ++i) {
         // Re += ar br + ai bi;  Im += ar bi - ai br  (hi*hi + hi*lo + lo*hi)
         re[i][j] = mfmabf(a[i][0], b[0], re[i][j]);
         re[i][j] = mfmabf(a[i][0], b[1], re[i][j]);
@@ -662,46 +677,48 @@ __global__ __launch_bounds__(256) void row_weights_bf_kernel(
   wp[r] = r < nrows ? (float)weight_m(h, k0 + r, h.omega[om_i]) : 0.0f;
 }
 
-template <bool kWeighted>
-__global__ __launch_bounds__(256, 2) void gram_f32_kernel(
+template <int kTs, bool kWeighted>
+__global__ __launch_bounds__(256, kTs == 128 ? 2 : 4) void gram_f32_kernel(
     const uint4 *__restrict__ wf, int ldb, int nkb, int T, int n_tiles,
     int kb_per_split, const float *__restrict__ wrow,
     double *__restrict__ partial) {
+  constexpr int kS = kTs / 32;    // 16 x 16 MFMA tiles per wave side
+  constexpr int kHc = kTs / 64;   // 64-column halves of a panel
   extern __shared__ uint4 fsm[];
   uint4 *As = fsm;                          // [part][col][kGColStride]
-  uint4 *Bs = fsm + 2 * kGT * kGColStride;
-  const int tile_id = xcd_remap(blockIdx.x, n_tiles);
-  const int split = blockIdx.y;
+  uint4 *Bs = fsm + 2 * kTs * kGColStride;
+  const int blk = xcd_linear(n_tiles);
+  const int split = blk / n_tiles, tile_id = blk - split * n_tiles;
   const int2 tile = tri_tile_blocked(tile_id, T);
-  const int I0 = tile.x * kGT, J0 = tile.y * kGT;
+  const int I0 = tile.x * kTs, J0 = tile.y * kTs;
   const int kb0 = split * kb_per_split;
   const int kb1 = min(nkb, kb0 + kb_per_split);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  const int wr = (wave >> 1) * (kTs / 2), wc = (wave & 1) * (kTs / 2);
   const int q = lane >> 4, cl = lane & 15;
-  double *pt = partial + ((long)split * n_tiles + tile_id) * 2L * kGT * kGT;
-  f4 re[4][4], im[4][4];
+  double *pt = partial + ((long)split * n_tiles + tile_id) * 2L * kTs * kTs;
+  f4 re[kS][kS], im[kS][kS];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < kS; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kS; ++j) {
       re[i][j] = f4{0, 0, 0, 0};
       im[i][j] = f4{0, 0, 0, 0};
     }
-  int foff = (wr + accf_row(lane, 0)) * kGT + wc + accf_col(lane);
+  int foff = (wr + accf_row(lane, 0)) * kTs + wc + accf_col(lane);
   int soff = (threadIdx.x >> 2) * 4 + (threadIdx.x & 3);
   auto flush = [&]() __attribute__((always_inline)) {
     asm volatile("" : "+v"(foff));
     double *pl = pt + foff;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < kS; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < kS; ++j)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          double *p0 = pl + (i * 16 + e) * kGT + j * 16;
+          double *p0 = pl + (i * 16 + e) * kTs + j * 16;
           p0[0] += (double)re[i][j][e];
-          p0[kGT * kGT] += (double)im[i][j][e];
+          p0[kTs * kTs] += (double)im[i][j][e];
           re[i][j][e] = 0.f;
           im[i][j][e] = 0.f;
         }
@@ -711,13 +728,13 @@ __global__ __launch_bounds__(256, 2) void gram_f32_kernel(
     __syncthreads();
     asm volatile("" : "+v"(soff));
     const uint4 *src = wf + (long)kb * 8 * ldb + soff;
-    // item it: operand it / 4, part (it / 2) % 2, columns + 64 (it % 2)
+    // item it: operand, part, 64-column half hc
 #pragma unroll
-    for (int it = 0; it < 8; ++it) {
-      const int op = it >> 2, part = (it >> 1) & 1, hc = it & 1;
+    for (int it = 0; it < 4 * kHc; ++it) {
+      const int op = it / (2 * kHc), part = (it / kHc) % 2, hc = it % kHc;
       const uint4 v = src[(part * ldb + (op ? J0 : I0) + 64 * hc) * 4];
       const int col = (soff >> 2) + 64 * hc;
-      (op ? Bs : As)[(part * kGT + col) * kGColStride + (soff & 3)] = v;
+      (op ? Bs : As)[(part * kTs + col) * kGColStride + (soff & 3)] = v;
     }
     __syncthreads();
     float wv[4] = {1.0f, 1.0f, 1.0f, 1.0f};
@@ -728,18 +745,18 @@ __global__ __launch_bounds__(256, 2) void gram_f32_kernel(
       wv[2] = w4.z;
       wv[3] = w4.w;
     }
-    uint4 a[4][2];
+    uint4 a[kS][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < kS; ++i)
 #pragma unroll
       for (int pp = 0; pp < 2; ++pp)
-        a[i][pp] = As[(pp * kGT + wr + i * 16 + cl) * kGColStride + q];
+        a[i][pp] = As[(pp * kTs + wr + i * 16 + cl) * kGColStride + q];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kS; ++j) {
       uint4 b[2];
 #pragma unroll
       for (int pp = 0; pp < 2; ++pp)
-        b[pp] = Bs[(pp * kGT + wc + j * 16 + cl) * kGColStride + q];
+        b[pp] = Bs[(pp * kTs + wc + j * 16 + cl) * kGColStride + q];
       float br[4] = {__uint_as_float(b[0].x), __uint_as_float(b[0].y),
                      __uint_as_float(b[0].z), __uint_as_float(b[0].w)};
       float bi[4] = {__uint_as_float(b[1].x), __uint_as_float(b[1].y),
@@ -753,7 +770,7 @@ __global__ __launch_bounds__(256, 2) void gram_f32_kernel(
         }
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < kS; ++i) {
         const float ar[4] = {__uint_as_float(a[i][0].x), __uint_as_float(a[i][0].y),
                              __uint_as_float(a[i][0].z), __uint_as_float(a[i][0].w)};
         const float ai[4] = {__uint_as_float(a[i][1].x), __uint_as_float(a[i][1].y),
@@ -1052,25 +1069,26 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_wide_kernel(
 
 // One block per (tile, 1/kGRedParts of its elements).
 constexpr int kGRedParts = 16;
+template <int kTs>
 __global__ void gram_reduce_kernel(const double *__restrict__ partial,
                                    int n_tiles, int T, int nsplit, int ncol,
                                    double sign, double *__restrict__ out,
                                    int beta) {
   const int tile_id = blockIdx.x;
   const int2 tile = tri_tile_blocked(tile_id, T);
-  const int I0 = tile.x * kGT, J0 = tile.y * kGT;
-  constexpr int per = kGT * kGT / kGRedParts;
+  const int I0 = tile.x * kTs, J0 = tile.y * kTs;
+  constexpr int per = kTs * kTs / kGRedParts;
   const int e0 = blockIdx.y * per;
   for (int e = e0 + threadIdx.x; e < e0 + per; e += blockDim.x) {
-    const int r = e / kGT, c = e % kGT;
+    const int r = e / kTs, c = e % kTs;
     const int g = I0 + r, gp = J0 + c;
     if (g >= ncol || gp >= ncol) continue;
     if (tile.x == tile.y && r < c) continue;
     double sr = 0.0, si = 0.0;
     for (int s = 0; s < nsplit; ++s) {
-      const double *p = partial + ((long)s * n_tiles + tile_id) * 2L * kGT * kGT;
+      const double *p = partial + ((long)s * n_tiles + tile_id) * 2L * kTs * kTs;
       sr += p[e];
-      si += p[kGT * kGT + e];
+      si += p[kTs * kTs + e];
     }
     sr *= sign;
     si *= sign;
@@ -1104,7 +1122,7 @@ __global__ void gram_reduce_kernel(const double *__restrict__ partial,
 //    once) and the row weights of a K chunk per frequency; the Gram kernel
 //    forms the weighted J operand from the I copy while staging it.
 struct GramPlan {
-  int ldb, T, n_tiles, nsplit, kb_per_split, rows_step;
+  int ts, ldb, T, n_tiles, nsplit, kb_per_split, rows_step;
   bool resident_i;
   long kc, nchunks;
   size_t partial_bytes, i_bytes, j_bytes, w_bytes;
@@ -1114,8 +1132,13 @@ static GramPlan gram_plan(const HerkArgs &h, ssrpa_precision prec) {
   GramPlan p{};
   const bool bf = prec == SSRPA_BF16X3;
   p.rows_step = bf ? 32 : 16;
+  // Outputs up to kGSmallCols columns take 64-wide tiles: at N = 400 the
+  // 128-wide grid computes 2.0x the lower triangle, the 64-wide one 1.4x
+  // (4 resident blocks per CU instead of 2, half the MFMA work per staged
+  // byte).
+  p.ts = h.ncol <= kGSmallCols ? kGSmallTile : kGT;
   p.ldb = round_up(std::max(h.ncol, 1), kGT);
-  p.T = p.ldb / kGT;
+  p.T = round_up(std::max(h.ncol, 1), p.ts) / p.ts;
   p.n_tiles = p.T * (p.T + 1) / 2;
   // 8 bytes per column and row in both forms (4 bf16 parts or 2 floats)
   const size_t row_bytes = (size_t)p.ldb * 8;
@@ -1133,7 +1156,9 @@ static GramPlan gram_plan(const HerkArgs &h, ssrpa_precision prec) {
   // 57.2 ms); 10 tiles in one wave of 49 splits beat two waves (31.2
   // against 32.8 ms) and 52 splits (520 blocks, a nearly empty second wave:
   // 35.5 ms).
-  constexpr long kResident = 512;
+  // resident blocks: 256 CUs x (2 on 128-wide tiles; on 64-wide tiles 4 for
+  // BF16x3 (VGPRs and LDS), 5 for FP32 (VGPRs))
+  const long kResident = 256L * (p.ts == kGT ? 2 : (bf ? 4 : 5));
   const long min_waves = p.n_tiles >= kResident / 2 ? 2 : 1;
   const int smax = std::max(1, std::min<int>(nkb, (int)(4 * kResident / p.n_tiles)));
   int nsplit = 1;
@@ -1153,7 +1178,7 @@ static GramPlan gram_plan(const HerkArgs &h, ssrpa_precision prec) {
   }
   p.kb_per_split = (nkb + nsplit - 1) / nsplit;
   p.nsplit = (nkb + p.kb_per_split - 1) / p.kb_per_split;
-  p.partial_bytes = sizeof(double) * 2L * kGT * kGT * p.n_tiles * p.nsplit;
+  p.partial_bytes = sizeof(double) * 2L * p.ts * p.ts * p.n_tiles * p.nsplit;
   // several frequencies: the I rows are converted once (BF16x3: unweighted
   // I copy; FP32: unweighted rows, Delta applied to B in the Gram kernel)
   p.resident_i = h.n_omega > 1 && !h.unit_weight;
@@ -1162,6 +1187,33 @@ static GramPlan gram_plan(const HerkArgs &h, ssrpa_precision prec) {
   p.j_bytes = (bf && !p.resident_i) ? (size_t)p.kc * row_bytes : 0;
   p.w_bytes = p.resident_i ? (size_t)p.kc * sizeof(float) : 0;
   return p;
+}
+
+// One Gram pass over nkb row blocks: BF16x3 with I operand a and J operand b
+// (weighted = J formed from a and the row weights w), or FP32 on the copy a
+// (weighted = row weights w applied to B).
+template <int kTs>
+static void launch_gram(const GramPlan &p, bool bf, bool weighted, const uint4 *a,
+                        const uint4 *b, int nkb, const float *w, double *partial,
+                        hipStream_t s) {
+  const dim3 gg((unsigned)p.n_tiles, (unsigned)p.nsplit);
+  if (bf) {
+    if (weighted)
+      hipLaunchKernelGGL((gram_bf16x3_kernel<kTs, true>), gg, dim3(256),
+                         gram_lds(4, kTs), s, a, a, p.ldb, nkb, p.T, p.n_tiles,
+                         p.kb_per_split, w, partial);
+    else
+      hipLaunchKernelGGL((gram_bf16x3_kernel<kTs, false>), gg, dim3(256),
+                         gram_lds(4, kTs), s, a, b, p.ldb, nkb, p.T, p.n_tiles,
+                         p.kb_per_split, nullptr, partial);
+  } else if (weighted) {
+    hipLaunchKernelGGL((gram_f32_kernel<kTs, true>), gg, dim3(256), gram_lds(2, kTs),
+                       s, a, p.ldb, nkb, p.T, p.n_tiles, p.kb_per_split, w, partial);
+  } else {
+    hipLaunchKernelGGL((gram_f32_kernel<kTs, false>), gg, dim3(256),
+                       gram_lds(2, kTs), s, a, p.ldb, nkb, p.T, p.n_tiles,
+                       p.kb_per_split, nullptr, partial);
+  }
 }
 
 size_t herk_gram_workspace(const HerkArgs &h, ssrpa_precision prec) {
@@ -1184,15 +1236,21 @@ void herk_gram(Context *ctx, const HerkArgs &h, ssrpa_precision prec,
                                           p.j_bytes);
   static bool attr = [] {
     SSRPA_HIP(hipFuncSetAttribute(
-        reinterpret_cast<const void *>(&gram_bf16x3_kernel<false>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGLds));
+        reinterpret_cast<const void *>(&gram_bf16x3_kernel<kGT, false>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)gram_lds(4, kGT)));
     SSRPA_HIP(hipFuncSetAttribute(
-        reinterpret_cast<const void *>(&gram_bf16x3_kernel<true>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGLds));
+        reinterpret_cast<const void *>(&gram_bf16x3_kernel<kGT, true>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)gram_lds(4, kGT)));
     return true;
   }();
   (void)attr;
-  const dim3 gg((unsigned)p.n_tiles, (unsigned)p.nsplit);
+  auto gram = [&](bool weighted, const uint4 *a, const uint4 *b, int nkb,
+                  const float *w) {
+    if (p.ts == kGT)
+      launch_gram<kGT>(p, bf, weighted, a, b, nkb, w, partial, s);
+    else
+      launch_gram<kGSmallTile>(p, bf, weighted, a, b, nkb, w, partial, s);
+  };
   const long blk_stride = 16L * p.ldb;  // uint4 per row block (both forms)
   auto chunk_rows = [&](long c) {
     return (int)std::max<long>(0, std::min(p.kc, h.k - c * p.kc));
@@ -1234,9 +1292,7 @@ void herk_gram(Context *ctx, const HerkArgs &h, ssrpa_precision prec,
           if (nkb > 0)
             hipLaunchKernelGGL(row_weights_bf_kernel, dim3((n_pos + 255) / 256),
                                dim3(256), 0, s, h, k0, nrows, n_pos, om, wrow);
-          hipLaunchKernelGGL(gram_bf16x3_kernel<true>, gg, dim3(256), kGLds, s, ci,
-                             ci, p.ldb, nkb, p.T, p.n_tiles, p.kb_per_split, wrow,
-                             partial);
+          gram(true, ci, ci, nkb, wrow);
         } else {
           // one matrix: both copies from one read of the rows (weighting J
           // while staged would be redone by every tile of a column; with
@@ -1245,9 +1301,7 @@ void herk_gram(Context *ctx, const HerkArgs &h, ssrpa_precision prec,
           if (nkb > 0)
             hipLaunchKernelGGL(split_rows_bf16_kernel<true>, split_grid(nkb),
                                dim3(256), 0, s, h, k0, nrows, p.ldb, om, 1, wi, wj);
-          hipLaunchKernelGGL(gram_bf16x3_kernel<false>, gg, dim3(256), kGLds, s, wi,
-                             wj, p.ldb, nkb, p.T, p.n_tiles, p.kb_per_split, nullptr,
-                             partial);
+          gram(false, wi, wj, nkb, nullptr);
         }
       } else if (p.resident_i) {
         // unweighted rows converted once; this frequency's Delta per row
@@ -1255,16 +1309,12 @@ void herk_gram(Context *ctx, const HerkArgs &h, ssrpa_precision prec,
         if (nkb > 0)
           hipLaunchKernelGGL(row_weights_f32_kernel, dim3((n_pos + 255) / 256),
                              dim3(256), 0, s, h, k0, nrows, n_pos, om, wrow);
-        hipLaunchKernelGGL(gram_f32_kernel<true>, gg, dim3(256), kFLds, s,
-                           wi + c * (p.kc / 32) * blk_stride, p.ldb, nkb, p.T,
-                           p.n_tiles, p.kb_per_split, wrow, partial);
+        gram(true, wi + c * (p.kc / 32) * blk_stride, nullptr, nkb, wrow);
       } else {
         if (nkb > 0)
           hipLaunchKernelGGL(split_rows_f32_kernel, split_grid(nkb), dim3(256), 0,
                              s, h, k0, nrows, p.ldb, om, wi);
-        hipLaunchKernelGGL(gram_f32_kernel<false>, gg, dim3(256), kFLds, s, wi,
-                           p.ldb, nkb, p.T, p.n_tiles, p.kb_per_split, nullptr,
-                           partial);
+        gram(false, wi, nullptr, nkb, nullptr);
       }
       SSRPA_HIP(hipGetLastError());
     }
@@ -1273,9 +1323,15 @@ void herk_gram(Context *ctx, const HerkArgs &h, ssrpa_precision prec,
     // frequencies) the signed Delta on one
     const double scale = bf ? (h.unit_weight ? 1.0 / kGJScale : 1.0)
                             : (h.unit_weight || p.resident_i ? 1.0 : -1.0);
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)p.n_tiles, kGRedParts),
-                       dim3(256), 0, s, partial, p.n_tiles, p.T, p.nsplit, h.ncol,
-                       scale, out + om * out_stride, beta);
+    const dim3 rg((unsigned)p.n_tiles, kGRedParts);
+    if (p.ts == kGT)
+      hipLaunchKernelGGL(gram_reduce_kernel<kGT>, rg, dim3(256), 0, s, partial,
+                         p.n_tiles, p.T, p.nsplit, h.ncol, scale,
+                         out + om * out_stride, beta);
+    else
+      hipLaunchKernelGGL(gram_reduce_kernel<kGSmallTile>, rg, dim3(256), 0, s,
+                         partial, p.n_tiles, p.T, p.nsplit, h.ncol, scale,
+                         out + om * out_stride, beta);
     SSRPA_HIP(hipGetLastError());
   }
   if (ti >= 0) h.timer->stop(ti, s);

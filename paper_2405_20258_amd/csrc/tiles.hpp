@@ -15,6 +15,16 @@ __device__ __forceinline__ int xcd_remap(int b, int total) {
   return (b & 7) * per + (b >> 3);
 }
 
+// Logical index of this block when the whole grid (x fastest, then y, z;
+// gridDim.x = nx) is spread over the XCDs in contiguous runs: the blocks
+// of one XCD then cover a contiguous range of (z, y, x).  Split-K kernels
+// with y = split (and z = frequency) give each XCD few K ranges, so the
+// rows its blocks stage are fetched into its L2 about once.
+__device__ __forceinline__ int xcd_linear(int nx) {
+  const int l = blockIdx.x + nx * (blockIdx.y + (int)gridDim.y * blockIdx.z);
+  return xcd_remap(l, nx * (int)gridDim.y * (int)gridDim.z);
+}
+
 // Lower-triangle tile t -> (I, J) in blocks of kSB x kSB tiles: blocks in
 // lower-triangle order, tiles row by row inside a block.  Consecutive tile
 // ids (which the XCD remap keeps on one XCD) then share few operand panels,
