@@ -451,15 +451,24 @@ size_t plane_lds_bytes(int ny1, int ny2, int nxo) {
                             (size_t)S::W * S::L * S::SL) + cm;
 }
 
-// Work-group b -> pair (vl, cl) of a chunk of nvb x ncc pairs.  Work-groups
-// are dealt round-robin to the eight XCDs; on each XCD consecutive ones walk
-// an 8 x 8 tile of pairs, so the groups resident on one XCD share eight
-// valence and eight conduction orbitals through its L2.
-__device__ __forceinline__ bool chunk_pair(int b, int nvb, int ncc, int &vl,
-                                           int &cl) {
+// Work-group b -> pair (vl, cl) of a chunk of nvb x ncc pairs and z slab
+// zs of nslab.  Work-groups are dealt round-robin to the eight XCDs; on each
+// XCD consecutive ones walk an 8 x 8 tile of pairs for one slab of planes,
+// then the same tile for the next slab, so the groups resident on one XCD
+// share the planes of one slab of eight valence and eight conduction
+// orbitals through its L2 (short slabs keep them from drifting apart).
+#ifndef SSRPA_PLANE_SLABS
+#define SSRPA_PLANE_SLABS 6
+#endif
+constexpr int kPlaneSlabs = SSRPA_PLANE_SLABS;  // z slabs per pair
+__device__ __forceinline__ bool chunk_pair(int b, int nvb, int ncc, int nslab,
+                                           int &vl, int &cl, int &zs) {
   const int tiles_c = (ncc + 7) >> 3;
   const int xcd = b & 7, s = b >> 3;
-  const int tile = (s >> 6) * 8 + xcd;
+  const int r = s >> 6;
+  const int tl = r / nslab;
+  zs = r - tl * nslab;
+  const int tile = tl * 8 + xcd;
   const int q = s & 63;
   const int tv = tile / tiles_c, tc = tile - tv * tiles_c;
   vl = tv * 8 + (q >> 3);
@@ -519,7 +528,7 @@ template <int R1, int R2>
 __global__ __launch_bounds__((64 * LineSplit<R1, R2>::W)) void pair_plane_kernel(
     const double2 *__restrict__ psi, const double2 *__restrict__ psi_c, int v0,
     int nvb, int n_v, int c0,
-    int ncc, int n3, int m1, int m2, int nxo, const int *__restrict__ cmap_g,
+    int ncc, int n3, int nslab, int m1, int m2, int nxo, const int *__restrict__ cmap_g,
     int ldy, const double2 *__restrict__ tw_g, double2 *__restrict__ yst) {
   using S = LineSplit<R1, R2>;
   constexpr int N = S::N;
@@ -529,8 +538,10 @@ __global__ __launch_bounds__((64 * LineSplit<R1, R2>::W)) void pair_plane_kernel
   double2 *xo0 = tw + N;
   double2 *scr_all = xo0 + nxo * ny1 * S::XS;
   int *cmap = reinterpret_cast<int *>(scr_all + S::W * S::L * S::SL);
-  int vl, cl;
-  if (!chunk_pair(blockIdx.x, nvb, ncc, vl, cl)) return;
+  int vl, cl, zs;
+  if (!chunk_pair(blockIdx.x, nvb, ncc, nslab, vl, cl, zs)) return;
+  const int pz = (n3 + nslab - 1) / nslab;
+  const int z0 = zs * pz, z1 = min(n3, z0 + pz);
   for (int t = threadIdx.x; t < N; t += blockDim.x) tw[t] = tw_g[t];
   for (int t = threadIdx.x; t < ny1 * ny2; t += blockDim.x) cmap[t] = cmap_g[t];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -550,7 +561,7 @@ __global__ __launch_bounds__((64 * LineSplit<R1, R2>::W)) void pair_plane_kernel
   constexpr int nbx = (N + S::L - 1) / S::L;
   const int nby = (ny1 + S::L - 1) / S::L;
   __syncthreads();
-  for (int j3 = 0; j3 < n3; ++j3) {
+  for (int j3 = z0; j3 < z1; ++j3) {
     double2 *xo = xo0 + (nxo == 2 ? (j3 & 1) : 0) * ny1 * S::XS;
     const double2 *sv = pv + j3 * plane;
     const double2 *sc = pc + j3 * plane;
@@ -765,10 +776,12 @@ void staged_pairs(System &sys, int v0, int nvb, const double *gscale,
   for (int c0 = 0; c0 < sys.orb_nc; c0 += ncc_max) {
     const int ncc = std::min(ncc_max, sys.orb_nc - c0);
     const long tiles = (long)((nvb + 7) / 8) * ((ncc + 7) / 8);
-    const long blocks = (tiles + 7) / 8 * 8 * 64;
+    const int nslab = std::min(kPlaneSlabs, g.n3);
+    const long blocks = (tiles + 7) / 8 * 8 * 64 * nslab;
     SSRPA_REQUIRE(blocks < (1L << 31), SSRPA_ERR_ARG, "pair grid too large");
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * S::W), lds, s,
-                       psi, psi_c, v0, nvb, sys.orb_c0, c0, ncc, g.n3, g.m1, g.m2, nxo,
+                       psi, psi_c, v0, nvb, sys.orb_c0, c0, ncc, g.n3, nslab, g.m1,
+                       g.m2, nxo,
                        sys.cmap.as<int>(), g.ldy, tw, yst);
     SSRPA_HIP(hipGetLastError());
     if (zfft) {
