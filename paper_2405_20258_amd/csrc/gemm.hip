@@ -182,6 +182,7 @@ __global__ __launch_bounds__(256, 2) void herk_f64_pair_kernel(
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const unsigned live = live_subtiles<2>(I0 + wr, J0 + wc, h.ncol);
   d4 re[2][2][2], im[2][2][2];   // [frequency][i][j]
 #pragma unroll
   for (int f = 0; f < 2; ++f)
@@ -252,6 +253,7 @@ __global__ __launch_bounds__(256, 2) void herk_f64_pair_kernel(
         for (int i = 0; i < 2; ++i)
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
+            if (!(live >> (2 * i + j) & 1u)) continue;
             re[f][i][j] = mfma64(ar[i], bw[j], re[f][i][j]);
             re[f][i][j] = mfma64(ai[i], biw[j], re[f][i][j]);
             im[f][i][j] = mfma64(ar[i], biw[j], im[f][i][j]);

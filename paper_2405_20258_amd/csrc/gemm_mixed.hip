@@ -490,7 +490,7 @@ __device__ __forceinline__ void reweight_quarter(const uint4 (&in)[4],
 template <int kTs, bool kWJ>
 __global__ __launch_bounds__(256, kTs == 128 ? 2 : 4) void gram_bf16x3_kernel(
     const uint4 *__restrict__ wi, const uint4 *__restrict__ wj, int ldb,
-    int nkb, int T, int n_tiles, int kb_per_split,
+    int ncol, int nkb, int T, int n_tiles, int kb_per_split,
     const float *__restrict__ wrow, double *__restrict__ partial) {
   constexpr int kS = kTs / 32;    // 16 x 16 MFMA tiles per wave side
   constexpr int kHc = kTs / 64;   // 64-column halves of a panel
@@ -505,6 +505,7 @@ __global__ __launch_bounds__(256, kTs == 128 ? 2 : 4) void gram_bf16x3_kernel(
   const int kb1 = min(nkb, kb0 + kb_per_split);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = (wave >> 1) * (kTs / 2), wc = (wave & 1) * (kTs / 2);
+  const unsigned live = live_subtiles<kS>(I0 + wr, J0 + wc, ncol);
   const int q = lane >> 4, cl = lane & 15;
   double *pt = partial + ((long)split * n_tiles + tile_id) * 2L * kTs * kTs;
   f4 re[kS][kS], im[kS][kS];
@@ -594,6 +595,7 @@ __global__ __launch_bounds__(256, kTs == 128 ? 2 : 4) void gram_bf16x3_kernel(
       const bf8 nbh = neg_bf8(b[0]), nbl = neg_bf8(b[1]);
 #pragma unroll
       for (int i = 0; i < kS; ++i) {
+        if (!(live >> (kS * i + j) & 1u)) continue;
         // Re += ar br + ai bi;  Im += ar bi - ai br  (hi*hi + hi*lo + lo*hi)
         re[i][j] = mfmabf(a[i][0], b[0], re[i][j]);
         re[i][j] = mfmabf(a[i][0], b[1], re[i][j]);
@@ -679,7 +681,7 @@ __global__ __launch_bounds__(256) void row_weights_bf_kernel(
 
 template <int kTs, bool kWeighted>
 __global__ __launch_bounds__(256, kTs == 128 ? 2 : 4) void gram_f32_kernel(
-    const uint4 *__restrict__ wf, int ldb, int nkb, int T, int n_tiles,
+    const uint4 *__restrict__ wf, int ldb, int ncol, int nkb, int T, int n_tiles,
     int kb_per_split, const float *__restrict__ wrow,
     double *__restrict__ partial) {
   constexpr int kS = kTs / 32;    // 16 x 16 MFMA tiles per wave side
@@ -695,6 +697,7 @@ __global__ __launch_bounds__(256, kTs == 128 ? 2 : 4) void gram_f32_kernel(
   const int kb1 = min(nkb, kb0 + kb_per_split);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = (wave >> 1) * (kTs / 2), wc = (wave & 1) * (kTs / 2);
+  const unsigned live = live_subtiles<kS>(I0 + wr, J0 + wc, ncol);
   const int q = lane >> 4, cl = lane & 15;
   double *pt = partial + ((long)split * n_tiles + tile_id) * 2L * kTs * kTs;
   f4 re[kS][kS], im[kS][kS];
@@ -771,6 +774,7 @@ __global__ __launch_bounds__(256, kTs == 128 ? 2 : 4) void gram_f32_kernel(
       }
 #pragma unroll
       for (int i = 0; i < kS; ++i) {
+        if (!(live >> (kS * i + j) & 1u)) continue;
         const float ar[4] = {__uint_as_float(a[i][0].x), __uint_as_float(a[i][0].y),
                              __uint_as_float(a[i][0].z), __uint_as_float(a[i][0].w)};
         const float ai[4] = {__uint_as_float(a[i][1].x), __uint_as_float(a[i][1].y),
@@ -1122,7 +1126,7 @@ __global__ void gram_reduce_kernel(const double *__restrict__ partial,
 //    once) and the row weights of a K chunk per frequency; the Gram kernel
 //    forms the weighted J operand from the I copy while staging it.
 struct GramPlan {
-  int ts, ldb, T, n_tiles, nsplit, kb_per_split, rows_step;
+  int ts, ncol, ldb, T, n_tiles, nsplit, kb_per_split, rows_step;
   bool resident_i;
   long kc, nchunks;
   size_t partial_bytes, i_bytes, j_bytes, w_bytes;
@@ -1137,6 +1141,7 @@ static GramPlan gram_plan(const HerkArgs &h, ssrpa_precision prec) {
   // (4 resident blocks per CU instead of 2, half the MFMA work per staged
   // byte).
   p.ts = h.ncol <= kGSmallCols ? kGSmallTile : kGT;
+  p.ncol = h.ncol;
   p.ldb = round_up(std::max(h.ncol, 1), kGT);
   p.T = round_up(std::max(h.ncol, 1), p.ts) / p.ts;
   p.n_tiles = p.T * (p.T + 1) / 2;
@@ -1157,8 +1162,8 @@ static GramPlan gram_plan(const HerkArgs &h, ssrpa_precision prec) {
   // against 32.8 ms) and 52 splits (520 blocks, a nearly empty second wave:
   // 35.5 ms).
   // resident blocks: 256 CUs x (2 on 128-wide tiles; on 64-wide tiles 4 for
-  // BF16x3 (VGPRs and LDS), 5 for FP32 (VGPRs))
-  const long kResident = 256L * (p.ts == kGT ? 2 : (bf ? 4 : 5));
+  // BF16x3 (VGPRs and LDS), 6 for FP32 (VGPRs))
+  const long kResident = 256L * (p.ts == kGT ? 2 : (bf ? 4 : 6));
   const long min_waves = p.n_tiles >= kResident / 2 ? 2 : 1;
   const int smax = std::max(1, std::min<int>(nkb, (int)(4 * kResident / p.n_tiles)));
   int nsplit = 1;
@@ -1200,18 +1205,19 @@ static void launch_gram(const GramPlan &p, bool bf, bool weighted, const uint4 *
   if (bf) {
     if (weighted)
       hipLaunchKernelGGL((gram_bf16x3_kernel<kTs, true>), gg, dim3(256),
-                         gram_lds(4, kTs), s, a, a, p.ldb, nkb, p.T, p.n_tiles,
+                         gram_lds(4, kTs), s, a, a, p.ldb, p.ncol, nkb, p.T, p.n_tiles,
                          p.kb_per_split, w, partial);
     else
       hipLaunchKernelGGL((gram_bf16x3_kernel<kTs, false>), gg, dim3(256),
-                         gram_lds(4, kTs), s, a, b, p.ldb, nkb, p.T, p.n_tiles,
+                         gram_lds(4, kTs), s, a, b, p.ldb, p.ncol, nkb, p.T, p.n_tiles,
                          p.kb_per_split, nullptr, partial);
   } else if (weighted) {
     hipLaunchKernelGGL((gram_f32_kernel<kTs, true>), gg, dim3(256), gram_lds(2, kTs),
-                       s, a, p.ldb, nkb, p.T, p.n_tiles, p.kb_per_split, w, partial);
+                       s, a, p.ldb, p.ncol, nkb, p.T, p.n_tiles, p.kb_per_split, w,
+                       partial);
   } else {
     hipLaunchKernelGGL((gram_f32_kernel<kTs, false>), gg, dim3(256),
-                       gram_lds(2, kTs), s, a, p.ldb, nkb, p.T, p.n_tiles,
+                       gram_lds(2, kTs), s, a, p.ldb, p.ncol, nkb, p.T, p.n_tiles,
                        p.kb_per_split, nullptr, partial);
   }
 }

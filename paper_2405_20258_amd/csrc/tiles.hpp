@@ -25,6 +25,25 @@ __device__ __forceinline__ int xcd_linear(int nx) {
   return xcd_remap(l, nx * (int)gridDim.y * (int)gridDim.z);
 }
 
+// Sub-tiles of one wave that the result needs: bit n i + j (i, j < n) is
+// set when the 16 x 16 sub-tile at rows r0 + 16 i, columns c0 + 16 j holds
+// an element of the lower triangle (row >= column) of an ncol x ncol
+// matrix.  The others (above the diagonal of a diagonal tile, or in the
+// padding past ncol) are dropped by the reductions, so their products are
+// skipped.  The mask is made wave-uniform.
+template <int n>
+__device__ __forceinline__ unsigned live_subtiles(int r0, int c0, int ncol) {
+  unsigned m = 0;
+#pragma unroll
+  for (int i = 0; i < n; ++i)
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+      const int r = r0 + 16 * i, c = c0 + 16 * j;
+      if (r < ncol && c < ncol && r + 15 >= c) m |= 1u << (n * i + j);
+    }
+  return __builtin_amdgcn_readfirstlane(m);
+}
+
 // Lower-triangle tile t -> (I, J) in blocks of kSB x kSB tiles: blocks in
 // lower-triangle order, tiles row by row inside a block.  Consecutive tile
 // ids (which the XCD remap keeps on one XCD) then share few operand panels,
