@@ -435,9 +435,11 @@ void gemm_mixed_launch(const GemmArgs &g, ssrpa_precision prec, int m_tiles,
 // Tiles, K split and partial-tile bytes of an FP64 HERK.  K is split so
 // that the blocks fill whole waves of the resident blocks (3 per CU for the
 // one-frequency kernel, 2 for the two-frequency one): the fewest splits
-// whose last wave is at least 95% full, else the fullest, with at least 8 K
-// chunks per split.  (Rounding 512 blocks up left 1953 medium chi0 tiles at
-// 2.5 waves, 85% full, and the 16 medium frequencies at 448 of 512.)
+// (up to 8, or 4 x the resident blocks) whose last wave is at least 98%
+// full, else the fullest, with at least 8 K chunks per split.  (Rounding 512
+// blocks up left 1953 medium chi0 tiles at 2.5 waves, 85% full, and the 16
+// medium frequencies at 448 of 512; 3 splits fill 95.4% of 8 waves, 7
+// splits 98.9% of 18.)
 struct HerkF64Plan {
   int T, n_tiles;
   long nsplit, kchunk;
@@ -454,14 +456,14 @@ static HerkF64Plan herk_f64_plan(const HerkArgs &h) {
   const int kst = kKc;
   const long kr = std::max(1L, (h.k + kst - 1) / kst);
   const long smax =
-      std::max(1L, std::min(kr / 8, std::max(4L, 4 * resident / std::max(1L, per_split))));
+      std::max(1L, std::min(kr / 8, std::max(8L, 4 * resident / std::max(1L, per_split))));
   long nsplit = 1;
   double best = 0.0;
   for (long sp = 1; sp <= smax; ++sp) {
     const long blocks = per_split * sp;
     const long waves = (blocks + resident - 1) / resident;
     const double fill = (double)blocks / (double)(waves * resident);
-    if (fill >= 0.95) {
+    if (fill >= 0.98) {
       nsplit = sp;
       break;
     }
