@@ -731,6 +731,15 @@ __global__ __launch_bounds__(256, kTs == 128 ? 2 : 4) void gram_f32_kernel(
     __syncthreads();
     asm volatile("" : "+v"(soff));
     const uint4 *src = wf + (long)kb * 8 * ldb + soff;
+    // the lane's row weights, loaded with the rows (used after the barrier)
+    float wv[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+    if constexpr (kWeighted) {
+      const float4 w4 = *reinterpret_cast<const float4 *>(wrow + kb * 16 + 4 * q);
+      wv[0] = w4.x;
+      wv[1] = w4.y;
+      wv[2] = w4.z;
+      wv[3] = w4.w;
+    }
     // item it: operand, part, 64-column half hc
 #pragma unroll
     for (int it = 0; it < 4 * kHc; ++it) {
@@ -740,14 +749,6 @@ __global__ __launch_bounds__(256, kTs == 128 ? 2 : 4) void gram_f32_kernel(
       (op ? Bs : As)[(part * kTs + col) * kGColStride + (soff & 3)] = v;
     }
     __syncthreads();
-    float wv[4] = {1.0f, 1.0f, 1.0f, 1.0f};
-    if constexpr (kWeighted) {
-      const float4 w4 = *reinterpret_cast<const float4 *>(wrow + kb * 16 + 4 * q);
-      wv[0] = w4.x;
-      wv[1] = w4.y;
-      wv[2] = w4.z;
-      wv[3] = w4.w;
-    }
     uint4 a[kS][2];
 #pragma unroll
     for (int i = 0; i < kS; ++i)
