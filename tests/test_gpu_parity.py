@@ -515,6 +515,35 @@ def test_medium_mixed_precision_sweep():
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("n_freq", [1, 2, 3, 5])
+def test_reduced_precision_frequency_counts(env, prec, n_freq):
+    """The reduced-precision subspace contraction for any number of
+    frequencies (FP32 takes two frequencies per Gram pass, with a
+    one-frequency pass for an odd count; one frequency alone uses the
+    single-matrix path): every F_j within 1e-5 of the FP64 path's on the same
+    subspace, and different from it (the reduced arithmetic ran)."""
+    torch, ssrpa, ctx = env
+    from synth import systems as sy
+    s = sy.make_system(sy.TINY, 1000)
+    om, wt = sy.frequency_grid(n_freq)
+    g = ssrpa.System.from_synthetic(ctx, s)
+    try:
+        g.chi0_static("fp64")
+        g.subspace(75)
+        ec64, f64 = g.correlation_energy(75, om, wt, "fp64")
+        ecp, fp = g.correlation_energy(75, om, wt, prec)
+    finally:
+        g.close()
+    rel = np.abs(fp - f64) / np.abs(f64)
+    _log(f"{prec} n_freq={n_freq}: max F_j rel {rel.max():.2e}, "
+         f"E_c {ecp!r} vs {ec64!r}")
+    assert len(fp) == n_freq
+    assert rel.max() < 1e-5
+    assert abs(ecp - ec64) < 1e-5 * abs(ec64)
+    assert rel.max() > 1e-14, "reduced precision path did not run"
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_precision_modes_tiny(env, prec):
     """Reduced-precision contractions: E_c within 1e-5 of the FP64 oracle.
 
