@@ -1181,17 +1181,17 @@ static GramPlan gram_plan(const HerkArgs &h, ssrpa_precision prec) {
   p.kc = std::min(kmax, k32);
   p.nchunks = std::max<long>(1, (h.k + p.kc - 1) / p.kc);
   const int nkb = (int)(p.kc / p.rows_step);
-  // Split K so that the blocks of one frequency fill whole waves of the 512
-  // resident blocks (two per CU): the fewest splits whose last wave is at
-  // least 95% full (and, from 256 tiles, that give two waves or more), else
-  // the fullest, within 2048 blocks.  Split s of every tile covers the same
-  // K range, so blocks of one wave share staged rows in L2.  Measured on
-  // BF16x3: 496 tiles in two waves of half K beat one wave (55.9 against
-  // 57.2 ms); 10 tiles in one wave of 49 splits beat two waves (31.2
-  // against 32.8 ms) and 52 splits (520 blocks, a nearly empty second wave:
-  // 35.5 ms).
-  // resident blocks: 256 CUs x (2 on 128-wide tiles; on 64-wide tiles 4 for
-  // BF16x3 (VGPRs and LDS), 6 for FP32 (VGPRs))
+  // Split K so that the blocks of one frequency fill whole waves of the
+  // resident blocks: the fewest splits whose last wave is at least 95% full
+  // (and, from half a wave of tiles, that give two waves or more), else the
+  // fullest, within 4 waves.  Split s of every tile covers the same K range,
+  // so blocks of one wave share staged rows in L2.  Measured on BF16x3 with
+  // 128-wide tiles (512 resident): 496 tiles in two waves of half K beat one
+  // wave (55.9 against 57.2 ms); 10 tiles in one wave of 49 splits beat two
+  // waves (31.2 against 32.8 ms) and 52 splits (520 blocks, a nearly empty
+  // second wave: 35.5 ms).
+  // Resident blocks: 256 CUs x (2 on 128-wide tiles; on 64-wide tiles 4 for
+  // BF16x3 (VGPRs and LDS), 6 for FP32 (VGPRs)).
   const long kResident = 256L * (p.ts == kGT ? 2 : (bf ? 4 : 6));
   const long min_waves = p.n_tiles >= kResident / 2 ? 2 : 1;
   const int smax = std::max(1, std::min<int>(nkb, (int)(4 * kResident / p.n_tiles)));
