@@ -8,8 +8,8 @@ compare every element of chi0 at the workloads' own N_G (304, 3958 and
 
 * tiny workload, all 16 x 240 pairs (the contraction splits K 30 ways):
   the symmetrized v^1/2 chi0 v^1/2 and the paper's chi0, 1e-10;
-* medium geometry (48^3, N_G = 3958) with 2 x 256 pairs, which gives the
-  same 3-way K split as the whole medium workload: every element of W
+* medium geometry (48^3, N_G = 3958) with 4 x 256 pairs, which gives the
+  same 7-way K split as the whole medium workload: every element of W
   (1e-12) and of chi0 (FP64 1e-10, FP32 and BF16x3 2e-5);
 * large-share geometry (72^3, N_G = 15966, 250 tiles per side) with
   2 x 48 pairs: every element of W (1e-12) and of chi0 (FP64 1e-10, FP32
@@ -107,8 +107,8 @@ def medium_geometry(env):
     torch, ssrpa, ctx = env
     from oracle import rpa
     from synth import systems as sy
-    s = sy.make_system(sy.MEDIUM, 2999, n_v=2, n_c=256)
-    _log("medium geometry (48^3, N_G = 3958, 2 x 256 pairs): system create")
+    s = sy.make_system(sy.MEDIUM, 2999, n_v=4, n_c=256)
+    _log("medium geometry (48^3, N_G = 3958, 4 x 256 pairs): system create")
     g = ssrpa.System.from_synthetic(ctx, s)
     mo, perm = _perm(g, s)
     _, w = _oracle_w(s, mo)
