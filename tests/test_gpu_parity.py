@@ -544,6 +544,30 @@ def test_reduced_precision_frequency_counts(env, prec, n_freq):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("n_eig", [1, 64, 65])
+def test_reduced_precision_subspace_edges(env, prec, n_eig):
+    """Subspace contractions on 64-wide Gram tiles at their edge sizes (one
+    column, exactly one tile, one tile and one column): every F_j of three
+    frequencies within 1e-5 of the FP64 path's on the same subspace."""
+    torch, ssrpa, ctx = env
+    from synth import systems as sy
+    s = sy.make_system(sy.TINY, 1000)
+    om, wt = sy.frequency_grid(3)
+    g = ssrpa.System.from_synthetic(ctx, s)
+    try:
+        g.chi0_static("fp64")
+        g.subspace(n_eig)
+        ec64, f64 = g.correlation_energy(n_eig, om, wt, "fp64")
+        ecp, fp = g.correlation_energy(n_eig, om, wt, prec)
+    finally:
+        g.close()
+    rel = np.abs(fp - f64) / np.abs(f64)
+    _log(f"{prec} n_eig={n_eig}: max F_j rel {rel.max():.2e}")
+    assert rel.max() < 1e-5
+    assert abs(ecp - ec64) < 1e-5 * abs(ec64)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_precision_modes_tiny(env, prec):
     """Reduced-precision contractions: E_c within 1e-5 of the FP64 oracle.
 
