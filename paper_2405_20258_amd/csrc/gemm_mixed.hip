@@ -344,14 +344,16 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_kernel(GemmArgs g,
 // sum_p conj(a_p[I]) b_p[J] over 128 x 128 tiles of the lower triangle
 // (64 x 64 for outputs of at most kGSmallCols columns).
 // FP32 accumulators are added into the block's own FP64 partial tile every
-// 1024 (FP32) or 4096 (BF16x3) rows, and gram_reduce_kernel sums the split-K partials in order and
-// mirrors the Hermitian half (deterministic).
+// 1024 (FP32) or 4096 (BF16x3) rows, and gram_reduce_kernel sums the
+// split-K partials in order and mirrors the Hermitian half (deterministic).
 //  * BF16x3: the I operand is the rows as they are, the J operand the rows
 //    times d_p; each real part is split hi + lo (bf16) and a product is
 //    hi hi' + hi lo' + lo hi'.  For several frequencies the I copy of the
-//    whole K range is split once and reused.
+//    whole K range is split once and reused, and the Gram kernel forms
+//    each frequency's J operand from it while staging.
 //  * FP32: one copy of the rows times sqrt|d_p| (the d_p of one HERK have
-//    one sign, restored by the reduction), rounded to FP32.
+//    one sign, restored by the reduction), rounded to FP32; for several
+//    frequencies the unweighted rows, d_p applied to the B fragments.
 
 constexpr int kGT = 128;          // Gram tile side (GEMMs; Gram kernels of
                                    // large outputs), also the column
